@@ -1,0 +1,168 @@
+"""Oracle -- TEST INFRASTRUCTURE ONLY.
+
+A plain serial FP64 CPU implementation of the per-particle Voronoi cell
+construction of Voro++ (Lu, Lazar & Rycroft, section 2.1), written in C
+(``voro_oracle.c``) and loaded here with ctypes, plus an exact rational brute
+force (``brute.py``).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the GPU library and imports nothing from it.
+
+Per-cell results (section 2.1.2 and the topology discussion of section 4):
+volume, centroid relative to the particle, vertex / edge / face counts, the
+face-order vector fo[k] = number of faces with k edges, and one neighbour label
+(j, image code) per face.  Labels -1..-6 are the walls x-, x+, y-, y+, z-, z+;
+the image code of a periodic shift s is 25(s_z+2) + 5(s_y+2) + (s_x+2).
+"""
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "voro_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+FO_LEN = 32
+TAU = 2.0 ** -30  # FP64 band inside which the side test is decided exactly
+
+COUNTER_NAMES = ["candidates", "radius_rejects", "vertex_tests", "cuts",
+                 "new_vertices", "fan_triangles", "exact_decisions", "shells"]
+
+
+def build(force=False):
+    """Compile the oracle with gcc (plain C11, no FMA contraction, OpenMP)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fopenmp",
+                           "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.vo_create.restype = P
+        lib.vo_create.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, P, P]
+        lib.vo_destroy.argtypes = [P]
+        lib.vo_cells.restype = ctypes.c_int
+        lib.vo_cells.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                                 P, P, P, P, P, P, P, P, ctypes.c_int, P, P, P]
+        lib.vo_exact_side.restype = ctypes.c_int
+        lib.vo_exact_side.argtypes = [ctypes.c_int, P]
+        lib.vo_num_threads.restype = ctypes.c_int
+        lib.vo_cell_vertices.restype = ctypes.c_int
+        lib.vo_cell_vertices.argtypes = [P, ctypes.c_int64, ctypes.c_double, P, ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def grid_size(n, lo, hi, n_opt=5.0):
+    """Block counts of section 2.1.4: lambda = (N / (N_opt Vol))^(1/d),
+    n_d = ceil(lambda (b_d - a_d))."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    d = len(lo)
+    vol = float(np.prod(hi - lo))
+    lam = (n / (n_opt * vol)) ** (1.0 / d)
+    return [max(1, int(math.ceil(lam * (hi[k] - lo[k])))) for k in range(d)]
+
+
+def exact_side(rows, dim=3):
+    """Exact sign of n_p.v - h_p at the vertex where planes rows[0..dim) meet;
+    rows = 4 x (n0, n1, n2, h, wall) (row 2 unused in 2D, row 3 is p)."""
+    r = np.ascontiguousarray(np.asarray(rows, dtype=np.float64).reshape(4, 5))
+    return _load().vo_exact_side(dim, r.ctypes.data)
+
+
+class Oracle:
+    """Serial FP64 cells of a container (box [lo, hi], per-axis periodicity)."""
+
+    def __init__(self, xyz, lo, hi, periodic, grid=None, n_opt=5.0):
+        lib = _load()
+        self.xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64))
+        self.n, self.dim = self.xyz.shape
+        self.lo = np.asarray(lo, float)
+        self.hi = np.asarray(hi, float)
+        self.periodic = [int(bool(p)) for p in periodic]
+        if grid is None:
+            grid = grid_size(self.n, self.lo, self.hi, n_opt)
+        self.grid = [int(g) for g in grid]
+        lo3 = np.zeros(3)
+        hi3 = np.ones(3)
+        lo3[:self.dim] = self.lo
+        hi3[:self.dim] = self.hi
+        per = np.zeros(3, np.int32)
+        per[:self.dim] = self.periodic
+        g = np.ones(3, np.int32)
+        g[:self.dim] = self.grid
+        self._keep = (lo3, hi3, per, g)
+        self._h = lib.vo_create(self.dim, self.xyz.ctypes.data, self.n, lo3.ctypes.data,
+                                hi3.ctypes.data, per.ctypes.data, g.ctypes.data)
+        if not self._h:
+            raise ValueError("oracle: bad container arguments")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _load().vo_destroy(self._h)
+            self._h = None
+
+    def cells(self, idx=None, nthreads=1, tau=TAU, maxnb=256, neighbors=True):
+        """Cells of the particles idx (default: all).  Returns a dict of numpy
+        arrays: vol, cen (m x dim), nv, ne, nf, fo (m x 32), perim, status,
+        nbr (list of sorted (label, image) int64 arrays, one per cell),
+        counters (dict)."""
+        lib = _load()
+        idx = np.arange(self.n, dtype=np.int64) if idx is None else np.ascontiguousarray(idx, dtype=np.int64)
+        m = len(idx)
+        vol = np.zeros(m)
+        cen = np.zeros((m, 3))
+        nv = np.zeros(m, np.int32)
+        ne = np.zeros(m, np.int32)
+        nf = np.zeros(m, np.int32)
+        fo = np.zeros((m, FO_LEN), np.int32)
+        perim = np.zeros(m)
+        status = np.zeros(m, np.int32)
+        cnt = np.zeros(len(COUNTER_NAMES), np.int64)
+        if neighbors:
+            nbr = np.zeros((m, maxnb), np.int32)
+            nsh = np.zeros((m, maxnb), np.int32)
+            pn, ps = nbr.ctypes.data, nsh.ctypes.data
+        else:
+            pn = ps = None
+        rc = lib.vo_cells(self._h, idx.ctypes.data, m, nthreads, tau, vol.ctypes.data, cen.ctypes.data,
+                          nv.ctypes.data, ne.ctypes.data, nf.ctypes.data, fo.ctypes.data, pn, ps, maxnb,
+                          perim.ctypes.data, status.ctypes.data, cnt.ctypes.data)
+        out = dict(vol=vol, cen=cen[:, :self.dim], nv=nv, ne=ne, nf=nf, fo=fo, perim=perim, status=status,
+                   rc=rc, counters=dict(zip(COUNTER_NAMES, cnt.tolist())))
+        if neighbors:
+            lists = []
+            for t in range(m):
+                k = int(nf[t])
+                lab = np.stack([nbr[t, :k].astype(np.int64), nsh[t, :k].astype(np.int64)], axis=1)
+                order = np.lexsort((lab[:, 1], lab[:, 0]))
+                lists.append(lab[order])
+            out["nbr"] = lists
+        if rc != 0:
+            raise RuntimeError(f"oracle: cell computation failed with code {rc}")
+        return out
+
+    def vertices(self, i, tau=TAU):
+        """Vertices of the cell of particle i, relative to the particle."""
+        buf = np.zeros((4096, 3))
+        k = _load().vo_cell_vertices(self._h, int(i), tau, buf.ctypes.data, 4096)
+        if k < 0:
+            raise RuntimeError(f"oracle: cell computation failed with code {k}")
+        return buf[:k, :self.dim].copy()
+
+
+def num_threads():
+    return _load().vo_num_threads()
