@@ -1,0 +1,190 @@
+/*
+ * vorohip.h -- C ABI of the MI355X (gfx950) Voronoi cell library.
+ *
+ * The library computes, for every particle of a container, its Voronoi cell
+ * by the cell-based method of Voro++ (Lu, Lazar & Rycroft, section 2.1): the
+ * cell starts as the container box (Eq. 1-2), is cut by the bisector
+ * half-space of each nearby particle (Eq. 3) taken from a grid of blocks in
+ * nearest-first order (section 2.1.3), and stops once no remaining particle
+ * can reach it (radius bound, section 2.1.3).  Statistics of each cell are
+ * then written out.
+ *
+ * Conventions shared by every call:
+ *  - Every function returns a vc_status: VC_OK (0) or a negative error code.
+ *    The message of the last error on the calling thread is vc_last_error().
+ *    Nothing throws across this boundary.
+ *  - Pointers named "device" are HIP device memory; "host" pointers are host
+ *    memory.  Positions may be either (the library detects which).
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    All GPU work of a call is enqueued on that stream; a call returns once
+ *    its work is enqueued, except where stated.
+ *  - Handles are owned by the library and freed by the matching destroy call.
+ *    A container or result may be used by one host thread at a time.
+ *  - Per-cell outputs are indexed by input order (particle id).
+ */
+#ifndef VOROHIP_H
+#define VOROHIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int vc_status;
+enum {
+    VC_OK = 0,
+    VC_E_ARG = -1,       /* null pointer, n < 1, hi <= lo, dim not 2 or 3, bad option */
+    VC_E_RANGE = -2,     /* a coordinate outside the box, or NaN / Inf */
+    VC_E_DUPLICATE = -3, /* two particles (or a particle and an image) coincide */
+    VC_E_NOMEM = -4,     /* device allocation failed */
+    VC_E_HIP = -5,       /* a HIP runtime call failed */
+    VC_E_CAPACITY = -6,  /* a cell exceeded the largest capacity the library has */
+    VC_E_STATE = -7      /* call made on a handle in the wrong state */
+};
+
+/* arithmetic of the plane-side vertex test (a5) */
+enum { VC_FP64 = 0, VC_F32_FILTER = 1 };
+
+/* statistics mask for vc_compute */
+enum {
+    VC_VOLUME = 1,          /* volume (3D) or area (2D) */
+    VC_CENTROID = 2,        /* centroid relative to the particle */
+    VC_COUNTS = 4,          /* vertex, edge and face counts */
+    VC_FACE_ORDERS = 8,     /* face-order vector (3D) */
+    VC_NEIGHBORS = 16,      /* neighbour list, CSR (implies the counts' face count) */
+    VC_NEIGHBOR_COUNT = 32, /* number of neighbours (faces) only */
+    VC_DIAG = 64,           /* run counters (exact decisions, rechecks, spills, ...) */
+    VC_ALL = 127
+};
+
+/* result fields for vc_result_get / vc_result_copy */
+enum {
+    VC_F_VOLUME = 0,      /* double[n] */
+    VC_F_CENTROID = 1,    /* double[n * dim], particle-major */
+    VC_F_NV = 2,          /* int32[n] vertex count */
+    VC_F_NE = 3,          /* int32[n] edge count */
+    VC_F_NF = 4,          /* int32[n] face (neighbour) count */
+    VC_F_FACE_ORDERS = 5, /* uint8[n * VC_FO_LEN]: fo[k] = faces with k edges */
+    VC_F_NBR_OFFSETS = 6, /* int64[n + 1] CSR offsets into the two arrays below */
+    VC_F_NBR_IDS = 7,     /* int32[total]: neighbour particle id, or -1..-6 for the
+                             walls x-, x+, y-, y+, z-, z+ (2D: -1..-4) */
+    VC_F_NBR_SHIFTS = 8,  /* uint8[total]: periodic image code
+                             25(s_z+2) + 5(s_y+2) + (s_x+2), 62 = no shift */
+    VC_F_STATUS = 9,      /* uint8[n]: VC_CELL_* */
+    VC_F_DIAG = 10        /* int64[VC_DIAG_LEN] */
+};
+#define VC_FO_LEN 32
+#define VC_DIAG_LEN 16
+
+/* per-cell status (VC_F_STATUS) */
+enum { VC_CELL_OK = 0, VC_CELL_SPILLED = 1, VC_CELL_CAPACITY = 2, VC_CELL_DUPLICATE = 3 };
+
+/* diagnostic counters (VC_F_DIAG) */
+enum {
+    VC_D_CANDIDATES = 0,  /* candidates taken in nearest-first order */
+    VC_D_TESTS = 1,       /* plane-side tests (candidates x live vertices) */
+    VC_D_CUTS = 2,        /* cuts that removed part of a cell */
+    VC_D_NEWV = 3,        /* vertices created */
+    VC_D_EXACT = 4,       /* side decisions taken exactly */
+    VC_D_RECHECK = 5,     /* FP32 tests re-done in FP64 (VC_F32_FILTER) */
+    VC_D_SPILLED = 6,     /* cells re-run in the large-capacity kernel */
+    VC_D_BLOCKS = 7,      /* blocks visited */
+    VC_D_FALLBACK = 8     /* cells that searched beyond the precomputed offsets */
+};
+
+typedef struct {
+    int dim;             /* 2 or 3 */
+    double lo[3], hi[3]; /* box [lo, hi] per axis (first dim entries used) */
+    int periodic[3];     /* nonzero: periodic axis */
+    double n_opt;        /* target particles per block (section 2.1.4); <= 0: 5.0 */
+    int grid[3];         /* explicit block counts; all 0: from n_opt */
+    int precision;       /* VC_FP64 or VC_F32_FILTER */
+    int slots;           /* triangles per lane in the main cell kernel (2 or 4); 0: auto */
+    int waves;           /* resident cell waves launched; 0: auto */
+    int chunk;           /* cells taken per work-queue grab; 0: auto */
+} vc_options;
+
+typedef struct vc_container vc_container;
+typedef struct vc_result vc_result;
+typedef struct vc_batch vc_batch;
+
+/* Fill *opt with defaults for a box (dim, lo, hi, periodic). */
+vc_status vc_options_init(vc_options *opt, int dim, const double *lo, const double *hi, const int *periodic);
+
+/* Create a container and bin the particles into its grid of blocks
+ * (section 2.1.1; the atomic slot capture of section 2.2.4 becomes a counting
+ * sort).  xyz: n x dim doubles, particle-major, host or device.  A walled
+ * axis requires lo <= x <= hi, a periodic axis lo <= x < hi; otherwise
+ * VC_E_RANGE.  The library copies the positions; the caller keeps ownership
+ * of xyz.  Block counts follow section 2.1.4 (lambda = (N/(N_opt V))^(1/d),
+ * n_d = ceil(lambda L_d)) unless opt->grid is set.  Synchronises `stream`
+ * once (to read the range check).  On success *out owns device memory. */
+vc_status vc_container_create(const double *xyz, int64_t n, const vc_options *opt, void *stream,
+                              vc_container **out);
+
+/* Re-bin new positions of the same count into an existing container (the
+ * container re-use of section 3.3): no allocation.  Same range rules and
+ * errors as vc_container_create; synchronises `stream` once to read the
+ * range check.  On VC_E_RANGE the container holds the rejected positions and
+ * must be re-binned before the next vc_compute. */
+vc_status vc_container_rebin(vc_container *c, const double *xyz, void *stream);
+
+/* Allocate a result for a container and a statistics mask (VC_* bits).  The
+ * result owns device arrays sized for the container; it can be filled many
+ * times. */
+vc_status vc_result_create(const vc_container *c, uint32_t mask, vc_result **out);
+
+/* Compute every cell of the container into r (section 2.1.2-2.1.3: box
+ * start, nearest-first bisector cuts, radius-bound termination, statistics).
+ * Asynchronous on `stream`. */
+vc_status vc_compute(vc_container *c, vc_result *r, void *stream);
+
+/* Elapsed time in milliseconds of the main cell kernel of the last
+ * vc_compute on r (HIP events recorded around that launch on its stream).
+ * Waits for that kernel to finish. */
+vc_status vc_result_kernel_ms(vc_result *r, float *ms);
+
+/* Device pointer and element count of a result field (no copy).  The pointer
+ * stays valid until vc_result_destroy.  For the neighbour id and shift
+ * arrays the count is known only after the compute finished: this call
+ * synchronises the stream of the last compute to read it. */
+vc_status vc_result_get(vc_result *r, int field, void **dev_ptr, int64_t *count);
+
+/* Copy a result field to host memory (synchronous); bytes must be >= the
+ * field size. */
+vc_status vc_result_copy(vc_result *r, int field, void *host_dst, int64_t bytes);
+
+void vc_result_destroy(vc_result *r);
+void vc_container_destroy(vc_container *c);
+
+/* --- batches of independent tessellations (one persistent launch) --------- */
+
+/* Create a batch of n_tess independent 3D containers.  xyz_concat holds all
+ * positions back to back (device or host), offsets[n_tess + 1] (host) the
+ * first particle of each; opts[n_tess] (host) the box of each.  Results are
+ * indexed by position in xyz_concat. */
+vc_status vc_batch_create(const double *xyz_concat, const int64_t *offsets, int64_t n_tess,
+                          const vc_options *opts, void *stream, vc_batch **out);
+
+/* Allocate a result for a batch (fields as for a container, over all
+ * particles of the batch). */
+vc_status vc_batch_result_create(const vc_batch *b, uint32_t mask, vc_result **out);
+
+/* Compute every cell of every tessellation in one persistent launch over a
+ * device work queue.  If `graph` is nonzero the launch sequence is captured
+ * once into a hipGraph and replayed on later calls. */
+vc_status vc_batch_compute(vc_batch *b, vc_result *r, int graph, void *stream);
+
+void vc_batch_destroy(vc_batch *b);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *vc_last_error(void);
+
+/* Library version string. */
+const char *vc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -47,6 +47,8 @@ def _planes(xyz, i, lo, hi, periodic):
         for s in product(*rng):
             if j == i and not any(s):
                 continue
+            if j == i and sum(abs(t) for t in s) == 1:
+                continue  # the own images at +-L e_d are the box planes already
             q = []
             for d in range(dim):
                 v = float(xyz[j, d]) - float(p[d])

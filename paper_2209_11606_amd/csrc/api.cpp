@@ -1,0 +1,533 @@
+// api.cpp -- host runtime behind the C ABI of vorohip.h: argument checks,
+// grid sizing (section 2.1.4), device allocation, the binning sequence, the
+// nearest-first block-offset list, cell-kernel launches with the spill pass,
+// and neighbour-list compaction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/vorohip.h"
+#include "vc_internal.h"
+
+using namespace vc;
+
+namespace {
+
+thread_local std::string g_err;
+
+vc_status fail(vc_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) return fail(VC_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+vc_status dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) return fail(VC_E_NOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+    return VC_OK;
+}
+
+bool is_device_ptr(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// Precomputed block offsets up to Chebyshev radius kOffRadius, ordered by a
+// lower bound of the distance between any point of the own block and the
+// offset block (nearest first), ties by centre distance then lexicographic.
+void build_offsets(const Grid &G, std::vector<Offset> &offs, std::vector<double> &gap2)
+{
+    struct E { double g, c; int dx, dy, dz; };
+    std::vector<E> v;
+    int rz = G.dim == 3 ? kOffRadius : 0;
+    for (int dz = -rz; dz <= rz; dz++)
+        for (int dy = -kOffRadius; dy <= kOffRadius; dy++)
+            for (int dx = -kOffRadius; dx <= kOffRadius; dx++) {
+                int d[3] = {dx, dy, dz};
+                double g = 0.0, c = 0.0;
+                for (int k = 0; k < 3; k++) {
+                    double t = std::max(std::abs(d[k]) - 1, 0) * G.bs[k];
+                    g += t * t;
+                    c += (d[k] * G.bs[k]) * (d[k] * G.bs[k]);
+                }
+                v.push_back({g, c, dx, dy, dz});
+            }
+    std::sort(v.begin(), v.end(), [](const E &a, const E &b) {
+        if (a.g != b.g) return a.g < b.g;
+        if (a.c != b.c) return a.c < b.c;
+        if (a.dz != b.dz) return a.dz < b.dz;
+        if (a.dy != b.dy) return a.dy < b.dy;
+        return a.dx < b.dx;
+    });
+    offs.clear();
+    gap2.clear();
+    for (auto &e : v) {
+        offs.push_back(Offset{e.dx, e.dy, e.dz, 0});
+        gap2.push_back(e.g);
+    }
+}
+
+}  // namespace
+
+struct vc_container {
+    vc_options opt;
+    Grid G;
+    int64_t n = 0;
+    double *xyz = nullptr;       // device copy of the input positions (n x dim)
+    Particle *part = nullptr;    // block-sorted particles
+    int32_t *start = nullptr;    // nb + 1
+    int32_t *count = nullptr;    // nb
+    int32_t *blk = nullptr;      // n
+    int32_t *rank = nullptr;     // n
+    int32_t *err = nullptr;      // range-error flag
+    int32_t *scan_tmp = nullptr;
+    Offset *offs = nullptr;
+    double *offgap2 = nullptr;
+    int noff = 0;
+    int32_t *queue = nullptr;    // [0]: main queue head, [1]: spill queue head, [2]: spill count
+    int32_t *spill_list = nullptr;
+    double *xscratch = nullptr;
+    int waves = 0;
+    int xscratch_len = 2048;
+};
+
+struct vc_result {
+    const vc_container *c = nullptr;
+    uint32_t mask = 0;
+    int64_t n = 0;
+    int dim = 3;
+    double *vol = nullptr, *cen = nullptr;
+    int32_t *nv = nullptr, *ne = nullptr, *nf = nullptr;
+    uint8_t *fo = nullptr;
+    int32_t *nbr = nullptr;  // fixed-stride scratch
+    uint8_t *nsh = nullptr;
+    int64_t *off = nullptr;  // CSR offsets (n + 1)
+    int32_t *ids = nullptr;
+    uint8_t *shifts = nullptr;
+    int64_t nbr_cap = 0;     // capacity of ids / shifts
+    int32_t *scan_tmp = nullptr;
+    uint8_t *status = nullptr;
+    unsigned long long *diag = nullptr;
+    hipStream_t last_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the main cell kernel
+};
+
+namespace {
+
+vc_status check_options(const vc_options *o)
+{
+    if (!o) return fail(VC_E_ARG, "options: null pointer");
+    if (o->dim != 2 && o->dim != 3) return fail(VC_E_ARG, "options: dim must be 2 or 3 (got %d)", o->dim);
+    for (int d = 0; d < o->dim; d++) {
+        if (!std::isfinite(o->lo[d]) || !std::isfinite(o->hi[d]) || !(o->hi[d] > o->lo[d]))
+            return fail(VC_E_ARG, "options: box axis %d needs finite lo < hi", d);
+        if (o->grid[d] < 0) return fail(VC_E_ARG, "options: negative grid size");
+    }
+    if (o->precision != VC_FP64 && o->precision != VC_F32_FILTER)
+        return fail(VC_E_ARG, "options: precision must be VC_FP64 or VC_F32_FILTER");
+    if (o->slots != 0 && o->slots != 2 && o->slots != 4) return fail(VC_E_ARG, "options: slots must be 0, 2 or 4");
+    if (o->waves < 0 || o->chunk < 0) return fail(VC_E_ARG, "options: negative waves or chunk");
+    return VC_OK;
+}
+
+// Section 2.1.4: lambda = (N / (N_opt V))^(1/d), n_d = ceil(lambda L_d).
+void size_grid(Grid &G, const vc_options &o, int64_t n)
+{
+    G.dim = o.dim;
+    double vol = 1.0;
+    for (int d = 0; d < o.dim; d++) vol *= (o.hi[d] - o.lo[d]);
+    double nopt = o.n_opt > 0 ? o.n_opt : 5.0;
+    double lam = std::pow((double)n / (nopt * vol), 1.0 / o.dim);
+    bool explicit_grid = o.grid[0] > 0;
+    G.nb = 1;
+    for (int d = 0; d < 3; d++) {
+        if (d < o.dim) {
+            G.lo[d] = o.lo[d];
+            G.hi[d] = o.hi[d];
+            G.per[d] = o.periodic[d] ? 1 : 0;
+            long long g = explicit_grid ? o.grid[d] : (long long)std::ceil(lam * (o.hi[d] - o.lo[d]));
+            G.g[d] = (int)std::max(1LL, std::min(g, 1LL << 20));
+        } else {
+            G.lo[d] = 0.0;
+            G.hi[d] = 1.0;
+            G.per[d] = 0;
+            G.g[d] = 1;
+        }
+        G.L[d] = G.hi[d] - G.lo[d];
+        G.bs[d] = G.L[d] / G.g[d];
+        G.inv_bs[d] = G.g[d] / G.L[d];
+        G.nb *= G.g[d];
+    }
+}
+
+vc_status bin(vc_container *c, hipStream_t s)
+{
+    int64_t nb = c->G.nb;
+    HIP_TRY(launch_fill_i32(c->count, nb, 0, s));
+    HIP_TRY(launch_fill_i32(c->err, 1, 0, s));
+    HIP_TRY(launch_bin_count(c->xyz, c->n, c->G, c->blk, c->rank, c->count, c->err, s));
+    HIP_TRY(launch_scan(c->count, c->start, nb, c->scan_tmp, s));
+    HIP_TRY(launch_scatter(c->xyz, c->n, c->G, c->blk, c->rank, c->start, c->part, s));
+    HIP_TRY(launch_block_order(c->part, c->start, nb, s));
+    return VC_OK;
+}
+
+void free_container(vc_container *c)
+{
+    if (!c) return;
+    void *ps[] = {c->xyz, c->part, c->start, c->count, c->blk, c->rank, c->err, c->scan_tmp,
+                  c->offs, c->offgap2, c->queue, c->spill_list, c->xscratch};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    delete c;
+}
+
+void free_result(vc_result *r)
+{
+    if (!r) return;
+    void *ps[] = {r->vol, r->cen, r->nv, r->ne, r->nf, r->fo, r->nbr, r->nsh, r->off, r->ids, r->shifts,
+                  r->scan_tmp, r->status, r->diag};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    if (r->ev0) (void)hipEventDestroy(r->ev0);
+    if (r->ev1) (void)hipEventDestroy(r->ev1);
+    delete r;
+}
+
+}  // namespace
+
+extern "C" {
+
+vc_status vc_options_init(vc_options *opt, int dim, const double *lo, const double *hi, const int *periodic)
+{
+    if (!opt || !lo || !hi || !periodic) return fail(VC_E_ARG, "vc_options_init: null pointer");
+    if (dim != 2 && dim != 3) return fail(VC_E_ARG, "vc_options_init: dim must be 2 or 3");
+    std::memset(opt, 0, sizeof(*opt));
+    opt->dim = dim;
+    for (int d = 0; d < dim; d++) {
+        opt->lo[d] = lo[d];
+        opt->hi[d] = hi[d];
+        opt->periodic[d] = periodic[d] ? 1 : 0;
+    }
+    opt->n_opt = 5.0;
+    opt->precision = VC_FP64;
+    return VC_OK;
+}
+
+vc_status vc_container_create(const double *xyz, int64_t n, const vc_options *opt, void *stream, vc_container **out)
+{
+    if (!out) return fail(VC_E_ARG, "vc_container_create: out is null");
+    *out = nullptr;
+    if (!xyz) return fail(VC_E_ARG, "vc_container_create: xyz is null");
+    if (n < 1) return fail(VC_E_ARG, "vc_container_create: n must be >= 1 (got %lld)", (long long)n);
+    if (n > (int64_t)INT32_MAX / 2) return fail(VC_E_ARG, "vc_container_create: n too large");
+    vc_status st = check_options(opt);
+    if (st) return st;
+    if (opt->dim != 3) return fail(VC_E_ARG, "vc_container_create: only dim 3 is built in this library version");
+    hipStream_t s = (hipStream_t)stream;
+    vc_container *c = new (std::nothrow) vc_container();
+    if (!c) return fail(VC_E_NOMEM, "host allocation failed");
+    c->opt = *opt;
+    c->n = n;
+    size_grid(c->G, *opt, n);
+    const int dim = opt->dim;
+    int64_t nb = c->G.nb;
+    int64_t ntiles = (nb + 2047) / 2048 + 2;
+    std::vector<Offset> offs;
+    std::vector<double> gap2;
+    build_offsets(c->G, offs, gap2);
+    c->noff = (int)offs.size();
+    int cu = device_cu_count();
+    c->waves = opt->waves > 0 ? opt->waves : cu * 16;
+#define TRY(x)                   \
+    do {                         \
+        vc_status e_ = (x);      \
+        if (e_) {                \
+            free_container(c);   \
+            return e_;           \
+        }                        \
+    } while (0)
+    TRY(dalloc(&c->xyz, (size_t)n * dim));
+    TRY(dalloc(&c->part, (size_t)n));
+    TRY(dalloc(&c->start, (size_t)nb + 1));
+    TRY(dalloc(&c->count, (size_t)nb));
+    TRY(dalloc(&c->blk, (size_t)n));
+    TRY(dalloc(&c->rank, (size_t)n));
+    TRY(dalloc(&c->err, 1));
+    TRY(dalloc(&c->scan_tmp, (size_t)ntiles * 2));
+    TRY(dalloc(&c->offs, offs.size()));
+    TRY(dalloc(&c->offgap2, gap2.size()));
+    TRY(dalloc(&c->queue, 4));
+    TRY(dalloc(&c->spill_list, (size_t)n));
+    TRY(dalloc(&c->xscratch, (size_t)c->waves * c->xscratch_len));
+#undef TRY
+    hipError_t e = hipMemcpyAsync(c->offs, offs.data(), offs.size() * sizeof(Offset), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->offgap2, gap2.data(), gap2.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->xyz, xyz, (size_t)n * dim * sizeof(double),
+                           is_device_ptr(xyz) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        free_container(c);
+        return fail(VC_E_HIP, "copy to device failed: %s", hipGetErrorString(e));
+    }
+    st = bin(c, s);
+    if (st) {
+        free_container(c);
+        return st;
+    }
+    int32_t herr = 0;
+    e = hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_container(c);
+        return fail(VC_E_HIP, "binning failed: %s", hipGetErrorString(e));
+    }
+    if (herr) {
+        free_container(c);
+        return fail(VC_E_RANGE, "a coordinate lies outside the box (walled: lo <= x <= hi, periodic: lo <= x < hi) or is not finite");
+    }
+    *out = c;
+    return VC_OK;
+}
+
+vc_status vc_container_rebin(vc_container *c, const double *xyz, void *stream)
+{
+    if (!c || !xyz) return fail(VC_E_ARG, "vc_container_rebin: null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(c->xyz, xyz, (size_t)c->n * c->opt.dim * sizeof(double),
+                           is_device_ptr(xyz) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    vc_status st = bin(c, s);
+    if (st) return st;
+    int32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (herr) return fail(VC_E_RANGE, "a coordinate lies outside the box or is not finite");
+    return VC_OK;
+}
+
+vc_status vc_result_create(const vc_container *c, uint32_t mask, vc_result **out)
+{
+    if (!out) return fail(VC_E_ARG, "vc_result_create: out is null");
+    *out = nullptr;
+    if (!c) return fail(VC_E_ARG, "vc_result_create: container is null");
+    if (mask & ~(uint32_t)VC_ALL) return fail(VC_E_ARG, "vc_result_create: unknown mask bits 0x%x", mask);
+    vc_result *r = new (std::nothrow) vc_result();
+    if (!r) return fail(VC_E_NOMEM, "host allocation failed");
+    r->c = c;
+    r->mask = mask;
+    r->n = c->n;
+    r->dim = c->opt.dim;
+    int64_t n = c->n;
+#define TRY(x)                \
+    do {                      \
+        vc_status e_ = (x);   \
+        if (e_) {             \
+            free_result(r);   \
+            return e_;        \
+        }                     \
+    } while (0)
+    if (mask & VC_VOLUME) TRY(dalloc(&r->vol, n));
+    if (mask & VC_CENTROID) TRY(dalloc(&r->cen, (size_t)n * 3));
+    if (mask & VC_COUNTS) {
+        TRY(dalloc(&r->nv, n));
+        TRY(dalloc(&r->ne, n));
+    }
+    TRY(dalloc(&r->nf, n));
+    if (mask & VC_FACE_ORDERS) TRY(dalloc(&r->fo, (size_t)n * kFoLen));
+    if (mask & VC_NEIGHBORS) {
+        TRY(dalloc(&r->nbr, (size_t)n * kMaxNbr));
+        TRY(dalloc(&r->nsh, (size_t)n * kMaxNbr));
+        TRY(dalloc(&r->off, (size_t)n + 1));
+        r->nbr_cap = n * kMaxNbr;
+        TRY(dalloc(&r->ids, (size_t)r->nbr_cap));
+        TRY(dalloc(&r->shifts, (size_t)r->nbr_cap));
+        TRY(dalloc(&r->scan_tmp, (size_t)((n + 2047) / 2048 + 2) * 2));
+    }
+    TRY(dalloc(&r->status, n));
+    TRY(dalloc(&r->diag, VC_DIAG_LEN));
+#undef TRY
+    if (hipEventCreate(&r->ev0) != hipSuccess || hipEventCreate(&r->ev1) != hipSuccess) {
+        free_result(r);
+        return fail(VC_E_HIP, "hipEventCreate failed");
+    }
+    *out = r;
+    return VC_OK;
+}
+
+vc_status vc_compute(vc_container *c, vc_result *r, void *stream)
+{
+    if (!c || !r) return fail(VC_E_ARG, "vc_compute: null handle");
+    if (r->c != c) return fail(VC_E_STATE, "vc_compute: result was created for another container");
+    hipStream_t s = (hipStream_t)stream;
+    CellArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.G = c->G;
+    A.part = c->part;
+    A.start = c->start;
+    A.offs = c->offs;
+    A.offgap2 = c->offgap2;
+    A.noff = c->noff;
+    A.off_radius = kOffRadius;
+    A.ncell = (int)c->n;
+    A.cell_list = nullptr;
+    A.queue = c->queue;
+    A.chunk = c->opt.chunk > 0 ? c->opt.chunk : 4;
+    A.tau = 0x1p-30;
+    A.mask = r->mask;
+    A.vol = r->vol;
+    A.cen = r->cen;
+    A.nv = r->nv;
+    A.ne = r->ne;
+    A.nf = r->nf;
+    A.fo = r->fo;
+    A.nbr = r->nbr;
+    A.nsh = r->nsh;
+    A.status = r->status;
+    A.spill_list = c->spill_list;
+    A.spill_count = c->queue + 2;
+    A.diag = r->diag;
+    A.xscratch = c->xscratch;
+    A.xscratch_len = c->xscratch_len;
+    HIP_TRY(launch_fill_i32(c->queue, 4, 0, s));
+    HIP_TRY(launch_fill_i32((int32_t *)r->diag, VC_DIAG_LEN * 2, 0, s));
+    int slots = c->opt.slots > 0 ? c->opt.slots : 2;
+    HIP_TRY(hipEventRecord(r->ev0, s));
+    HIP_TRY(launch_cells(A, c->opt.precision, slots, c->waves, s));
+    HIP_TRY(hipEventRecord(r->ev1, s));
+    // cells beyond the main kernel's capacity: large-capacity pass over the
+    // spill list (its length is read on the device)
+    CellArgs B = A;
+    B.cell_list = c->spill_list;
+    B.queue = c->queue + 1;
+    B.ncell_dev = c->queue + 2;
+    B.ncell = (int)c->n;
+    B.chunk = 1;
+    HIP_TRY(launch_cells_spill(B, std::min(c->waves, 1024), s));
+    if (r->mask & VC_NEIGHBORS) {
+        // CSR offsets by a scan of the face counts, then each cell's sorted
+        // labels copied to its offset (capacity n * kMaxNbr always suffices)
+        HIP_TRY(launch_nbr_offsets(r->nf, r->n, r->off, r->scan_tmp, s));
+        HIP_TRY(launch_nbr_compact(r->nf, r->n, r->nbr, r->nsh, r->off, r->ids, r->shifts, nullptr, s));
+    }
+    r->last_stream = s;
+    return VC_OK;
+}
+
+vc_status vc_result_kernel_ms(vc_result *r, float *ms)
+{
+    if (!r || !ms) return fail(VC_E_ARG, "vc_result_kernel_ms: null pointer");
+    HIP_TRY(hipEventSynchronize(r->ev1));
+    HIP_TRY(hipEventElapsedTime(ms, r->ev0, r->ev1));
+    return VC_OK;
+}
+
+static vc_status ensure_neighbors(vc_result *r)
+{
+    if (!(r->mask & VC_NEIGHBORS)) return fail(VC_E_STATE, "neighbour lists were not requested in the mask");
+    HIP_TRY(hipStreamSynchronize(r->last_stream));
+    return VC_OK;
+}
+
+vc_status vc_result_get(vc_result *r, int field, void **dev_ptr, int64_t *count)
+{
+    if (!r || !dev_ptr || !count) return fail(VC_E_ARG, "vc_result_get: null pointer");
+    int64_t n = r->n;
+    void *p = nullptr;
+    int64_t k = 0;
+    switch (field) {
+    case VC_F_VOLUME: p = r->vol; k = n; break;
+    case VC_F_CENTROID: p = r->cen; k = n * 3; break;
+    case VC_F_NV: p = r->nv; k = n; break;
+    case VC_F_NE: p = r->ne; k = n; break;
+    case VC_F_NF: p = r->nf; k = n; break;
+    case VC_F_FACE_ORDERS: p = r->fo; k = n * kFoLen; break;
+    case VC_F_NBR_OFFSETS: p = r->off; k = n + 1; break;
+    case VC_F_NBR_IDS:
+    case VC_F_NBR_SHIFTS: {
+        vc_status st = ensure_neighbors(r);
+        if (st) return st;
+        HIP_TRY(hipMemcpy(&k, r->off + n, sizeof(int64_t), hipMemcpyDeviceToHost));
+        p = field == VC_F_NBR_IDS ? (void *)r->ids : (void *)r->shifts;
+        break;
+    }
+    case VC_F_STATUS: p = r->status; k = n; break;
+    case VC_F_DIAG: p = r->diag; k = VC_DIAG_LEN; break;
+    default: return fail(VC_E_ARG, "vc_result_get: unknown field %d", field);
+    }
+    if (!p) return fail(VC_E_STATE, "field %d was not requested in the statistics mask", field);
+    *dev_ptr = p;
+    *count = k;
+    return VC_OK;
+}
+
+vc_status vc_result_copy(vc_result *r, int field, void *host_dst, int64_t bytes)
+{
+    if (!host_dst) return fail(VC_E_ARG, "vc_result_copy: null destination");
+    void *p;
+    int64_t k;
+    vc_status st = vc_result_get(r, field, &p, &k);
+    if (st) return st;
+    static const int esz[] = {8, 8, 4, 4, 4, 1, 8, 4, 1, 1, 8};
+    int64_t need = k * esz[field];
+    if (bytes < need) return fail(VC_E_ARG, "vc_result_copy: need %lld bytes, got %lld", (long long)need, (long long)bytes);
+    HIP_TRY(hipStreamSynchronize(r->last_stream));
+    HIP_TRY(hipMemcpy(host_dst, p, (size_t)need, hipMemcpyDeviceToHost));
+    return VC_OK;
+}
+
+void vc_result_destroy(vc_result *r) { free_result(r); }
+
+void vc_container_destroy(vc_container *c) { free_container(c); }
+
+vc_status vc_batch_create(const double *, const int64_t *, int64_t, const vc_options *, void *, vc_batch **out)
+{
+    if (out) *out = nullptr;
+    return fail(VC_E_STATE, "vc_batch_create: not available in this library version");
+}
+
+vc_status vc_batch_result_create(const vc_batch *, uint32_t, vc_result **out)
+{
+    if (out) *out = nullptr;
+    return fail(VC_E_STATE, "vc_batch_result_create: not available in this library version");
+}
+
+vc_status vc_batch_compute(vc_batch *, vc_result *, int, void *)
+{
+    return fail(VC_E_STATE, "vc_batch_compute: not available in this library version");
+}
+
+void vc_batch_destroy(vc_batch *) {}
+
+const char *vc_last_error(void) { return g_err.c_str(); }
+
+const char *vc_version(void) { return "vorohip 0.1 (gfx950)"; }
+
+}  // extern "C"

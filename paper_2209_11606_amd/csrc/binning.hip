@@ -1,0 +1,268 @@
+// binning.hip -- container construction on the GPU: block index per
+// particle, per-block counts, exclusive scan, scatter into a block-sorted
+// particle array, and a deterministic in-block order (by input id).
+//
+// This replaces the serial put() and the atomic slot capture of the paper's
+// parallel insertion (section 2.2.4): the atomic counter gives each particle
+// a slot, and an exact prefix sum over the counts sizes every block, so no
+// overflow buffer is needed.  Sorting each block by id removes the run-to-run
+// order dependence that the paper notes for parallel insertion.
+#include "vc_internal.h"
+
+namespace vc {
+
+namespace {
+
+constexpr int kTB = 256;          // threads per block of the streaming kernels
+constexpr int kScanItems = 8;     // elements per thread in the scan
+constexpr int kScanTile = kTB * kScanItems;
+
+__global__ __launch_bounds__(kTB) void k_bin_count(const double *__restrict__ xyz, int64_t n, Grid G,
+                                                   int32_t *__restrict__ blk, int32_t *__restrict__ rank,
+                                                   int32_t *__restrict__ count, int32_t *__restrict__ err)
+{
+    const int dim = G.dim;
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+        int k[3] = {0, 0, 0};
+        bool bad = false;
+        for (int d = 0; d < dim; d++) {
+            double x = xyz[i * dim + d];
+            // walled: lo <= x <= hi; periodic: lo <= x < hi; NaN fails both
+            bool ok = G.per[d] ? (x >= G.lo[d] && x < G.hi[d]) : (x >= G.lo[d] && x <= G.hi[d]);
+            bad |= !ok;
+            k[d] = ok ? block_coord(G, x, d) : 0;
+        }
+        if (bad) atomicOr(err, 1);
+        int32_t b = k[0] + G.g[0] * (k[1] + G.g[1] * k[2]);
+        blk[i] = b;
+        rank[i] = atomicAdd(&count[b], 1);
+    }
+}
+
+// exclusive scan, phase 1: per-tile totals
+template <typename T>
+__global__ __launch_bounds__(kTB) void k_scan_tiles(const int32_t *__restrict__ in, int64_t n, T *__restrict__ tiles)
+{
+    __shared__ T red[kTB];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    T s = 0;
+    for (int j = 0; j < kScanItems; j++) {
+        int64_t i = base + (int64_t)j * kTB + threadIdx.x;
+        if (i < n) s += (T)in[i];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kTB / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tiles[blockIdx.x] = red[0];
+}
+
+// phase 2: exclusive scan of the tile totals in one workgroup
+template <typename T>
+__global__ __launch_bounds__(kTB) void k_scan_top(T *__restrict__ tiles, int64_t ntiles, T *__restrict__ total)
+{
+    __shared__ T buf[kTB];
+    T carry = 0;
+    for (int64_t c = 0; c < ntiles; c += kTB) {
+        int64_t i = c + threadIdx.x;
+        T v = i < ntiles ? tiles[i] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kTB; o <<= 1) {
+            T w = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += w;
+            __syncthreads();
+        }
+        T incl = buf[threadIdx.x];
+        if (i < ntiles) tiles[i] = carry + incl - v;
+        T chunk_total = buf[kTB - 1];
+        __syncthreads();
+        carry += chunk_total;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// phase 3: scan inside each tile plus the tile offset
+template <typename T>
+__global__ __launch_bounds__(kTB) void k_scan_final(const int32_t *__restrict__ in, int64_t n,
+                                                    const T *__restrict__ tiles, T *__restrict__ out)
+{
+    __shared__ T buf[kTB];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T loc[kScanItems];
+    T s = 0;
+    for (int j = 0; j < kScanItems; j++) {
+        int64_t i = base + j;
+        loc[j] = i < n ? (T)in[i] : 0;
+        s += loc[j];
+    }
+    buf[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < kTB; o <<= 1) {
+        T w = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+        __syncthreads();
+        buf[threadIdx.x] += w;
+        __syncthreads();
+    }
+    T run = tiles[blockIdx.x] + buf[threadIdx.x] - s;
+    for (int j = 0; j < kScanItems; j++) {
+        int64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += loc[j];
+    }
+}
+
+template <typename T>
+__global__ void k_store_total(const T *__restrict__ total, T *__restrict__ dst)
+{
+    *dst = *total;
+}
+
+__global__ __launch_bounds__(kTB) void k_scatter(const double *__restrict__ xyz, int64_t n, Grid G,
+                                                 const int32_t *__restrict__ blk, const int32_t *__restrict__ rank,
+                                                 const int32_t *__restrict__ start, Particle *__restrict__ part)
+{
+    const int dim = G.dim;
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+        Particle p;
+        p.x = xyz[i * dim];
+        p.y = xyz[i * dim + 1];
+        p.z = dim == 3 ? xyz[i * dim + 2] : 0.0;
+        p.id = (int32_t)i;
+        p.pad = 0;
+        part[start[blk[i]] + rank[i]] = p;
+    }
+}
+
+// one thread per block: insertion sort of the block's particles by id
+__global__ __launch_bounds__(kTB) void k_block_order(Particle *__restrict__ part, const int32_t *__restrict__ start,
+                                                     int64_t nb)
+{
+    for (int64_t b = (int64_t)blockIdx.x * kTB + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kTB) {
+        int s = start[b], e = start[b + 1];
+        for (int i = s + 1; i < e; i++) {
+            Particle v = part[i];
+            int j = i - 1;
+            while (j >= s && part[j].id > v.id) {
+                part[j + 1] = part[j];
+                j--;
+            }
+            part[j + 1] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kTB) void k_fill(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) p[i] = v;
+}
+
+// neighbour lists: per cell, sort the labels (id, image) and copy them into
+// the CSR arrays at the cell's offset
+__global__ __launch_bounds__(kTB) void k_nbr_compact(const int32_t *__restrict__ nf, int64_t n,
+                                                     const int32_t *__restrict__ nbr, const uint8_t *__restrict__ nsh,
+                                                     const int64_t *__restrict__ off, int32_t *__restrict__ ids,
+                                                     uint8_t *__restrict__ shifts)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+        int k = nf[i];
+        if (k > kMaxNbr) k = kMaxNbr;
+        int64_t key[kMaxNbr];
+        for (int t = 0; t < k; t++)
+            key[t] = ((int64_t)nbr[i * kMaxNbr + t] << 8) | (int64_t)nsh[i * kMaxNbr + t];
+        for (int t = 1; t < k; t++) {
+            int64_t v = key[t];
+            int u = t - 1;
+            while (u >= 0 && key[u] > v) {
+                key[u + 1] = key[u];
+                u--;
+            }
+            key[u + 1] = v;
+        }
+        int64_t o = off[i];
+        for (int t = 0; t < k; t++) {
+            ids[o + t] = (int32_t)(key[t] >> 8);
+            shifts[o + t] = (uint8_t)(key[t] & 0xff);
+        }
+    }
+}
+
+int grid_for(int64_t n)
+{
+    int64_t g = (n + kTB - 1) / kTB;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+template <typename T>
+hipError_t scan_impl(const int32_t *in, int64_t n, T *out, T *tmp, hipStream_t s)
+{
+    // out has n + 1 entries; tmp holds ceil(n / tile) + 1 entries
+    int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ntiles < 1) ntiles = 1;
+    k_scan_tiles<T><<<(unsigned)ntiles, kTB, 0, s>>>(in, n, tmp);
+    k_scan_top<T><<<1, kTB, 0, s>>>(tmp, ntiles, tmp + ntiles);
+    k_scan_final<T><<<(unsigned)ntiles, kTB, 0, s>>>(in, n, tmp, out);
+    k_store_total<T><<<1, 1, 0, s>>>(tmp + ntiles, out + n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bin_count(const double *xyz, int64_t n, const Grid &G, int32_t *blk, int32_t *rank,
+                            int32_t *count, int32_t *err, hipStream_t s)
+{
+    k_bin_count<<<grid_for(n), kTB, 0, s>>>(xyz, n, G, blk, rank, count, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const int32_t *count, int32_t *start, int64_t nb, int32_t *tmp, hipStream_t s)
+{
+    return scan_impl<int32_t>(count, nb, start, tmp, s);
+}
+
+hipError_t launch_scatter(const double *xyz, int64_t n, const Grid &G, const int32_t *blk, const int32_t *rank,
+                          const int32_t *start, Particle *part, hipStream_t s)
+{
+    k_scatter<<<grid_for(n), kTB, 0, s>>>(xyz, n, G, blk, rank, start, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_order(Particle *part, const int32_t *start, int64_t nb, hipStream_t s)
+{
+    k_block_order<<<grid_for(nb), kTB, 0, s>>>(part, start, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
+{
+    k_fill<<<grid_for(n), kTB, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_nbr_offsets(const int32_t *nf, int64_t n, int64_t *offsets, int32_t *tmp, hipStream_t s)
+{
+    return scan_impl<int64_t>(nf, n, offsets, reinterpret_cast<int64_t *>(tmp), s);
+}
+
+hipError_t launch_nbr_compact(const int32_t *nf, int64_t n, const int32_t *nbr, const uint8_t *nsh, int64_t *offsets,
+                              int32_t *ids, uint8_t *shifts, int32_t *tmp, hipStream_t s)
+{
+    (void)tmp;
+    k_nbr_compact<<<grid_for(n), kTB, 0, s>>>(nf, n, nbr, nsh, offsets, ids, shifts);
+    return hipGetLastError();
+}
+
+int device_cu_count()
+{
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) return 256;
+    return cu;
+}
+
+}  // namespace vc

@@ -1,0 +1,975 @@
+// cell3d.hip -- per-particle 3D Voronoi cell construction, one wavefront
+// per cell (Voro++ method, section 2.1.2-2.1.3 of Lu, Lazar & Rycroft).
+//
+// Cell representation (dual / triangle form): the cell is a convex polytope
+// given by its planes (box walls, own periodic images, and neighbour
+// bisectors, Eq. 1-3) and by one triangle (a, b, c) of plane ids per vertex,
+// listing the faces that meet there counter-clockwise seen from outside.
+// Each lane owns S triangle slots in registers (vertex position in FP64).
+// An LDS table etab[a][b] names the slot holding the directed edge a -> b,
+// so the triangle across any edge is one LDS read.
+//
+// A cut by plane p (Eq. 3): every lane tests its vertices, s = q.v - q.q/2,
+// a ballot gives the conflict set (vertices strictly outside).  Conflict
+// triangles whose neighbour across an edge (a -> b) survives contribute the
+// boundary edge (a, b); each becomes a new triangle (a, b, p), whose vertex is
+// the intersection of planes a, b, p (Cramer's rule).  New triangles fill free
+// slots in lane order.  No cyclic walk of the new face is needed.
+//
+// Side decisions: |s| <= tau * M (M >= sum |q_d v_d| + |h|) is decided
+// exactly from the three planes of the vertex (s * det3 = det4 of the plane
+// rows), with floating-point expansions.  A vertex exactly on the plane is
+// kept.  With exact decisions the cell does not depend on the cut order.
+//
+// Candidates come block by block from a precomputed list of block offsets in
+// nearest-first order; the particles of up to 64 blocks are loaded at once
+// and taken in increasing distance.  A candidate at distance >= 2R (R the
+// largest vertex distance) is skipped and the sweep stops when the next block
+// is farther than 2R (the radius bound of section 2.1.3).
+#include "vc_internal.h"
+
+namespace vc {
+
+namespace {
+
+constexpr double kMargin = 1.0 + 0x1p-30;  // radius-bound safety factor on squared distances
+constexpr int kMaxShell = 64;              // largest Chebyshev shell searched; beyond it the cell fails
+
+struct PlaneD {
+    double n0, n1, n2, h;
+    int wall;
+};
+
+// ---------------------------------------------------------------------------
+// Exact sign with floating-point expansions (Shewchuk 1997): a list of
+// doubles, nonoverlapping and increasing in magnitude, whose exact sum is the
+// value; Grow-Expansion adds one double exactly.  Runs on one lane at a time
+// with the wave's workspace in global memory.
+// ---------------------------------------------------------------------------
+#pragma clang fp contract(off)
+
+__device__ inline void xs_two_sum(double a, double b, double &x, double &y)
+{
+    double s = a + b;
+    double bv = s - a;
+    double av = s - bv;
+    x = s;
+    y = (a - av) + (b - bv);
+}
+
+__device__ inline void xs_two_prod(double a, double b, double &x, double &y)
+{
+    double p = a * b;
+    x = p;
+    y = __builtin_fma(a, b, -p);
+}
+
+// e <- e + b (in place: output component k is written at index <= its input)
+__device__ inline int xs_grow(double *e, int n, double b)
+{
+    double q = b;
+    int k = 0;
+    for (int i = 0; i < n; i++) {
+        double x, y;
+        xs_two_sum(q, e[i], x, y);
+        if (y != 0.0) e[k++] = y;
+        q = x;
+    }
+    if (q != 0.0 || k == 0) e[k++] = q;
+    return k;
+}
+
+__device__ inline int xs_add_prod(double *e, int n, double a, double b)
+{
+    double x, y;
+    xs_two_prod(a, b, x, y);
+    if (y != 0.0) n = xs_grow(e, n, y);
+    return xs_grow(e, n, x);
+}
+
+__device__ inline int xs_sign(const double *e, int n)
+{
+    double t = e[n - 1];
+    return (t > 0.0) - (t < 0.0);
+}
+
+// The exact offset of a plane as a short list of doubles summing to it:
+// q.q/2 for a bisector (three exact squares, halved), h for a wall.
+__device__ inline int xs_offset(const PlaneD &p, double *out)
+{
+    if (p.wall) {
+        out[0] = p.h;
+        return 1;
+    }
+    double v[3] = {p.n0, p.n1, p.n2};
+    int k = 0;
+    for (int d = 0; d < 3; d++) {
+        double x, y;
+        xs_two_prod(v[d], v[d], x, y);
+        out[k++] = 0.5 * x;
+        out[k++] = 0.5 * y;
+    }
+    return k;
+}
+
+// acc += sgn * h_list * det3(u, v, w) over the six permutation products.
+__device__ int xs_acc_hdet(double *acc, int n, const double *hl, int nh, double sgn, const double *u,
+                           const double *v, const double *w)
+{
+    const int pm[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {1, 0, 2}, {2, 1, 0}};
+    for (int k = 0; k < 6; k++) {
+        double sg = k < 3 ? sgn : -sgn;
+        double x, y;
+        xs_two_prod(sg * u[pm[k][0]], v[pm[k][1]], x, y);
+        // (x + y) * w exactly = four doubles
+        double t[4];
+        xs_two_prod(x, w[pm[k][2]], t[0], t[1]);
+        xs_two_prod(y, w[pm[k][2]], t[2], t[3]);
+        for (int a = 0; a < 4; a++) {
+            if (t[a] == 0.0) continue;
+            for (int b = 0; b < nh; b++) {
+                if (hl[b] == 0.0) continue;
+                n = xs_add_prod(acc, n, t[a], hl[b]);
+            }
+        }
+    }
+    return n;
+}
+
+// Exact sign of n_p.v - h_p at v = planes a, b, c:
+//   s * D(a,b,c) = h_a D(b,c,p) - h_b D(a,c,p) + h_c D(a,b,p) - h_p D(a,b,c).
+__device__ __noinline__ int exact_side3(PlaneD a, PlaneD b, PlaneD c, PlaneD p, double *ws)
+{
+    const PlaneD *r[4] = {&a, &b, &c, &p};
+    double nv[4][3];
+    for (int i = 0; i < 4; i++) {
+        nv[i][0] = r[i]->n0;
+        nv[i][1] = r[i]->n1;
+        nv[i][2] = r[i]->n2;
+    }
+    const int mi[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    double hl[6];
+    int n = 0;
+    for (int i = 0; i < 4; i++) {
+        int nh = xs_offset(*r[i], hl);
+        n = xs_acc_hdet(ws, n, hl, nh, (i & 1) ? -1.0 : 1.0, nv[mi[i][0]], nv[mi[i][1]], nv[mi[i][2]]);
+    }
+    int s4 = n ? xs_sign(ws, n) : 0;
+    double one = 1.0;
+    int m = xs_acc_hdet(ws, 0, &one, 1, 1.0, nv[0], nv[1], nv[2]);
+    int s3 = m ? xs_sign(ws, m) : 0;
+    return s4 * s3;
+}
+
+#pragma clang fp contract(fast)
+
+// ---------------------------------------------------------------------------
+// Wave helpers
+// ---------------------------------------------------------------------------
+__device__ inline int lane_rank(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline int wave_isum(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline unsigned long long wave_min_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+__device__ inline unsigned long long wave_or_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline int wave_incl_scan(int v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int w = __shfl_up(v, o);
+        if (lane >= o) v += w;
+    }
+    return v;
+}
+
+template <int S, int MAXP, int K>
+struct CellLDS {
+    double pq[MAXP][4];       // plane normal q (or wall normal) and offset h
+    int32_t plab[MAXP];       // neighbour id, or wall label
+    uint8_t psh[MAXP];        // image code
+    uint8_t pwall[MAXP];      // 1: wall plane (exact offset stored)
+    uint8_t etab[MAXP][MAXP]; // slot of the triangle holding directed edge a -> b
+    union {
+        struct {              // statistics
+            double pos[S * 64][3];
+            uint32_t tpl[S * 64];
+            int32_t lab[S * 64];
+        } st;
+        struct {              // candidate sweep: the current batch, and the
+            double cq[64 * K][3];           // new vertices of a cut
+            int32_t cid[64 * K];
+            uint8_t ccode[64 * K];
+            double npos[S * 64 + 8][3];
+        } gc;
+    } u;
+    uint16_t bedge[S * 64 + 8];
+    int32_t cpre[64];
+    int32_t cbeg[64];
+    uint8_t csh[64];
+    int32_t forder[MAXP];
+    int32_t fref[MAXP];
+    int32_t fo[kFoLen];
+};
+
+template <int MAXP>
+struct PlaneSet {
+    static constexpr int W = (MAXP + 63) / 64;
+    unsigned long long w[W];
+    // bits of slots beyond MAXP in the last word (kept set: never free)
+    static constexpr unsigned long long pad = (MAXP % 64) ? ~((1ull << (MAXP % 64)) - 1) : 0ull;
+};
+
+// vertex of planes A, B, C by Cramer's rule
+__device__ __forceinline__ void cramer(const double *A, const double *B, const double *C, double &x, double &y, double &z)
+{
+    double bc0 = B[1] * C[2] - B[2] * C[1], bc1 = B[2] * C[0] - B[0] * C[2], bc2 = B[0] * C[1] - B[1] * C[0];
+    double ca0 = C[1] * A[2] - C[2] * A[1], ca1 = C[2] * A[0] - C[0] * A[2], ca2 = C[0] * A[1] - C[1] * A[0];
+    double ab0 = A[1] * B[2] - A[2] * B[1], ab1 = A[2] * B[0] - A[0] * B[2], ab2 = A[0] * B[1] - A[1] * B[0];
+    double det = A[0] * bc0 + A[1] * bc1 + A[2] * bc2;
+    double inv = 1.0 / det;
+    x = (A[3] * bc0 + B[3] * ca0 + C[3] * ab0) * inv;
+    y = (A[3] * bc1 + B[3] * ca1 + C[3] * ab1) * inv;
+    z = (A[3] * bc2 + B[3] * ca2 + C[3] * ab2) * inv;
+}
+
+template <int S, int MAXP, int K>
+__device__ __forceinline__ PlaneD plane_of(const CellLDS<S, MAXP, K> &sh, int k)
+{
+    PlaneD p;
+    p.n0 = sh.pq[k][0];
+    p.n1 = sh.pq[k][1];
+    p.n2 = sh.pq[k][2];
+    p.h = sh.pq[k][3];
+    p.wall = sh.pwall[k];
+    return p;
+}
+
+enum { ST_OK = 0, ST_CAP = 1, ST_DUP = 3 };
+enum { DC_CAND, DC_TESTS, DC_CUTS, DC_NEWV, DC_EXACT, DC_RECHECK, DC_SPILL, DC_BLOCKS, DC_FALLBACK, DC_N };
+
+// State of one cell held by a wave (registers are per lane; masks uniform).
+template <int S, int MAXP, bool F32>
+struct Cell {
+    uint32_t tp[S];
+    double vx[S], vy[S], vz[S];
+    float fx[S], fy[S], fz[S];
+    unsigned long long live[S];
+    PlaneSet<MAXP> used;
+    double R2;
+    double R;
+};
+
+template <int S, int MAXP, bool F32>
+__device__ __forceinline__ void update_radius(Cell<S, MAXP, F32> &c, int lane)
+{
+    double m = 0.0;
+#pragma unroll
+    for (int s = 0; s < S; s++)
+        if ((c.live[s] >> lane) & 1) m = fmax(m, c.vx[s] * c.vx[s] + c.vy[s] * c.vy[s] + c.vz[s] * c.vz[s]);
+    c.R2 = wave_max(m);
+    c.R = sqrt(c.R2);
+}
+
+template <int S, int MAXP, bool F32>
+__device__ __forceinline__ bool radius_ok(const Cell<S, MAXP, F32> &c)
+{
+    return c.R2 < 1e300;  // false for NaN / Inf
+}
+
+// Collect the planes used by live triangles (when the plane slots run out).
+template <int S, int MAXP, bool F32>
+__device__ __forceinline__ void collect_planes(Cell<S, MAXP, F32> &c, int lane)
+{
+#pragma unroll
+    for (int w = 0; w < PlaneSet<MAXP>::W; w++) {
+        unsigned long long u = 0;
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            if ((c.live[s] >> lane) & 1) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    int pl = (c.tp[s] >> (8 * k)) & 0xff;
+                    if ((pl >> 6) == w) u |= 1ull << (pl & 63);
+                }
+            }
+        }
+        c.used.w[w] = wave_or_u64(u);
+    }
+    c.used.w[PlaneSet<MAXP>::W - 1] |= PlaneSet<MAXP>::pad;
+}
+
+template <int S, int MAXP, bool F32>
+__device__ __forceinline__ int free_plane(Cell<S, MAXP, F32> &c)
+{
+#pragma unroll
+    for (int w = 0; w < PlaneSet<MAXP>::W; w++)
+        if (~c.used.w[w]) return w * 64 + __builtin_ctzll(~c.used.w[w]);
+    return -1;
+}
+
+// Test the cell against the bisector of candidate q (|q|^2 = d2) and cut it.
+// Returns ST_OK or ST_CAP.
+template <int S, int MAXP, bool F32, int K>
+__device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &sh, Cell<S, MAXP, F32> &c, double q0, double q1,
+                        double q2, double d2, int32_t lab, int code, double *ws, unsigned long long *cnt, int lane)
+{
+    const double h = 0.5 * d2;
+    const double Mub = (fabs(q0) + fabs(q1) + fabs(q2)) * c.R + h;
+    const double band = A.tau * Mub;
+    unsigned long long conf[S], inb[S];
+    int ntest = 0;
+    if (F32) {
+        const float g0 = (float)q0, g1 = (float)q1, g2 = (float)q2, gh = (float)h;
+        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + gh);
+        unsigned long long uns = 0;
+        unsigned long long unsr[S];
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            bool lv = (c.live[s] >> lane) & 1;
+            float sv = fmaf(g0, c.fx[s], fmaf(g1, c.fy[s], fmaf(g2, c.fz[s], -gh)));
+            conf[s] = __ballot(lv && sv > band32);
+            unsr[s] = __ballot(lv && !(sv > band32) && !(sv < -band32));
+            inb[s] = 0;
+            uns |= unsr[s];
+            ntest += __popcll(c.live[s]);
+        }
+        if (uns) {
+#pragma unroll
+            for (int s = 0; s < S; s++) {
+                if (!unsr[s]) continue;
+                bool u = (unsr[s] >> lane) & 1;
+                double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
+                conf[s] |= __ballot(u && sv > band);
+                inb[s] = __ballot(u && !(sv > band) && !(sv < -band));
+                cnt[DC_RECHECK] += __popcll(unsr[s]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            bool lv = (c.live[s] >> lane) & 1;
+            double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
+            conf[s] = __ballot(lv && sv > band);
+            inb[s] = __ballot(lv && !(sv > band) && !(sv < -band));
+            ntest += __popcll(c.live[s]);
+        }
+    }
+    cnt[DC_TESTS] += ntest;
+    // in-band vertices: exact decision, one lane at a time
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        unsigned long long m = inb[s];
+        while (m) {
+            int l = __builtin_ctzll(m);
+            m &= m - 1;
+            int sg = 0;
+            if (lane == l) {
+                PlaneD pp = {q0, q1, q2, h, 0};
+                sg = exact_side3(plane_of(sh, c.tp[s] & 0xff), plane_of(sh, (c.tp[s] >> 8) & 0xff),
+                                 plane_of(sh, (c.tp[s] >> 16) & 0xff), pp, ws);
+            }
+            sg = __shfl(sg, l);
+            if (sg > 0) conf[s] |= 1ull << l;
+            cnt[DC_EXACT]++;
+        }
+    }
+    unsigned long long anyc = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) anyc |= conf[s];
+    if (!anyc) return ST_OK;
+
+    // ---- cut ----
+    int p = free_plane(c);
+    if (p < 0) {
+        collect_planes(c, lane);
+        p = free_plane(c);
+        if (p < 0) return ST_CAP;
+    }
+    // boundary edges of the conflict region
+    uint32_t bfl = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        if ((conf[s] >> lane) & 1) {
+            uint32_t t3 = c.tp[s];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
+                int tw = sh.etab[b][a] & (S * 64 - 1);
+                unsigned long long cw = 0;
+#pragma unroll
+                for (int r = 0; r < S; r++)
+                    if ((tw >> 6) == r) cw = conf[r];
+                if (!((cw >> (tw & 63)) & 1)) bfl |= 1u << (s * 3 + k);
+            }
+        }
+    }
+    int nb = __popc(bfl);
+    int incl = wave_incl_scan(nb, lane);
+    int m = __shfl(incl, 63);
+    int nfree = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) nfree += __popcll(~c.live[s] | conf[s]);
+    if (m > nfree || m > S * 64 + 8) return ST_CAP;
+    int o = incl - nb;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            if ((bfl >> (s * 3 + k)) & 1) {
+                uint32_t t3 = c.tp[s];
+                int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
+                sh.bedge[o++] = (uint16_t)(a | (b << 8));
+            }
+        }
+    }
+    if (lane == 0) {
+        sh.pq[p][0] = q0;
+        sh.pq[p][1] = q1;
+        sh.pq[p][2] = q2;
+        sh.pq[p][3] = h;
+        sh.plab[p] = lab;
+        sh.psh[p] = (uint8_t)code;
+        sh.pwall[p] = 0;
+    }
+    __syncthreads();
+    // vertices of the new triangles (a, b, p), one per lane, staged in LDS
+    for (int k = lane; k < m; k += 64) {
+        uint16_t e = sh.bedge[k];
+        double x, y, z;
+        cramer(sh.pq[e & 0xff], sh.pq[e >> 8], sh.pq[p], x, y, z);
+        sh.u.gc.npos[k][0] = x;
+        sh.u.gc.npos[k][1] = y;
+        sh.u.gc.npos[k][2] = z;
+    }
+    __syncthreads();
+    // new triangles fill the free slots in slot order
+    int before = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        unsigned long long fr = ~c.live[s] | conf[s];
+        int rank = before + lane_rank(fr);
+        bool take = ((fr >> lane) & 1) && rank < m;
+        unsigned long long nw = __ballot(take);
+        if (take) {
+            uint16_t e = sh.bedge[rank];
+            int a = e & 0xff, b = e >> 8;
+            c.tp[s] = (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)p << 16);
+            c.vx[s] = sh.u.gc.npos[rank][0];
+            c.vy[s] = sh.u.gc.npos[rank][1];
+            c.vz[s] = sh.u.gc.npos[rank][2];
+            if (F32) {
+                c.fx[s] = (float)c.vx[s];
+                c.fy[s] = (float)c.vy[s];
+                c.fz[s] = (float)c.vz[s];
+            }
+            uint8_t t = (uint8_t)(s * 64 + lane);
+            sh.etab[a][b] = t;
+            sh.etab[b][p] = t;
+            sh.etab[p][a] = t;
+        }
+        c.live[s] = (c.live[s] & ~conf[s]) | nw;
+        before += __popcll(fr);
+    }
+    c.used.w[p >> 6] |= 1ull << (p & 63);
+    __syncthreads();
+    update_radius(c, lane);
+    cnt[DC_CUTS]++;
+    cnt[DC_NEWV] += m;
+    return radius_ok(c) ? ST_OK : ST_CAP;
+}
+
+// Load the particles of up to 64 blocks (one per lane: offset dx,dy,dz,
+// valid) and feed them to the cell in increasing distance.
+template <int S, int MAXP, bool F32, int K>
+__device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh, Cell<S, MAXP, F32> &c, int si, const double *p,
+                      const int *bc, int dx, int dy, int dz, bool valid, double *ws, unsigned long long *cnt, int lane)
+{
+    const Grid &G = A.G;
+    int dd[3] = {dx, dy, dz};
+    int bb[3], sv[3];
+    bool ok = valid;
+    double d2b = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        int t = bc[d] + dd[d];
+        if (G.per[d]) {
+            int g = G.g[d];
+            int w = ((t % g) + g) % g;
+            sv[d] = (t - w) / g;
+            bb[d] = w;
+            if (sv[d] > 2 || sv[d] < -2) ok = false;
+        } else {
+            sv[d] = 0;
+            bb[d] = t;
+            if (t < 0 || t >= G.g[d]) ok = false;
+        }
+        double blo = G.lo[d] + t * G.bs[d];
+        double e = fmax(0.0, fmax(blo - p[d], p[d] - (blo + G.bs[d])));
+        d2b += e * e;
+    }
+    if (d2b >= 4.0 * c.R2 * kMargin) ok = false;
+    int cntb = 0, beg = 0;
+    if (ok) {
+        int64_t blk = bb[0] + (int64_t)G.g[0] * (bb[1] + (int64_t)G.g[1] * bb[2]);
+        beg = A.start[blk];
+        cntb = A.start[blk + 1] - beg;
+    }
+    cnt[DC_BLOCKS] += __popcll(__ballot(ok));
+    int incl = wave_incl_scan(cntb, lane);
+    int total = __shfl(incl, 63);
+    if (total == 0) return ST_OK;
+    __syncthreads();
+    sh.cpre[lane] = incl - cntb;
+    sh.cbeg[lane] = beg;
+    sh.csh[lane] = (uint8_t)(25 * (sv[2] + 2) + 5 * (sv[1] + 2) + (sv[0] + 2));
+    __syncthreads();
+    for (int c0 = 0; c0 < total; c0 += 64 * K) {
+        unsigned long long key[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            int ci = c0 + k * 64 + lane;
+            key[k] = ~0ull;
+            if (ci < total) {
+                // last block whose exclusive prefix is <= ci
+                int lo = 0, hi = 63;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (sh.cpre[mid] <= ci) lo = mid; else hi = mid - 1;
+                }
+                int idx = sh.cbeg[lo] + (ci - sh.cpre[lo]);
+                int code = sh.csh[lo];
+                int s0 = code % 5 - 2, s1 = (code / 5) % 5 - 2, s2 = code / 25 - 2;
+                Particle q = A.part[idx];
+                double a0 = q.x - p[0], a1 = q.y - p[1], a2 = q.z - p[2];
+                if (s0) a0 = a0 + s0 * G.L[0];
+                if (s1) a1 = a1 + s1 * G.L[1];
+                if (s2) a2 = a2 + s2 * G.L[2];
+                double d2 = a0 * a0 + a1 * a1 + a2 * a2;
+                bool self = (idx == si) && code == kNoShift;
+                if (!self && d2 < 4.0 * c.R2 * kMargin) key[k] = __double_as_longlong(d2);
+                int slot = k * 64 + lane;
+                sh.u.gc.cq[slot][0] = a0;
+                sh.u.gc.cq[slot][1] = a1;
+                sh.u.gc.cq[slot][2] = a2;
+                sh.u.gc.cid[slot] = q.id;
+                sh.u.gc.ccode[slot] = (uint8_t)code;
+            }
+        }
+        __syncthreads();
+        for (;;) {
+            unsigned long long mk = key[0];
+#pragma unroll
+            for (int k = 1; k < K; k++) mk = key[k] < mk ? key[k] : mk;
+            mk = wave_min_u64(mk);
+            if (mk == ~0ull) break;
+            double md2 = __longlong_as_double((long long)mk);
+            if (!(md2 < 4.0 * c.R2 * kMargin)) break;
+            int kk = -1, ol = 0;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                unsigned long long b = __ballot(key[k] == mk);
+                if (kk < 0 && b) {
+                    kk = k;
+                    ol = __builtin_ctzll(b);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; k++)
+                if (k == kk && lane == ol) key[k] = ~0ull;
+            int slot = kk * 64 + ol;
+            double q0 = sh.u.gc.cq[slot][0], q1 = sh.u.gc.cq[slot][1], q2 = sh.u.gc.cq[slot][2];
+            int32_t id = sh.u.gc.cid[slot];
+            int code = sh.u.gc.ccode[slot];
+            cnt[DC_CAND]++;
+            if (md2 == 0.0) return ST_DUP;
+            int st = consider<S, MAXP, F32, K>(A, sh, c, q0, q1, q2, md2, id, code, ws, cnt, lane);
+            if (st != ST_OK) return st;
+        }
+        __syncthreads();
+    }
+    return ST_OK;
+}
+
+template <int S, int MAXP, bool F32, int K>
+__device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &sh, int si, double *ws, unsigned long long *cnt)
+{
+    const int lane = __lane_id();
+    const Grid &G = A.G;
+    const Particle me = A.part[si];
+    const double p[3] = {me.x, me.y, me.z};
+    const int id = me.id;
+    int bc[3];
+    double mrg[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        bc[d] = block_coord(G, p[d], d);
+        double blo = G.lo[d] + bc[d] * G.bs[d];
+        mrg[d] = fmin(p[d] - blo, blo + G.bs[d] - p[d]);
+    }
+    Cell<S, MAXP, F32> c;
+    // box planes (Eq. 1-2): walls, or bisectors with the own images at +-L
+    if (lane < 6) {
+        int d = lane >> 1, side = lane & 1;
+        double sg = side ? 1.0 : -1.0;
+        double n[3] = {0.0, 0.0, 0.0};
+        double h;
+        if (G.per[d]) {
+            double L = G.L[d];
+            n[d] = sg * L;
+            h = 0.5 * (L * L);
+            sh.pwall[lane] = 0;
+            sh.plab[lane] = id;
+            sh.psh[lane] = (uint8_t)(kNoShift + (side ? 1 : -1) * (d == 0 ? 1 : (d == 1 ? 5 : 25)));
+        } else {
+            n[d] = sg;
+            h = side ? (G.hi[d] - p[d]) : -(G.lo[d] - p[d]);
+            sh.pwall[lane] = 1;
+            sh.plab[lane] = -(2 * d + side + 1);
+            sh.psh[lane] = kNoShift;
+        }
+        sh.pq[lane][0] = n[0];
+        sh.pq[lane][1] = n[1];
+        sh.pq[lane][2] = n[2];
+        sh.pq[lane][3] = h;
+    }
+    // corners: triangle (X, Y, Z) counter-clockwise when det(nX, nY, nZ) > 0
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        c.tp[s] = 0;
+        c.vx[s] = c.vy[s] = c.vz[s] = 0.0;
+        c.fx[s] = c.fy[s] = c.fz[s] = 0.0f;
+        c.live[s] = 0;
+    }
+    c.live[0] = 0xffull;
+    if (lane < 8) {
+        int bx = lane & 1, by = (lane >> 1) & 1, bz = (lane >> 2) & 1;
+        int X = bx, Y = 2 + by, Z = 4 + bz;
+        int neg = 3 - bx - by - bz;
+        c.tp[0] = (neg & 1) ? (X | (Z << 8) | (Y << 16)) : (X | (Y << 8) | (Z << 16));
+        double e[3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            int b = (lane >> d) & 1;
+            if (G.per[d]) e[d] = b ? 0.5 * G.L[d] : -(0.5 * G.L[d]);
+            else e[d] = b ? (G.hi[d] - p[d]) : (G.lo[d] - p[d]);
+        }
+        c.vx[0] = e[0];
+        c.vy[0] = e[1];
+        c.vz[0] = e[2];
+        c.fx[0] = (float)e[0];
+        c.fy[0] = (float)e[1];
+        c.fz[0] = (float)e[2];
+        uint32_t t3 = c.tp[0];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
+            sh.etab[a][b] = (uint8_t)lane;
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < PlaneSet<MAXP>::W; w++) c.used.w[w] = 0;
+    c.used.w[0] = 0x3full;
+    c.used.w[PlaneSet<MAXP>::W - 1] |= PlaneSet<MAXP>::pad;
+    __syncthreads();
+    update_radius(c, lane);
+
+    // nearest-first sweep over the precomputed block offsets
+    bool finished = false;
+    for (int o0 = 0; o0 < A.noff; o0 += 64) {
+        if (A.offgap2[o0] >= 4.0 * c.R2 * kMargin) {
+            finished = true;
+            break;
+        }
+        int o = o0 + lane;
+        bool v = o < A.noff;
+        Offset of = v ? A.offs[o] : Offset{0, 0, 0, 0};
+        int st = gather<S, MAXP, F32, K>(A, sh, c, si, p, bc, of.dx, of.dy, of.dz, v, ws, cnt, lane);
+        if (st != ST_OK) return st;
+    }
+    // beyond the list: whole Chebyshev shells until the radius bound holds
+    if (!finished) {
+        cnt[DC_FALLBACK]++;
+        for (int r = A.off_radius + 1;; r++) {
+            if (r > kMaxShell || !radius_ok(c)) return ST_CAP;
+            double lb = 1e300;
+            bool exists = false;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                lb = fmin(lb, (r - 1) * G.bs[d] + mrg[d]);
+                if (G.per[d] || bc[d] - r >= 0 || bc[d] + r < G.g[d]) exists = true;
+            }
+            if (!exists) break;
+            if (lb > 0.0 && lb * lb >= 4.0 * c.R2 * kMargin) break;
+            int side = 2 * r + 1;
+            int tot = side * side * side;
+            for (int c0 = 0; c0 < tot; c0 += 64) {
+                int ix = c0 + lane;
+                int dx = ix % side - r, dy = (ix / side) % side - r, dz = ix / (side * side) - r;
+                int ch = max(abs(dx), max(abs(dy), abs(dz)));
+                bool v = ix < tot && ch == r;
+                if (!__ballot(v)) continue;
+                int st = gather<S, MAXP, F32, K>(A, sh, c, si, p, bc, dx, dy, dz, v, ws, cnt, lane);
+                if (st != ST_OK) return st;
+            }
+        }
+    }
+
+    // ---- statistics (a8) ----
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        int t = s * 64 + lane;
+        bool lv = (c.live[s] >> lane) & 1;
+        sh.u.st.tpl[t] = lv ? c.tp[s] : 0xffffffffu;
+        sh.u.st.pos[t][0] = c.vx[s];
+        sh.u.st.pos[t][1] = c.vy[s];
+        sh.u.st.pos[t][2] = c.vz[s];
+        sh.u.st.lab[t] = t;
+    }
+    for (int k = lane; k < MAXP; k += 64) {
+        sh.forder[k] = 0;
+        sh.fref[k] = 0x7fffffff;
+    }
+    if (lane < kFoLen) sh.fo[lane] = 0;
+    __syncthreads();
+    for (int t = lane; t < S * 64; t += 64) {
+        uint32_t t3 = sh.u.st.tpl[t];
+        if (t3 == 0xffffffffu) continue;
+        for (int k = 0; k < 3; k++) atomicMin(&sh.fref[(t3 >> (8 * k)) & 0xff], t);
+    }
+    __syncthreads();
+    // Zero-length edges (a degenerate vertex split over several triangles):
+    // the edge (a, b) between slot t and its twin has zero length when the
+    // vertex of t lies on the twin's third plane d.  Bit (s*3+k) of zb.
+    uint32_t zb = 0, ib = 0;
+    for (int j = 0; j < 3 * S; j++) {
+        int t = (j / 3) * 64 + lane, k = j % 3;
+        uint32_t t3 = sh.u.st.tpl[t];
+        if (t3 == 0xffffffffu) continue;
+        int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
+        uint32_t w3 = sh.u.st.tpl[sh.etab[b][a] & (S * 64 - 1)];
+        int d = (int)(w3 & 0xff) + (int)((w3 >> 8) & 0xff) + (int)((w3 >> 16) & 0xff) - a - b;
+        d = min(max(d, 0), MAXP - 1);
+        const double *nd = sh.pq[d];
+        const double *v = sh.u.st.pos[t];
+        double sd = nd[0] * v[0] + nd[1] * v[1] + nd[2] * v[2] - nd[3];
+        double bd = A.tau * ((fabs(nd[0]) + fabs(nd[1]) + fabs(nd[2])) * c.R + fabs(nd[3]));
+        if (!(sd < -bd)) ib |= 1u << j;
+    }
+    if (__ballot(ib != 0)) {
+        for (int j = 0; j < 3 * S; j++) {
+            unsigned long long m = __ballot((ib >> j) & 1);
+            while (m) {
+                int l = __builtin_ctzll(m);
+                m &= m - 1;
+                if (lane == l) {
+                    int t = (j / 3) * 64 + lane, k = j % 3;
+                    uint32_t t3 = sh.u.st.tpl[t];
+                    int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
+                    uint32_t w3 = sh.u.st.tpl[sh.etab[b][a] & (S * 64 - 1)];
+                    int d = (int)(w3 & 0xff) + (int)((w3 >> 8) & 0xff) + (int)((w3 >> 16) & 0xff) - a - b;
+                    d = min(max(d, 0), MAXP - 1);
+                    int sg = exact_side3(plane_of(sh, t3 & 0xff), plane_of(sh, (t3 >> 8) & 0xff),
+                                         plane_of(sh, (t3 >> 16) & 0xff), plane_of(sh, d), ws);
+                    if (sg == 0) zb |= 1u << j;
+                }
+                cnt[DC_EXACT]++;
+            }
+        }
+    }
+    // face orders and the fan over each face from its reference vertex:
+    // tetrahedra (0, r_a, v_twin, v_t), the twin across a -> b being the
+    // previous vertex of face a counter-clockwise
+    double v6 = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    for (int j = 0; j < 3 * S; j++) {
+        int t = (j / 3) * 64 + lane, k = j % 3;
+        uint32_t t3 = sh.u.st.tpl[t];
+        if (t3 == 0xffffffffu) continue;
+        int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
+        if (!((zb >> j) & 1)) atomicAdd(&sh.forder[a], 1);
+        const double *r = sh.u.st.pos[sh.fref[a]];
+        const double *w = sh.u.st.pos[sh.etab[b][a] & (S * 64 - 1)];
+        const double *v = sh.u.st.pos[t];
+        double det = r[0] * (w[1] * v[2] - w[2] * v[1]) - r[1] * (w[0] * v[2] - w[2] * v[0]) +
+                     r[2] * (w[0] * v[1] - w[1] * v[0]);
+        v6 += det;
+        m0 += det * (r[0] + w[0] + v[0]);
+        m1 += det * (r[1] + w[1] + v[1]);
+        m2 += det * (r[2] + w[2] + v[2]);
+    }
+    // vertices: triangles joined by zero-length edges are one vertex
+    int nvert = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) nvert += __popcll(c.live[s]);
+    if (__ballot(zb != 0)) {
+        for (int it = 0; it < 4 * S * 64; it++) {
+            bool ch = false;
+            for (int j = 0; j < 3 * S; j++) {
+                if (!((zb >> j) & 1)) continue;
+                int t = (j / 3) * 64 + lane, k = j % 3;
+                uint32_t t3 = sh.u.st.tpl[t];
+                int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
+                int o = sh.u.st.lab[sh.etab[b][a] & (S * 64 - 1)];
+                if (o < sh.u.st.lab[t]) {
+                    sh.u.st.lab[t] = o;
+                    ch = true;
+                }
+            }
+            __syncthreads();
+            if (!__ballot(ch)) break;
+        }
+        nvert = 0;
+        for (int t0 = 0; t0 < S * 64; t0 += 64) {
+            int t = t0 + lane;
+            nvert += __popcll(__ballot(sh.u.st.tpl[t] != 0xffffffffu && sh.u.st.lab[t] == t));
+        }
+    }
+    __syncthreads();
+    // faces with at least three distinct vertices are the cell's faces
+    int nface = 0, sumord = 0, rk = 0;
+    bool capfail = false;
+    for (int k0 = 0; k0 < MAXP; k0 += 64) {
+        int k = k0 + lane;
+        int ord = k < MAXP ? sh.forder[k] : 0;
+        bool real = ord >= 3;
+        unsigned long long rb = __ballot(real);
+        int rank = rk + lane_rank(rb);
+        if (real) {
+            if (ord < kFoLen) atomicAdd(&sh.fo[ord], 1);
+            if ((A.mask & (16 | 32)) && A.nbr) {
+                if (rank < kMaxNbr) {
+                    A.nbr[(int64_t)id * kMaxNbr + rank] = sh.plab[k];
+                    A.nsh[(int64_t)id * kMaxNbr + rank] = sh.psh[k];
+                }
+            }
+        }
+        rk += __popcll(rb);
+        sumord += wave_isum(real ? ord : 0);
+    }
+    nface = rk;
+    if (nface > kMaxNbr) capfail = true;
+    double vol6 = wave_sum(v6);
+    double M0 = wave_sum(m0), M1 = wave_sum(m1), M2 = wave_sum(m2);
+    __syncthreads();
+    if (lane == 0) {
+        double vol = vol6 / 6.0;
+        if (A.vol) A.vol[id] = vol;
+        if (A.cen) {
+            A.cen[3 * (int64_t)id + 0] = M0 / (4.0 * vol6);
+            A.cen[3 * (int64_t)id + 1] = M1 / (4.0 * vol6);
+            A.cen[3 * (int64_t)id + 2] = M2 / (4.0 * vol6);
+        }
+        if (A.nv) A.nv[id] = nvert;
+        if (A.ne) A.ne[id] = sumord / 2;
+        if (A.nf) A.nf[id] = nface;
+    }
+    if (A.fo && lane < kFoLen) A.fo[(int64_t)id * kFoLen + lane] = (uint8_t)min(sh.fo[lane], 255);
+    return capfail ? ST_CAP : ST_OK;
+}
+
+template <int S, int MAXP, bool F32, int K>
+__global__ __launch_bounds__(64) void k_cells(CellArgs A, int spill_mode)
+{
+    __shared__ CellLDS<S, MAXP, K> sh;
+    const int lane = __lane_id();
+    double *ws = A.xscratch + (size_t)blockIdx.x * A.xscratch_len;
+    unsigned long long cnt[DC_N];
+#pragma unroll
+    for (int k = 0; k < DC_N; k++) cnt[k] = 0;
+    const int ncell = A.ncell_dev ? __builtin_amdgcn_readfirstlane(*A.ncell_dev) : A.ncell;
+    for (;;) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(A.queue, A.chunk);
+        base = __shfl(base, 0);
+        if (base >= ncell) break;
+        int end = min(base + A.chunk, ncell);
+        for (int ci = base; ci < end; ci++) {
+            int si = A.cell_list ? A.cell_list[ci] : ci;
+            int st = cell_run<S, MAXP, F32, K>(A, sh, si, ws, cnt);
+            if (lane == 0) {
+                int id = A.part[si].id;
+                if (st == ST_OK) {
+                    A.status[id] = spill_mode ? 1 : 0;
+                } else if (st == ST_DUP) {
+                    A.status[id] = 3;
+                } else if (!spill_mode) {
+                    A.status[id] = 1;
+                    int pos = atomicAdd(A.spill_count, 1);
+                    A.spill_list[pos] = si;
+                } else {
+                    A.status[id] = 2;
+                }
+                if (st == ST_CAP && !spill_mode) cnt[DC_SPILL]++;
+            }
+            __syncthreads();
+        }
+    }
+    if (lane < DC_N) {
+        unsigned long long v = 0;
+#pragma unroll
+        for (int k = 0; k < DC_N; k++)
+            if (k == lane) v = cnt[k];
+        // counters are wave-uniform except the spill count (lane 0)
+        if (lane == DC_SPILL) v = __shfl(cnt[DC_SPILL], 0);
+        if (v) atomicAdd(&A.diag[lane], v);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_cells(const CellArgs &a, int precision, int slots, int waves, hipStream_t s)
+{
+    if (slots == 4) {
+        if (precision == 1) k_cells<4, 48, true, 1><<<waves, 64, 0, s>>>(a, 0);
+        else k_cells<4, 48, false, 1><<<waves, 64, 0, s>>>(a, 0);
+    } else {
+        if (precision == 1) k_cells<2, 48, true, 1><<<waves, 64, 0, s>>>(a, 0);
+        else k_cells<2, 48, false, 1><<<waves, 64, 0, s>>>(a, 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cells_spill(const CellArgs &a, int waves, hipStream_t s)
+{
+    k_cells<4, 128, false, 1><<<waves, 64, 0, s>>>(a, 1);
+    return hipGetLastError();
+}
+
+}  // namespace vc

@@ -1,0 +1,97 @@
+// vc_internal.h -- data shared by the host runtime and the HIP kernels of
+// the Voronoi cell library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vc {
+
+constexpr int kWave = 64;
+constexpr int kFoLen = 32;      // face-order vector length
+constexpr int kMaxNbr = 64;     // neighbour slots per cell in the fixed-stride scratch
+constexpr int kOffRadius = 4;   // Chebyshev radius of the precomputed block-offset list
+constexpr int kNoShift = 62;    // image code of the zero shift: 25*2 + 5*2 + 2
+
+// One particle in the block-sorted array (32 bytes: one aligned pair of
+// 16-byte loads per lane).
+struct alignas(32) Particle {
+    double x, y, z;
+    int32_t id;   // input index
+    int32_t pad;
+};
+
+// Geometry of a container's grid of blocks (section 2.1.1, 2.1.4).
+struct Grid {
+    int dim;
+    int g[3];         // blocks per axis
+    int per[3];       // periodic flags
+    double lo[3], hi[3], L[3];
+    double bs[3];     // block side L/g
+    double inv_bs[3]; // g/L
+    int64_t nb;       // total blocks
+};
+
+// Block index of a coordinate along one axis: floor((x - lo) g / L), clamped.
+__host__ __device__ inline int block_coord(const Grid &G, double x, int d)
+{
+    double t = (x - G.lo[d]) * G.inv_bs[d];
+    int k = (int)floor(t);
+    if (k < 0) k = 0;
+    if (k >= G.g[d]) k = G.g[d] - 1;
+    return k;
+}
+
+// Block offset relative to a particle's own block, with the squared lower
+// bound of the distance from any point of the own block to that block.
+struct Offset {
+    int dx, dy, dz, pad;
+};
+
+// Arguments of the cell kernels.
+struct CellArgs {
+    Grid G;
+    const Particle *part;      // block-sorted particles
+    const int32_t *start;      // block start offsets, nb + 1
+    const Offset *offs;        // nearest-first block offsets
+    const double *offgap2;     // lower bound of squared distance per offset
+    int noff;
+    int off_radius;            // Chebyshev radius covered by offs
+    int ncell;                 // cells in this launch
+    const int32_t *ncell_dev;  // if set: the cell count is read from device memory
+    const int32_t *cell_list;  // sorted indices to compute (NULL: 0..ncell-1)
+    int32_t *queue;            // work-queue head (zeroed before the launch)
+    int chunk;                 // cells per queue grab
+    double tau;                // FP64 band, relative
+    uint32_t mask;             // statistics mask
+    // outputs, by particle id
+    double *vol;
+    double *cen;
+    int32_t *nv, *ne, *nf;
+    uint8_t *fo;
+    int32_t *nbr;              // id * kMaxNbr + k
+    uint8_t *nsh;
+    uint8_t *status;
+    // spill queue for cells beyond the kernel's capacity
+    int32_t *spill_list;
+    int32_t *spill_count;
+    unsigned long long *diag;  // VC_DIAG_LEN counters
+    double *xscratch;          // per-wave workspace of the exact predicate
+    int xscratch_len;          // doubles per wave
+};
+
+// Launchers (defined in the .hip translation unit).
+hipError_t launch_bin_count(const double *xyz, int64_t n, const Grid &G, int32_t *blk, int32_t *rank,
+                            int32_t *count, int32_t *err, hipStream_t s);
+hipError_t launch_scan(const int32_t *count, int32_t *start, int64_t nb, int32_t *tmp, hipStream_t s);
+hipError_t launch_scatter(const double *xyz, int64_t n, const Grid &G, const int32_t *blk, const int32_t *rank,
+                          const int32_t *start, Particle *part, hipStream_t s);
+hipError_t launch_block_order(Particle *part, const int32_t *start, int64_t nb, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_cells(const CellArgs &a, int precision, int slots, int waves, hipStream_t s);
+hipError_t launch_cells_spill(const CellArgs &a, int waves, hipStream_t s);
+hipError_t launch_nbr_compact(const int32_t *nf, int64_t n, const int32_t *nbr, const uint8_t *nsh,
+                              int64_t *offsets, int32_t *ids, uint8_t *shifts, int32_t *tmp, hipStream_t s);
+hipError_t launch_nbr_offsets(const int32_t *nf, int64_t n, int64_t *offsets, int32_t *tmp, hipStream_t s);
+int device_cu_count();
+
+}  // namespace vc

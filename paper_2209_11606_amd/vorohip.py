@@ -1,0 +1,216 @@
+"""Thin Python binding of the vorohip C ABI (include/vorohip.h).
+
+Argument marshalling only: every step of the cell computation runs in the HIP
+library.  Functions keep the C names.  PyTorch provides device memory and the
+stream; results are copied out with vc_result_copy.  If the library has not
+been built the import fails loudly -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvorohip.so")
+
+VC_OK, VC_E_ARG, VC_E_RANGE, VC_E_DUPLICATE, VC_E_NOMEM, VC_E_HIP, VC_E_CAPACITY, VC_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+VC_FP64, VC_F32_FILTER = 0, 1
+VC_VOLUME, VC_CENTROID, VC_COUNTS, VC_FACE_ORDERS, VC_NEIGHBORS, VC_NEIGHBOR_COUNT, VC_DIAG = 1, 2, 4, 8, 16, 32, 64
+VC_ALL = 127
+(VC_F_VOLUME, VC_F_CENTROID, VC_F_NV, VC_F_NE, VC_F_NF, VC_F_FACE_ORDERS, VC_F_NBR_OFFSETS, VC_F_NBR_IDS,
+ VC_F_NBR_SHIFTS, VC_F_STATUS, VC_F_DIAG) = range(11)
+VC_FO_LEN = 32
+VC_DIAG_LEN = 16
+DIAG_NAMES = ["candidates", "tests", "cuts", "new_vertices", "exact", "recheck", "spilled", "blocks", "fallback"]
+_FIELD_DTYPE = {VC_F_VOLUME: np.float64, VC_F_CENTROID: np.float64, VC_F_NV: np.int32, VC_F_NE: np.int32,
+                VC_F_NF: np.int32, VC_F_FACE_ORDERS: np.uint8, VC_F_NBR_OFFSETS: np.int64, VC_F_NBR_IDS: np.int32,
+                VC_F_NBR_SHIFTS: np.uint8, VC_F_STATUS: np.uint8, VC_F_DIAG: np.uint64}
+
+
+class vc_options(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("periodic", ctypes.c_int * 3), ("n_opt", ctypes.c_double), ("grid", ctypes.c_int * 3),
+                ("precision", ctypes.c_int), ("slots", ctypes.c_int), ("waves", ctypes.c_int),
+                ("chunk", ctypes.c_int)]
+
+
+class VcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vorohip error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"vorohip: {LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, U32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32
+    sig = {
+        "vc_options_init": (I32, [P, I32, P, P, P]),
+        "vc_container_create": (I32, [P, I64, P, P, P]),
+        "vc_container_rebin": (I32, [P, P, P]),
+        "vc_result_create": (I32, [P, U32, P]),
+        "vc_compute": (I32, [P, P, P]),
+        "vc_result_get": (I32, [P, I32, P, P]),
+        "vc_result_copy": (I32, [P, I32, P, I64]),
+        "vc_result_destroy": (None, [P]),
+        "vc_container_destroy": (None, [P]),
+        "vc_batch_create": (I32, [P, P, I64, P, P, P]),
+        "vc_batch_result_create": (I32, [P, U32, P]),
+        "vc_batch_compute": (I32, [P, P, I32, P]),
+        "vc_batch_destroy": (None, [P]),
+        "vc_result_kernel_ms": (I32, [P, P]),
+        "vc_last_error": (ctypes.c_char_p, []),
+        "vc_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_result_create", "vc_compute",
+            "vc_result_get", "vc_result_copy", "vc_result_kernel_ms", "vc_result_destroy", "vc_container_destroy", "vc_batch_create",
+            "vc_batch_result_create", "vc_batch_compute", "vc_batch_destroy", "vc_last_error", "vc_version"]
+
+
+def lib():
+    return _lib
+
+
+def vc_last_error():
+    return _lib.vc_last_error().decode()
+
+
+def vc_version():
+    return _lib.vc_version().decode()
+
+
+def _check(code):
+    if code != VC_OK:
+        raise VcError(code, vc_last_error())
+
+
+def vc_options_init(dim, lo, hi, periodic, **kw):
+    o = vc_options()
+    lo_a = (ctypes.c_double * 3)(*[float(v) for v in lo])
+    hi_a = (ctypes.c_double * 3)(*[float(v) for v in hi])
+    pe_a = (ctypes.c_int * 3)(*[int(bool(v)) for v in periodic])
+    _check(_lib.vc_options_init(ctypes.byref(o), dim, lo_a, hi_a, pe_a))
+    for k, v in kw.items():
+        if k == "grid":
+            for d, g in enumerate(v):
+                o.grid[d] = int(g)
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def vc_container_create(xyz, opts, stream=None):
+    """xyz: a contiguous float64 torch tensor (n x dim) on the GPU, or a numpy
+    array on the host.  Returns the container handle (c_void_p)."""
+    n = xyz.shape[0]
+    ptr = xyz.data_ptr() if hasattr(xyz, "data_ptr") else xyz.ctypes.data
+    h = ctypes.c_void_p()
+    _check(_lib.vc_container_create(ctypes.c_void_p(ptr), n, ctypes.byref(opts), ctypes.c_void_p(_stream_ptr(stream)),
+                                    ctypes.byref(h)))
+    return h
+
+
+def vc_container_rebin(c, xyz, stream=None):
+    ptr = xyz.data_ptr() if hasattr(xyz, "data_ptr") else xyz.ctypes.data
+    _check(_lib.vc_container_rebin(c, ctypes.c_void_p(ptr), ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def vc_result_create(c, mask):
+    h = ctypes.c_void_p()
+    _check(_lib.vc_result_create(c, mask, ctypes.byref(h)))
+    return h
+
+
+def vc_compute(c, r, stream=None):
+    _check(_lib.vc_compute(c, r, ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def vc_result_get(r, field):
+    p = ctypes.c_void_p()
+    k = ctypes.c_int64()
+    _check(_lib.vc_result_get(r, field, ctypes.byref(p), ctypes.byref(k)))
+    return p.value, k.value
+
+
+def vc_result_copy(r, field):
+    _, k = vc_result_get(r, field)
+    out = np.empty(k, dtype=_FIELD_DTYPE[field])
+    _check(_lib.vc_result_copy(r, field, out.ctypes.data, out.nbytes))
+    return out
+
+
+def vc_result_kernel_ms(r):
+    ms = ctypes.c_float()
+    _check(_lib.vc_result_kernel_ms(r, ctypes.byref(ms)))
+    return ms.value
+
+
+def vc_result_destroy(r):
+    _lib.vc_result_destroy(r)
+
+
+def vc_container_destroy(c):
+    _lib.vc_container_destroy(c)
+
+
+def fetch(r, mask, n, dim=3):
+    """Copy every field of a result that the mask produced into numpy arrays."""
+    out = {"status": vc_result_copy(r, VC_F_STATUS), "nf": vc_result_copy(r, VC_F_NF)}
+    if mask & VC_VOLUME:
+        out["vol"] = vc_result_copy(r, VC_F_VOLUME)
+    if mask & VC_CENTROID:
+        out["cen"] = vc_result_copy(r, VC_F_CENTROID).reshape(n, 3)[:, :dim]
+    if mask & VC_COUNTS:
+        out["nv"] = vc_result_copy(r, VC_F_NV)
+        out["ne"] = vc_result_copy(r, VC_F_NE)
+    if mask & VC_FACE_ORDERS:
+        out["fo"] = vc_result_copy(r, VC_F_FACE_ORDERS).reshape(n, VC_FO_LEN).astype(np.int32)
+    if mask & VC_NEIGHBORS:
+        off = vc_result_copy(r, VC_F_NBR_OFFSETS)
+        ids = vc_result_copy(r, VC_F_NBR_IDS)
+        sh = vc_result_copy(r, VC_F_NBR_SHIFTS)
+        out["nbr_off"], out["nbr_ids"], out["nbr_sh"] = off, ids, sh
+    d = vc_result_copy(r, VC_F_DIAG)
+    out["diag"] = dict(zip(DIAG_NAMES, d[:len(DIAG_NAMES)].tolist()))
+    return out
+
+
+def neighbor_lists(res):
+    """Per-cell sorted (label, image) arrays from the CSR fields of fetch()."""
+    off, ids, sh = res["nbr_off"], res["nbr_ids"], res["nbr_sh"]
+    return [np.stack([ids[off[i]:off[i + 1]].astype(np.int64), sh[off[i]:off[i + 1]].astype(np.int64)], 1)
+            for i in range(len(off) - 1)]
+
+
+def tessellate(xyz, lo, hi, periodic, mask=VC_ALL, stream=None, **opts):
+    """Create a container from device positions, compute all cells, fetch the
+    results to the host, and free everything.  Convenience for tests."""
+    dim = xyz.shape[1]
+    o = vc_options_init(dim, lo, hi, periodic, **opts)
+    c = vc_container_create(xyz, o, stream)
+    try:
+        r = vc_result_create(c, mask)
+        try:
+            vc_compute(c, r, stream)
+            return fetch(r, mask, xyz.shape[0], dim)
+        finally:
+            vc_result_destroy(r)
+    finally:
+        vc_container_destroy(c)

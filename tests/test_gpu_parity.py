@@ -1,0 +1,184 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Topology (vertex, edge, face counts, face-order vectors, sorted neighbour
+lists) must be identical; volumes within 1e-12 relative and centroids within
+1e-12 * vol^(1/3) (the tolerance the target states for FP64).  The FP32-filter
+form must be bitwise identical to the FP64 form: its filter only ever defers
+to FP64 inside a band that covers the FP32 rounding error.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_2209_11606_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def v():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_11606_amd import vorohip
+    return vorohip
+
+
+def run(v, x, lo, hi, per, **opt):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+    out = v.tessellate(xt, lo, hi, per, v.VC_ALL, **opt)
+    out["nbr"] = v.neighbor_lists(out)
+    return out
+
+
+def assert_parity(g, r, idx=None, vol_tol=1e-12):
+    idx = np.arange(len(g["vol"])) if idx is None else np.asarray(idx)
+    assert np.all(g["status"][idx] <= 1), np.unique(g["status"][idx])
+    for key in ("nv", "ne", "nf"):
+        bad = np.nonzero(g[key][idx] != r[key])[0]
+        assert len(bad) == 0, (key, idx[bad[:5]], g[key][idx][bad[:5]], r[key][bad[:5]])
+    assert np.array_equal(g["fo"][idx], r["fo"])
+    for t, i in enumerate(idx):
+        assert np.array_equal(g["nbr"][i], r["nbr"][t]), (i, g["nbr"][i].tolist(), r["nbr"][t].tolist())
+    rel = np.abs(g["vol"][idx] - r["vol"]) / r["vol"]
+    assert rel.max() <= vol_tol, rel.max()
+    scale = r["vol"] ** (1.0 / 3.0)
+    cerr = np.abs(g["cen"][idx] - r["cen"]).max(1) / scale
+    assert cerr.max() <= 1e-12, cerr.max()
+
+
+def same_bits(a, b):
+    for k in ("vol", "cen", "nv", "ne", "nf", "fo", "status", "nbr_off", "nbr_ids", "nbr_sh"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_walled_1k_all_cells(v):
+    w = W.walled_1k()
+    g = run(v, w["xyz"], w["lo"], w["hi"], w["periodic"])
+    r = oracle.Oracle(w["xyz"], w["lo"], w["hi"], w["periodic"]).cells()
+    assert_parity(g, r)
+
+
+@pytest.mark.parametrize("n,per,seed", [(30, [0, 0, 0], 7), (24, [1, 1, 1], 8), (20, [1, 0, 1], 11)])
+def test_tiny_against_exact_brute_force(v, n, per, seed):
+    x = W.uniform(n, 3, 1.0, seed)
+    g = run(v, x, [0] * 3, [1] * 3, per)
+    for i in range(n):
+        b = brute.cell(x, i, [0] * 3, [1] * 3, per)
+        assert g["nv"][i] == b["nv"] and g["ne"][i] == b["ne"] and g["nf"][i] == b["nf"]
+        assert list(g["fo"][i]) == b["fo"]
+        assert [tuple(t) for t in g["nbr"][i].tolist()] == b["nbr"]
+        assert abs(g["vol"][i] - float(b["vol"])) <= 1e-13 * float(b["vol"])
+
+
+@pytest.mark.parametrize("n", [1, 2, 7])
+def test_ragged_small_counts(v, n):
+    x = W.uniform(n, 3, 1.0, 100 + n)
+    for per in ([0, 0, 0], [1, 1, 1]):
+        g = run(v, x, [0] * 3, [1] * 3, per)
+        r = oracle.Oracle(x, [0] * 3, [1] * 3, per).cells()
+        assert_parity(g, r)
+        assert math.fsum(g["vol"]) == pytest.approx(1.0, rel=1e-13)
+
+
+def test_nonunit_offset_box(v):
+    lo, hi = [-1.5, 2.0, 0.25], [0.5, 2.75, 1.75]
+    u = W.uniform(500, 3, 1.0, 21)
+    x = np.array(lo) + u * (np.array(hi) - np.array(lo))
+    x = np.minimum(x, np.nextafter(np.array(hi), -np.inf))
+    per = [1, 0, 1]
+    g = run(v, x, lo, hi, per)
+    r = oracle.Oracle(x, lo, hi, per).cells()
+    assert_parity(g, r)
+
+
+@pytest.mark.parametrize("a", [1.0, 2.0])
+def test_lattices_degenerate(v, a):
+    """Exact lattices: every degenerate contact is an exact zero; the GPU
+    merges split vertices and drops zero-area faces like the oracle."""
+    for (x, hi), V, E, F, vol in [(W.sc(5, a), 8, 12, 6, a ** 3), (W.bcc(4, a), 24, 36, 14, a ** 3 / 2),
+                                  (W.fcc((3, 3, 4), a), 14, 24, 12, a ** 3 / 4)]:
+        g = run(v, x, [0] * 3, hi, [1, 1, 1])
+        assert set(g["nv"]) == {V} and set(g["ne"]) == {E} and set(g["nf"]) == {F}
+        assert np.allclose(g["vol"], vol, rtol=1e-13)
+        r = oracle.Oracle(x, [0] * 3, hi, [1, 1, 1]).cells()
+        assert_parity(g, r)
+    x, hi = W.sc(4, a)
+    g = run(v, x, [0] * 3, hi, [0, 0, 0])
+    r = oracle.Oracle(x, [0] * 3, hi, [0, 0, 0]).cells()
+    assert_parity(g, r)
+
+
+def test_periodic_20k_all_cells_and_f32_bitwise(v):
+    side = 20000 ** (1 / 3)
+    x = W.uniform(20000, 3, side, 31)
+    g = run(v, x, [0] * 3, [side] * 3, [1, 1, 1])
+    r = oracle.Oracle(x, [0] * 3, [side] * 3, [1, 1, 1]).cells(nthreads=oracle.num_threads())
+    assert_parity(g, r)
+    f = run(v, x, [0] * 3, [side] * 3, [1, 1, 1], precision=v.VC_F32_FILTER)
+    same_bits(g, f)
+    assert f["diag"]["recheck"] > 0
+    g2 = run(v, x, [0] * 3, [side] * 3, [1, 1, 1])
+    same_bits(g, g2)  # run-to-run determinism
+
+
+def test_perturbed_fcc_near_degenerate(v):
+    x, hi = W.fcc((8, 8, 8), 1.0, 1e-3, seed=3)
+    g = run(v, x, [0] * 3, hi, [1, 1, 1])
+    r = oracle.Oracle(x, [0] * 3, hi, [1, 1, 1]).cells(nthreads=oracle.num_threads())
+    assert_parity(g, r)
+    f = run(v, x, [0] * 3, hi, [1, 1, 1], precision=v.VC_F32_FILTER)
+    same_bits(g, f)
+
+
+def test_slots4_and_chunk_variants_agree(v):
+    side = 3000 ** (1 / 3)
+    x = W.uniform(3000, 3, side, 41)
+    base = run(v, x, [0] * 3, [side] * 3, [1, 1, 1])
+    for opt in (dict(slots=4), dict(chunk=1), dict(chunk=64), dict(waves=7)):
+        same_bits(base, run(v, x, [0] * 3, [side] * 3, [1, 1, 1], **opt))
+
+
+def test_full_size_periodic_1m(v):
+    """The 1M-particle periodic workload in the benchmark's launch
+    configuration: sampled cells against the oracle, invariants over all."""
+    w = W.periodic_1m()
+    x = w["xyz"]
+    g = run(v, x, w["lo"], w["hi"], w["periodic"])
+    n = len(x)
+    assert np.all(g["status"] == 0)
+    assert math.fsum(g["vol"]) == pytest.approx(100.0 ** 3, rel=1e-12)
+    assert np.all(g["nv"] - g["ne"] + g["nf"] == 2)
+    assert np.all(2 * g["ne"] == 3 * g["nv"])
+    assert np.all(g["fo"].sum(1) == g["nf"])
+    assert np.all((g["fo"] * np.arange(32)).sum(1) == 2 * g["ne"])
+    # neighbour symmetry over the CSR arrays: (i -> j, s) pairs with (j -> i, -s)
+    off, ids, sh = g["nbr_off"], g["nbr_ids"].astype(np.int64), g["nbr_sh"].astype(np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
+    s = np.stack([sh % 5 - 2, (sh // 5) % 5 - 2, sh // 25 - 2], 1)
+    negc = 25 * (-s[:, 2] + 2) + 5 * (-s[:, 1] + 2) + (-s[:, 0] + 2)
+    fwd = np.sort(src * (n * 128) + ids * 128 + sh)
+    bwd = np.sort(ids * (n * 128) + src * 128 + negc)
+    assert np.array_equal(fwd, bwd)
+    ef = 2 + 48 * math.pi ** 2 / 35
+    assert abs(g["nf"].mean() - ef) < 0.02
+    idx = np.random.default_rng(0).choice(n, 1500, replace=False)
+    r = oracle.Oracle(x, w["lo"], w["hi"], w["periodic"]).cells(idx, nthreads=oracle.num_threads())
+    assert_parity(g, r, idx)
+
+
+def test_errors(v):
+    x = W.uniform(100, 3, 1.0, 5)
+    x[3, 1] = 1.5
+    xt = torch.from_numpy(x).to("cuda:0")
+    with pytest.raises(v.VcError) as e:
+        v.tessellate(xt, [0] * 3, [1] * 3, [0, 0, 0])
+    assert e.value.code == v.VC_E_RANGE
+    x = W.uniform(100, 3, 1.0, 5)
+    x[7] = x[8]
+    g = run(v, x, [0] * 3, [1] * 3, [0, 0, 0])
+    assert g["status"][7] == 3 and g["status"][8] == 3
