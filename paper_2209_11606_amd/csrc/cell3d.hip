@@ -923,8 +923,17 @@ __global__ __launch_bounds__(64) void k_cells(CellArgs A, int spill_mode)
         for (int ci = base; ci < end; ci++) {
             int si = A.cell_list ? A.cell_list[ci] : ci;
             int st = cell_run<S, MAXP, F32, K>(A, sh, si, ws, cnt);
+            if (st != ST_OK && A.fo && lane < kFoLen) A.fo[(int64_t)A.part[si].id * kFoLen + lane] = 0;
             if (lane == 0) {
                 int id = A.part[si].id;
+                if (st != ST_OK) {
+                    // no statistics for this cell (yet): empty outputs
+                    if (A.vol) A.vol[id] = __builtin_nan("");
+                    if (A.cen) A.cen[3 * (int64_t)id] = A.cen[3 * (int64_t)id + 1] = A.cen[3 * (int64_t)id + 2] = __builtin_nan("");
+                    if (A.nv) A.nv[id] = 0;
+                    if (A.ne) A.ne[id] = 0;
+                    if (A.nf) A.nf[id] = 0;
+                }
                 if (st == ST_OK) {
                     A.status[id] = spill_mode ? 1 : 0;
                 } else if (st == ST_DUP) {
