@@ -164,59 +164,132 @@ __device__ __noinline__ int exact_side3(PlaneD a, PlaneD b, PlaneD c, PlaneD p, 
 #pragma clang fp contract(fast)
 
 // ---------------------------------------------------------------------------
-// Wave helpers
+// Wave helpers.  Reductions and scans use DPP lane movement (quad
+// permutations, row mirrors, row shifts and the row broadcasts of the
+// 64-wide wave) and end with a readlane, so the result is wave-uniform and
+// no LDS round trip is taken.
 // ---------------------------------------------------------------------------
-__device__ inline int lane_rank(uint64_t m)
+enum {
+    DPP_QUAD_1032 = 0xB1,     // quad_perm [1,0,3,2]
+    DPP_QUAD_2301 = 0x4E,     // quad_perm [2,3,0,1]
+    DPP_ROW_SHR1 = 0x111,
+    DPP_ROW_SHR2 = 0x112,
+    DPP_ROW_SHR4 = 0x114,
+    DPP_ROW_SHR8 = 0x118,
+    DPP_ROW_MIRROR = 0x140,
+    DPP_ROW_HALF_MIRROR = 0x141,
+    DPP_ROW_BCAST15 = 0x142,  // lane 15 of each row to the next row
+    DPP_ROW_BCAST31 = 0x143   // lane 31 to rows 2 and 3
+};
+
+template <int CTRL, int RM>
+__device__ __forceinline__ int dpp_i32(int old, int v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, RM, 0xf, false);
+}
+
+template <int CTRL, int RM>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long old, unsigned long long v)
+{
+    int lo = __builtin_amdgcn_update_dpp((int)(unsigned)old, (int)(unsigned)v, CTRL, RM, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(old >> 32), (int)(unsigned)(v >> 32), CTRL, RM, 0xf, false);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_f64(double old, double v)
+{
+    return __builtin_bit_cast(double, dpp_u64<CTRL, RM>(__builtin_bit_cast(unsigned long long, old),
+                                                         __builtin_bit_cast(unsigned long long, v)));
+}
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l)
+{
+    unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+    unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    return __builtin_bit_cast(double, readlane_u64(__builtin_bit_cast(unsigned long long, v), l));
+}
+
+__device__ __forceinline__ int lane_rank(uint64_t m)
 {
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-__device__ inline double wave_max(double v)
+__device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    v = fmax(v, dpp_f64<DPP_QUAD_1032, 0xf>(v, v));
+    v = fmax(v, dpp_f64<DPP_QUAD_2301, 0xf>(v, v));
+    v = fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR, 0xf>(v, v));
+    v = fmax(v, dpp_f64<DPP_ROW_MIRROR, 0xf>(v, v));
+    v = fmax(v, dpp_f64<DPP_ROW_BCAST15, 0xa>(v, v));
+    v = fmax(v, dpp_f64<DPP_ROW_BCAST31, 0xc>(v, v));
+    return readlane_f64(v, 63);
+}
+
+// fixed combination order: the sum is the same on every run
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v = v + dpp_f64<DPP_QUAD_1032, 0xf>(0.0, v);
+    v = v + dpp_f64<DPP_QUAD_2301, 0xf>(0.0, v);
+    v = v + dpp_f64<DPP_ROW_HALF_MIRROR, 0xf>(0.0, v);
+    v = v + dpp_f64<DPP_ROW_MIRROR, 0xf>(0.0, v);
+    v = v + dpp_f64<DPP_ROW_BCAST15, 0xa>(0.0, v);
+    v = v + dpp_f64<DPP_ROW_BCAST31, 0xc>(0.0, v);
+    return readlane_f64(v, 63);
+}
+
+__device__ __forceinline__ int wave_isum(int v)
+{
+    v = v + dpp_i32<DPP_QUAD_1032, 0xf>(0, v);
+    v = v + dpp_i32<DPP_QUAD_2301, 0xf>(0, v);
+    v = v + dpp_i32<DPP_ROW_HALF_MIRROR, 0xf>(0, v);
+    v = v + dpp_i32<DPP_ROW_MIRROR, 0xf>(0, v);
+    v = v + dpp_i32<DPP_ROW_BCAST15, 0xa>(0, v);
+    v = v + dpp_i32<DPP_ROW_BCAST31, 0xc>(0, v);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ unsigned long long wave_or_u64(unsigned long long v)
+{
+    v |= dpp_u64<DPP_QUAD_1032, 0xf>(0ull, v);
+    v |= dpp_u64<DPP_QUAD_2301, 0xf>(0ull, v);
+    v |= dpp_u64<DPP_ROW_HALF_MIRROR, 0xf>(0ull, v);
+    v |= dpp_u64<DPP_ROW_MIRROR, 0xf>(0ull, v);
+    v |= dpp_u64<DPP_ROW_BCAST15, 0xa>(0ull, v);
+    v |= dpp_u64<DPP_ROW_BCAST31, 0xc>(0ull, v);
+    return readlane_u64(v, 63);
+}
+
+// inclusive prefix sum over the wave (row shifts, then row broadcasts)
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    v = v + dpp_i32<DPP_ROW_SHR1, 0xf>(0, v);
+    v = v + dpp_i32<DPP_ROW_SHR2, 0xf>(0, v);
+    v = v + dpp_i32<DPP_ROW_SHR4, 0xf>(0, v);
+    v = v + dpp_i32<DPP_ROW_SHR8, 0xf>(0, v);
+    v = v + dpp_i32<DPP_ROW_BCAST15, 0xa>(0, v);
+    v = v + dpp_i32<DPP_ROW_BCAST31, 0xc>(0, v);
     return v;
 }
 
-__device__ inline double wave_sum(double v)
+// exclusive prefix of small non-negative counts (< 2^BITS) by bit ballots
+template <int BITS>
+__device__ __forceinline__ int ballot_excl_scan(int v, int &total)
 {
+    int r = 0, t = 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ inline int wave_isum(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ inline unsigned long long wave_min_u64(unsigned long long v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long w = __shfl_xor(v, o);
-        v = w < v ? w : v;
+    for (int b = 0; b < BITS; b++) {
+        unsigned long long m = __ballot((v >> b) & 1);
+        r += lane_rank(m) << b;
+        t += __popcll(m) << b;
     }
-    return v;
-}
-
-__device__ inline unsigned long long wave_or_u64(unsigned long long v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
-    return v;
-}
-
-__device__ inline int wave_incl_scan(int v, int lane)
-{
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int w = __shfl_up(v, o);
-        if (lane >= o) v += w;
-    }
-    return v;
+    total = t;
+    return r;
 }
 
 template <int S, int MAXP, int K>
@@ -232,10 +305,10 @@ struct CellLDS {
             uint32_t tpl[S * 64];
             int32_t lab[S * 64];
         } st;
-        struct {              // candidate sweep: the current batch, and the
-            double cq[64 * K][3];           // new vertices of a cut
-            int32_t cid[64 * K];
-            uint8_t ccode[64 * K];
+        struct {              // candidate sweep: the current batch sorted by
+            double cq[64][4];               // distance (q, |q|^2), and the
+            int32_t cid[64];                // new vertices of a cut
+            uint8_t ccode[64];
             double npos[S * 64 + 8][3];
         } gc;
     } u;
@@ -405,7 +478,7 @@ __device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &
                 sg = exact_side3(plane_of(sh, c.tp[s] & 0xff), plane_of(sh, (c.tp[s] >> 8) & 0xff),
                                  plane_of(sh, (c.tp[s] >> 16) & 0xff), pp, ws);
             }
-            sg = __shfl(sg, l);
+            sg = __builtin_amdgcn_readlane(sg, l);
             if (sg > 0) conf[s] |= 1ull << l;
             cnt[DC_EXACT]++;
         }
@@ -441,13 +514,12 @@ __device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &
         }
     }
     int nb = __popc(bfl);
-    int incl = wave_incl_scan(nb, lane);
-    int m = __shfl(incl, 63);
+    int m;
+    int o = ballot_excl_scan<(S == 2 ? 3 : 4)>(nb, m);
     int nfree = 0;
 #pragma unroll
     for (int s = 0; s < S; s++) nfree += __popcll(~c.live[s] | conf[s]);
     if (m > nfree || m > S * 64 + 8) return ST_CAP;
-    int o = incl - nb;
 #pragma unroll
     for (int s = 0; s < S; s++) {
 #pragma unroll
@@ -552,77 +624,73 @@ __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh
         cntb = A.start[blk + 1] - beg;
     }
     cnt[DC_BLOCKS] += __popcll(__ballot(ok));
-    int incl = wave_incl_scan(cntb, lane);
-    int total = __shfl(incl, 63);
+    int incl = wave_incl_scan(cntb);
+    int total = __builtin_amdgcn_readlane(incl, 63);
     if (total == 0) return ST_OK;
     __syncthreads();
     sh.cpre[lane] = incl - cntb;
     sh.cbeg[lane] = beg;
     sh.csh[lane] = (uint8_t)(25 * (sv[2] + 2) + 5 * (sv[1] + 2) + (sv[0] + 2));
     __syncthreads();
-    for (int c0 = 0; c0 < total; c0 += 64 * K) {
-        unsigned long long key[K];
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            int ci = c0 + k * 64 + lane;
-            key[k] = ~0ull;
-            if (ci < total) {
-                // last block whose exclusive prefix is <= ci
-                int lo = 0, hi = 63;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (sh.cpre[mid] <= ci) lo = mid; else hi = mid - 1;
-                }
-                int idx = sh.cbeg[lo] + (ci - sh.cpre[lo]);
-                int code = sh.csh[lo];
-                int s0 = code % 5 - 2, s1 = (code / 5) % 5 - 2, s2 = code / 25 - 2;
-                Particle q = A.part[idx];
-                double a0 = q.x - p[0], a1 = q.y - p[1], a2 = q.z - p[2];
-                if (s0) a0 = a0 + s0 * G.L[0];
-                if (s1) a1 = a1 + s1 * G.L[1];
-                if (s2) a2 = a2 + s2 * G.L[2];
-                double d2 = a0 * a0 + a1 * a1 + a2 * a2;
-                bool self = (idx == si) && code == kNoShift;
-                if (!self && d2 < 4.0 * c.R2 * kMargin) key[k] = __double_as_longlong(d2);
-                int slot = k * 64 + lane;
-                sh.u.gc.cq[slot][0] = a0;
-                sh.u.gc.cq[slot][1] = a1;
-                sh.u.gc.cq[slot][2] = a2;
-                sh.u.gc.cid[slot] = q.id;
-                sh.u.gc.ccode[slot] = (uint8_t)code;
+    for (int c0 = 0; c0 < total; c0 += 64) {
+        // load one candidate per lane
+        int ci = c0 + lane;
+        unsigned long long key = ~0ull;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, d2 = 0.0;
+        int32_t qid = 0;
+        int code = kNoShift;
+        if (ci < total) {
+            // last block whose exclusive prefix is <= ci
+            int lo = 0, hi = 63;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (sh.cpre[mid] <= ci) lo = mid; else hi = mid - 1;
             }
+            int idx = sh.cbeg[lo] + (ci - sh.cpre[lo]);
+            code = sh.csh[lo];
+            int s0 = code % 5 - 2, s1 = (code / 5) % 5 - 2, s2 = code / 25 - 2;
+            Particle q = A.part[idx];
+            a0 = q.x - p[0];
+            a1 = q.y - p[1];
+            a2 = q.z - p[2];
+            if (s0) a0 = a0 + s0 * G.L[0];
+            if (s1) a1 = a1 + s1 * G.L[1];
+            if (s2) a2 = a2 + s2 * G.L[2];
+            d2 = a0 * a0 + a1 * a1 + a2 * a2;
+            bool self = (idx == si) && code == kNoShift;
+            if (!self && d2 < 4.0 * c.R2 * kMargin) key = __double_as_longlong(d2);
+            qid = q.id;
+        }
+        // rank the batch by (distance, lane) and store it sorted
+        unsigned long long vm = __ballot(key != ~0ull);
+        int nval = __popcll(vm);
+        if (nval == 0) continue;
+        int rank = 0;
+        for (unsigned long long m = vm; m; m &= m - 1) {
+            int j = __builtin_ctzll(m);
+            unsigned long long kj = readlane_u64(key, j);
+            rank += (kj < key) || (kj == key && j < lane);
         }
         __syncthreads();
-        for (;;) {
-            unsigned long long mk = key[0];
-#pragma unroll
-            for (int k = 1; k < K; k++) mk = key[k] < mk ? key[k] : mk;
-            mk = wave_min_u64(mk);
-            if (mk == ~0ull) break;
-            double md2 = __longlong_as_double((long long)mk);
+        if (key != ~0ull) {
+            sh.u.gc.cq[rank][0] = a0;
+            sh.u.gc.cq[rank][1] = a1;
+            sh.u.gc.cq[rank][2] = a2;
+            sh.u.gc.cq[rank][3] = d2;
+            sh.u.gc.cid[rank] = qid;
+            sh.u.gc.ccode[rank] = (uint8_t)code;
+        }
+        __syncthreads();
+        // nearest first; stop at the first candidate beyond 2R
+        for (int k = 0; k < nval; k++) {
+            double md2 = sh.u.gc.cq[k][3];
             if (!(md2 < 4.0 * c.R2 * kMargin)) break;
-            int kk = -1, ol = 0;
-#pragma unroll
-            for (int k = 0; k < K; k++) {
-                unsigned long long b = __ballot(key[k] == mk);
-                if (kk < 0 && b) {
-                    kk = k;
-                    ol = __builtin_ctzll(b);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < K; k++)
-                if (k == kk && lane == ol) key[k] = ~0ull;
-            int slot = kk * 64 + ol;
-            double q0 = sh.u.gc.cq[slot][0], q1 = sh.u.gc.cq[slot][1], q2 = sh.u.gc.cq[slot][2];
-            int32_t id = sh.u.gc.cid[slot];
-            int code = sh.u.gc.ccode[slot];
             cnt[DC_CAND]++;
             if (md2 == 0.0) return ST_DUP;
-            int st = consider<S, MAXP, F32, K>(A, sh, c, q0, q1, q2, md2, id, code, ws, cnt, lane);
+            int st = consider<S, MAXP, F32, K>(A, sh, c, sh.u.gc.cq[k][0], sh.u.gc.cq[k][1], sh.u.gc.cq[k][2], md2,
+                                               sh.u.gc.cid[k], sh.u.gc.ccode[k], ws, cnt, lane);
             if (st != ST_OK) return st;
         }
-        __syncthreads();
     }
     return ST_OK;
 }
@@ -917,7 +985,7 @@ __global__ __launch_bounds__(64) void k_cells(CellArgs A, int spill_mode)
     for (;;) {
         int base = 0;
         if (lane == 0) base = atomicAdd(A.queue, A.chunk);
-        base = __shfl(base, 0);
+        base = __builtin_amdgcn_readfirstlane(base);
         if (base >= ncell) break;
         int end = min(base + A.chunk, ncell);
         for (int ci = base; ci < end; ci++) {
@@ -956,7 +1024,7 @@ __global__ __launch_bounds__(64) void k_cells(CellArgs A, int spill_mode)
         for (int k = 0; k < DC_N; k++)
             if (k == lane) v = cnt[k];
         // counters are wave-uniform except the spill count (lane 0)
-        if (lane == DC_SPILL) v = __shfl(cnt[DC_SPILL], 0);
+        if (lane == DC_SPILL) v = readlane_u64(cnt[DC_SPILL], 0);
         if (v) atomicAdd(&A.diag[lane], v);
     }
 }
