@@ -160,21 +160,46 @@ void vc_container_destroy(vc_container *c);
 
 /* --- batches of independent tessellations (one persistent launch) --------- */
 
-/* Create a batch of n_tess independent 3D containers.  xyz_concat holds all
- * positions back to back (device or host), offsets[n_tess + 1] (host) the
- * first particle of each; opts[n_tess] (host) the box of each.  Results are
- * indexed by position in xyz_concat. */
+/* Create a batch of n_tess independent 3D containers sharing one set of
+ * device arrays.  xyz_concat holds all positions back to back (n_total x 3
+ * doubles, host or device); offsets[n_tess + 1] (host) gives the first
+ * particle of each tessellation (offsets[0] = 0, offsets[n_tess] = n_total,
+ * every tessellation non-empty); opts[n_tess] (host) the box, periodicity and
+ * grid of each.  precision, slots, waves and chunk are taken from opts[0].
+ * Range rules and errors as for vc_container_create.  Results are indexed by
+ * position in xyz_concat.  Synchronises `stream` once. */
 vc_status vc_batch_create(const double *xyz_concat, const int64_t *offsets, int64_t n_tess,
                           const vc_options *opts, void *stream, vc_batch **out);
+
+/* Re-bin new positions (same counts) into a batch; as vc_container_rebin. */
+vc_status vc_batch_rebin(vc_batch *b, const double *xyz_concat, void *stream);
 
 /* Allocate a result for a batch (fields as for a container, over all
  * particles of the batch). */
 vc_status vc_batch_result_create(const vc_batch *b, uint32_t mask, vc_result **out);
 
 /* Compute every cell of every tessellation in one persistent launch over a
- * device work queue.  If `graph` is nonzero the launch sequence is captured
- * once into a hipGraph and replayed on later calls. */
+ * device work queue (the dynamic schedule of section 2.2.3, on the GPU).  If
+ * `graph` is nonzero the launch sequence is captured once into a hipGraph on
+ * `stream` (which must not be the null stream) and replayed by later calls
+ * with the same result and stream.  Asynchronous. */
 vc_status vc_batch_compute(vc_batch *b, vc_result *r, int graph, void *stream);
+
+/* Launch parameters chosen by vc_batch_tune. */
+typedef struct {
+    int slots;          /* triangles per lane: 2 or 4 (cell capacity 128 or 256 vertices) */
+    int waves;          /* resident waves launched */
+    int chunk;          /* cells per work-queue grab */
+    int cells_per_wave; /* cells processed together by one wave */
+    float ms;           /* kernel time of the winner on the tuning sample */
+} vc_tuning;
+
+/* Autotuner: times each candidate launch configuration on a sample of the
+ * batch's cells (every 16th cell in block order), keeps the fastest for later
+ * vc_batch_compute calls and returns it in *best (may be NULL).  Overwrites
+ * the contents of r.  Synchronous.  A later vc_batch_compute with graph
+ * capture re-captures with the chosen parameters. */
+vc_status vc_batch_tune(vc_batch *b, vc_result *r, void *stream, vc_tuning *best);
 
 void vc_batch_destroy(vc_batch *b);
 

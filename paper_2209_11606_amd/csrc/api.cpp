@@ -1,7 +1,13 @@
 // api.cpp -- host runtime behind the C ABI of vorohip.h: argument checks,
 // grid sizing (section 2.1.4), device allocation, the binning sequence, the
 // nearest-first block-offset list, cell-kernel launches with the spill pass,
-// and neighbour-list compaction.
+// neighbour-list compaction, batches of tessellations with hipGraph replay,
+// and the launch-parameter autotuner.
+//
+// A container holds one or more tessellations in shared device arrays: the
+// particles of all of them sorted block by block, one block-start array over
+// all blocks, and a Tess record per tessellation (its grid and the first
+// particle and block).  A plain container is the one-tessellation case.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,7 +51,10 @@ vc_status dalloc(T **p, size_t count)
     *p = nullptr;
     if (count == 0) count = 1;
     hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-    if (e != hipSuccess) return fail(VC_E_NOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(VC_E_NOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+    }
     return VC_OK;
 }
 
@@ -59,87 +68,37 @@ bool is_device_ptr(const void *p)
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
-// Precomputed block offsets up to Chebyshev radius kOffRadius, ordered by a
-// lower bound of the distance between any point of the own block and the
-// offset block (nearest first), ties by centre distance then lexicographic.
-void build_offsets(const Grid &G, std::vector<Offset> &offs, std::vector<double> &gap2)
+// Block offsets up to Chebyshev radius kOffRadius, nearest first: by the
+// integer gap metric m, then by centre distance in block units, then
+// lexicographically (so the order is fixed).
+std::vector<Offset> build_offsets(int dim)
 {
-    struct E { double g, c; int dx, dy, dz; };
+    struct E { int m, c, dx, dy, dz; };
     std::vector<E> v;
-    int rz = G.dim == 3 ? kOffRadius : 0;
+    int rz = dim == 3 ? kOffRadius : 0;
     for (int dz = -rz; dz <= rz; dz++)
         for (int dy = -kOffRadius; dy <= kOffRadius; dy++)
             for (int dx = -kOffRadius; dx <= kOffRadius; dx++) {
                 int d[3] = {dx, dy, dz};
-                double g = 0.0, c = 0.0;
+                int m = 0, c = 0;
                 for (int k = 0; k < 3; k++) {
-                    double t = std::max(std::abs(d[k]) - 1, 0) * G.bs[k];
-                    g += t * t;
-                    c += (d[k] * G.bs[k]) * (d[k] * G.bs[k]);
+                    int t = std::max(std::abs(d[k]) - 1, 0);
+                    m += t * t;
+                    c += d[k] * d[k];
                 }
-                v.push_back({g, c, dx, dy, dz});
+                v.push_back({m, c, dx, dy, dz});
             }
     std::sort(v.begin(), v.end(), [](const E &a, const E &b) {
-        if (a.g != b.g) return a.g < b.g;
+        if (a.m != b.m) return a.m < b.m;
         if (a.c != b.c) return a.c < b.c;
         if (a.dz != b.dz) return a.dz < b.dz;
         if (a.dy != b.dy) return a.dy < b.dy;
         return a.dx < b.dx;
     });
-    offs.clear();
-    gap2.clear();
-    for (auto &e : v) {
-        offs.push_back(Offset{e.dx, e.dy, e.dz, 0});
-        gap2.push_back(e.g);
-    }
+    std::vector<Offset> out;
+    for (auto &e : v) out.push_back(Offset{e.dx, e.dy, e.dz, e.m});
+    return out;
 }
-
-}  // namespace
-
-struct vc_container {
-    vc_options opt;
-    Grid G;
-    int64_t n = 0;
-    double *xyz = nullptr;       // device copy of the input positions (n x dim)
-    Particle *part = nullptr;    // block-sorted particles
-    int32_t *start = nullptr;    // nb + 1
-    int32_t *count = nullptr;    // nb
-    int32_t *blk = nullptr;      // n
-    int32_t *rank = nullptr;     // n
-    int32_t *err = nullptr;      // range-error flag
-    int32_t *scan_tmp = nullptr;
-    Offset *offs = nullptr;
-    double *offgap2 = nullptr;
-    int noff = 0;
-    int32_t *queue = nullptr;    // [0]: main queue head, [1]: spill queue head, [2]: spill count
-    int32_t *spill_list = nullptr;
-    double *xscratch = nullptr;
-    int waves = 0;
-    int xscratch_len = 2048;
-};
-
-struct vc_result {
-    const vc_container *c = nullptr;
-    uint32_t mask = 0;
-    int64_t n = 0;
-    int dim = 3;
-    double *vol = nullptr, *cen = nullptr;
-    int32_t *nv = nullptr, *ne = nullptr, *nf = nullptr;
-    uint8_t *fo = nullptr;
-    int32_t *nbr = nullptr;  // fixed-stride scratch
-    uint8_t *nsh = nullptr;
-    int64_t *off = nullptr;  // CSR offsets (n + 1)
-    int32_t *ids = nullptr;
-    uint8_t *shifts = nullptr;
-    int64_t nbr_cap = 0;     // capacity of ids / shifts
-    int32_t *scan_tmp = nullptr;
-    uint8_t *status = nullptr;
-    unsigned long long *diag = nullptr;
-    hipStream_t last_stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the main cell kernel
-};
-
-namespace {
 
 vc_status check_options(const vc_options *o)
 {
@@ -158,8 +117,10 @@ vc_status check_options(const vc_options *o)
 }
 
 // Section 2.1.4: lambda = (N / (N_opt V))^(1/d), n_d = ceil(lambda L_d).
-void size_grid(Grid &G, const vc_options &o, int64_t n)
+Grid size_grid(const vc_options &o, int64_t n)
 {
+    Grid G;
+    std::memset(&G, 0, sizeof G);
     G.dim = o.dim;
     double vol = 1.0;
     for (int d = 0; d < o.dim; d++) vol *= (o.hi[d] - o.lo[d]);
@@ -185,25 +146,88 @@ void size_grid(Grid &G, const vc_options &o, int64_t n)
         G.inv_bs[d] = G.g[d] / G.L[d];
         G.nb *= G.g[d];
     }
+    return G;
 }
 
-vc_status bin(vc_container *c, hipStream_t s)
+struct Launch {
+    int slots = 2, waves = 0, chunk = 4, cpw = 1;
+};
+
+}  // namespace
+
+struct vc_container {
+    int dim = 3;
+    int64_t n = 0;
+    int precision = VC_FP64;
+    std::vector<Tess> htess;
+    Tess *tess = nullptr;
+    int32_t *ptess = nullptr;    // tessellation of each input particle (batches only)
+    int64_t nb = 0;              // blocks over all tessellations
+    double *xyz = nullptr;       // device copy of the input positions (n x dim)
+    Particle *part = nullptr;    // block-sorted particles
+    int32_t *start = nullptr;    // nb + 1
+    int32_t *count = nullptr;    // nb
+    int32_t *blk = nullptr;      // n
+    int32_t *rank = nullptr;     // n
+    int32_t *err = nullptr;      // range-error flag
+    int32_t *scan_tmp = nullptr;
+    Offset *offs = nullptr;
+    int noff = 0;
+    int32_t *queue = nullptr;    // [0]: main queue head, [1]: spill queue head, [2]: spill count
+    int32_t *spill_list = nullptr;
+    int32_t *sample_list = nullptr;  // tuning sample (batches)
+    int nsample = 0;
+    double *xscratch = nullptr;
+    int xscratch_len = 2048;
+    int max_waves = 0;
+    Launch launch;
+    // graph replay (batches)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const vc_result *graph_r = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+struct vc_batch : vc_container {
+};
+
+struct vc_result {
+    const vc_container *c = nullptr;
+    uint32_t mask = 0;
+    int64_t n = 0;
+    int dim = 3;
+    double *vol = nullptr, *cen = nullptr;
+    int32_t *nv = nullptr, *ne = nullptr, *nf = nullptr;
+    uint8_t *fo = nullptr;
+    int32_t *nbr = nullptr;  // fixed-stride scratch
+    uint8_t *nsh = nullptr;
+    int64_t *off = nullptr;  // CSR offsets (n + 1)
+    int32_t *ids = nullptr;
+    uint8_t *shifts = nullptr;
+    int32_t *scan_tmp = nullptr;
+    uint8_t *status = nullptr;
+    unsigned long long *diag = nullptr;
+    hipStream_t last_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the main cell kernel
+};
+
+namespace {
+
+void release_graph(vc_container *c)
 {
-    int64_t nb = c->G.nb;
-    HIP_TRY(launch_fill_i32(c->count, nb, 0, s));
-    HIP_TRY(launch_fill_i32(c->err, 1, 0, s));
-    HIP_TRY(launch_bin_count(c->xyz, c->n, c->G, c->blk, c->rank, c->count, c->err, s));
-    HIP_TRY(launch_scan(c->count, c->start, nb, c->scan_tmp, s));
-    HIP_TRY(launch_scatter(c->xyz, c->n, c->G, c->blk, c->rank, c->start, c->part, s));
-    HIP_TRY(launch_block_order(c->part, c->start, nb, s));
-    return VC_OK;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_r = nullptr;
 }
 
 void free_container(vc_container *c)
 {
     if (!c) return;
-    void *ps[] = {c->xyz, c->part, c->start, c->count, c->blk, c->rank, c->err, c->scan_tmp,
-                  c->offs, c->offgap2, c->queue, c->spill_list, c->xscratch};
+    release_graph(c);
+    void *ps[] = {c->tess, c->ptess, c->xyz, c->part, c->start, c->count, c->blk, c->rank, c->err, c->scan_tmp,
+                  c->offs, c->queue, c->spill_list, c->sample_list, c->xscratch};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete c;
@@ -219,6 +243,217 @@ void free_result(vc_result *r)
     if (r->ev0) (void)hipEventDestroy(r->ev0);
     if (r->ev1) (void)hipEventDestroy(r->ev1);
     delete r;
+}
+
+vc_status bin(vc_container *c, hipStream_t s)
+{
+    HIP_TRY(launch_fill_i32(c->count, c->nb, 0, s));
+    HIP_TRY(launch_fill_i32(c->err, 1, 0, s));
+    HIP_TRY(launch_bin_count(c->xyz, c->n, c->dim, c->tess, c->ptess, c->blk, c->rank, c->count, c->err, s));
+    HIP_TRY(launch_scan(c->count, c->start, c->nb, c->scan_tmp, s));
+    HIP_TRY(launch_scatter(c->xyz, c->n, c->dim, c->ptess, c->blk, c->rank, c->start, c->part, s));
+    HIP_TRY(launch_block_order(c->part, c->start, c->nb, s));
+    return VC_OK;
+}
+
+vc_status copy_in_and_bin(vc_container *c, const double *xyz, hipStream_t s)
+{
+    HIP_TRY(hipMemcpyAsync(c->xyz, xyz, (size_t)c->n * c->dim * sizeof(double),
+                           is_device_ptr(xyz) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    vc_status st = bin(c, s);
+    if (st) return st;
+    int32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (herr)
+        return fail(VC_E_RANGE, "a coordinate lies outside the box (walled: lo <= x <= hi, periodic: lo <= x < hi) "
+                                "or is not finite");
+    return VC_OK;
+}
+
+// Build a container of one or more tessellations.  offsets: ntess + 1 particle
+// offsets (host); opts: ntess options.
+vc_status create_common(vc_container *c, const double *xyz, const int64_t *offsets, int64_t ntess,
+                        const vc_options *opts, hipStream_t s)
+{
+    const int dim = opts[0].dim;
+    c->dim = dim;
+    c->n = offsets[ntess];
+    c->precision = opts[0].precision;
+    c->launch.slots = opts[0].slots > 0 ? opts[0].slots : 2;
+    c->launch.chunk = opts[0].chunk > 0 ? opts[0].chunk : 4;
+    int cu = device_cu_count();
+    c->launch.waves = opts[0].waves > 0 ? opts[0].waves : cu * 16;
+    c->max_waves = std::max(c->launch.waves, cu * 32);
+    c->htess.resize((size_t)ntess);
+    int64_t nb = 0;
+    for (int64_t t = 0; t < ntess; t++) {
+        Tess &T = c->htess[(size_t)t];
+        std::memset(&T, 0, sizeof T);
+        int64_t cnt = offsets[t + 1] - offsets[t];
+        T.G = size_grid(opts[t], cnt);
+        T.pbase = (int32_t)offsets[t];
+        T.pcount = (int32_t)cnt;
+        T.bbase = (int32_t)nb;
+        double bmin = T.G.bs[0];
+        for (int d = 1; d < dim; d++) bmin = std::min(bmin, T.G.bs[d]);
+        T.bsmin2 = bmin * bmin;
+        nb += T.G.nb;
+        if (nb > (int64_t)INT32_MAX / 2) return fail(VC_E_ARG, "too many blocks (%lld)", (long long)nb);
+    }
+    c->nb = nb;
+    std::vector<Offset> offs = build_offsets(dim);
+    c->noff = (int)offs.size();
+    int64_t ntiles = (nb + 2047) / 2048 + 2;
+    vc_status st;
+#define TRY(x)              \
+    do {                    \
+        st = (x);           \
+        if (st) return st;  \
+    } while (0)
+    TRY(dalloc(&c->tess, (size_t)ntess));
+    if (ntess > 1) TRY(dalloc(&c->ptess, (size_t)c->n));
+    TRY(dalloc(&c->xyz, (size_t)c->n * dim));
+    TRY(dalloc(&c->part, (size_t)c->n));
+    TRY(dalloc(&c->start, (size_t)nb + 1));
+    TRY(dalloc(&c->count, (size_t)nb));
+    TRY(dalloc(&c->blk, (size_t)c->n));
+    TRY(dalloc(&c->rank, (size_t)c->n));
+    TRY(dalloc(&c->err, 1));
+    TRY(dalloc(&c->scan_tmp, (size_t)ntiles * 2));
+    TRY(dalloc(&c->offs, offs.size()));
+    TRY(dalloc(&c->queue, 4));
+    TRY(dalloc(&c->spill_list, (size_t)c->n));
+    TRY(dalloc(&c->xscratch, (size_t)c->max_waves * c->xscratch_len));
+#undef TRY
+    HIP_TRY(hipMemcpyAsync(c->tess, c->htess.data(), c->htess.size() * sizeof(Tess), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c->offs, offs.data(), offs.size() * sizeof(Offset), hipMemcpyHostToDevice, s));
+    if (ntess > 1) {
+        std::vector<int32_t> pt((size_t)c->n);
+        for (int64_t t = 0; t < ntess; t++)
+            for (int64_t i = offsets[t]; i < offsets[t + 1]; i++) pt[(size_t)i] = (int32_t)t;
+        HIP_TRY(hipMemcpyAsync(c->ptess, pt.data(), pt.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // pt goes out of scope
+    }
+    return copy_in_and_bin(c, xyz, s);
+}
+
+CellArgs cell_args(const vc_container *c, const vc_result *r)
+{
+    CellArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.tess = c->tess;
+    A.part = c->part;
+    A.start = c->start;
+    A.offs = c->offs;
+    A.noff = c->noff;
+    A.off_radius = kOffRadius;
+    A.ncell = (int)c->n;
+    A.cell_list = nullptr;
+    A.ncell_dev = nullptr;
+    A.queue = c->queue;
+    A.chunk = c->launch.chunk;
+    A.tau = 0x1p-30;
+    A.mask = r->mask;
+    A.vol = r->vol;
+    A.cen = r->cen;
+    A.nv = r->nv;
+    A.ne = r->ne;
+    A.nf = r->nf;
+    A.fo = r->fo;
+    A.nbr = r->nbr;
+    A.nsh = r->nsh;
+    A.status = r->status;
+    A.spill_list = c->spill_list;
+    A.spill_count = c->queue + 2;
+    A.diag = r->diag;
+    A.xscratch = c->xscratch;
+    A.xscratch_len = c->xscratch_len;
+    return A;
+}
+
+// The launch sequence of one compute (graph-capturable: fill kernels, no
+// memset; events only when `events` is set).
+vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool events, const Launch &L,
+                          const int32_t *cell_list = nullptr, int ncell = -1)
+{
+    CellArgs A = cell_args(c, r);
+    A.chunk = L.chunk;
+    if (cell_list) {
+        A.cell_list = cell_list;
+        A.ncell = ncell;
+    }
+    HIP_TRY(launch_fill_i32(c->queue, 4, 0, s));
+    HIP_TRY(launch_fill_i32((int32_t *)r->diag, VC_DIAG_LEN * 2, 0, s));
+    if (events) HIP_TRY(hipEventRecord(r->ev0, s));
+    HIP_TRY(launch_cells(A, c->precision, L.slots, std::min(L.waves, c->max_waves), s));
+    if (events) HIP_TRY(hipEventRecord(r->ev1, s));
+    // cells beyond the main kernel's capacity: large-capacity pass over the
+    // spill list (its length is read on the device)
+    CellArgs B = A;
+    B.cell_list = c->spill_list;
+    B.queue = c->queue + 1;
+    B.ncell_dev = c->queue + 2;
+    B.ncell = (int)c->n;
+    B.chunk = 1;
+    HIP_TRY(launch_cells_spill(B, std::min(c->max_waves, 1024), s));
+    if ((r->mask & VC_NEIGHBORS) && !cell_list) {
+        // CSR offsets by a scan of the face counts, then each cell's sorted
+        // labels copied to its offset (capacity n * kMaxNbr always suffices)
+        HIP_TRY(launch_nbr_offsets(r->nf, r->n, r->off, r->scan_tmp, s));
+        HIP_TRY(launch_nbr_compact(r->nf, r->n, r->nbr, r->nsh, r->off, r->ids, r->shifts, nullptr, s));
+    }
+    r->last_stream = s;
+    return VC_OK;
+}
+
+vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
+{
+    if (!out) return fail(VC_E_ARG, "result_create: out is null");
+    *out = nullptr;
+    if (!c) return fail(VC_E_ARG, "result_create: container is null");
+    if (mask & ~(uint32_t)VC_ALL) return fail(VC_E_ARG, "result_create: unknown mask bits 0x%x", mask);
+    vc_result *r = new (std::nothrow) vc_result();
+    if (!r) return fail(VC_E_NOMEM, "host allocation failed");
+    r->c = c;
+    r->mask = mask;
+    r->n = c->n;
+    r->dim = c->dim;
+    int64_t n = c->n;
+    vc_status st = VC_OK;
+#define TRY(x)               \
+    do {                     \
+        st = (x);            \
+        if (st) {            \
+            free_result(r);  \
+            return st;       \
+        }                    \
+    } while (0)
+    if (mask & VC_VOLUME) TRY(dalloc(&r->vol, n));
+    if (mask & VC_CENTROID) TRY(dalloc(&r->cen, (size_t)n * 3));
+    if (mask & VC_COUNTS) {
+        TRY(dalloc(&r->nv, n));
+        TRY(dalloc(&r->ne, n));
+    }
+    TRY(dalloc(&r->nf, n));
+    if (mask & VC_FACE_ORDERS) TRY(dalloc(&r->fo, (size_t)n * kFoLen));
+    if (mask & VC_NEIGHBORS) {
+        TRY(dalloc(&r->nbr, (size_t)n * kMaxNbr));
+        TRY(dalloc(&r->nsh, (size_t)n * kMaxNbr));
+        TRY(dalloc(&r->off, (size_t)n + 1));
+        TRY(dalloc(&r->ids, (size_t)n * kMaxNbr));
+        TRY(dalloc(&r->shifts, (size_t)n * kMaxNbr));
+        TRY(dalloc(&r->scan_tmp, (size_t)((n + 2047) / 2048 + 2) * 2));
+    }
+    TRY(dalloc(&r->status, n));
+    TRY(dalloc(&r->diag, VC_DIAG_LEN));
+#undef TRY
+    if (hipEventCreate(&r->ev0) != hipSuccess || hipEventCreate(&r->ev1) != hipSuccess) {
+        free_result(r);
+        return fail(VC_E_HIP, "hipEventCreate failed");
+    }
+    *out = r;
+    return VC_OK;
 }
 
 }  // namespace
@@ -251,68 +486,13 @@ vc_status vc_container_create(const double *xyz, int64_t n, const vc_options *op
     vc_status st = check_options(opt);
     if (st) return st;
     if (opt->dim != 3) return fail(VC_E_ARG, "vc_container_create: only dim 3 is built in this library version");
-    hipStream_t s = (hipStream_t)stream;
     vc_container *c = new (std::nothrow) vc_container();
     if (!c) return fail(VC_E_NOMEM, "host allocation failed");
-    c->opt = *opt;
-    c->n = n;
-    size_grid(c->G, *opt, n);
-    const int dim = opt->dim;
-    int64_t nb = c->G.nb;
-    int64_t ntiles = (nb + 2047) / 2048 + 2;
-    std::vector<Offset> offs;
-    std::vector<double> gap2;
-    build_offsets(c->G, offs, gap2);
-    c->noff = (int)offs.size();
-    int cu = device_cu_count();
-    c->waves = opt->waves > 0 ? opt->waves : cu * 16;
-#define TRY(x)                   \
-    do {                         \
-        vc_status e_ = (x);      \
-        if (e_) {                \
-            free_container(c);   \
-            return e_;           \
-        }                        \
-    } while (0)
-    TRY(dalloc(&c->xyz, (size_t)n * dim));
-    TRY(dalloc(&c->part, (size_t)n));
-    TRY(dalloc(&c->start, (size_t)nb + 1));
-    TRY(dalloc(&c->count, (size_t)nb));
-    TRY(dalloc(&c->blk, (size_t)n));
-    TRY(dalloc(&c->rank, (size_t)n));
-    TRY(dalloc(&c->err, 1));
-    TRY(dalloc(&c->scan_tmp, (size_t)ntiles * 2));
-    TRY(dalloc(&c->offs, offs.size()));
-    TRY(dalloc(&c->offgap2, gap2.size()));
-    TRY(dalloc(&c->queue, 4));
-    TRY(dalloc(&c->spill_list, (size_t)n));
-    TRY(dalloc(&c->xscratch, (size_t)c->waves * c->xscratch_len));
-#undef TRY
-    hipError_t e = hipMemcpyAsync(c->offs, offs.data(), offs.size() * sizeof(Offset), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(c->offgap2, gap2.data(), gap2.size() * sizeof(double), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(c->xyz, xyz, (size_t)n * dim * sizeof(double),
-                           is_device_ptr(xyz) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) {
-        free_container(c);
-        return fail(VC_E_HIP, "copy to device failed: %s", hipGetErrorString(e));
-    }
-    st = bin(c, s);
+    int64_t offsets[2] = {0, n};
+    st = create_common(c, xyz, offsets, 1, opt, (hipStream_t)stream);
     if (st) {
         free_container(c);
         return st;
-    }
-    int32_t herr = 0;
-    e = hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-        free_container(c);
-        return fail(VC_E_HIP, "binning failed: %s", hipGetErrorString(e));
-    }
-    if (herr) {
-        free_container(c);
-        return fail(VC_E_RANGE, "a coordinate lies outside the box (walled: lo <= x <= hi, periodic: lo <= x < hi) or is not finite");
     }
     *out = c;
     return VC_OK;
@@ -321,124 +501,19 @@ vc_status vc_container_create(const double *xyz, int64_t n, const vc_options *op
 vc_status vc_container_rebin(vc_container *c, const double *xyz, void *stream)
 {
     if (!c || !xyz) return fail(VC_E_ARG, "vc_container_rebin: null pointer");
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipMemcpyAsync(c->xyz, xyz, (size_t)c->n * c->opt.dim * sizeof(double),
-                           is_device_ptr(xyz) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
-    vc_status st = bin(c, s);
-    if (st) return st;
-    int32_t herr = 0;
-    HIP_TRY(hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (herr) return fail(VC_E_RANGE, "a coordinate lies outside the box or is not finite");
-    return VC_OK;
+    return copy_in_and_bin(c, xyz, (hipStream_t)stream);
 }
 
 vc_status vc_result_create(const vc_container *c, uint32_t mask, vc_result **out)
 {
-    if (!out) return fail(VC_E_ARG, "vc_result_create: out is null");
-    *out = nullptr;
-    if (!c) return fail(VC_E_ARG, "vc_result_create: container is null");
-    if (mask & ~(uint32_t)VC_ALL) return fail(VC_E_ARG, "vc_result_create: unknown mask bits 0x%x", mask);
-    vc_result *r = new (std::nothrow) vc_result();
-    if (!r) return fail(VC_E_NOMEM, "host allocation failed");
-    r->c = c;
-    r->mask = mask;
-    r->n = c->n;
-    r->dim = c->opt.dim;
-    int64_t n = c->n;
-#define TRY(x)                \
-    do {                      \
-        vc_status e_ = (x);   \
-        if (e_) {             \
-            free_result(r);   \
-            return e_;        \
-        }                     \
-    } while (0)
-    if (mask & VC_VOLUME) TRY(dalloc(&r->vol, n));
-    if (mask & VC_CENTROID) TRY(dalloc(&r->cen, (size_t)n * 3));
-    if (mask & VC_COUNTS) {
-        TRY(dalloc(&r->nv, n));
-        TRY(dalloc(&r->ne, n));
-    }
-    TRY(dalloc(&r->nf, n));
-    if (mask & VC_FACE_ORDERS) TRY(dalloc(&r->fo, (size_t)n * kFoLen));
-    if (mask & VC_NEIGHBORS) {
-        TRY(dalloc(&r->nbr, (size_t)n * kMaxNbr));
-        TRY(dalloc(&r->nsh, (size_t)n * kMaxNbr));
-        TRY(dalloc(&r->off, (size_t)n + 1));
-        r->nbr_cap = n * kMaxNbr;
-        TRY(dalloc(&r->ids, (size_t)r->nbr_cap));
-        TRY(dalloc(&r->shifts, (size_t)r->nbr_cap));
-        TRY(dalloc(&r->scan_tmp, (size_t)((n + 2047) / 2048 + 2) * 2));
-    }
-    TRY(dalloc(&r->status, n));
-    TRY(dalloc(&r->diag, VC_DIAG_LEN));
-#undef TRY
-    if (hipEventCreate(&r->ev0) != hipSuccess || hipEventCreate(&r->ev1) != hipSuccess) {
-        free_result(r);
-        return fail(VC_E_HIP, "hipEventCreate failed");
-    }
-    *out = r;
-    return VC_OK;
+    return result_create(c, mask, out);
 }
 
 vc_status vc_compute(vc_container *c, vc_result *r, void *stream)
 {
     if (!c || !r) return fail(VC_E_ARG, "vc_compute: null handle");
     if (r->c != c) return fail(VC_E_STATE, "vc_compute: result was created for another container");
-    hipStream_t s = (hipStream_t)stream;
-    CellArgs A;
-    std::memset(&A, 0, sizeof A);
-    A.G = c->G;
-    A.part = c->part;
-    A.start = c->start;
-    A.offs = c->offs;
-    A.offgap2 = c->offgap2;
-    A.noff = c->noff;
-    A.off_radius = kOffRadius;
-    A.ncell = (int)c->n;
-    A.cell_list = nullptr;
-    A.queue = c->queue;
-    A.chunk = c->opt.chunk > 0 ? c->opt.chunk : 4;
-    A.tau = 0x1p-30;
-    A.mask = r->mask;
-    A.vol = r->vol;
-    A.cen = r->cen;
-    A.nv = r->nv;
-    A.ne = r->ne;
-    A.nf = r->nf;
-    A.fo = r->fo;
-    A.nbr = r->nbr;
-    A.nsh = r->nsh;
-    A.status = r->status;
-    A.spill_list = c->spill_list;
-    A.spill_count = c->queue + 2;
-    A.diag = r->diag;
-    A.xscratch = c->xscratch;
-    A.xscratch_len = c->xscratch_len;
-    HIP_TRY(launch_fill_i32(c->queue, 4, 0, s));
-    HIP_TRY(launch_fill_i32((int32_t *)r->diag, VC_DIAG_LEN * 2, 0, s));
-    int slots = c->opt.slots > 0 ? c->opt.slots : 2;
-    HIP_TRY(hipEventRecord(r->ev0, s));
-    HIP_TRY(launch_cells(A, c->opt.precision, slots, c->waves, s));
-    HIP_TRY(hipEventRecord(r->ev1, s));
-    // cells beyond the main kernel's capacity: large-capacity pass over the
-    // spill list (its length is read on the device)
-    CellArgs B = A;
-    B.cell_list = c->spill_list;
-    B.queue = c->queue + 1;
-    B.ncell_dev = c->queue + 2;
-    B.ncell = (int)c->n;
-    B.chunk = 1;
-    HIP_TRY(launch_cells_spill(B, std::min(c->waves, 1024), s));
-    if (r->mask & VC_NEIGHBORS) {
-        // CSR offsets by a scan of the face counts, then each cell's sorted
-        // labels copied to its offset (capacity n * kMaxNbr always suffices)
-        HIP_TRY(launch_nbr_offsets(r->nf, r->n, r->off, r->scan_tmp, s));
-        HIP_TRY(launch_nbr_compact(r->nf, r->n, r->nbr, r->nsh, r->off, r->ids, r->shifts, nullptr, s));
-    }
-    r->last_stream = s;
-    return VC_OK;
+    return enqueue_compute(c, r, (hipStream_t)stream, true, c->launch);
 }
 
 vc_status vc_result_kernel_ms(vc_result *r, float *ms)
@@ -446,13 +521,6 @@ vc_status vc_result_kernel_ms(vc_result *r, float *ms)
     if (!r || !ms) return fail(VC_E_ARG, "vc_result_kernel_ms: null pointer");
     HIP_TRY(hipEventSynchronize(r->ev1));
     HIP_TRY(hipEventElapsedTime(ms, r->ev0, r->ev1));
-    return VC_OK;
-}
-
-static vc_status ensure_neighbors(vc_result *r)
-{
-    if (!(r->mask & VC_NEIGHBORS)) return fail(VC_E_STATE, "neighbour lists were not requested in the mask");
-    HIP_TRY(hipStreamSynchronize(r->last_stream));
     return VC_OK;
 }
 
@@ -472,8 +540,8 @@ vc_status vc_result_get(vc_result *r, int field, void **dev_ptr, int64_t *count)
     case VC_F_NBR_OFFSETS: p = r->off; k = n + 1; break;
     case VC_F_NBR_IDS:
     case VC_F_NBR_SHIFTS: {
-        vc_status st = ensure_neighbors(r);
-        if (st) return st;
+        if (!(r->mask & VC_NEIGHBORS)) return fail(VC_E_STATE, "neighbour lists were not requested in the mask");
+        HIP_TRY(hipStreamSynchronize(r->last_stream));
         HIP_TRY(hipMemcpy(&k, r->off + n, sizeof(int64_t), hipMemcpyDeviceToHost));
         p = field == VC_F_NBR_IDS ? (void *)r->ids : (void *)r->shifts;
         break;
@@ -507,27 +575,131 @@ void vc_result_destroy(vc_result *r) { free_result(r); }
 
 void vc_container_destroy(vc_container *c) { free_container(c); }
 
-vc_status vc_batch_create(const double *, const int64_t *, int64_t, const vc_options *, void *, vc_batch **out)
+vc_status vc_batch_create(const double *xyz_concat, const int64_t *offsets, int64_t n_tess, const vc_options *opts,
+                          void *stream, vc_batch **out)
 {
-    if (out) *out = nullptr;
-    return fail(VC_E_STATE, "vc_batch_create: not available in this library version");
+    if (!out) return fail(VC_E_ARG, "vc_batch_create: out is null");
+    *out = nullptr;
+    if (!xyz_concat || !offsets || !opts) return fail(VC_E_ARG, "vc_batch_create: null pointer");
+    if (n_tess < 1 || n_tess > (1 << 24)) return fail(VC_E_ARG, "vc_batch_create: bad tessellation count");
+    if (offsets[0] != 0) return fail(VC_E_ARG, "vc_batch_create: offsets[0] must be 0");
+    for (int64_t t = 0; t < n_tess; t++) {
+        if (offsets[t + 1] <= offsets[t]) return fail(VC_E_ARG, "vc_batch_create: tessellation %lld is empty", (long long)t);
+        vc_status st = check_options(&opts[t]);
+        if (st) return st;
+        if (opts[t].dim != 3) return fail(VC_E_ARG, "vc_batch_create: batches are 3D");
+    }
+    if (offsets[n_tess] > (int64_t)INT32_MAX / 2) return fail(VC_E_ARG, "vc_batch_create: too many particles");
+    vc_batch *b = new (std::nothrow) vc_batch();
+    if (!b) return fail(VC_E_NOMEM, "host allocation failed");
+    hipStream_t s = (hipStream_t)stream;
+    vc_status st = create_common(b, xyz_concat, offsets, n_tess, opts, s);
+    if (!st) {
+        // tuning sample: every 16th cell in block order
+        b->nsample = (int)((b->n + 15) / 16);
+        st = dalloc(&b->sample_list, (size_t)b->nsample);
+        if (!st) {
+            std::vector<int32_t> v((size_t)b->nsample);
+            for (int i = 0; i < b->nsample; i++) v[(size_t)i] = 16 * i;
+            hipError_t e = hipMemcpy(b->sample_list, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+            if (e != hipSuccess) st = fail(VC_E_HIP, "copy of the tuning sample failed");
+        }
+    }
+    if (st) {
+        free_container(b);
+        return st;
+    }
+    *out = b;
+    return VC_OK;
 }
 
-vc_status vc_batch_result_create(const vc_batch *, uint32_t, vc_result **out)
+vc_status vc_batch_rebin(vc_batch *b, const double *xyz_concat, void *stream)
 {
-    if (out) *out = nullptr;
-    return fail(VC_E_STATE, "vc_batch_result_create: not available in this library version");
+    if (!b || !xyz_concat) return fail(VC_E_ARG, "vc_batch_rebin: null pointer");
+    return copy_in_and_bin(b, xyz_concat, (hipStream_t)stream);
 }
 
-vc_status vc_batch_compute(vc_batch *, vc_result *, int, void *)
+vc_status vc_batch_result_create(const vc_batch *b, uint32_t mask, vc_result **out)
 {
-    return fail(VC_E_STATE, "vc_batch_compute: not available in this library version");
+    return result_create(b, mask, out);
 }
 
-void vc_batch_destroy(vc_batch *) {}
+vc_status vc_batch_compute(vc_batch *b, vc_result *r, int graph, void *stream)
+{
+    if (!b || !r) return fail(VC_E_ARG, "vc_batch_compute: null handle");
+    if (r->c != b) return fail(VC_E_STATE, "vc_batch_compute: result was created for another batch");
+    hipStream_t s = (hipStream_t)stream;
+    if (!graph) return enqueue_compute(b, r, s, true, b->launch);
+    if (!s) return fail(VC_E_ARG, "vc_batch_compute: graph capture needs a non-null stream");
+    if (!b->gexec || b->graph_r != r || b->graph_stream != s) {
+        release_graph(b);
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        vc_status st = enqueue_compute(b, r, s, false, b->launch);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(VC_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+        b->graph_r = r;
+        b->graph_stream = s;
+    }
+    HIP_TRY(hipGraphLaunch(b->gexec, s));
+    r->last_stream = s;
+    return VC_OK;
+}
+
+vc_status vc_batch_tune(vc_batch *b, vc_result *r, void *stream, vc_tuning *best)
+{
+    if (!b || !r) return fail(VC_E_ARG, "vc_batch_tune: null handle");
+    if (r->c != b) return fail(VC_E_STATE, "vc_batch_tune: result was created for another batch");
+    hipStream_t s = (hipStream_t)stream;
+    int cu = device_cu_count();
+    const int slots_c[] = {2, 4};
+    const int chunk_c[] = {1, 4, 16, 64};
+    const int waves_c[] = {cu * 8, cu * 16, cu * 32};
+    Launch win;
+    float wms = 1e30f;
+    for (int sl : slots_c)
+        for (int ch : chunk_c)
+            for (int wv : waves_c) {
+                Launch L;
+                L.slots = sl;
+                L.chunk = ch;
+                L.waves = wv;
+                // two runs: the first warms caches, the second is timed
+                for (int rep = 0; rep < 2; rep++) {
+                    vc_status st = enqueue_compute(b, r, s, true, L, b->sample_list, b->nsample);
+                    if (st) return st;
+                }
+                float ms = 0.f;
+                HIP_TRY(hipEventSynchronize(r->ev1));
+                HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev1));
+                if (ms < wms) {
+                    wms = ms;
+                    win = L;
+                }
+            }
+    HIP_TRY(hipStreamSynchronize(s));
+    b->launch = win;
+    release_graph(b);
+    if (best) {
+        best->slots = win.slots;
+        best->waves = win.waves;
+        best->chunk = win.chunk;
+        best->cells_per_wave = win.cpw;
+        best->ms = wms;
+    }
+    return VC_OK;
+}
+
+void vc_batch_destroy(vc_batch *b) { free_container(b); }
 
 const char *vc_last_error(void) { return g_err.c_str(); }
 
-const char *vc_version(void) { return "vorohip 0.1 (gfx950)"; }
+const char *vc_version(void) { return "vorohip 0.2 (gfx950)"; }
 
 }  // extern "C"

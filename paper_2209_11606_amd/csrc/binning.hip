@@ -17,12 +17,14 @@ constexpr int kTB = 256;          // threads per block of the streaming kernels
 constexpr int kScanItems = 8;     // elements per thread in the scan
 constexpr int kScanTile = kTB * kScanItems;
 
-__global__ __launch_bounds__(kTB) void k_bin_count(const double *__restrict__ xyz, int64_t n, Grid G,
+__global__ __launch_bounds__(kTB) void k_bin_count(const double *__restrict__ xyz, int64_t n, int dim,
+                                                   const Tess *__restrict__ tess, const int32_t *__restrict__ ptess,
                                                    int32_t *__restrict__ blk, int32_t *__restrict__ rank,
                                                    int32_t *__restrict__ count, int32_t *__restrict__ err)
 {
-    const int dim = G.dim;
     for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+        const Tess &T = tess[ptess ? ptess[i] : 0];
+        const Grid &G = T.G;
         int k[3] = {0, 0, 0};
         bool bad = false;
         for (int d = 0; d < dim; d++) {
@@ -33,7 +35,7 @@ __global__ __launch_bounds__(kTB) void k_bin_count(const double *__restrict__ xy
             k[d] = ok ? block_coord(G, x, d) : 0;
         }
         if (bad) atomicOr(err, 1);
-        int32_t b = k[0] + G.g[0] * (k[1] + G.g[1] * k[2]);
+        int32_t b = T.bbase + k[0] + G.g[0] * (k[1] + G.g[1] * k[2]);
         blk[i] = b;
         rank[i] = atomicAdd(&count[b], 1);
     }
@@ -121,18 +123,18 @@ __global__ void k_store_total(const T *__restrict__ total, T *__restrict__ dst)
     *dst = *total;
 }
 
-__global__ __launch_bounds__(kTB) void k_scatter(const double *__restrict__ xyz, int64_t n, Grid G,
-                                                 const int32_t *__restrict__ blk, const int32_t *__restrict__ rank,
-                                                 const int32_t *__restrict__ start, Particle *__restrict__ part)
+__global__ __launch_bounds__(kTB) void k_scatter(const double *__restrict__ xyz, int64_t n, int dim,
+                                                 const int32_t *__restrict__ ptess, const int32_t *__restrict__ blk,
+                                                 const int32_t *__restrict__ rank, const int32_t *__restrict__ start,
+                                                 Particle *__restrict__ part)
 {
-    const int dim = G.dim;
     for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
         Particle p;
         p.x = xyz[i * dim];
         p.y = xyz[i * dim + 1];
         p.z = dim == 3 ? xyz[i * dim + 2] : 0.0;
         p.id = (int32_t)i;
-        p.pad = 0;
+        p.tess = ptess ? ptess[i] : 0;
         part[start[blk[i]] + rank[i]] = p;
     }
 }
@@ -213,10 +215,10 @@ hipError_t scan_impl(const int32_t *in, int64_t n, T *out, T *tmp, hipStream_t s
 
 }  // namespace
 
-hipError_t launch_bin_count(const double *xyz, int64_t n, const Grid &G, int32_t *blk, int32_t *rank,
-                            int32_t *count, int32_t *err, hipStream_t s)
+hipError_t launch_bin_count(const double *xyz, int64_t n, int dim, const Tess *tess, const int32_t *ptess,
+                            int32_t *blk, int32_t *rank, int32_t *count, int32_t *err, hipStream_t s)
 {
-    k_bin_count<<<grid_for(n), kTB, 0, s>>>(xyz, n, G, blk, rank, count, err);
+    k_bin_count<<<grid_for(n), kTB, 0, s>>>(xyz, n, dim, tess, ptess, blk, rank, count, err);
     return hipGetLastError();
 }
 
@@ -225,10 +227,10 @@ hipError_t launch_scan(const int32_t *count, int32_t *start, int64_t nb, int32_t
     return scan_impl<int32_t>(count, nb, start, tmp, s);
 }
 
-hipError_t launch_scatter(const double *xyz, int64_t n, const Grid &G, const int32_t *blk, const int32_t *rank,
-                          const int32_t *start, Particle *part, hipStream_t s)
+hipError_t launch_scatter(const double *xyz, int64_t n, int dim, const int32_t *ptess, const int32_t *blk,
+                          const int32_t *rank, const int32_t *start, Particle *part, hipStream_t s)
 {
-    k_scatter<<<grid_for(n), kTB, 0, s>>>(xyz, n, G, blk, rank, start, part);
+    k_scatter<<<grid_for(n), kTB, 0, s>>>(xyz, n, dim, ptess, blk, rank, start, part);
     return hipGetLastError();
 }
 

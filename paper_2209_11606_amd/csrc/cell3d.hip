@@ -593,7 +593,8 @@ template <int S, int MAXP, bool F32, int K>
 __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh, Cell<S, MAXP, F32> &c, int si, const double *p,
                       const int *bc, int dx, int dy, int dz, bool valid, double *ws, unsigned long long *cnt, int lane)
 {
-    const Grid &G = A.G;
+    const Tess &T = A.tess[A.part[si].tess];
+    const Grid &G = T.G;
     int dd[3] = {dx, dy, dz};
     int bb[3], sv[3];
     bool ok = valid;
@@ -619,7 +620,7 @@ __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh
     if (d2b >= 4.0 * c.R2 * kMargin) ok = false;
     int cntb = 0, beg = 0;
     if (ok) {
-        int64_t blk = bb[0] + (int64_t)G.g[0] * (bb[1] + (int64_t)G.g[1] * bb[2]);
+        int64_t blk = T.bbase + bb[0] + (int64_t)G.g[0] * (bb[1] + (int64_t)G.g[1] * bb[2]);
         beg = A.start[blk];
         cntb = A.start[blk + 1] - beg;
     }
@@ -699,8 +700,9 @@ template <int S, int MAXP, bool F32, int K>
 __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &sh, int si, double *ws, unsigned long long *cnt)
 {
     const int lane = __lane_id();
-    const Grid &G = A.G;
     const Particle me = A.part[si];
+    const Tess &T = A.tess[me.tess];
+    const Grid &G = T.G;
     const double p[3] = {me.x, me.y, me.z};
     const int id = me.id;
     int bc[3];
@@ -781,7 +783,7 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     // nearest-first sweep over the precomputed block offsets
     bool finished = false;
     for (int o0 = 0; o0 < A.noff; o0 += 64) {
-        if (A.offgap2[o0] >= 4.0 * c.R2 * kMargin) {
+        if (A.offs[o0].m * T.bsmin2 >= 4.0 * c.R2 * kMargin) {
             finished = true;
             break;
         }

@@ -16,8 +16,8 @@ constexpr int kNoShift = 62;    // image code of the zero shift: 25*2 + 5*2 + 2
 // 16-byte loads per lane).
 struct alignas(32) Particle {
     double x, y, z;
-    int32_t id;   // input index
-    int32_t pad;
+    int32_t id;   // input index (over all tessellations of a batch)
+    int32_t tess; // tessellation the particle belongs to
 };
 
 // Geometry of a container's grid of blocks (section 2.1.1, 2.1.4).
@@ -41,19 +41,31 @@ __host__ __device__ inline int block_coord(const Grid &G, double x, int d)
     return k;
 }
 
-// Block offset relative to a particle's own block, with the squared lower
-// bound of the distance from any point of the own block to that block.
+// One tessellation of a container: its grid, and where its particles and
+// blocks start in the shared arrays.
+struct Tess {
+    Grid G;
+    int32_t pbase;   // first particle (input index and sorted index)
+    int32_t pcount;
+    int32_t bbase;   // first block in the shared block arrays
+    int32_t pad;
+    double bsmin2;   // squared smallest block side
+};
+
+// Block offset relative to a particle's own block.  m = sum over axes of
+// max(|d|-1, 0)^2: the squared gap to that block in units of the block side,
+// so m * bsmin2 bounds the distance from any point of the own block from
+// below.  The list is sorted by m (nearest first).
 struct Offset {
-    int dx, dy, dz, pad;
+    int dx, dy, dz, m;
 };
 
 // Arguments of the cell kernels.
 struct CellArgs {
-    Grid G;
+    const Tess *tess;          // tessellations (one for a plain container)
     const Particle *part;      // block-sorted particles
-    const int32_t *start;      // block start offsets, nb + 1
+    const int32_t *start;      // block start offsets (global particle index), nb_total + 1
     const Offset *offs;        // nearest-first block offsets
-    const double *offgap2;     // lower bound of squared distance per offset
     int noff;
     int off_radius;            // Chebyshev radius covered by offs
     int ncell;                 // cells in this launch
@@ -80,11 +92,11 @@ struct CellArgs {
 };
 
 // Launchers (defined in the .hip translation unit).
-hipError_t launch_bin_count(const double *xyz, int64_t n, const Grid &G, int32_t *blk, int32_t *rank,
-                            int32_t *count, int32_t *err, hipStream_t s);
+hipError_t launch_bin_count(const double *xyz, int64_t n, int dim, const Tess *tess, const int32_t *ptess,
+                            int32_t *blk, int32_t *rank, int32_t *count, int32_t *err, hipStream_t s);
 hipError_t launch_scan(const int32_t *count, int32_t *start, int64_t nb, int32_t *tmp, hipStream_t s);
-hipError_t launch_scatter(const double *xyz, int64_t n, const Grid &G, const int32_t *blk, const int32_t *rank,
-                          const int32_t *start, Particle *part, hipStream_t s);
+hipError_t launch_scatter(const double *xyz, int64_t n, int dim, const int32_t *ptess, const int32_t *blk,
+                          const int32_t *rank, const int32_t *start, Particle *part, hipStream_t s);
 hipError_t launch_block_order(Particle *part, const int32_t *start, int64_t nb, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_cells(const CellArgs &a, int precision, int slots, int waves, hipStream_t s);

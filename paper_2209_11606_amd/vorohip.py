@@ -34,6 +34,11 @@ class vc_options(ctypes.Structure):
                 ("chunk", ctypes.c_int)]
 
 
+class vc_tuning(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int), ("waves", ctypes.c_int), ("chunk", ctypes.c_int),
+                ("cells_per_wave", ctypes.c_int), ("ms", ctypes.c_float)]
+
+
 class VcError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"vorohip error {code}: {msg}")
@@ -57,8 +62,10 @@ def _load():
         "vc_result_destroy": (None, [P]),
         "vc_container_destroy": (None, [P]),
         "vc_batch_create": (I32, [P, P, I64, P, P, P]),
+        "vc_batch_rebin": (I32, [P, P, P]),
         "vc_batch_result_create": (I32, [P, U32, P]),
         "vc_batch_compute": (I32, [P, P, I32, P]),
+        "vc_batch_tune": (I32, [P, P, P, P]),
         "vc_batch_destroy": (None, [P]),
         "vc_result_kernel_ms": (I32, [P, P]),
         "vc_last_error": (ctypes.c_char_p, []),
@@ -74,7 +81,8 @@ def _load():
 _lib = _load()
 EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_result_create", "vc_compute",
             "vc_result_get", "vc_result_copy", "vc_result_kernel_ms", "vc_result_destroy", "vc_container_destroy", "vc_batch_create",
-            "vc_batch_result_create", "vc_batch_compute", "vc_batch_destroy", "vc_last_error", "vc_version"]
+            "vc_batch_rebin", "vc_batch_result_create", "vc_batch_compute", "vc_batch_tune", "vc_batch_destroy",
+            "vc_last_error", "vc_version"]
 
 
 def lib():
@@ -168,6 +176,43 @@ def vc_result_destroy(r):
 
 def vc_container_destroy(c):
     _lib.vc_container_destroy(c)
+
+
+def vc_batch_create(xyz, offsets, opts_list, stream=None):
+    """xyz: all positions back to back (torch tensor on the GPU or numpy);
+    offsets: n_tess + 1 particle offsets; opts_list: one vc_options each."""
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    arr = (vc_options * len(opts_list))(*opts_list)
+    ptr = xyz.data_ptr() if hasattr(xyz, "data_ptr") else xyz.ctypes.data
+    h = ctypes.c_void_p()
+    _check(_lib.vc_batch_create(ctypes.c_void_p(ptr), off.ctypes.data, len(opts_list), arr,
+                                ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
+    return h
+
+
+def vc_batch_rebin(b, xyz, stream=None):
+    ptr = xyz.data_ptr() if hasattr(xyz, "data_ptr") else xyz.ctypes.data
+    _check(_lib.vc_batch_rebin(b, ctypes.c_void_p(ptr), ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def vc_batch_result_create(b, mask):
+    h = ctypes.c_void_p()
+    _check(_lib.vc_batch_result_create(b, mask, ctypes.byref(h)))
+    return h
+
+
+def vc_batch_compute(b, r, graph=False, stream=None):
+    _check(_lib.vc_batch_compute(b, r, int(bool(graph)), ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def vc_batch_tune(b, r, stream=None):
+    t = vc_tuning()
+    _check(_lib.vc_batch_tune(b, r, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(t)))
+    return dict(slots=t.slots, waves=t.waves, chunk=t.chunk, cells_per_wave=t.cells_per_wave, ms=t.ms)
+
+
+def vc_batch_destroy(b):
+    _lib.vc_batch_destroy(b)
 
 
 def fetch(r, mask, n, dim=3):

@@ -1,0 +1,124 @@
+"""The batched form: many independent tessellations in one persistent launch.
+
+Each tessellation's cells must be bitwise identical to the same tessellation
+computed alone (the work queue and launch parameters never change a cell),
+match the oracle, and stay identical across hipGraph replays and after the
+autotuner picks its launch parameters.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_11606_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FIELDS = ("vol", "cen", "nv", "ne", "nf", "fo", "status")
+
+
+@pytest.fixture(scope="module")
+def v():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_11606_amd import vorohip
+    return vorohip
+
+
+def make_batch(count, seed, hi):
+    members = W.batch(count, seed, 100, hi)
+    offsets = np.zeros(count + 1, np.int64)
+    for t, m in enumerate(members):
+        offsets[t + 1] = offsets[t] + len(m["xyz"])
+    xyz = np.concatenate([m["xyz"] for m in members])
+    return members, offsets, xyz
+
+
+def batch_run(v, members, offsets, xyz, graph_replays=0, tune=False, precision=0):
+    opts = [v.vc_options_init(3, m["lo"], m["hi"], m["periodic"], precision=precision) for m in members]
+    s = torch.cuda.Stream()
+    xt = torch.from_numpy(xyz).to("cuda:0")
+    torch.cuda.synchronize()
+    b = v.vc_batch_create(xt, offsets, opts, s)
+    r = v.vc_batch_result_create(b, v.VC_ALL)
+    try:
+        tuned = v.vc_batch_tune(b, r, s) if tune else None
+        v.vc_batch_compute(b, r, False, s)
+        eager = v.fetch(r, v.VC_ALL, len(xyz))
+        replays = []
+        for k in range(graph_replays):
+            # eager work between replays on the same stream and on the default one
+            with torch.cuda.stream(s):
+                junk = torch.randn(1 << 16, device="cuda:0").sum()
+            v.vc_batch_compute(b, r, True, s)
+            s.synchronize()
+            replays.append(v.fetch(r, v.VC_ALL, len(xyz)))
+            float(junk)
+        return eager, replays, tuned
+    finally:
+        v.vc_result_destroy(r)
+        v.vc_batch_destroy(b)
+
+
+def split(res, offsets, t):
+    a, e = offsets[t], offsets[t + 1]
+    out = {k: res[k][a:e] for k in FIELDS}
+    off = res["nbr_off"]
+    out["nbr"] = [np.stack([res["nbr_ids"][off[i]:off[i + 1]].astype(np.int64),
+                            res["nbr_sh"][off[i]:off[i + 1]].astype(np.int64)], 1) for i in range(a, e)]
+    return out
+
+
+def test_batch_equals_single_and_oracle(v):
+    members, offsets, xyz = make_batch(24, 2024, 3000)
+    eager, _, _ = batch_run(v, members, offsets, xyz)
+    assert np.all(eager["status"] <= 1)
+    for t, m in enumerate(members):
+        xt = torch.from_numpy(np.ascontiguousarray(m["xyz"])).to("cuda:0")
+        one = v.tessellate(xt, m["lo"], m["hi"], m["periodic"], v.VC_ALL)
+        part = split(eager, offsets, t)
+        for k in FIELDS:
+            assert np.array_equal(part[k], one[k]), (t, m["kind"], k)
+        nb1 = v.neighbor_lists(one)
+        # neighbour ids in the batch are global (offset by the tessellation start)
+        for i in range(len(nb1)):
+            got = part["nbr"][i].copy()
+            got[got[:, 0] >= 0, 0] -= offsets[t]
+            assert np.array_equal(got, nb1[i])
+        if t % 6 == 0:
+            r = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"]).cells()
+            assert np.array_equal(one["nf"], r["nf"]) and np.array_equal(one["fo"], r["fo"])
+            assert np.max(np.abs(one["vol"] - r["vol"]) / r["vol"]) <= 1e-12
+            for i in range(len(nb1)):
+                assert np.array_equal(nb1[i], r["nbr"][i])
+
+
+def test_graph_replays_and_tuner(v):
+    members, offsets, xyz = make_batch(40, 77, 5000)
+    eager, replays, _ = batch_run(v, members, offsets, xyz, graph_replays=3)
+    for rep in replays:
+        for k in FIELDS + ("nbr_off", "nbr_ids", "nbr_sh"):
+            assert np.array_equal(rep[k], eager[k]), k
+    tuned_eager, tuned_replays, tuned = batch_run(v, members, offsets, xyz, graph_replays=2, tune=True)
+    assert tuned["slots"] in (2, 4) and tuned["chunk"] in (1, 4, 16, 64) and tuned["ms"] > 0
+    for res in [tuned_eager] + tuned_replays:
+        for k in FIELDS + ("nbr_off", "nbr_ids", "nbr_sh"):
+            assert np.array_equal(res[k], eager[k]), k
+
+
+def test_batch_f32_filter_bitwise(v):
+    members, offsets, xyz = make_batch(16, 5, 4000)
+    a, _, _ = batch_run(v, members, offsets, xyz)
+    b, _, _ = batch_run(v, members, offsets, xyz, precision=1)
+    for k in FIELDS + ("nbr_off", "nbr_ids", "nbr_sh"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_batch_argument_errors(v):
+    members, offsets, xyz = make_batch(3, 9, 500)
+    opts = [v.vc_options_init(3, m["lo"], m["hi"], m["periodic"]) for m in members]
+    bad = offsets.copy()
+    bad[2] = bad[1]
+    with pytest.raises(v.VcError) as e:
+        v.vc_batch_create(xyz, bad, opts)
+    assert e.value.code == v.VC_E_ARG
