@@ -6,6 +6,11 @@ neighbour lists).  One step = the whole hot path on positions already resident
 in HBM: binning (count, scan, scatter, in-block order), every cell, the
 large-capacity spill pass and the neighbour compaction.
 
+Variants: the plain form (one container, FP64 or FP32-filter side tests) and
+the batched form (vc_batch: autotuned launch parameters, compute replayed
+from a hipGraph).  `value` is the fastest variant.  --workload batch4096
+measures the 4,096-tessellation set instead.
+
 Prints one JSON line.  The roofline object covers the dominant kernel (the
 cell kernel): its algorithmic FP64 flops per launch -- the oracle's operation
 counts on a sample of the same workload, weighted (candidate distance 9,
@@ -36,57 +41,115 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--cpu-sample", type=int, default=200_000, help="oracle cells timed on the host")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--calibration-copy-mib", type=int, default=0,
+                   help="first copy a device buffer of this size (reference for HBM byte counters)")
+    p.add_argument("--variants", default="all", help="comma list of variants to run (default all)")
+    p.add_argument("--workload", default="periodic1m", choices=["periodic1m", "batch4096"],
+                   help="periodic1m: the metric's configuration (default); batch4096: the batched set")
     return p.parse_args()
 
 
+def _timed(torch, stream, steps, step_fn):
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        step_fn()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
 def time_variant(v, torch, xt, w, precision, steps, warmup):
+    """Plain form: one container; step = rebin + compute."""
     stream = torch.cuda.current_stream()
     o = v.vc_options_init(3, w["lo"], w["hi"], w["periodic"], precision=precision)
     c = v.vc_container_create(xt, o, stream)
     r = v.vc_result_create(c, v.VC_ALL)
+    kms = []
+
+    def step():
+        v.vc_container_rebin(c, xt, stream)
+        v.vc_compute(c, r, stream)
+        kms.append(v.vc_result_kernel_ms(r))
     try:
         for _ in range(warmup):
-            v.vc_container_rebin(c, xt, stream)
-            v.vc_compute(c, r, stream)
-        torch.cuda.synchronize()
-        kms = []
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        for _ in range(steps):
-            v.vc_container_rebin(c, xt, stream)
-            v.vc_compute(c, r, stream)
-            kms.append(v.vc_result_kernel_ms(r))
-        t1.record(stream)
-        torch.cuda.synchronize()
-        total_ms = t0.elapsed_time(t1)
-        status = v.vc_result_copy(r, v.VC_F_STATUS)
-        diag = dict(zip(v.DIAG_NAMES, v.vc_result_copy(r, v.VC_F_DIAG)[:len(v.DIAG_NAMES)].tolist()))
-        vol = v.vc_result_copy(r, v.VC_F_VOLUME)
+            step()
+        kms.clear()
+        ms = _timed(torch, stream, steps, step)
+        out = _summary(v, r, ms, float(np.mean(kms)))
     finally:
         v.vc_result_destroy(r)
         v.vc_container_destroy(c)
-    return dict(ms_per_step=total_ms / steps, kernel_ms=float(np.mean(kms)), status_ok=bool(np.all(status <= 1)),
+    return out
+
+
+def time_batched(v, torch, xt, offsets, opts, steps, warmup):
+    """Batched form: autotuned launch parameters, compute replayed from a
+    hipGraph; step = rebin + graph launch.  The cell-kernel duration for the
+    roofline comes from eager launches with the same parameters."""
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    b = v.vc_batch_create(xt, offsets, opts, stream)
+    r = v.vc_batch_result_create(b, v.VC_ALL)
+    try:
+        tuned = v.vc_batch_tune(b, r, stream)
+        kms = []
+        for _ in range(max(1, warmup)):
+            v.vc_batch_compute(b, r, False, stream)
+            kms.append(v.vc_result_kernel_ms(r))
+
+        def step():
+            v.vc_batch_rebin(b, xt, stream)
+            v.vc_batch_compute(b, r, True, stream)
+        for _ in range(warmup):
+            step()
+        ms = _timed(torch, stream, steps, step)
+        for _ in range(3):
+            v.vc_batch_compute(b, r, False, stream)
+            kms.append(v.vc_result_kernel_ms(r))
+        out = _summary(v, r, ms, float(np.median(kms)))
+        out["tuned"] = tuned
+    finally:
+        v.vc_result_destroy(r)
+        v.vc_batch_destroy(b)
+    return out
+
+
+def _summary(v, r, ms, kernel_ms):
+    status = v.vc_result_copy(r, v.VC_F_STATUS)
+    diag = dict(zip(v.DIAG_NAMES, v.vc_result_copy(r, v.VC_F_DIAG)[:len(v.DIAG_NAMES)].tolist()))
+    vol = v.vc_result_copy(r, v.VC_F_VOLUME)
+    return dict(ms_per_step=ms, kernel_ms=kernel_ms, status_ok=bool(np.all(status <= 1)),
                 vol_sum=float(np.sum(vol)), diag=diag)
 
 
-def cpu_baseline(w, sample):
+def cpu_baseline(members, sample):
+    """The oracle on the host cores: the first `sample` cells of the
+    workload (in member order), OpenMP dynamic schedule over cells."""
     import oracle
     cores = len(os.sched_getaffinity(0))
-    o = oracle.Oracle(w["xyz"], w["lo"], w["hi"], w["periodic"])
-    idx = np.arange(min(sample, len(w["xyz"])), dtype=np.int64)
-    t = time.perf_counter()
-    r = o.cells(idx, nthreads=cores, neighbors=False)
-    dt = time.perf_counter() - t
-    cnt = r["counters"]
-    per_cell = {k: cnt[k] / len(idx) for k in cnt}
-    flops = (FLOP_WEIGHTS["candidates"] * (cnt["candidates"] - cnt["radius_rejects"])
-             + FLOP_WEIGHTS["vertex_tests"] * cnt["vertex_tests"]
-             + FLOP_WEIGHTS["new_vertices"] * cnt["new_vertices"]
-             + FLOP_WEIGHTS["fan_triangles"] * cnt["fan_triangles"]) / len(idx)
-    return dict(value=len(idx) / dt, unit="cells/s", cores=cores, kind="oracle",
-                sample=f"first {len(idx)} cells of the same 1M-particle periodic set, OpenMP dynamic,64 over cells",
-                seconds=dt), flops, per_cell
+    done, secs = 0, 0.0
+    tot = {}
+    for m in members:
+        if done >= sample:
+            break
+        o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"])
+        k = min(sample - done, len(m["xyz"]))
+        idx = np.arange(k, dtype=np.int64)
+        t = time.perf_counter()
+        r = o.cells(idx, nthreads=cores, neighbors=False)
+        secs += time.perf_counter() - t
+        done += k
+        for key, val in r["counters"].items():
+            tot[key] = tot.get(key, 0) + val
+    flops = (FLOP_WEIGHTS["candidates"] * (tot["candidates"] - tot["radius_rejects"])
+             + FLOP_WEIGHTS["vertex_tests"] * tot["vertex_tests"]
+             + FLOP_WEIGHTS["new_vertices"] * tot["new_vertices"]
+             + FLOP_WEIGHTS["fan_triangles"] * tot["fan_triangles"]) / done
+    per_cell = {k: val / done for k, val in tot.items()}
+    return dict(value=done / secs, unit="cells/s", cores=cores, kind="oracle", seconds=secs), flops, per_cell
 
 
 def main():
@@ -102,19 +165,49 @@ def main():
     from paper_2209_11606_amd import vorohip as v
     from paper_2209_11606_amd import workloads as W
 
-    w = W.periodic_1m()
-    n = len(w["xyz"])
-    xt = torch.from_numpy(w["xyz"]).to("cuda:0")
+    if a.workload == "periodic1m":
+        w = W.periodic_1m()
+        members = [w]
+        desc = ("periodic_uniform_1M: 1,000,000 uniform particles, periodic cube side 100, full statistics")
+        sample_desc = "first {} cells of the same 1M-particle periodic set"
+    else:
+        members = W.batch(4096)
+        desc = ("batch_4096: 4,096 independent 3D tessellations, sizes log-uniform in [100, 100000], "
+                "periodic/walled x uniform/perturbed BCC, full statistics")
+        sample_desc = "first {} cells of the batch in tessellation order"
+    offsets = np.zeros(len(members) + 1, np.int64)
+    for t, m in enumerate(members):
+        offsets[t + 1] = offsets[t] + len(m["xyz"])
+    n = int(offsets[-1])
+    xyz = members[0]["xyz"] if len(members) == 1 else np.concatenate([m["xyz"] for m in members])
+    xt = torch.from_numpy(xyz).to("cuda:0")
+    if a.calibration_copy_mib > 0:
+        src = torch.ones(a.calibration_copy_mib << 17, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        del src, dst
     torch.cuda.synchronize()
     res = {}
-    for name, prec in (("fp64", v.VC_FP64), ("f32_filter", v.VC_F32_FILTER)):
-        res[name] = time_variant(v, torch, xt, w, prec, a.steps, a.warmup)
+    variants = []
+    if len(members) == 1:
+        variants += [("fp64", v.VC_FP64, False), ("f32_filter", v.VC_F32_FILTER, False)]
+    variants += [("fp64_batched", v.VC_FP64, True), ("f32_filter_batched", v.VC_F32_FILTER, True)]
+    if a.variants != "all":
+        keep = set(a.variants.split(","))
+        variants = [x for x in variants if x[0] in keep]
+    for name, prec, batched in variants:
+        if batched:
+            opts = [v.vc_options_init(3, m["lo"], m["hi"], m["periodic"], precision=prec) for m in members]
+            res[name] = time_batched(v, torch, xt, offsets, opts, a.steps, a.warmup)
+        else:
+            res[name] = time_variant(v, torch, xt, members[0], prec, a.steps, a.warmup)
         print(f"# {name}: {res[name]['ms_per_step']:.3f} ms/step, cell kernel {res[name]['kernel_ms']:.3f} ms, "
-              f"diag {res[name]['diag']}", file=sys.stderr, flush=True)
+              f"tuned {res[name].get('tuned')}, diag {res[name]['diag']}", file=sys.stderr, flush=True)
     if a.no_cpu_baseline:
         cpu, flops_per_cell = None, None
     else:
-        cpu, flops_per_cell, per_cell = cpu_baseline(w, a.cpu_sample)
+        cpu, flops_per_cell, per_cell = cpu_baseline(members, a.cpu_sample)
+        cpu["sample"] = sample_desc.format(min(a.cpu_sample, n)) + ", OpenMP dynamic,64 over cells"
         print(f"# oracle: {cpu['value']:.0f} cells/s on {cpu['cores']} cores; per cell {per_cell}",
               file=sys.stderr, flush=True)
     best = max(res, key=lambda k: n / res[k]["ms_per_step"])
@@ -137,12 +230,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if best == "fp64" else "f32-filter+f64",
+        "dtype": "f64" if best.startswith("fp64") else "f32-filter+f64",
         "data": "synthetic",
-        "config": {"workload": "periodic_uniform_1M: 1,000,000 uniform particles, periodic cube side 100, "
-                               "full statistics", "n": n, "grid": "59^3 blocks (N_opt 5)", "variant": best},
+        "config": {"workload": desc, "n": n, "tessellations": len(members), "variant": best},
         "variants": {k: dict(cells_per_s=n / (r["ms_per_step"] / 1e3), ms_per_step=r["ms_per_step"],
-                             cell_kernel_ms=r["kernel_ms"], all_cells_ok=r["status_ok"], diag=r["diag"])
+                             cell_kernel_ms=r["kernel_ms"], all_cells_ok=r["status_ok"], tuned=r.get("tuned"),
+                             diag=r["diag"])
                      for k, r in res.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
