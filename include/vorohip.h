@@ -103,6 +103,7 @@ typedef struct {
     int slots;           /* triangles per lane in the main cell kernel (2 or 4); 0: auto */
     int waves;           /* resident cell waves launched; 0: auto */
     int chunk;           /* cells taken per work-queue grab; 0: auto */
+    int cells_per_wave;  /* cells sharing one wavefront: 1, 2 or 4; 0: 1 */
 } vc_options;
 
 typedef struct vc_container vc_container;

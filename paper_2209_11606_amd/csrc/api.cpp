@@ -113,6 +113,8 @@ vc_status check_options(const vc_options *o)
         return fail(VC_E_ARG, "options: precision must be VC_FP64 or VC_F32_FILTER");
     if (o->slots != 0 && o->slots != 2 && o->slots != 4) return fail(VC_E_ARG, "options: slots must be 0, 2 or 4");
     if (o->waves < 0 || o->chunk < 0) return fail(VC_E_ARG, "options: negative waves or chunk");
+    if (o->cells_per_wave != 0 && o->cells_per_wave != 1 && o->cells_per_wave != 2 && o->cells_per_wave != 4)
+        return fail(VC_E_ARG, "options: cells_per_wave must be 0, 1, 2 or 4");
     return VC_OK;
 }
 
@@ -282,6 +284,7 @@ vc_status create_common(vc_container *c, const double *xyz, const int64_t *offse
     c->precision = opts[0].precision;
     c->launch.slots = opts[0].slots > 0 ? opts[0].slots : 2;
     c->launch.chunk = opts[0].chunk > 0 ? opts[0].chunk : 4;
+    c->launch.cpw = opts[0].cells_per_wave > 0 ? opts[0].cells_per_wave : 1;
     int cu = device_cu_count();
     c->launch.waves = opts[0].waves > 0 ? opts[0].waves : cu * 16;
     c->max_waves = std::max(c->launch.waves, cu * 32);
@@ -386,7 +389,8 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
     HIP_TRY(launch_fill_i32(c->queue, 4, 0, s));
     HIP_TRY(launch_fill_i32((int32_t *)r->diag, VC_DIAG_LEN * 2, 0, s));
     if (events) HIP_TRY(hipEventRecord(r->ev0, s));
-    HIP_TRY(launch_cells(A, c->precision, L.slots, std::min(L.waves, c->max_waves), s));
+    if (L.cpw > 1) HIP_TRY(launch_cells_group(A, c->precision, L.cpw, std::min(L.waves, c->max_waves), s));
+    else HIP_TRY(launch_cells(A, c->precision, L.slots, std::min(L.waves, c->max_waves), s));
     if (events) HIP_TRY(hipEventRecord(r->ev1, s));
     // cells beyond the main kernel's capacity: large-capacity pass over the
     // spill list (its length is read on the device)
@@ -658,16 +662,18 @@ vc_status vc_batch_tune(vc_batch *b, vc_result *r, void *stream, vc_tuning *best
     if (r->c != b) return fail(VC_E_STATE, "vc_batch_tune: result was created for another batch");
     hipStream_t s = (hipStream_t)stream;
     int cu = device_cu_count();
-    const int slots_c[] = {2, 4};
+    // (cells per wave, slots) pairs; slots only matter for one cell per wave
+    const int form_c[][2] = {{1, 2}, {1, 4}, {2, 2}, {4, 4}};
     const int chunk_c[] = {1, 4, 16, 64};
     const int waves_c[] = {cu * 8, cu * 16, cu * 32};
     Launch win;
     float wms = 1e30f;
-    for (int sl : slots_c)
+    for (auto &f : form_c)
         for (int ch : chunk_c)
             for (int wv : waves_c) {
                 Launch L;
-                L.slots = sl;
+                L.cpw = f[0];
+                L.slots = f[1];
                 L.chunk = ch;
                 L.waves = wv;
                 // two runs: the first warms caches, the second is timed

@@ -26,271 +26,11 @@
 // and taken in increasing distance.  A candidate at distance >= 2R (R the
 // largest vertex distance) is skipped and the sweep stops when the next block
 // is farther than 2R (the radius bound of section 2.1.3).
-#include "vc_internal.h"
+#include "cell_common.h"
 
 namespace vc {
 
 namespace {
-
-constexpr double kMargin = 1.0 + 0x1p-30;  // radius-bound safety factor on squared distances
-constexpr int kMaxShell = 64;              // largest Chebyshev shell searched; beyond it the cell fails
-
-struct PlaneD {
-    double n0, n1, n2, h;
-    int wall;
-};
-
-// ---------------------------------------------------------------------------
-// Exact sign with floating-point expansions (Shewchuk 1997): a list of
-// doubles, nonoverlapping and increasing in magnitude, whose exact sum is the
-// value; Grow-Expansion adds one double exactly.  Runs on one lane at a time
-// with the wave's workspace in global memory.
-// ---------------------------------------------------------------------------
-#pragma clang fp contract(off)
-
-__device__ inline void xs_two_sum(double a, double b, double &x, double &y)
-{
-    double s = a + b;
-    double bv = s - a;
-    double av = s - bv;
-    x = s;
-    y = (a - av) + (b - bv);
-}
-
-__device__ inline void xs_two_prod(double a, double b, double &x, double &y)
-{
-    double p = a * b;
-    x = p;
-    y = __builtin_fma(a, b, -p);
-}
-
-// e <- e + b (in place: output component k is written at index <= its input)
-__device__ inline int xs_grow(double *e, int n, double b)
-{
-    double q = b;
-    int k = 0;
-    for (int i = 0; i < n; i++) {
-        double x, y;
-        xs_two_sum(q, e[i], x, y);
-        if (y != 0.0) e[k++] = y;
-        q = x;
-    }
-    if (q != 0.0 || k == 0) e[k++] = q;
-    return k;
-}
-
-__device__ inline int xs_add_prod(double *e, int n, double a, double b)
-{
-    double x, y;
-    xs_two_prod(a, b, x, y);
-    if (y != 0.0) n = xs_grow(e, n, y);
-    return xs_grow(e, n, x);
-}
-
-__device__ inline int xs_sign(const double *e, int n)
-{
-    double t = e[n - 1];
-    return (t > 0.0) - (t < 0.0);
-}
-
-// The exact offset of a plane as a short list of doubles summing to it:
-// q.q/2 for a bisector (three exact squares, halved), h for a wall.
-__device__ inline int xs_offset(const PlaneD &p, double *out)
-{
-    if (p.wall) {
-        out[0] = p.h;
-        return 1;
-    }
-    double v[3] = {p.n0, p.n1, p.n2};
-    int k = 0;
-    for (int d = 0; d < 3; d++) {
-        double x, y;
-        xs_two_prod(v[d], v[d], x, y);
-        out[k++] = 0.5 * x;
-        out[k++] = 0.5 * y;
-    }
-    return k;
-}
-
-// acc += sgn * h_list * det3(u, v, w) over the six permutation products.
-__device__ int xs_acc_hdet(double *acc, int n, const double *hl, int nh, double sgn, const double *u,
-                           const double *v, const double *w)
-{
-    const int pm[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {1, 0, 2}, {2, 1, 0}};
-    for (int k = 0; k < 6; k++) {
-        double sg = k < 3 ? sgn : -sgn;
-        double x, y;
-        xs_two_prod(sg * u[pm[k][0]], v[pm[k][1]], x, y);
-        // (x + y) * w exactly = four doubles
-        double t[4];
-        xs_two_prod(x, w[pm[k][2]], t[0], t[1]);
-        xs_two_prod(y, w[pm[k][2]], t[2], t[3]);
-        for (int a = 0; a < 4; a++) {
-            if (t[a] == 0.0) continue;
-            for (int b = 0; b < nh; b++) {
-                if (hl[b] == 0.0) continue;
-                n = xs_add_prod(acc, n, t[a], hl[b]);
-            }
-        }
-    }
-    return n;
-}
-
-// Exact sign of n_p.v - h_p at v = planes a, b, c:
-//   s * D(a,b,c) = h_a D(b,c,p) - h_b D(a,c,p) + h_c D(a,b,p) - h_p D(a,b,c).
-__device__ __noinline__ int exact_side3(PlaneD a, PlaneD b, PlaneD c, PlaneD p, double *ws)
-{
-    const PlaneD *r[4] = {&a, &b, &c, &p};
-    double nv[4][3];
-    for (int i = 0; i < 4; i++) {
-        nv[i][0] = r[i]->n0;
-        nv[i][1] = r[i]->n1;
-        nv[i][2] = r[i]->n2;
-    }
-    const int mi[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
-    double hl[6];
-    int n = 0;
-    for (int i = 0; i < 4; i++) {
-        int nh = xs_offset(*r[i], hl);
-        n = xs_acc_hdet(ws, n, hl, nh, (i & 1) ? -1.0 : 1.0, nv[mi[i][0]], nv[mi[i][1]], nv[mi[i][2]]);
-    }
-    int s4 = n ? xs_sign(ws, n) : 0;
-    double one = 1.0;
-    int m = xs_acc_hdet(ws, 0, &one, 1, 1.0, nv[0], nv[1], nv[2]);
-    int s3 = m ? xs_sign(ws, m) : 0;
-    return s4 * s3;
-}
-
-#pragma clang fp contract(fast)
-
-// ---------------------------------------------------------------------------
-// Wave helpers.  Reductions and scans use DPP lane movement (quad
-// permutations, row mirrors, row shifts and the row broadcasts of the
-// 64-wide wave) and end with a readlane, so the result is wave-uniform and
-// no LDS round trip is taken.
-// ---------------------------------------------------------------------------
-enum {
-    DPP_QUAD_1032 = 0xB1,     // quad_perm [1,0,3,2]
-    DPP_QUAD_2301 = 0x4E,     // quad_perm [2,3,0,1]
-    DPP_ROW_SHR1 = 0x111,
-    DPP_ROW_SHR2 = 0x112,
-    DPP_ROW_SHR4 = 0x114,
-    DPP_ROW_SHR8 = 0x118,
-    DPP_ROW_MIRROR = 0x140,
-    DPP_ROW_HALF_MIRROR = 0x141,
-    DPP_ROW_BCAST15 = 0x142,  // lane 15 of each row to the next row
-    DPP_ROW_BCAST31 = 0x143   // lane 31 to rows 2 and 3
-};
-
-template <int CTRL, int RM>
-__device__ __forceinline__ int dpp_i32(int old, int v)
-{
-    return __builtin_amdgcn_update_dpp(old, v, CTRL, RM, 0xf, false);
-}
-
-template <int CTRL, int RM>
-__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long old, unsigned long long v)
-{
-    int lo = __builtin_amdgcn_update_dpp((int)(unsigned)old, (int)(unsigned)v, CTRL, RM, 0xf, false);
-    int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(old >> 32), (int)(unsigned)(v >> 32), CTRL, RM, 0xf, false);
-    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
-}
-
-template <int CTRL, int RM>
-__device__ __forceinline__ double dpp_f64(double old, double v)
-{
-    return __builtin_bit_cast(double, dpp_u64<CTRL, RM>(__builtin_bit_cast(unsigned long long, old),
-                                                         __builtin_bit_cast(unsigned long long, v)));
-}
-
-__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l)
-{
-    unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
-    unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int l)
-{
-    return __builtin_bit_cast(double, readlane_u64(__builtin_bit_cast(unsigned long long, v), l));
-}
-
-__device__ __forceinline__ int lane_rank(uint64_t m)
-{
-    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
-
-__device__ __forceinline__ double wave_max(double v)
-{
-    v = fmax(v, dpp_f64<DPP_QUAD_1032, 0xf>(v, v));
-    v = fmax(v, dpp_f64<DPP_QUAD_2301, 0xf>(v, v));
-    v = fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR, 0xf>(v, v));
-    v = fmax(v, dpp_f64<DPP_ROW_MIRROR, 0xf>(v, v));
-    v = fmax(v, dpp_f64<DPP_ROW_BCAST15, 0xa>(v, v));
-    v = fmax(v, dpp_f64<DPP_ROW_BCAST31, 0xc>(v, v));
-    return readlane_f64(v, 63);
-}
-
-// fixed combination order: the sum is the same on every run
-__device__ __forceinline__ double wave_sum(double v)
-{
-    v = v + dpp_f64<DPP_QUAD_1032, 0xf>(0.0, v);
-    v = v + dpp_f64<DPP_QUAD_2301, 0xf>(0.0, v);
-    v = v + dpp_f64<DPP_ROW_HALF_MIRROR, 0xf>(0.0, v);
-    v = v + dpp_f64<DPP_ROW_MIRROR, 0xf>(0.0, v);
-    v = v + dpp_f64<DPP_ROW_BCAST15, 0xa>(0.0, v);
-    v = v + dpp_f64<DPP_ROW_BCAST31, 0xc>(0.0, v);
-    return readlane_f64(v, 63);
-}
-
-__device__ __forceinline__ int wave_isum(int v)
-{
-    v = v + dpp_i32<DPP_QUAD_1032, 0xf>(0, v);
-    v = v + dpp_i32<DPP_QUAD_2301, 0xf>(0, v);
-    v = v + dpp_i32<DPP_ROW_HALF_MIRROR, 0xf>(0, v);
-    v = v + dpp_i32<DPP_ROW_MIRROR, 0xf>(0, v);
-    v = v + dpp_i32<DPP_ROW_BCAST15, 0xa>(0, v);
-    v = v + dpp_i32<DPP_ROW_BCAST31, 0xc>(0, v);
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
-__device__ __forceinline__ unsigned long long wave_or_u64(unsigned long long v)
-{
-    v |= dpp_u64<DPP_QUAD_1032, 0xf>(0ull, v);
-    v |= dpp_u64<DPP_QUAD_2301, 0xf>(0ull, v);
-    v |= dpp_u64<DPP_ROW_HALF_MIRROR, 0xf>(0ull, v);
-    v |= dpp_u64<DPP_ROW_MIRROR, 0xf>(0ull, v);
-    v |= dpp_u64<DPP_ROW_BCAST15, 0xa>(0ull, v);
-    v |= dpp_u64<DPP_ROW_BCAST31, 0xc>(0ull, v);
-    return readlane_u64(v, 63);
-}
-
-// inclusive prefix sum over the wave (row shifts, then row broadcasts)
-__device__ __forceinline__ int wave_incl_scan(int v)
-{
-    v = v + dpp_i32<DPP_ROW_SHR1, 0xf>(0, v);
-    v = v + dpp_i32<DPP_ROW_SHR2, 0xf>(0, v);
-    v = v + dpp_i32<DPP_ROW_SHR4, 0xf>(0, v);
-    v = v + dpp_i32<DPP_ROW_SHR8, 0xf>(0, v);
-    v = v + dpp_i32<DPP_ROW_BCAST15, 0xa>(0, v);
-    v = v + dpp_i32<DPP_ROW_BCAST31, 0xc>(0, v);
-    return v;
-}
-
-// exclusive prefix of small non-negative counts (< 2^BITS) by bit ballots
-template <int BITS>
-__device__ __forceinline__ int ballot_excl_scan(int v, int &total)
-{
-    int r = 0, t = 0;
-#pragma unroll
-    for (int b = 0; b < BITS; b++) {
-        unsigned long long m = __ballot((v >> b) & 1);
-        r += lane_rank(m) << b;
-        t += __popcll(m) << b;
-    }
-    total = t;
-    return r;
-}
 
 template <int S, int MAXP, int K>
 struct CellLDS {
@@ -329,19 +69,6 @@ struct PlaneSet {
     static constexpr unsigned long long pad = (MAXP % 64) ? ~((1ull << (MAXP % 64)) - 1) : 0ull;
 };
 
-// vertex of planes A, B, C by Cramer's rule
-__device__ __forceinline__ void cramer(const double *A, const double *B, const double *C, double &x, double &y, double &z)
-{
-    double bc0 = B[1] * C[2] - B[2] * C[1], bc1 = B[2] * C[0] - B[0] * C[2], bc2 = B[0] * C[1] - B[1] * C[0];
-    double ca0 = C[1] * A[2] - C[2] * A[1], ca1 = C[2] * A[0] - C[0] * A[2], ca2 = C[0] * A[1] - C[1] * A[0];
-    double ab0 = A[1] * B[2] - A[2] * B[1], ab1 = A[2] * B[0] - A[0] * B[2], ab2 = A[0] * B[1] - A[1] * B[0];
-    double det = A[0] * bc0 + A[1] * bc1 + A[2] * bc2;
-    double inv = 1.0 / det;
-    x = (A[3] * bc0 + B[3] * ca0 + C[3] * ab0) * inv;
-    y = (A[3] * bc1 + B[3] * ca1 + C[3] * ab1) * inv;
-    z = (A[3] * bc2 + B[3] * ca2 + C[3] * ab2) * inv;
-}
-
 template <int S, int MAXP, int K>
 __device__ __forceinline__ PlaneD plane_of(const CellLDS<S, MAXP, K> &sh, int k)
 {
@@ -353,9 +80,6 @@ __device__ __forceinline__ PlaneD plane_of(const CellLDS<S, MAXP, K> &sh, int k)
     p.wall = sh.pwall[k];
     return p;
 }
-
-enum { ST_OK = 0, ST_CAP = 1, ST_DUP = 3 };
-enum { DC_CAND, DC_TESTS, DC_CUTS, DC_NEWV, DC_EXACT, DC_RECHECK, DC_SPILL, DC_BLOCKS, DC_FALLBACK, DC_N };
 
 // State of one cell held by a wave (registers are per lane; masks uniform).
 template <int S, int MAXP, bool F32>

@@ -101,9 +101,15 @@ def test_graph_replays_and_tuner(v):
             assert np.array_equal(rep[k], eager[k]), k
     tuned_eager, tuned_replays, tuned = batch_run(v, members, offsets, xyz, graph_replays=2, tune=True)
     assert tuned["slots"] in (2, 4) and tuned["chunk"] in (1, 4, 16, 64) and tuned["ms"] > 0
+    assert tuned["cells_per_wave"] in (1, 2, 4)
     for res in [tuned_eager] + tuned_replays:
-        for k in FIELDS + ("nbr_off", "nbr_ids", "nbr_sh"):
+        # the tuned form may lay vertices out differently: same cells to rounding
+        for k in ("nv", "ne", "nf", "fo", "status", "nbr_off", "nbr_ids", "nbr_sh"):
             assert np.array_equal(res[k], eager[k]), k
+        assert np.max(np.abs(res["vol"] - eager["vol"]) / eager["vol"]) <= 1e-13
+    for res in tuned_replays:
+        for k in FIELDS + ("nbr_off", "nbr_ids", "nbr_sh"):
+            assert np.array_equal(res[k], tuned_eager[k]), k
 
 
 def test_batch_f32_filter_bitwise(v):

@@ -135,12 +135,43 @@ def test_perturbed_fcc_near_degenerate(v):
     same_bits(g, f)
 
 
-def test_slots4_and_chunk_variants_agree(v):
+def same_cells(a, b, tol=1e-13):
+    """Same topology and neighbour lists; volumes and centroids to rounding
+    (different launch forms lay the vertices out differently, so the fan sums
+    run in a different order)."""
+    for k in ("nv", "ne", "nf", "fo", "status", "nbr_off", "nbr_ids", "nbr_sh"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.max(np.abs(a["vol"] - b["vol"]) / a["vol"]) <= tol
+    assert np.max(np.abs(a["cen"] - b["cen"]).max(1) / a["vol"] ** (1 / 3)) <= tol
+
+
+def test_launch_forms_agree(v):
+    """Slots, chunk, waves and cells per wave never change a cell; within one
+    form the FP32 filter is bitwise identical to FP64."""
     side = 3000 ** (1 / 3)
     x = W.uniform(3000, 3, side, 41)
     base = run(v, x, [0] * 3, [side] * 3, [1, 1, 1])
     for opt in (dict(slots=4), dict(chunk=1), dict(chunk=64), dict(waves=7)):
         same_bits(base, run(v, x, [0] * 3, [side] * 3, [1, 1, 1], **opt))
+    r = oracle.Oracle(x, [0] * 3, [side] * 3, [1, 1, 1]).cells()
+    for cpw in (2, 4):
+        g = run(v, x, [0] * 3, [side] * 3, [1, 1, 1], cells_per_wave=cpw)
+        same_cells(base, g)
+        assert_parity(g, r)
+        f = run(v, x, [0] * 3, [side] * 3, [1, 1, 1], cells_per_wave=cpw, precision=v.VC_F32_FILTER, chunk=1)
+        same_bits(g, f)
+
+
+@pytest.mark.parametrize("cpw", [2, 4])
+def test_grouped_forms_on_hard_inputs(v, cpw):
+    """Several cells per wave on the walled 1k set, exact lattices and the
+    near-degenerate perturbed FCC."""
+    w = W.walled_1k()
+    g = run(v, w["xyz"], w["lo"], w["hi"], w["periodic"], cells_per_wave=cpw)
+    assert_parity(g, oracle.Oracle(w["xyz"], w["lo"], w["hi"], w["periodic"]).cells())
+    for (x, hi) in [W.sc(5, 1.0), W.bcc(4, 2.0), W.fcc((3, 3, 4), 2.0), W.fcc((6, 6, 6), 1.0, 1e-3, seed=3)]:
+        g = run(v, x, [0] * 3, hi, [1, 1, 1], cells_per_wave=cpw)
+        assert_parity(g, oracle.Oracle(x, [0] * 3, hi, [1, 1, 1]).cells())
 
 
 def test_full_size_periodic_1m(v):
