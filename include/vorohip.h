@@ -55,7 +55,8 @@ enum {
     VC_NEIGHBORS = 16,      /* neighbour list, CSR (implies the counts' face count) */
     VC_NEIGHBOR_COUNT = 32, /* number of neighbours (faces) only */
     VC_DIAG = 64,           /* run counters (exact decisions, rechecks, spills, ...) */
-    VC_ALL = 127
+    VC_ALL = 127,           /* every field above */
+    VC_PERIMETER = 128      /* 2D only: cell perimeter */
 };
 
 /* result fields for vc_result_get / vc_result_copy */
@@ -72,7 +73,8 @@ enum {
     VC_F_NBR_SHIFTS = 8,  /* uint8[total]: periodic image code
                              25(s_z+2) + 5(s_y+2) + (s_x+2), 62 = no shift */
     VC_F_STATUS = 9,      /* uint8[n]: VC_CELL_* */
-    VC_F_DIAG = 10        /* int64[VC_DIAG_LEN] */
+    VC_F_DIAG = 10,       /* int64[VC_DIAG_LEN] */
+    VC_F_PERIMETER = 11   /* double[n], 2D */
 };
 #define VC_FO_LEN 32
 #define VC_DIAG_LEN 16

@@ -21,7 +21,8 @@
  * Representation: a convex polyhedron as a list of faces, each face a cyclic
  * list of vertex ids, counter-clockwise seen from outside.  A cut classifies
  * every vertex, clips each face (Sutherland-Hodgman), and closes the hole
- * with a new face chained from the cut segments of the clipped faces.
+ * with a new face chained from the cut segments of the clipped faces.  Each
+ * new vertex is placed at the intersection of its three defining planes.
  *
  * Side decisions: s = n.v - h in FP64; if |s| <= tau*M (M = sum|n_d v_d|+|h|)
  * the sign is taken exactly from the symbolic definition of the vertex (the
@@ -447,6 +448,35 @@ static void interp(const ocell *c, int a, int b, double *out)
     for (int d = 0; d < 3; d++) out[d] = c->v[a][d] + t * (c->v[b][d] - c->v[a][d]);
 }
 
+/* The point where three planes meet (Cramer's rule on n.r = h).  A new
+ * vertex is placed here from its defining planes rather than interpolated
+ * along the cut edge, so its rounding does not grow with the distance to
+ * earlier (possibly far-away) vertices. */
+static int solve3(const oplane *a, const oplane *b, const oplane *c, double *out)
+{
+    double bc[3] = {b->n[1] * c->n[2] - b->n[2] * c->n[1], b->n[2] * c->n[0] - b->n[0] * c->n[2],
+                    b->n[0] * c->n[1] - b->n[1] * c->n[0]};
+    double ca[3] = {c->n[1] * a->n[2] - c->n[2] * a->n[1], c->n[2] * a->n[0] - c->n[0] * a->n[2],
+                    c->n[0] * a->n[1] - c->n[1] * a->n[0]};
+    double ab[3] = {a->n[1] * b->n[2] - a->n[2] * b->n[1], a->n[2] * b->n[0] - a->n[0] * b->n[2],
+                    a->n[0] * b->n[1] - a->n[1] * b->n[0]};
+    double det = a->n[0] * bc[0] + a->n[1] * bc[1] + a->n[2] * bc[2];
+    if (det == 0.0) return 0;
+    for (int d = 0; d < 3; d++) out[d] = (a->h * bc[d] + b->h * ca[d] + c->h * ab[d]) / det;
+    return 1;
+}
+
+/* the point where two lines meet (2D) */
+static int solve2(const oplane *a, const oplane *b, double *out)
+{
+    double det = a->n[0] * b->n[1] - a->n[1] * b->n[0];
+    if (det == 0.0) return 0;
+    out[0] = (a->h * b->n[1] - a->n[1] * b->h) / det;
+    out[1] = (a->n[0] * b->h - a->h * b->n[0]) / det;
+    out[2] = 0.0;
+    return 1;
+}
+
 /* Cut the 3D cell by plane *P.  Returns 1 if it cut, 0 if not, <0 on error. */
 static int cut3(ocell *c, const oplane *P)
 {
@@ -515,6 +545,14 @@ static int cut3(ocell *c, const oplane *P)
         }
     }
     if (nseg < 3) return VO_ERR_TOPO;
+    /* new vertices from their three defining planes (the interpolated point
+     * is kept only if the planes were found singular) */
+    for (int x = nv0; x < c->nv; x++) {
+        if (c->vp[x][1] < 0) return VO_ERR_TOPO;
+        double w[3];
+        if (solve3(&c->pl[c->vp[x][0]], &c->pl[c->vp[x][1]], &c->pl[c->vp[x][2]], w))
+            memcpy(c->v[x], w, sizeof(w));
+    }
     /* drop emptied faces */
     int nf = 0;
     for (int f = 0; f < c->nf; f++) {
@@ -595,6 +633,10 @@ static int cut2(ocell *c, const oplane *P)
             c->vp[x][0] = line;
             c->vp[x][1] = pid;
             c->vp[x][2] = -1;
+            {
+                double pt[3];
+                if (solve2(&c->pl[line], &c->pl[pid], pt)) memcpy(c->v[x], pt, sizeof(pt));
+            }
             c->cnt[C_NEWV]++;
             nv_[m] = x;
             ne_[m] = (su < 0) ? pid : line;

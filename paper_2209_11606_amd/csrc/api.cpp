@@ -198,7 +198,7 @@ struct vc_result {
     uint32_t mask = 0;
     int64_t n = 0;
     int dim = 3;
-    double *vol = nullptr, *cen = nullptr;
+    double *vol = nullptr, *cen = nullptr, *perim = nullptr;
     int32_t *nv = nullptr, *ne = nullptr, *nf = nullptr;
     uint8_t *fo = nullptr;
     int32_t *nbr = nullptr;  // fixed-stride scratch
@@ -238,7 +238,7 @@ void free_container(vc_container *c)
 void free_result(vc_result *r)
 {
     if (!r) return;
-    void *ps[] = {r->vol, r->cen, r->nv, r->ne, r->nf, r->fo, r->nbr, r->nsh, r->off, r->ids, r->shifts,
+    void *ps[] = {r->vol, r->cen, r->perim, r->nv, r->ne, r->nf, r->fo, r->nbr, r->nsh, r->off, r->ids, r->shifts,
                   r->scan_tmp, r->status, r->diag};
     for (void *p : ps)
         if (p) (void)hipFree(p);
@@ -360,6 +360,7 @@ CellArgs cell_args(const vc_container *c, const vc_result *r)
     A.mask = r->mask;
     A.vol = r->vol;
     A.cen = r->cen;
+    A.perim = r->perim;
     A.nv = r->nv;
     A.ne = r->ne;
     A.nf = r->nf;
@@ -389,7 +390,8 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
     HIP_TRY(launch_fill_i32(c->queue, 4, 0, s));
     HIP_TRY(launch_fill_i32((int32_t *)r->diag, VC_DIAG_LEN * 2, 0, s));
     if (events) HIP_TRY(hipEventRecord(r->ev0, s));
-    if (L.cpw > 1) HIP_TRY(launch_cells_group(A, c->precision, L.cpw, std::min(L.waves, c->max_waves), s));
+    if (c->dim == 2) HIP_TRY(launch_cells2d(A, c->precision, std::min(L.waves, c->max_waves), s));
+    else if (L.cpw > 1) HIP_TRY(launch_cells_group(A, c->precision, L.cpw, std::min(L.waves, c->max_waves), s));
     else HIP_TRY(launch_cells(A, c->precision, L.slots, std::min(L.waves, c->max_waves), s));
     if (events) HIP_TRY(hipEventRecord(r->ev1, s));
     // cells beyond the main kernel's capacity: large-capacity pass over the
@@ -400,7 +402,8 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
     B.ncell_dev = c->queue + 2;
     B.ncell = (int)c->n;
     B.chunk = 1;
-    HIP_TRY(launch_cells_spill(B, std::min(c->max_waves, 1024), s));
+    if (c->dim == 2) HIP_TRY(launch_cells2d_spill(B, std::min(c->max_waves, 1024), s));
+    else HIP_TRY(launch_cells_spill(B, std::min(c->max_waves, 1024), s));
     if ((r->mask & VC_NEIGHBORS) && !cell_list) {
         // CSR offsets by a scan of the face counts, then each cell's sorted
         // labels copied to its offset (capacity n * kMaxNbr always suffices)
@@ -416,7 +419,8 @@ vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
     if (!out) return fail(VC_E_ARG, "result_create: out is null");
     *out = nullptr;
     if (!c) return fail(VC_E_ARG, "result_create: container is null");
-    if (mask & ~(uint32_t)VC_ALL) return fail(VC_E_ARG, "result_create: unknown mask bits 0x%x", mask);
+    if (mask & ~(uint32_t)(VC_ALL | VC_PERIMETER)) return fail(VC_E_ARG, "result_create: unknown mask bits 0x%x", mask);
+    if ((mask & VC_PERIMETER) && c->dim != 2) return fail(VC_E_ARG, "result_create: the perimeter is a 2D field");
     vc_result *r = new (std::nothrow) vc_result();
     if (!r) return fail(VC_E_NOMEM, "host allocation failed");
     r->c = c;
@@ -435,6 +439,7 @@ vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
     } while (0)
     if (mask & VC_VOLUME) TRY(dalloc(&r->vol, n));
     if (mask & VC_CENTROID) TRY(dalloc(&r->cen, (size_t)n * 3));
+    if (mask & VC_PERIMETER) TRY(dalloc(&r->perim, n));
     if (mask & VC_COUNTS) {
         TRY(dalloc(&r->nv, n));
         TRY(dalloc(&r->ne, n));
@@ -489,7 +494,6 @@ vc_status vc_container_create(const double *xyz, int64_t n, const vc_options *op
     if (n > (int64_t)INT32_MAX / 2) return fail(VC_E_ARG, "vc_container_create: n too large");
     vc_status st = check_options(opt);
     if (st) return st;
-    if (opt->dim != 3) return fail(VC_E_ARG, "vc_container_create: only dim 3 is built in this library version");
     vc_container *c = new (std::nothrow) vc_container();
     if (!c) return fail(VC_E_NOMEM, "host allocation failed");
     int64_t offsets[2] = {0, n};
@@ -552,6 +556,7 @@ vc_status vc_result_get(vc_result *r, int field, void **dev_ptr, int64_t *count)
     }
     case VC_F_STATUS: p = r->status; k = n; break;
     case VC_F_DIAG: p = r->diag; k = VC_DIAG_LEN; break;
+    case VC_F_PERIMETER: p = r->perim; k = n; break;
     default: return fail(VC_E_ARG, "vc_result_get: unknown field %d", field);
     }
     if (!p) return fail(VC_E_STATE, "field %d was not requested in the statistics mask", field);
@@ -567,7 +572,7 @@ vc_status vc_result_copy(vc_result *r, int field, void *host_dst, int64_t bytes)
     int64_t k;
     vc_status st = vc_result_get(r, field, &p, &k);
     if (st) return st;
-    static const int esz[] = {8, 8, 4, 4, 4, 1, 8, 4, 1, 1, 8};
+    static const int esz[] = {8, 8, 4, 4, 4, 1, 8, 4, 1, 1, 8, 8};
     int64_t need = k * esz[field];
     if (bytes < need) return fail(VC_E_ARG, "vc_result_copy: need %lld bytes, got %lld", (long long)need, (long long)bytes);
     HIP_TRY(hipStreamSynchronize(r->last_stream));
@@ -706,6 +711,6 @@ void vc_batch_destroy(vc_batch *b) { free_container(b); }
 
 const char *vc_last_error(void) { return g_err.c_str(); }
 
-const char *vc_version(void) { return "vorohip 0.2 (gfx950)"; }
+const char *vc_version(void) { return "vorohip 0.3 (gfx950)"; }
 
 }  // extern "C"

@@ -136,6 +136,64 @@ __device__ __noinline__ int exact_side3(PlaneD a, PlaneD b, PlaneD c, PlaneD p, 
     return s4 * s3;
 }
 
+// Exact sign of n_p.v - h_p at the 2D vertex v = lines a, b:
+//   s * D(a,b) = -h_a D(b,p) + h_b D(a,p) - h_p D(a,b),  D = 2x2 determinant.
+__device__ int xs_acc_hdet2(double *acc, int n, const double *hl, int nh, double sgn, const double *u,
+                            const double *v)
+{
+    double t[4];
+    xs_two_prod(sgn * u[0], v[1], t[0], t[1]);
+    xs_two_prod(-sgn * u[1], v[0], t[2], t[3]);
+    for (int a = 0; a < 4; a++) {
+        if (t[a] == 0.0) continue;
+        for (int b = 0; b < nh; b++) {
+            if (hl[b] == 0.0) continue;
+            n = xs_add_prod(acc, n, t[a], hl[b]);
+        }
+    }
+    return n;
+}
+
+__device__ inline int xs_offset2(const PlaneD &p, double *out)
+{
+    if (p.wall) {
+        out[0] = p.h;
+        return 1;
+    }
+    double v[2] = {p.n0, p.n1};
+    int k = 0;
+    for (int d = 0; d < 2; d++) {
+        double x, y;
+        xs_two_prod(v[d], v[d], x, y);
+        out[k++] = 0.5 * x;
+        out[k++] = 0.5 * y;
+    }
+    return k;
+}
+
+__device__ __noinline__ int exact_side2(PlaneD a, PlaneD b, PlaneD p, double *ws)
+{
+    const PlaneD *r[3] = {&a, &b, &p};
+    double nv[3][2];
+    for (int i = 0; i < 3; i++) {
+        nv[i][0] = r[i]->n0;
+        nv[i][1] = r[i]->n1;
+    }
+    const int mi[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+    const double sg[3] = {-1.0, 1.0, -1.0};
+    double hl[4];
+    int n = 0;
+    for (int i = 0; i < 3; i++) {
+        int nh = xs_offset2(*r[i], hl);
+        n = xs_acc_hdet2(ws, n, hl, nh, sg[i], nv[mi[i][0]], nv[mi[i][1]]);
+    }
+    int s3 = n ? xs_sign(ws, n) : 0;
+    double one = 1.0;
+    int m = xs_acc_hdet2(ws, 0, &one, 1, 1.0, nv[0], nv[1]);
+    int s2 = m ? xs_sign(ws, m) : 0;
+    return s3 * s2;
+}
+
 #pragma clang fp contract(fast)
 
 // ---------------------------------------------------------------------------
@@ -268,6 +326,15 @@ __device__ __forceinline__ int ballot_excl_scan(int v, int &total)
 }
 
 // vertex of planes A, B, C by Cramer's rule
+// vertex of lines A, B (n.r = h, rows n0 n1 h) by Cramer's rule
+__device__ __forceinline__ void cramer2(const double *A, const double *B, double &x, double &y)
+{
+    double det = A[0] * B[1] - A[1] * B[0];
+    double inv = 1.0 / det;
+    x = (A[2] * B[1] - A[1] * B[2]) * inv;
+    y = (A[0] * B[2] - A[2] * B[0]) * inv;
+}
+
 __device__ __forceinline__ void cramer(const double *A, const double *B, const double *C, double &x, double &y, double &z)
 {
     double bc0 = B[1] * C[2] - B[2] * C[1], bc1 = B[2] * C[0] - B[0] * C[2], bc2 = B[0] * C[1] - B[1] * C[0];

@@ -78,6 +78,7 @@ struct CellArgs {
     // outputs, by particle id
     double *vol;
     double *cen;
+    double *perim;             // 2D
     int32_t *nv, *ne, *nf;
     uint8_t *fo;
     int32_t *nbr;              // id * kMaxNbr + k
@@ -102,6 +103,8 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_cells(const CellArgs &a, int precision, int slots, int waves, hipStream_t s);
 hipError_t launch_cells_spill(const CellArgs &a, int waves, hipStream_t s);
 hipError_t launch_cells_group(const CellArgs &a, int precision, int cells_per_wave, int waves, hipStream_t s);
+hipError_t launch_cells2d(const CellArgs &a, int precision, int waves, hipStream_t s);
+hipError_t launch_cells2d_spill(const CellArgs &a, int waves, hipStream_t s);
 hipError_t launch_nbr_compact(const int32_t *nf, int64_t n, const int32_t *nbr, const uint8_t *nsh,
                               int64_t *offsets, int32_t *ids, uint8_t *shifts, int32_t *tmp, hipStream_t s);
 hipError_t launch_nbr_offsets(const int32_t *nf, int64_t n, int64_t *offsets, int32_t *tmp, hipStream_t s);

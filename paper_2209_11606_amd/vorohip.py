@@ -17,14 +17,15 @@ VC_OK, VC_E_ARG, VC_E_RANGE, VC_E_DUPLICATE, VC_E_NOMEM, VC_E_HIP, VC_E_CAPACITY
 VC_FP64, VC_F32_FILTER = 0, 1
 VC_VOLUME, VC_CENTROID, VC_COUNTS, VC_FACE_ORDERS, VC_NEIGHBORS, VC_NEIGHBOR_COUNT, VC_DIAG = 1, 2, 4, 8, 16, 32, 64
 VC_ALL = 127
+VC_PERIMETER = 128
 (VC_F_VOLUME, VC_F_CENTROID, VC_F_NV, VC_F_NE, VC_F_NF, VC_F_FACE_ORDERS, VC_F_NBR_OFFSETS, VC_F_NBR_IDS,
- VC_F_NBR_SHIFTS, VC_F_STATUS, VC_F_DIAG) = range(11)
+ VC_F_NBR_SHIFTS, VC_F_STATUS, VC_F_DIAG, VC_F_PERIMETER) = range(12)
 VC_FO_LEN = 32
 VC_DIAG_LEN = 16
 DIAG_NAMES = ["candidates", "tests", "cuts", "new_vertices", "exact", "recheck", "spilled", "blocks", "fallback"]
 _FIELD_DTYPE = {VC_F_VOLUME: np.float64, VC_F_CENTROID: np.float64, VC_F_NV: np.int32, VC_F_NE: np.int32,
                 VC_F_NF: np.int32, VC_F_FACE_ORDERS: np.uint8, VC_F_NBR_OFFSETS: np.int64, VC_F_NBR_IDS: np.int32,
-                VC_F_NBR_SHIFTS: np.uint8, VC_F_STATUS: np.uint8, VC_F_DIAG: np.uint64}
+                VC_F_NBR_SHIFTS: np.uint8, VC_F_STATUS: np.uint8, VC_F_DIAG: np.uint64, VC_F_PERIMETER: np.float64}
 
 
 class vc_options(ctypes.Structure):
@@ -222,6 +223,8 @@ def fetch(r, mask, n, dim=3):
         out["vol"] = vc_result_copy(r, VC_F_VOLUME)
     if mask & VC_CENTROID:
         out["cen"] = vc_result_copy(r, VC_F_CENTROID).reshape(n, 3)[:, :dim]
+    if mask & VC_PERIMETER:
+        out["perim"] = vc_result_copy(r, VC_F_PERIMETER)
     if mask & VC_COUNTS:
         out["nv"] = vc_result_copy(r, VC_F_NV)
         out["ne"] = vc_result_copy(r, VC_F_NE)

@@ -55,6 +55,20 @@ def test_brute_force_2d(per):
         _same_cell(r, i, brute.cell(x, i, [0] * 2, [1] * 2, per))
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_brute_force_scale(dim):
+    """A tight cluster (side 1e-5) in the walled unit box: inner cells are
+    ~1e-15 of the box volume, outer ones reach the walls.  Vertex rounding
+    must not grow with the box size (interpolating new vertices along edges
+    from the box corners would be off by ~1e-11 here)."""
+    u = W.uniform(30, dim, 1.0, 23)
+    x = 0.5 + 1e-5 * u
+    o = oracle.Oracle(x, [0] * dim, [1] * dim, [0] * dim)
+    r = o.cells()
+    for i in range(30):
+        _same_cell(r, i, brute.cell(x, i, [0] * dim, [1] * dim, [0] * dim))
+
+
 def test_brute_force_nonunit_box():
     """A box with non-unit, unequal sides and an offset origin."""
     lo, hi = [-1.5, 2.0, 0.25], [0.5, 2.75, 1.75]
