@@ -44,8 +44,9 @@ def parse():
     p.add_argument("--calibration-copy-mib", type=int, default=0,
                    help="first copy a device buffer of this size (reference for HBM byte counters)")
     p.add_argument("--variants", default="all", help="comma list of variants to run (default all)")
-    p.add_argument("--workload", default="periodic1m", choices=["periodic1m", "batch4096"],
-                   help="periodic1m: the metric's configuration (default); batch4096: the batched set")
+    p.add_argument("--workload", default="periodic1m",
+                   choices=["periodic1m", "batch4096", "fcc10m", "periodic2d10m", "periodic102m"],
+                   help="periodic1m: the metric's configuration (default); the others measure the remaining sets")
     return p.parse_args()
 
 
@@ -61,12 +62,12 @@ def _timed(torch, stream, steps, step_fn):
     return t0.elapsed_time(t1) / steps
 
 
-def time_variant(v, torch, xt, w, precision, steps, warmup):
+def time_variant(v, torch, xt, w, precision, steps, warmup, mask):
     """Plain form: one container; step = rebin + compute."""
     stream = torch.cuda.current_stream()
-    o = v.vc_options_init(3, w["lo"], w["hi"], w["periodic"], precision=precision)
+    o = v.vc_options_init(xt.shape[1], w["lo"], w["hi"], w["periodic"], precision=precision)
     c = v.vc_container_create(xt, o, stream)
-    r = v.vc_result_create(c, v.VC_ALL)
+    r = v.vc_result_create(c, mask)
     kms = []
 
     def step():
@@ -85,14 +86,14 @@ def time_variant(v, torch, xt, w, precision, steps, warmup):
     return out
 
 
-def time_batched(v, torch, xt, offsets, opts, steps, warmup):
+def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask):
     """Batched form: autotuned launch parameters, compute replayed from a
     hipGraph; step = rebin + graph launch.  The cell-kernel duration for the
     roofline comes from eager launches with the same parameters."""
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     b = v.vc_batch_create(xt, offsets, opts, stream)
-    r = v.vc_batch_result_create(b, v.VC_ALL)
+    r = v.vc_batch_result_create(b, mask)
     try:
         tuned = v.vc_batch_tune(b, r, stream)
         kms = []
@@ -120,9 +121,7 @@ def time_batched(v, torch, xt, offsets, opts, steps, warmup):
 def _summary(v, r, ms, kernel_ms):
     status = v.vc_result_copy(r, v.VC_F_STATUS)
     diag = dict(zip(v.DIAG_NAMES, v.vc_result_copy(r, v.VC_F_DIAG)[:len(v.DIAG_NAMES)].tolist()))
-    vol = v.vc_result_copy(r, v.VC_F_VOLUME)
-    return dict(ms_per_step=ms, kernel_ms=kernel_ms, status_ok=bool(np.all(status <= 1)),
-                vol_sum=float(np.sum(vol)), diag=diag)
+    return dict(ms_per_step=ms, kernel_ms=kernel_ms, status_ok=bool(np.all(status <= 1)), diag=diag)
 
 
 def cpu_baseline(members, sample):
@@ -170,6 +169,19 @@ def main():
         members = [w]
         desc = ("periodic_uniform_1M: 1,000,000 uniform particles, periodic cube side 100, full statistics")
         sample_desc = "first {} cells of the same 1M-particle periodic set"
+    elif a.workload == "fcc10m":
+        members = [W.fcc_10m()]
+        desc = "fcc_perturbed_10M: perturbed FCC (sigma 1e-3 a), 10,000,000 particles, periodic, full statistics"
+        sample_desc = "first {} cells of the perturbed FCC set"
+    elif a.workload == "periodic2d10m":
+        members = [W.periodic_2d_10m()]
+        desc = "periodic_uniform_2d_10M: 10,000,000 uniform particles, periodic unit square, full statistics"
+        sample_desc = "first {} cells of the 2D set"
+    elif a.workload == "periodic102m":
+        members = [W.periodic_102m()]
+        desc = ("periodic_uniform_102M: 102,400,000 uniform particles, periodic unit cube, "
+                "face-order vector and neighbour count only")
+        sample_desc = "first {} cells of the 102.4M set"
     else:
         members = W.batch(4096)
         desc = ("batch_4096: 4,096 independent 3D tessellations, sizes log-uniform in [100, 100000], "
@@ -189,24 +201,29 @@ def main():
     torch.cuda.synchronize()
     res = {}
     variants = []
+    dim = xyz.shape[1]
+    mask = v.VC_FACE_ORDERS | v.VC_NEIGHBOR_COUNT if a.workload == "periodic102m" else v.VC_ALL
     if len(members) == 1:
         variants += [("fp64", v.VC_FP64, False), ("f32_filter", v.VC_F32_FILTER, False)]
-    variants += [("fp64_batched", v.VC_FP64, True), ("f32_filter_batched", v.VC_F32_FILTER, True)]
+    if dim == 3:
+        variants += [("fp64_batched", v.VC_FP64, True), ("f32_filter_batched", v.VC_F32_FILTER, True)]
     if a.variants != "all":
         keep = set(a.variants.split(","))
         variants = [x for x in variants if x[0] in keep]
     for name, prec, batched in variants:
         if batched:
             opts = [v.vc_options_init(3, m["lo"], m["hi"], m["periodic"], precision=prec) for m in members]
-            res[name] = time_batched(v, torch, xt, offsets, opts, a.steps, a.warmup)
+            res[name] = time_batched(v, torch, xt, offsets, opts, a.steps, a.warmup, mask)
         else:
-            res[name] = time_variant(v, torch, xt, members[0], prec, a.steps, a.warmup)
+            res[name] = time_variant(v, torch, xt, members[0], prec, a.steps, a.warmup, mask)
         print(f"# {name}: {res[name]['ms_per_step']:.3f} ms/step, cell kernel {res[name]['kernel_ms']:.3f} ms, "
               f"tuned {res[name].get('tuned')}, diag {res[name]['diag']}", file=sys.stderr, flush=True)
     if a.no_cpu_baseline:
         cpu, flops_per_cell = None, None
     else:
         cpu, flops_per_cell, per_cell = cpu_baseline(members, a.cpu_sample)
+        if dim == 2:
+            flops_per_cell = None  # the flop model is the 3D one
         cpu["sample"] = sample_desc.format(min(a.cpu_sample, n)) + ", OpenMP dynamic,64 over cells"
         print(f"# oracle: {cpu['value']:.0f} cells/s on {cpu['cores']} cores; per cell {per_cell}",
               file=sys.stderr, flush=True)
@@ -220,7 +237,8 @@ def main():
                     frac=achieved / FP64_VECTOR_PEAK, traffic=None, kernel="k_cells (cell construction)",
                     flops_per_cell=flops_per_cell, kernel_ms=b["kernel_ms"])
     out = {
-        "metric": "3D Voronoi cells/s on 1 MI355X, FP32-filter vs FP64 plain; oracle-exact topology",
+        "metric": ("3D" if dim == 3 else "2D") + " Voronoi cells/s on 1 MI355X, FP32-filter vs FP64 plain; "
+                  "oracle-exact topology",
         "value": value,
         "unit": "cells/s",
         "n_gpus": 1,
