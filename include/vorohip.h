@@ -116,7 +116,7 @@ typedef struct vc_batch vc_batch;
 vc_status vc_options_init(vc_options *opt, int dim, const double *lo, const double *hi, const int *periodic);
 
 /* Create a container and bin the particles into its grid of blocks
- * (section 2.1.1; the atomic slot capture of section 2.2.4 becomes a counting
+ * (section 2.1.1; the atomic slot capture of section 2.2.5 becomes a counting
  * sort).  xyz: n x dim doubles, particle-major, host or device.  A walled
  * axis requires lo <= x <= hi, a periodic axis lo <= x < hi; otherwise
  * VC_E_RANGE.  The library copies the positions; the caller keeps ownership
@@ -127,11 +127,23 @@ vc_status vc_container_create(const double *xyz, int64_t n, const vc_options *op
                               vc_container **out);
 
 /* Re-bin new positions of the same count into an existing container (the
- * container re-use of section 3.3): no allocation.  Same range rules and
+ * container clearing and re-use of section 3.2): no allocation.  Same range rules and
  * errors as vc_container_create; synchronises `stream` once to read the
  * range check.  On VC_E_RANGE the container holds the rejected positions and
  * must be re-binned before the next vc_compute. */
 vc_status vc_container_rebin(vc_container *c, const double *xyz, void *stream);
+
+/* Block counts the library uses for n particles in the box of *opt
+ * (section 2.1.4: lambda = (N/(N_opt V))^(1/d), n_d = ceil(lambda L_d),
+ * unless opt->grid is set).  Host only: touches no GPU.  grid_out[3]
+ * receives the counts (1 on unused axes). */
+vc_status vc_grid_size(const vc_options *opt, int64_t n, int *grid_out);
+
+/* Copy the container's binning to host memory (synchronous): block_start
+ * (nb + 1 int32, nb = product of the block counts, summed over tessellations
+ * for a batch; pass NULL to skip) and the input ids in block-sorted order
+ * (n int32; NULL to skip).  nb_out (may be NULL) receives nb. */
+vc_status vc_container_blocks(const vc_container *c, int32_t *block_start, int32_t *sorted_ids, int64_t *nb_out);
 
 /* Allocate a result for a container and a statistics mask (VC_* bits).  The
  * result owns device arrays sized for the container; it can be filled many
@@ -182,7 +194,7 @@ vc_status vc_batch_rebin(vc_batch *b, const double *xyz_concat, void *stream);
 vc_status vc_batch_result_create(const vc_batch *b, uint32_t mask, vc_result **out);
 
 /* Compute every cell of every tessellation in one persistent launch over a
- * device work queue (the dynamic schedule of section 2.2.3, on the GPU).  If
+ * device work queue (the dynamic schedule of section 2.2.4, on the GPU).  If
  * `graph` is nonzero the launch sequence is captured once into a hipGraph on
  * `stream` (which must not be the null stream) and replayed by later calls
  * with the same result and stream.  Asynchronous. */

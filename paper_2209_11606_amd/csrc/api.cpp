@@ -517,6 +517,32 @@ vc_status vc_result_create(const vc_container *c, uint32_t mask, vc_result **out
     return result_create(c, mask, out);
 }
 
+vc_status vc_grid_size(const vc_options *opt, int64_t n, int *grid_out)
+{
+    if (!grid_out) return fail(VC_E_ARG, "vc_grid_size: null output");
+    if (n < 1) return fail(VC_E_ARG, "vc_grid_size: n must be >= 1");
+    vc_status st = check_options(opt);
+    if (st) return st;
+    Grid G = size_grid(*opt, n);
+    for (int d = 0; d < 3; d++) grid_out[d] = G.g[d];
+    return VC_OK;
+}
+
+vc_status vc_container_blocks(const vc_container *c, int32_t *block_start, int32_t *sorted_ids, int64_t *nb_out)
+{
+    if (!c) return fail(VC_E_ARG, "vc_container_blocks: null container");
+    if (nb_out) *nb_out = c->nb;
+    HIP_TRY(hipDeviceSynchronize());
+    if (block_start)
+        HIP_TRY(hipMemcpy(block_start, c->start, (size_t)(c->nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (sorted_ids) {
+        std::vector<Particle> p((size_t)c->n);
+        HIP_TRY(hipMemcpy(p.data(), c->part, p.size() * sizeof(Particle), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < p.size(); i++) sorted_ids[i] = p[i].id;
+    }
+    return VC_OK;
+}
+
 vc_status vc_compute(vc_container *c, vc_result *r, void *stream)
 {
     if (!c || !r) return fail(VC_E_ARG, "vc_compute: null handle");

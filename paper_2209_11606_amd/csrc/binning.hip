@@ -3,7 +3,7 @@
 // particle array, and a deterministic in-block order (by input id).
 //
 // This replaces the serial put() and the atomic slot capture of the paper's
-// parallel insertion (section 2.2.4): the atomic counter gives each particle
+// parallel insertion (section 2.2.5): the atomic counter gives each particle
 // a slot, and an exact prefix sum over the counts sizes every block, so no
 // overflow buffer is needed.  Sorting each block by id removes the run-to-run
 // order dependence that the paper notes for parallel insertion.

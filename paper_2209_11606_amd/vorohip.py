@@ -57,6 +57,8 @@ def _load():
         "vc_container_create": (I32, [P, I64, P, P, P]),
         "vc_container_rebin": (I32, [P, P, P]),
         "vc_result_create": (I32, [P, U32, P]),
+        "vc_grid_size": (I32, [P, I64, P]),
+        "vc_container_blocks": (I32, [P, P, P, P]),
         "vc_compute": (I32, [P, P, P]),
         "vc_result_get": (I32, [P, I32, P, P]),
         "vc_result_copy": (I32, [P, I32, P, I64]),
@@ -80,7 +82,8 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_result_create", "vc_compute",
+EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_grid_size", "vc_container_blocks",
+            "vc_result_create", "vc_compute",
             "vc_result_get", "vc_result_copy", "vc_result_kernel_ms", "vc_result_destroy", "vc_container_destroy", "vc_batch_create",
             "vc_batch_rebin", "vc_batch_result_create", "vc_batch_compute", "vc_batch_tune", "vc_batch_destroy",
             "vc_last_error", "vc_version"]
@@ -139,6 +142,21 @@ def vc_container_create(xyz, opts, stream=None):
 def vc_container_rebin(c, xyz, stream=None):
     ptr = xyz.data_ptr() if hasattr(xyz, "data_ptr") else xyz.ctypes.data
     _check(_lib.vc_container_rebin(c, ctypes.c_void_p(ptr), ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def vc_grid_size(opts, n):
+    g = (ctypes.c_int * 3)()
+    _check(_lib.vc_grid_size(ctypes.byref(opts), int(n), g))
+    return list(g)
+
+
+def vc_container_blocks(c, n):
+    nb = ctypes.c_int64()
+    _check(_lib.vc_container_blocks(c, None, None, ctypes.byref(nb)))
+    start = np.empty(nb.value + 1, np.int32)
+    ids = np.empty(n, np.int32)
+    _check(_lib.vc_container_blocks(c, start.ctypes.data, ids.ctypes.data, None))
+    return start, ids
 
 
 def vc_result_create(c, mask):

@@ -6,7 +6,7 @@ the oracle-based tests can use it.
 
 All draws come from numpy's Philox counter-based generator with an explicit
 seed.  The paper's own inputs are ``rand()`` uniform draws (section 3.1 and
-the listing of section 2.2.2), which cannot be reproduced; these stand in.
+the example listing of section 2.2.3), which cannot be reproduced; these stand in.
 """
 import math
 

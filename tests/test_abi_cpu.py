@@ -70,3 +70,22 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(os.path, "exists", lambda p: False if p.endswith("libvorohip.so") else True)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+def test_grid_rule_host():
+    """The library's grid sizing (section 2.1.4, ceiling rule) on the host,
+    against the plain formula."""
+    import math
+    v = _lib()
+    for dim, n, side, nopt in [(3, 1000, 1.0, 5.0), (3, 1_000_000, 100.0, 5.0), (2, 10_000_000, 1.0, 5.0),
+                               (3, 102_400_000, 1.0, 5.0), (3, 10, 1.0, 5.0), (2, 100_000, 1.0, 3.4),
+                               (3, 100_000_000, 1.0, 4.6)]:
+        o = v.vc_options_init(dim, [0.0] * dim, [side] * dim, [1] * dim, n_opt=nopt)
+        g = v.vc_grid_size(o, n)
+        lam = (n / (nopt * side ** dim)) ** (1.0 / dim)
+        want = [max(1, math.ceil(lam * side))] * dim + [1] * (3 - dim)
+        assert g == want, (dim, n, g, want)
+    o = v.vc_options_init(3, [0, 0, 0], [2.0, 1.0, 0.5], [0, 0, 0], grid=[7, 3, 2])
+    assert v.vc_grid_size(o, 12345) == [7, 3, 2]
+    o = v.vc_options_init(3, [0, 0, 0], [4.0, 1.0, 0.5], [0, 0, 0])
+    assert v.vc_grid_size(o, 2000) == [math.ceil((2000 / 10) ** (1 / 3) * s) for s in (4.0, 1.0, 0.5)]
