@@ -1,18 +1,32 @@
-// cell3d_group.hip -- the 3D cell kernel with several cells per wavefront.
+// cell3d_group.hip -- the 3D cell kernel with several cells per wavefront and
+// synchronised cuts.
 //
-// The algorithm is the one of cell3d.hip (dual triangle cells, ballot side
-// tests with an exact fallback, cuts that re-triangulate the conflict region,
-// nearest-first candidates with the radius bound, fan statistics); only the
-// mapping differs: each cell is owned by a group of G lanes (G = 16 or 32,
-// so 64/G cells per wave) and every cross-lane step stays inside the group:
-// ballots are read through the group's bit field, reductions and scans use
-// DPP row operations (plus one lane exchange across rows for G = 32), and
-// the groups share the wave's instruction stream.  Per-cell work that is the
-// same for every lane of a cell (candidate selection, plane bookkeeping,
-// radius updates, statistics reductions) is thus issued once for 64/G cells.
+// The method is the one of cell3d.hip: a cell is a set of dual triangles
+// (one per vertex, three plane ids each) with an edge table in LDS; a
+// candidate plane (the bisector of Eq. 3) is tested against every vertex
+// with a ballot, in-band vertices are decided exactly, and a cut replaces the
+// conflict region by a fan of new triangles around the new plane.  The
+// candidates come from the grid blocks in nearest-first order (section
+// 2.1.3) and the search ends by the radius bound (section 2.1.3).
 //
-// Groups take different control paths, so LDS hand-offs use a workgroup-scope
-// fence (one wave per workgroup) instead of a barrier.
+// Mapping.  A cell is owned by a group of G lanes (G = 16 or 32, so 64/G
+// cells share a wavefront).  Each group runs a small state machine:
+//
+//   NEW -> GATHER -> BATCH -> TEST -> (CUT -> TEST)* -> ... -> STATS -> NEW
+//
+// GATHER reads the particle counts of up to G blocks, BATCH loads up to G
+// particles, keeps those inside the radius bound and sorts them by distance
+// (a rank count over the group's keys), TEST takes the sorted candidates one
+// at a time, and a conflict parks the group in CUT.  The cut itself (the
+// costliest step) runs only once no group of the wave can advance without
+// one, so that the cuts of the wave's cells run in the same instructions
+// instead of one after another.  STATS (volume, centroid, counts, face
+// orders, neighbours) is deferred in the same way.
+//
+// All masks are the group's bit fields (32 bits), reductions are DPP row
+// operations plus one swizzle across the two rows of a 32-lane group.  Each
+// group is one workgroup's slice of LDS; LDS hand-offs use a workgroup-scope
+// fence (one wave per workgroup).
 #include "cell_common.h"
 
 namespace vc {
@@ -20,51 +34,44 @@ namespace vc {
 namespace {
 
 template <int G>
-struct Grp {
+struct Gw {
     static constexpr int CPW = 64 / G;
-    static constexpr unsigned long long MASK = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    static constexpr uint32_t FULL = G >= 32 ? 0xffffffffu : ((1u << G) - 1u);
 };
 
-__device__ __forceinline__ void lds_sync()
+enum { PH_NEW, PH_GATHER, PH_BATCH, PH_TEST, PH_CUT, PH_STATS, PH_DONE };
+
+__device__ __forceinline__ void lds_fence()
 {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
 }
 
+// the group's bits of a wave ballot
 template <int G>
-__device__ __forceinline__ unsigned long long gballot(bool p, int gb)
+__device__ __forceinline__ uint32_t gbal(bool p, int gb)
 {
-    return (__ballot(p) >> gb) & Grp<G>::MASK;
+    unsigned long long b = __builtin_amdgcn_ballot_w64(p);
+    if (G == 32) return gb ? (uint32_t)(b >> 32) : (uint32_t)b;
+    return (uint32_t)(b >> gb) & Gw<G>::FULL;
 }
 
-__device__ __forceinline__ int grank(unsigned long long m, int gl)
+// lane i of a 32-lane group exchanges with lane i ^ 16
+__device__ __forceinline__ int swz16(int v)
 {
-    return __popcll(m & ((1ull << gl) - 1ull));
-}
-
-// reductions over the group; every lane of the group gets the result
-template <int G>
-__device__ __forceinline__ double gmax(double v)
-{
-    v = fmax(v, dpp_f64<DPP_QUAD_1032, 0xf>(v, v));
-    v = fmax(v, dpp_f64<DPP_QUAD_2301, 0xf>(v, v));
-    v = fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR, 0xf>(v, v));
-    v = fmax(v, dpp_f64<DPP_ROW_MIRROR, 0xf>(v, v));
-    if (G >= 32) v = fmax(v, __shfl_xor(v, 16));
-    if (G >= 64) v = fmax(v, __shfl_xor(v, 32));
-    return v;
+    return __builtin_amdgcn_ds_swizzle(v, 0x401f);
 }
 
 template <int G>
-__device__ __forceinline__ double gsum(double v)
+__device__ __forceinline__ uint32_t gmax_u32(uint32_t v)
 {
-    v = v + dpp_f64<DPP_QUAD_1032, 0xf>(0.0, v);
-    v = v + dpp_f64<DPP_QUAD_2301, 0xf>(0.0, v);
-    v = v + dpp_f64<DPP_ROW_HALF_MIRROR, 0xf>(0.0, v);
-    v = v + dpp_f64<DPP_ROW_MIRROR, 0xf>(0.0, v);
-    if (G >= 32) v = v + __shfl_xor(v, 16);
-    if (G >= 64) v = v + __shfl_xor(v, 32);
-    return v;
+    int x = (int)v;
+    x = (int)max((uint32_t)x, (uint32_t)dpp_i32<DPP_QUAD_1032, 0xf>(x, x));
+    x = (int)max((uint32_t)x, (uint32_t)dpp_i32<DPP_QUAD_2301, 0xf>(x, x));
+    x = (int)max((uint32_t)x, (uint32_t)dpp_i32<DPP_ROW_HALF_MIRROR, 0xf>(x, x));
+    x = (int)max((uint32_t)x, (uint32_t)dpp_i32<DPP_ROW_MIRROR, 0xf>(x, x));
+    if (G >= 32) x = (int)max((uint32_t)x, (uint32_t)swz16(x));
+    return (uint32_t)x;
 }
 
 template <int G>
@@ -74,43 +81,25 @@ __device__ __forceinline__ int gisum(int v)
     v = v + dpp_i32<DPP_QUAD_2301, 0xf>(0, v);
     v = v + dpp_i32<DPP_ROW_HALF_MIRROR, 0xf>(0, v);
     v = v + dpp_i32<DPP_ROW_MIRROR, 0xf>(0, v);
-    if (G >= 32) v = v + __shfl_xor(v, 16);
-    if (G >= 64) v = v + __shfl_xor(v, 32);
+    if (G >= 32) v = v + swz16(v);
     return v;
 }
 
+// fixed combination order: the same sum on every run
 template <int G>
-__device__ __forceinline__ unsigned long long gmin_u64(unsigned long long v)
+__device__ __forceinline__ double gsum(double v)
 {
-    unsigned long long w;
-    w = dpp_u64<DPP_QUAD_1032, 0xf>(v, v);
-    v = w < v ? w : v;
-    w = dpp_u64<DPP_QUAD_2301, 0xf>(v, v);
-    v = w < v ? w : v;
-    w = dpp_u64<DPP_ROW_HALF_MIRROR, 0xf>(v, v);
-    v = w < v ? w : v;
-    w = dpp_u64<DPP_ROW_MIRROR, 0xf>(v, v);
-    v = w < v ? w : v;
+    v = v + dpp_f64<DPP_QUAD_1032, 0xf>(0.0, v);
+    v = v + dpp_f64<DPP_QUAD_2301, 0xf>(0.0, v);
+    v = v + dpp_f64<DPP_ROW_HALF_MIRROR, 0xf>(0.0, v);
+    v = v + dpp_f64<DPP_ROW_MIRROR, 0xf>(0.0, v);
     if (G >= 32) {
-        w = __shfl_xor(v, 16);
-        v = w < v ? w : v;
+        unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        unsigned lo = (unsigned)swz16((int)(unsigned)u), hi = (unsigned)swz16((int)(unsigned)(u >> 32));
+        double w = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+        // both rows add the same two partial sums in the same order
+        v = (threadIdx.x & 16) ? w + v : v + w;
     }
-    if (G >= 64) {
-        w = __shfl_xor(v, 32);
-        v = w < v ? w : v;
-    }
-    return v;
-}
-
-template <int G>
-__device__ __forceinline__ unsigned long long gor_u64(unsigned long long v)
-{
-    v |= dpp_u64<DPP_QUAD_1032, 0xf>(0ull, v);
-    v |= dpp_u64<DPP_QUAD_2301, 0xf>(0ull, v);
-    v |= dpp_u64<DPP_ROW_HALF_MIRROR, 0xf>(0ull, v);
-    v |= dpp_u64<DPP_ROW_MIRROR, 0xf>(0ull, v);
-    if (G >= 32) v |= __shfl_xor(v, 16);
-    if (G >= 64) v |= __shfl_xor(v, 32);
     return v;
 }
 
@@ -123,56 +112,73 @@ __device__ __forceinline__ int gscan_incl(int v)
     v = v + dpp_i32<DPP_ROW_SHR4, 0xf>(0, v);
     v = v + dpp_i32<DPP_ROW_SHR8, 0xf>(0, v);
     if (G >= 32) v = v + dpp_i32<DPP_ROW_BCAST15, 0xa>(0, v);
-    if (G >= 64) v = v + dpp_i32<DPP_ROW_BCAST31, 0xc>(0, v);
     return v;
 }
 
-// exclusive prefix of small counts (< 2^BITS) inside the group
+// exclusive prefix of small counts (< 2^BITS) inside the group, by ballots
 template <int G, int BITS>
-__device__ __forceinline__ int gballot_scan(int v, int gb, int gl, int &total)
+__device__ __forceinline__ int gballot_scan(int v, int gb, uint32_t below, int &total)
 {
     int r = 0, t = 0;
 #pragma unroll
     for (int b = 0; b < BITS; b++) {
-        unsigned long long m = gballot<G>((v >> b) & 1, gb);
-        r += grank(m, gl) << b;
-        t += __popcll(m) << b;
+        uint32_t m = gbal<G>((v >> b) & 1, gb);
+        r += __popc(m & below) << b;
+        t += __popc(m) << b;
     }
     total = t;
     return r;
 }
 
-template <int G, int S, int MAXP>
-struct GLDS {
-    double pq[MAXP][4];
-    int32_t plab[MAXP];
-    uint8_t psh[MAXP];
-    uint8_t pwall[MAXP];
-    uint8_t etab[MAXP][MAXP];
-    union {
-        struct {
-            double pos[G * S][3];
-            uint32_t tpl[G * S];
-            int32_t lab[G * S];
-        } st;
-        struct {
-            double cq[G][4];
-            int32_t cid[G];
-            uint8_t ccode[G];
-            double npos[G][3];
-        } gc;
-    } u;
-    uint16_t bedge[G * S + 8];
-    int32_t cpre[G];
-    int32_t cbeg[G];
-    uint8_t csh[G];
-    int32_t forder[MAXP];
-    int32_t fref[MAXP];
-    int32_t fo[kFoLen];
+// search state of a group that only the phase steps read (kept in LDS to
+// leave registers for the side tests and cuts)
+struct GState {
+    double p[3];            // the particle
+    int bc[3];              // its block
+    int si, id;             // sorted index, input index
+    int shell;              // 0: offset list; r > 0: Chebyshev shell r
+    int cur;                // next offset index, or position in the shell
+    int gtot, gc0;          // candidates of the gather, next batch start
+    int cell, cend;         // claimed range of the work queue
+    uint32_t cnt[DC_N];     // counters other than candidates and tests
 };
 
 template <int G, int S, int MAXP>
-__device__ __forceinline__ PlaneD gplane(const GLDS<G, S, MAXP> &sh, int k)
+struct SL {
+    GState gs;
+    Tess T;                 // the cell's tessellation
+    double pq[MAXP][4];     // planes n.r = h (n = q for a bisector, h = |q|^2 / 2)
+    int32_t plab[MAXP];
+    uint8_t psh[MAXP];
+    uint8_t pwall[MAXP];
+    uint8_t etab[MAXP][MAXP];  // slot of the triangle holding directed edge a->b
+    union {
+        struct {               // the search
+            double cq[G][4];   // the batch's candidates, nearest first: q, |q|^2
+            int32_t cid[G];
+            int32_t cpre[G];   // the gather's blocks: candidates before, first particle, image code
+            int32_t cbeg[G];
+            uint8_t csh[G];
+            uint8_t ccode[G];
+            uint16_t bedge[G * S + 8];
+            union {
+                double npos[G][3];
+                unsigned long long key[G];
+            } x;
+        } w;
+        struct {               // the statistics of the finished cell
+            double pos[G * S][3];
+            uint32_t tpl[G * S];
+            int32_t lab[G * S];
+            int32_t forder[MAXP];
+            int32_t fref[MAXP];
+            int32_t fo[kFoLen];
+        } st;
+    } u;
+};
+
+template <int G, int S, int MAXP>
+__device__ __forceinline__ PlaneD splane(const SL<G, S, MAXP> &sh, int k)
 {
     PlaneD p;
     p.n0 = sh.pq[k][0];
@@ -183,350 +189,132 @@ __device__ __forceinline__ PlaneD gplane(const GLDS<G, S, MAXP> &sh, int k)
     return p;
 }
 
-// one cell, held by a group (all masks are the group's bit fields)
+// one cell and its search state, held by a group (values are the same on
+// every lane of the group, apart from the per-lane slots)
 template <int S, bool F32>
-struct GCell {
-    uint32_t tp[S];
-    double vx[S], vy[S], vz[S];
+struct SCell {
+    uint32_t tp[S];              // plane ids a | b << 8 | c << 16
+    double vx[S], vy[S], vz[S];  // vertex, relative to the particle
     float fx[S], fy[S], fz[S];
-    unsigned long long live[S];
-    unsigned long long used;  // plane slots in use (bit k)
-    double R2, R;
+    uint32_t live[S];            // live slots (group bit fields)
+    uint32_t conf[S];            // conflict slots of the pending cut
+    unsigned long long used;     // plane slots in use
+    double R2, R;                // upper bounds of the squared / plain radius
+    int nlive;                   // live slots (vertices) of the cell
+    int phase;
+    int bn, bk;                  // candidates of the batch, next one
 };
 
-template <int G, int S, bool F32>
-__device__ __forceinline__ void g_update_radius(GCell<S, F32> &c, int gl)
-{
-    double m = 0.0;
-#pragma unroll
-    for (int s = 0; s < S; s++)
-        if ((c.live[s] >> gl) & 1) m = fmax(m, c.vx[s] * c.vx[s] + c.vy[s] * c.vy[s] + c.vz[s] * c.vz[s]);
-    c.R2 = gmax<G>(m);
-    c.R = sqrt(c.R2);
-}
-
 template <int MAXP>
-__device__ __forceinline__ int g_free_plane(unsigned long long used)
+__device__ __forceinline__ int free_plane(unsigned long long used)
 {
     constexpr unsigned long long valid = MAXP >= 64 ? ~0ull : ((1ull << MAXP) - 1ull);
     unsigned long long fr = ~used & valid;
     return fr ? __builtin_ctzll(fr) : -1;
 }
 
-template <int G, int S, int MAXP, bool F32>
-__device__ __forceinline__ int g_consider(const CellArgs &A, GLDS<G, S, MAXP> &sh, GCell<S, F32> &c, double q0,
-                                          double q1, double q2, double d2, int32_t lab, int code, double *ws,
-                                          unsigned long long *cnt, int lane, int gl, int gb)
+// Radius bound: the largest squared vertex norm, rounded up to 20 mantissa
+// bits (the high word of the double plus one unit), so the group maximum is
+// a 32-bit DPP reduction.  Both R2 and R are upper bounds, which is all the
+// radius test and the error bands need.
+template <int G, int S, bool F32>
+__device__ __forceinline__ void update_radius(SCell<S, F32> &c, int gl)
 {
-    const double h = 0.5 * d2;
-    const double Mub = (fabs(q0) + fabs(q1) + fabs(q2)) * c.R + h;
-    const double band = A.tau * Mub;
-    unsigned long long conf[S], inb[S];
-    int ntest = 0;
-    if (F32) {
-        const float g0 = (float)q0, g1 = (float)q1, g2 = (float)q2, gh = (float)h;
-        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + gh);
-        unsigned long long uns = 0, unsr[S];
-#pragma unroll
-        for (int s = 0; s < S; s++) {
-            bool lv = (c.live[s] >> gl) & 1;
-            float sv = fmaf(g0, c.fx[s], fmaf(g1, c.fy[s], fmaf(g2, c.fz[s], -gh)));
-            conf[s] = gballot<G>(lv && sv > band32, gb);
-            unsr[s] = gballot<G>(lv && !(sv > band32) && !(sv < -band32), gb);
-            inb[s] = 0;
-            uns |= unsr[s];
-            ntest += __popcll(c.live[s]);
-        }
-        if (uns) {
-#pragma unroll
-            for (int s = 0; s < S; s++) {
-                bool u = (unsr[s] >> gl) & 1;
-                double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
-                conf[s] |= gballot<G>(u && sv > band, gb);
-                inb[s] = gballot<G>(u && !(sv > band) && !(sv < -band), gb);
-                cnt[DC_RECHECK] += __popcll(unsr[s]);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int s = 0; s < S; s++) {
-            bool lv = (c.live[s] >> gl) & 1;
-            double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
-            conf[s] = gballot<G>(lv && sv > band, gb);
-            inb[s] = gballot<G>(lv && !(sv > band) && !(sv < -band), gb);
-            ntest += __popcll(c.live[s]);
-        }
-    }
-    cnt[DC_TESTS] += ntest;
-    // in-band vertices: exact decision, one lane of the wave at a time
+    uint32_t m = 0;
 #pragma unroll
     for (int s = 0; s < S; s++) {
-        unsigned long long wm = __ballot((inb[s] >> gl) & 1);
-        while (wm) {
-            int l = __builtin_ctzll(wm);
-            wm &= wm - 1;
-            int sg = 0;
-            if (lane == l) {
-                PlaneD pp = {q0, q1, q2, h, 0};
-                sg = exact_side3(gplane(sh, c.tp[s] & 0xff), gplane(sh, (c.tp[s] >> 8) & 0xff),
-                                 gplane(sh, (c.tp[s] >> 16) & 0xff), pp, ws);
-            }
-            sg = __builtin_amdgcn_readlane(sg, l);
-            if ((l / G) == (lane / G)) {
-                if (sg > 0) conf[s] |= 1ull << (l % G);
-                cnt[DC_EXACT]++;
-            }
-        }
+        double x = c.vx[s] * c.vx[s] + c.vy[s] * c.vy[s] + c.vz[s] * c.vz[s];
+        uint32_t hw = (uint32_t)(__builtin_bit_cast(unsigned long long, x) >> 32) + 1u;
+        if ((c.live[s] >> gl) & 1) m = max(m, hw);
     }
-    unsigned long long anyc = 0;
-#pragma unroll
-    for (int s = 0; s < S; s++) anyc |= conf[s];
-    if (!anyc) return ST_OK;
+    m = gmax_u32<G>(m);
+    c.R2 = __builtin_bit_cast(double, (unsigned long long)m << 32);
+    if (c.R2 > 1e-30 && c.R2 < 1e30)
+        c.R = (double)__builtin_amdgcn_sqrtf((float)c.R2) * (1.0 + 0x1p-18);
+    else
+        c.R = sqrt(c.R2) * (1.0 + 0x1p-40);
+}
 
-    // ---- cut ----
-    int p = g_free_plane<MAXP>(c.used);
-    if (p < 0) {
-        unsigned long long u = 0;
-#pragma unroll
-        for (int s = 0; s < S; s++)
-            if ((c.live[s] >> gl) & 1)
-#pragma unroll
-                for (int k = 0; k < 3; k++) u |= 1ull << ((c.tp[s] >> (8 * k)) & 0xff);
-        c.used = gor_u64<G>(u);
-        p = g_free_plane<MAXP>(c.used);
-        if (p < 0) return ST_CAP;
-    }
-    uint32_t bfl = 0;
-#pragma unroll
-    for (int s = 0; s < S; s++) {
-        if ((conf[s] >> gl) & 1) {
-            uint32_t t3 = c.tp[s];
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
-                int tw = sh.etab[b][a] & (G * S - 1);
-                unsigned long long cw = 0;
-#pragma unroll
-                for (int r = 0; r < S; r++)
-                    if (tw / G == r) cw = conf[r];
-                if (!((cw >> (tw % G)) & 1)) bfl |= 1u << (s * 3 + k);
-            }
-        }
-    }
-    int nb = __popc(bfl);
-    int m;
-    int o = gballot_scan<G, (S <= 2 ? 3 : 4)>(nb, gb, gl, m);
-    int nfree = 0;
-#pragma unroll
-    for (int s = 0; s < S; s++) nfree += __popcll((~c.live[s] | conf[s]) & Grp<G>::MASK);
-    if (m > nfree || m > G * S + 8) return ST_CAP;
-#pragma unroll
-    for (int s = 0; s < S; s++) {
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            if ((bfl >> (s * 3 + k)) & 1) {
-                uint32_t t3 = c.tp[s];
-                int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
-                sh.bedge[o++] = (uint16_t)(a | (b << 8));
-            }
-        }
-    }
+template <int G, int S, int MAXP, bool F32>
+__device__ __forceinline__ void cell_fail(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, int st, int gl)
+{
+    const int id = sh.gs.id;
+    if (A.fo)
+        for (int k = gl; k < kFoLen; k += G) A.fo[(int64_t)id * kFoLen + k] = 0;
     if (gl == 0) {
-        sh.pq[p][0] = q0;
-        sh.pq[p][1] = q1;
-        sh.pq[p][2] = q2;
-        sh.pq[p][3] = h;
-        sh.plab[p] = lab;
-        sh.psh[p] = (uint8_t)code;
-        sh.pwall[p] = 0;
-    }
-    lds_sync();
-    // free slots in slot order take the new triangles (a, b, p) by rank
-    int rk[S];
-    bool take[S];
-    int before = 0;
-#pragma unroll
-    for (int s = 0; s < S; s++) {
-        unsigned long long fr = (~c.live[s] | conf[s]) & Grp<G>::MASK;
-        rk[s] = before + grank(fr, gl);
-        take[s] = ((fr >> gl) & 1) && rk[s] < m;
-        before += __popcll(fr);
-    }
-    // new vertices, G at a time, staged in LDS
-    for (int k0 = 0; k0 < m; k0 += G) {
-        int k = k0 + gl;
-        if (k < m) {
-            uint16_t e = sh.bedge[k];
-            double x, y, z;
-            cramer(sh.pq[e & 0xff], sh.pq[e >> 8], sh.pq[p], x, y, z);
-            sh.u.gc.npos[gl][0] = x;
-            sh.u.gc.npos[gl][1] = y;
-            sh.u.gc.npos[gl][2] = z;
-        }
-        lds_sync();
-#pragma unroll
-        for (int s = 0; s < S; s++) {
-            if (take[s] && rk[s] >= k0 && rk[s] < k0 + G) {
-                uint16_t e = sh.bedge[rk[s]];
-                int a = e & 0xff, b = e >> 8;
-                c.tp[s] = (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)p << 16);
-                c.vx[s] = sh.u.gc.npos[rk[s] - k0][0];
-                c.vy[s] = sh.u.gc.npos[rk[s] - k0][1];
-                c.vz[s] = sh.u.gc.npos[rk[s] - k0][2];
-                if (F32) {
-                    c.fx[s] = (float)c.vx[s];
-                    c.fy[s] = (float)c.vy[s];
-                    c.fz[s] = (float)c.vz[s];
-                }
-                uint8_t t = (uint8_t)(s * G + gl);
-                sh.etab[a][b] = t;
-                sh.etab[b][p] = t;
-                sh.etab[p][a] = t;
-            }
-        }
-        lds_sync();
-    }
-#pragma unroll
-    for (int s = 0; s < S; s++) c.live[s] = (c.live[s] & ~conf[s]) | gballot<G>(take[s], gb);
-    c.used |= 1ull << p;
-    lds_sync();
-    g_update_radius<G, S, F32>(c, gl);
-    cnt[DC_CUTS]++;
-    cnt[DC_NEWV] += m;
-    return c.R2 < 1e300 ? ST_OK : ST_CAP;
-}
-
-// particles of up to G blocks (one per lane), fed to the cell nearest first
-template <int G, int S, int MAXP, bool F32>
-__device__ __forceinline__ int g_gather(const CellArgs &A, GLDS<G, S, MAXP> &sh, GCell<S, F32> &c, const Tess &T,
-                                        int si, const double *p, const int *bc, int dx, int dy, int dz, bool valid,
-                                        double *ws, unsigned long long *cnt, int lane, int gl, int gb)
-{
-    const Grid &G3 = T.G;
-    int dd[3] = {dx, dy, dz};
-    int bb[3], sv[3];
-    bool ok = valid;
-    double d2b = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        int t = bc[d] + dd[d];
-        if (G3.per[d]) {
-            int g = G3.g[d];
-            int w = ((t % g) + g) % g;
-            sv[d] = (t - w) / g;
-            bb[d] = w;
-            if (sv[d] > 2 || sv[d] < -2) ok = false;
+        if (A.vol) A.vol[id] = __builtin_nan("");
+        if (A.cen) A.cen[3 * (int64_t)id] = A.cen[3 * (int64_t)id + 1] = A.cen[3 * (int64_t)id + 2] = __builtin_nan("");
+        if (A.nv) A.nv[id] = 0;
+        if (A.ne) A.ne[id] = 0;
+        if (A.nf) A.nf[id] = 0;
+        if (st == ST_DUP) {
+            A.status[id] = 3;
         } else {
-            sv[d] = 0;
-            bb[d] = t;
-            if (t < 0 || t >= G3.g[d]) ok = false;
+            A.status[id] = 1;
+            int pos = atomicAdd(A.spill_count, 1);
+            A.spill_list[pos] = sh.gs.si;
         }
-        double blo = G3.lo[d] + t * G3.bs[d];
-        double e = fmax(0.0, fmax(blo - p[d], p[d] - (blo + G3.bs[d])));
-        d2b += e * e;
     }
-    if (d2b >= 4.0 * c.R2 * kMargin) ok = false;
-    int cntb = 0, beg = 0;
-    if (ok) {
-        int64_t blk = T.bbase + bb[0] + (int64_t)G3.g[0] * (bb[1] + (int64_t)G3.g[1] * bb[2]);
-        beg = A.start[blk];
-        cntb = A.start[blk + 1] - beg;
-    }
-    cnt[DC_BLOCKS] += __popcll(gballot<G>(ok, gb));
-    int incl = gscan_incl<G>(cntb);
-    int total = __shfl(incl, gb + G - 1);
-    if (total == 0) return ST_OK;
-    lds_sync();
-    sh.cpre[gl] = incl - cntb;
-    sh.cbeg[gl] = beg;
-    sh.csh[gl] = (uint8_t)(25 * (sv[2] + 2) + 5 * (sv[1] + 2) + (sv[0] + 2));
-    lds_sync();
-    for (int c0 = 0; c0 < total; c0 += G) {
-        int ci = c0 + gl;
-        unsigned long long key = ~0ull;
-        if (ci < total) {
-            int lo = 0, hi = G - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (sh.cpre[mid] <= ci) lo = mid; else hi = mid - 1;
-            }
-            int idx = sh.cbeg[lo] + (ci - sh.cpre[lo]);
-            int code = sh.csh[lo];
-            int s0 = code % 5 - 2, s1 = (code / 5) % 5 - 2, s2 = code / 25 - 2;
-            Particle q = A.part[idx];
-            double a0 = q.x - p[0], a1 = q.y - p[1], a2 = q.z - p[2];
-            if (s0) a0 = a0 + s0 * G3.L[0];
-            if (s1) a1 = a1 + s1 * G3.L[1];
-            if (s2) a2 = a2 + s2 * G3.L[2];
-            double d2 = a0 * a0 + a1 * a1 + a2 * a2;
-            bool self = (idx == si) && code == kNoShift;
-            if (!self && d2 < 4.0 * c.R2 * kMargin) key = __double_as_longlong(d2);
-            sh.u.gc.cq[gl][0] = a0;
-            sh.u.gc.cq[gl][1] = a1;
-            sh.u.gc.cq[gl][2] = a2;
-            sh.u.gc.cq[gl][3] = d2;
-            sh.u.gc.cid[gl] = q.id;
-            sh.u.gc.ccode[gl] = (uint8_t)code;
-        }
-        lds_sync();
-        for (;;) {
-            unsigned long long mk = gmin_u64<G>(key);
-            if (mk == ~0ull) break;
-            double md2 = __longlong_as_double((long long)mk);
-            if (!(md2 < 4.0 * c.R2 * kMargin)) break;
-            int ol = __builtin_ctzll(gballot<G>(key == mk, gb));
-            if (gl == ol) key = ~0ull;
-            cnt[DC_CAND]++;
-            if (md2 == 0.0) return ST_DUP;
-            int st = g_consider<G, S, MAXP, F32>(A, sh, c, sh.u.gc.cq[ol][0], sh.u.gc.cq[ol][1], sh.u.gc.cq[ol][2],
-                                                 md2, sh.u.gc.cid[ol], sh.u.gc.ccode[ol], ws, cnt, lane, gl, gb);
-            if (st != ST_OK) return st;
-        }
-        lds_sync();
-    }
-    return ST_OK;
+    if (st != ST_DUP) sh.gs.cnt[DC_SPILL]++;
+    c.phase = PH_NEW;
 }
 
+// ---- NEW: claim the next cell and set up the box (Eq. 1-2) ----
 template <int G, int S, int MAXP, bool F32>
-__device__ __forceinline__ int g_cell_run(const CellArgs &A, GLDS<G, S, MAXP> &sh, int si, double *ws,
-                                          unsigned long long *cnt, int lane, int gl, int gb)
+__device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, int ncell, int gl,
+                                       int gb)
 {
-    const Particle me = A.part[si];
-    const Tess &T = A.tess[me.tess];
-    const Grid &G3 = T.G;
-    const double p[3] = {me.x, me.y, me.z};
-    const int id = me.id;
-    int bc[3];
-    double mrg[3];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        bc[d] = block_coord(G3, p[d], d);
-        double blo = G3.lo[d] + bc[d] * G3.bs[d];
-        mrg[d] = fmin(p[d] - blo, blo + G3.bs[d] - p[d]);
+    if (sh.gs.cell >= sh.gs.cend) {
+        int base = 0;
+        if (gl == 0) base = atomicAdd(A.queue, A.chunk);
+        base = __shfl(base, gb);
+        sh.gs.cell = base;
+        sh.gs.cend = min(base + A.chunk, ncell);
     }
-    GCell<S, F32> c;
+    if (sh.gs.cell >= sh.gs.cend) {
+        c.phase = PH_DONE;
+        return;
+    }
+    const int si = A.cell_list ? A.cell_list[sh.gs.cell] : sh.gs.cell;
+    sh.gs.cell++;
+    const Particle me = A.part[si];
+    sh.gs.si = si;
+    sh.gs.id = me.id;
+    sh.gs.p[0] = me.x;
+    sh.gs.p[1] = me.y;
+    sh.gs.p[2] = me.z;
+    {
+        const int32_t *src = (const int32_t *)&A.tess[me.tess];
+        int32_t *dst = (int32_t *)&sh.T;
+        for (int k = gl; k < (int)(sizeof(Tess) / 4); k += G) dst[k] = src[k];
+    }
+    lds_fence();
+    const Grid &G3 = sh.T.G;
+#pragma unroll
+    for (int d = 0; d < 3; d++) sh.gs.bc[d] = block_coord(G3, sh.gs.p[d], d);
     if (gl < 6) {
-        int d = gl >> 1, side = gl & 1;
-        double sg = side ? 1.0 : -1.0;
-        double n[3] = {0.0, 0.0, 0.0};
-        double h;
+        // face 2d + side of the box; no register array is indexed by d
+        const int d = gl >> 1, side = gl & 1;
+        const double sg = side ? 1.0 : -1.0;
+        const double pd = d == 0 ? sh.gs.p[0] : (d == 1 ? sh.gs.p[1] : sh.gs.p[2]);
+        double nn, h;
         if (G3.per[d]) {
             double L = G3.L[d];
-            n[d] = sg * L;
+            nn = sg * L;
             h = 0.5 * (L * L);
             sh.pwall[gl] = 0;
-            sh.plab[gl] = id;
+            sh.plab[gl] = sh.gs.id;
             sh.psh[gl] = (uint8_t)(kNoShift + (side ? 1 : -1) * (d == 0 ? 1 : (d == 1 ? 5 : 25)));
         } else {
-            n[d] = sg;
-            h = side ? (G3.hi[d] - p[d]) : -(G3.lo[d] - p[d]);
+            nn = sg;
+            h = side ? (G3.hi[d] - pd) : -(G3.lo[d] - pd);
             sh.pwall[gl] = 1;
             sh.plab[gl] = -(2 * d + side + 1);
             sh.psh[gl] = kNoShift;
         }
-        sh.pq[gl][0] = n[0];
-        sh.pq[gl][1] = n[1];
-        sh.pq[gl][2] = n[2];
+        sh.pq[gl][0] = d == 0 ? nn : 0.0;
+        sh.pq[gl][1] = d == 1 ? nn : 0.0;
+        sh.pq[gl][2] = d == 2 ? nn : 0.0;
         sh.pq[gl][3] = h;
     }
 #pragma unroll
@@ -535,8 +323,9 @@ __device__ __forceinline__ int g_cell_run(const CellArgs &A, GLDS<G, S, MAXP> &s
         c.vx[s] = c.vy[s] = c.vz[s] = 0.0;
         c.fx[s] = c.fy[s] = c.fz[s] = 0.0f;
         c.live[s] = 0;
+        c.conf[s] = 0;
     }
-    c.live[0] = 0xffull;
+    c.live[0] = 0xffu;
     if (gl < 8) {
         int bx = gl & 1, by = (gl >> 1) & 1, bz = (gl >> 2) & 1;
         int X = bx, Y = 2 + by, Z = 4 + bz;
@@ -547,7 +336,7 @@ __device__ __forceinline__ int g_cell_run(const CellArgs &A, GLDS<G, S, MAXP> &s
         for (int d = 0; d < 3; d++) {
             int b = (gl >> d) & 1;
             if (G3.per[d]) e[d] = b ? 0.5 * G3.L[d] : -(0.5 * G3.L[d]);
-            else e[d] = b ? (G3.hi[d] - p[d]) : (G3.lo[d] - p[d]);
+            else e[d] = b ? (G3.hi[d] - sh.gs.p[d]) : (G3.lo[d] - sh.gs.p[d]);
         }
         c.vx[0] = e[0];
         c.vy[0] = e[1];
@@ -563,50 +352,430 @@ __device__ __forceinline__ int g_cell_run(const CellArgs &A, GLDS<G, S, MAXP> &s
         }
     }
     c.used = 0x3full;
-    lds_sync();
-    g_update_radius<G, S, F32>(c, gl);
+    c.nlive = 8;
+    lds_fence();
+    update_radius<G, S, F32>(c, gl);
+    sh.gs.shell = 0;
+    sh.gs.cur = 0;
+    c.phase = PH_GATHER;
+}
 
-    bool finished = false;
-    for (int o0 = 0; o0 < A.noff; o0 += G) {
-        if (A.offs[o0].m * T.bsmin2 >= 4.0 * c.R2 * kMargin) {
-            finished = true;
-            break;
+// ---- GATHER: particle counts of the next (up to) G blocks ----
+template <int G, int S, int MAXP, bool F32>
+__device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, int gl, int gb,
+                                          uint32_t *cnt)
+{
+    const Tess &T = sh.T;
+    const Grid &G3 = T.G;
+    const double lim = 4.0 * c.R2 * kMargin;
+    int dd[3] = {0, 0, 0};
+    bool v = false;
+    if (sh.gs.shell == 0) {
+        if (sh.gs.cur >= A.noff) {
+            sh.gs.shell = A.off_radius + 1;
+            sh.gs.cur = 0;
+            sh.gs.cnt[DC_FALLBACK]++;
+        } else if (A.offs[sh.gs.cur].m * T.bsmin2 >= lim) {
+            c.phase = PH_STATS;  // no block left in the offset list can hold a cutting particle
+            return;
+        } else {
+            int o = sh.gs.cur + gl;
+            v = o < A.noff;
+            Offset of = v ? A.offs[o] : Offset{0, 0, 0, 0};
+            dd[0] = of.dx;
+            dd[1] = of.dy;
+            dd[2] = of.dz;
+            sh.gs.cur += G;
         }
-        int o = o0 + gl;
-        bool v = o < A.noff;
-        Offset of = v ? A.offs[o] : Offset{0, 0, 0, 0};
-        int st = g_gather<G, S, MAXP, F32>(A, sh, c, T, si, p, bc, of.dx, of.dy, of.dz, v, ws, cnt, lane, gl, gb);
-        if (st != ST_OK) return st;
     }
-    if (!finished) {
-        cnt[DC_FALLBACK]++;
-        for (int r = A.off_radius + 1;; r++) {
-            if (r > kMaxShell || !(c.R2 < 1e300)) return ST_CAP;
+    if (sh.gs.shell > 0) {
+        const int r = sh.gs.shell;
+        if (sh.gs.cur == 0) {
+            if (r > kMaxShell || !(c.R2 < 1e300)) {
+                c.phase = -ST_CAP;
+                return;
+            }
             double lb = 1e300;
             bool exists = false;
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                lb = fmin(lb, (r - 1) * G3.bs[d] + mrg[d]);
-                if (G3.per[d] || bc[d] - r >= 0 || bc[d] + r < G3.g[d]) exists = true;
+                double blo = G3.lo[d] + sh.gs.bc[d] * G3.bs[d];
+                double mrg = fmin(sh.gs.p[d] - blo, blo + G3.bs[d] - sh.gs.p[d]);
+                lb = fmin(lb, (r - 1) * G3.bs[d] + mrg);
+                if (G3.per[d] || sh.gs.bc[d] - r >= 0 || sh.gs.bc[d] + r < G3.g[d]) exists = true;
             }
-            if (!exists) break;
-            if (lb > 0.0 && lb * lb >= 4.0 * c.R2 * kMargin) break;
-            int side = 2 * r + 1;
-            int tot = side * side * side;
-            for (int c0 = 0; c0 < tot; c0 += G) {
-                int ix = c0 + gl;
-                int dx = ix % side - r, dy = (ix / side) % side - r, dz = ix / (side * side) - r;
-                int ch = max(abs(dx), max(abs(dy), abs(dz)));
-                bool v = ix < tot && ch == r;
-                if (!gballot<G>(v, gb)) continue;
-                int st = g_gather<G, S, MAXP, F32>(A, sh, c, T, si, p, bc, dx, dy, dz, v, ws, cnt, lane, gl, gb);
-                if (st != ST_OK) return st;
+            if (!exists || (lb > 0.0 && lb * lb >= lim)) {
+                c.phase = PH_STATS;
+                return;
+            }
+        }
+        const int side = 2 * r + 1;
+        const int tot = side * side * side;
+        int ix = sh.gs.cur + gl;
+        dd[0] = ix % side - r;
+        dd[1] = (ix / side) % side - r;
+        dd[2] = ix / (side * side) - r;
+        int ch = max(abs(dd[0]), max(abs(dd[1]), abs(dd[2])));
+        v = ix < tot && ch == r;
+        sh.gs.cur += G;
+        if (sh.gs.cur >= tot) {
+            sh.gs.shell++;
+            sh.gs.cur = 0;
+        }
+    }
+    // the blocks: periodic wrap by whole periods (at most two each way), walls
+    int bb[3], sv[3];
+    bool ok = v;
+    double d2b = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int g = G3.g[d];
+        int t = sh.gs.bc[d] + dd[d];
+        int w = t, s = 0;
+        if (G3.per[d]) {
+            while (w < 0 && s > -3) {
+                w += g;
+                s--;
+            }
+            while (w >= g && s < 3) {
+                w -= g;
+                s++;
+            }
+            if (s > 2 || s < -2) ok = false;
+        } else if (t < 0 || t >= g) {
+            ok = false;
+        }
+        bb[d] = w;
+        sv[d] = s;
+        double blo = G3.lo[d] + t * G3.bs[d];
+        double e = fmax(0.0, fmax(blo - sh.gs.p[d], sh.gs.p[d] - (blo + G3.bs[d])));
+        d2b += e * e;
+    }
+    if (d2b >= lim) ok = false;
+    int cntb = 0, beg = 0;
+    if (ok) {
+        int blk = T.bbase + bb[0] + G3.g[0] * (bb[1] + G3.g[1] * bb[2]);
+        beg = A.start[blk];
+        cntb = A.start[blk + 1] - beg;
+    }
+    sh.gs.cnt[DC_BLOCKS] += __popc(gbal<G>(ok, gb));
+    int incl = gscan_incl<G>(cntb);
+    int total = __shfl(incl, gb + G - 1);
+    if (total == 0) return;  // stay in GATHER: next blocks
+    sh.u.w.cpre[gl] = incl - cntb;
+    sh.u.w.cbeg[gl] = beg;
+    sh.u.w.csh[gl] = (uint8_t)(25 * (sv[2] + 2) + 5 * (sv[1] + 2) + (sv[0] + 2));
+    lds_fence();
+    sh.gs.gtot = total;
+    sh.gs.gc0 = 0;
+    c.phase = PH_BATCH;
+}
+
+// ---- BATCH: the next G particles of the gather, sorted by distance ----
+template <int G, int S, int MAXP, bool F32>
+__device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, int gl, int gb,
+                                         uint32_t below)
+{
+    if (sh.gs.gc0 >= sh.gs.gtot) {
+        c.phase = PH_GATHER;
+        return;
+    }
+    const Grid &G3 = sh.T.G;
+    const int ci = sh.gs.gc0 + gl;
+    unsigned long long key = ~0ull;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, d2 = 0.0;
+    int pid = 0, code = 0;
+    if (ci < sh.gs.gtot) {
+        int lo = 0, hi = G - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (sh.u.w.cpre[mid] <= ci) lo = mid;
+            else hi = mid - 1;
+        }
+        int idx = sh.u.w.cbeg[lo] + (ci - sh.u.w.cpre[lo]);
+        code = sh.u.w.csh[lo];
+        int s0 = code % 5 - 2, s1 = (code / 5) % 5 - 2, s2 = code / 25 - 2;
+        Particle q = A.part[idx];
+        a0 = q.x - sh.gs.p[0];
+        a1 = q.y - sh.gs.p[1];
+        a2 = q.z - sh.gs.p[2];
+        if (s0) a0 = a0 + s0 * G3.L[0];
+        if (s1) a1 = a1 + s1 * G3.L[1];
+        if (s2) a2 = a2 + s2 * G3.L[2];
+        d2 = a0 * a0 + a1 * a1 + a2 * a2;
+        pid = q.id;
+        bool self = (idx == sh.gs.si) && code == kNoShift;
+        // unique keys: the distance with its low five bits replaced by the
+        // lane; candidates closer than 32 ulps may swap, which the radius
+        // margin (2^-30) absorbs when the batch is cut short
+        if (!self && d2 < 4.0 * c.R2 * kMargin)
+            key = (__builtin_bit_cast(unsigned long long, d2) & ~31ull) | (unsigned long long)gl;
+    }
+    // the valid keys, compacted; each counts the smaller ones
+    const bool valid = key != ~0ull;
+    const uint32_t gv = gbal<G>(valid, gb);
+    const int bn = __popc(gv);
+    if (valid) sh.u.w.x.key[__popc(gv & below)] = key;
+    lds_fence();
+    int rank = 0;
+    if (valid && bn > 1)
+        for (int j = 0; j < bn; j++) rank += sh.u.w.x.key[j] < key;
+    if (valid) {
+        sh.u.w.cq[rank][0] = a0;
+        sh.u.w.cq[rank][1] = a1;
+        sh.u.w.cq[rank][2] = a2;
+        sh.u.w.cq[rank][3] = d2;
+        sh.u.w.cid[rank] = pid;
+        sh.u.w.ccode[rank] = (uint8_t)code;
+    }
+    lds_fence();
+    sh.gs.gc0 += G;
+    c.bn = bn;
+    c.bk = 0;
+    if (bn) c.phase = PH_TEST;
+}
+
+// ---- TEST: side of every vertex against the next candidate ----
+// Side masks are whole-wave ballots (only the testing groups' lanes are
+// active), so the per-slot work is three FMAs and two compares; a group's
+// bits are taken out only when it has a conflict and parks in CUT.
+template <int G, int S, int MAXP, bool F32>
+__device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, double *ws,
+                                        uint32_t *cnt, int lane, int gl, int gb)
+{
+    if (c.bk >= c.bn) {
+        c.phase = PH_BATCH;
+        return;
+    }
+    const int k = c.bk;
+    const double q0 = sh.u.w.cq[k][0], q1 = sh.u.w.cq[k][1], q2 = sh.u.w.cq[k][2], d2 = sh.u.w.cq[k][3];
+    if (!(d2 < 4.0 * c.R2 * kMargin)) {
+        c.phase = PH_BATCH;  // sorted: the rest of the batch is farther still
+        return;
+    }
+    cnt[0]++;
+    if (d2 == 0.0) {
+        c.phase = -ST_DUP;
+        return;
+    }
+    const double h = 0.5 * d2;
+    const double band = A.tau * ((fabs(q0) + fabs(q1) + fabs(q2)) * c.R + h);
+    unsigned long long wc[S], wi[S];
+    if (F32) {
+        const float g0 = (float)q0, g1 = (float)q1, g2 = (float)q2, gh = (float)h;
+        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + gh);
+        unsigned long long wu[S], wun = 0;
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            const bool lv = (c.live[s] >> gl) & 1;
+            wc[s] = wu[s] = wi[s] = 0;
+            if (!__builtin_amdgcn_ballot_w64(lv)) continue;
+            float sv = fmaf(g0, c.fx[s], fmaf(g1, c.fy[s], fmaf(g2, c.fz[s], -gh)));
+            wc[s] = __builtin_amdgcn_ballot_w64(lv && sv > band32);
+            wu[s] = __builtin_amdgcn_ballot_w64(lv && !(sv > band32) && !(sv < -band32));
+            wun |= wu[s];
+        }
+        if (wun) {
+#pragma unroll
+            for (int s = 0; s < S; s++) {
+                if (!wu[s]) continue;
+                const bool u = (wu[s] >> lane) & 1;
+                double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
+                wc[s] |= __builtin_amdgcn_ballot_w64(u && sv > band);
+                wi[s] = __builtin_amdgcn_ballot_w64(u && !(sv > band) && !(sv < -band));
+                sh.gs.cnt[DC_RECHECK] += __popc((uint32_t)(wu[s] >> gb) & Gw<G>::FULL);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            const bool lv = (c.live[s] >> gl) & 1;
+            wc[s] = wi[s] = 0;
+            if (!__builtin_amdgcn_ballot_w64(lv)) continue;
+            double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
+            wc[s] = __builtin_amdgcn_ballot_w64(lv && sv > band);
+            wi[s] = __builtin_amdgcn_ballot_w64(lv && !(sv > band) && !(sv < -band));
+        }
+    }
+    cnt[1] += c.nlive;
+    // in-band vertices: exact decision, one lane of the wave at a time
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        unsigned long long wm = wi[s];
+        while (wm) {
+            int l = __builtin_ctzll(wm);
+            wm &= wm - 1;
+            int sg = 0;
+            if (lane == l) {
+                PlaneD pp = {q0, q1, q2, h, 0};
+                sg = exact_side3(splane(sh, c.tp[s] & 0xff), splane(sh, (c.tp[s] >> 8) & 0xff),
+                                 splane(sh, (c.tp[s] >> 16) & 0xff), pp, ws);
+            }
+            sg = __builtin_amdgcn_readlane(sg, l);
+            if (sg > 0) wc[s] |= 1ull << l;
+            if ((l / G) == (lane / G)) sh.gs.cnt[DC_EXACT]++;
+        }
+    }
+    unsigned long long wany = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) wany |= wc[s];
+    if ((uint32_t)(wany >> gb) & Gw<G>::FULL) {
+#pragma unroll
+        for (int s = 0; s < S; s++) c.conf[s] = (uint32_t)(wc[s] >> gb) & Gw<G>::FULL;
+        c.phase = PH_CUT;
+    } else {
+        c.bk++;
+    }
+}
+
+// ---- CUT: remove the conflict region, fan new triangles around the plane ----
+template <int G, int S, int MAXP, bool F32>
+__device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, uint32_t *cnt,
+                                       int gl, int gb, uint32_t below)
+{
+    const int k = c.bk;
+    int p = free_plane<MAXP>(c.used);
+    if (p < 0) {
+        unsigned long long u = 0;
+#pragma unroll
+        for (int s = 0; s < S; s++)
+            if ((c.live[s] >> gl) & 1)
+#pragma unroll
+                for (int j = 0; j < 3; j++) u |= 1ull << ((c.tp[s] >> (8 * j)) & 0xff);
+        // group OR of the 64-bit plane masks
+        unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+#pragma unroll
+        for (int sh_ = 1; sh_ < G; sh_ <<= 1) {
+            lo |= (unsigned)__shfl_xor((int)lo, sh_);
+            hi |= (unsigned)__shfl_xor((int)hi, sh_);
+        }
+        c.used = ((unsigned long long)hi << 32) | lo;
+        p = free_plane<MAXP>(c.used);
+        if (p < 0) {
+            c.phase = -ST_CAP;
+            return;
+        }
+    }
+    // boundary edges of the conflict region: conflict triangle edges whose
+    // twin triangle is kept
+    uint32_t bfl = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        if ((c.conf[s] >> gl) & 1) {
+            uint32_t t3 = c.tp[s];
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                int a = (t3 >> (8 * j)) & 0xff, b = (t3 >> (8 * ((j + 1) % 3))) & 0xff;
+                int tw = sh.etab[b][a] & (G * S - 1);
+                uint32_t cw = 0;
+#pragma unroll
+                for (int r = 0; r < S; r++)
+                    if (tw / G == r) cw = c.conf[r];
+                if (!((cw >> (tw % G)) & 1)) bfl |= 1u << (s * 3 + j);
             }
         }
     }
+    int nb = __popc(bfl);
+    int m;
+    int o = gballot_scan<G, (S <= 2 ? 3 : 4)>(nb, gb, below, m);
+    int nfree = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) nfree += __popc(~c.live[s] | c.conf[s]);
+    if (G < 32) nfree -= S * (32 - G);
+    if (m > nfree || m > G * S + 8) {
+        c.phase = -ST_CAP;
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            if ((bfl >> (s * 3 + j)) & 1) {
+                uint32_t t3 = c.tp[s];
+                int a = (t3 >> (8 * j)) & 0xff, b = (t3 >> (8 * ((j + 1) % 3))) & 0xff;
+                sh.u.w.bedge[o++] = (uint16_t)(a | (b << 8));
+            }
+        }
+    }
+    if (gl == 0) {
+        sh.pq[p][0] = sh.u.w.cq[k][0];
+        sh.pq[p][1] = sh.u.w.cq[k][1];
+        sh.pq[p][2] = sh.u.w.cq[k][2];
+        sh.pq[p][3] = 0.5 * sh.u.w.cq[k][3];
+        sh.plab[p] = sh.u.w.cid[k];
+        sh.psh[p] = sh.u.w.ccode[k];
+        sh.pwall[p] = 0;
+    }
+    lds_fence();
+    // free slots in slot order take the new triangles (a, b, p) by rank
+    int rk[S];
+    bool take[S];
+    int before = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        uint32_t fr = (~c.live[s] | c.conf[s]) & Gw<G>::FULL;
+        rk[s] = before + __popc(fr & below);
+        take[s] = ((fr >> gl) & 1) && rk[s] < m;
+        before += __popc(fr);
+    }
+    // new vertices, G at a time, staged in LDS
+    for (int k0 = 0; k0 < m; k0 += G) {
+        int kk = k0 + gl;
+        if (kk < m) {
+            uint16_t e = sh.u.w.bedge[kk];
+            double x, y, z;
+            cramer(sh.pq[e & 0xff], sh.pq[e >> 8], sh.pq[p], x, y, z);
+            sh.u.w.x.npos[gl][0] = x;
+            sh.u.w.x.npos[gl][1] = y;
+            sh.u.w.x.npos[gl][2] = z;
+        }
+        lds_fence();
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            if (take[s] && rk[s] >= k0 && rk[s] < k0 + G) {
+                uint16_t e = sh.u.w.bedge[rk[s]];
+                int a = e & 0xff, b = e >> 8;
+                c.tp[s] = (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)p << 16);
+                c.vx[s] = sh.u.w.x.npos[rk[s] - k0][0];
+                c.vy[s] = sh.u.w.x.npos[rk[s] - k0][1];
+                c.vz[s] = sh.u.w.x.npos[rk[s] - k0][2];
+                if (F32) {
+                    c.fx[s] = (float)c.vx[s];
+                    c.fy[s] = (float)c.vy[s];
+                    c.fz[s] = (float)c.vz[s];
+                }
+                uint8_t t = (uint8_t)(s * G + gl);
+                sh.etab[a][b] = t;
+                sh.etab[b][p] = t;
+                sh.etab[p][a] = t;
+            }
+        }
+        lds_fence();
+    }
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        c.live[s] = (c.live[s] & ~c.conf[s]) | gbal<G>(take[s], gb);
+        c.conf[s] = 0;
+    }
+    c.used |= 1ull << p;
+    int nl = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) nl += __popc(c.live[s]);
+    c.nlive = nl;
+    update_radius<G, S, F32>(c, gl);
+    sh.gs.cnt[DC_CUTS]++;
+    sh.gs.cnt[DC_NEWV] += m;
+    c.bk++;
+    c.phase = c.R2 < 1e300 ? PH_TEST : -ST_CAP;
+}
 
-    // ---- statistics ----
-    lds_sync();
+// ---- STATS: volume, centroid, V/E/F, face orders, neighbours ----
+template <int G, int S, int MAXP, bool F32>
+__device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, double *ws,
+                                         uint32_t *cnt, int lane, int gl, int gb, uint32_t below)
+{
+    const int id = sh.gs.id;
+    lds_fence();
 #pragma unroll
     for (int s = 0; s < S; s++) {
         int t = s * G + gl;
@@ -618,17 +787,19 @@ __device__ __forceinline__ int g_cell_run(const CellArgs &A, GLDS<G, S, MAXP> &s
         sh.u.st.lab[t] = t;
     }
     for (int k = gl; k < MAXP; k += G) {
-        sh.forder[k] = 0;
-        sh.fref[k] = 0x7fffffff;
+        sh.u.st.forder[k] = 0;
+        sh.u.st.fref[k] = 0x7fffffff;
     }
-    for (int k = gl; k < kFoLen; k += G) sh.fo[k] = 0;
-    lds_sync();
+    for (int k = gl; k < kFoLen; k += G) sh.u.st.fo[k] = 0;
+    lds_fence();
     for (int t = gl; t < S * G; t += G) {
         uint32_t t3 = sh.u.st.tpl[t];
         if (t3 == 0xffffffffu) continue;
-        for (int k = 0; k < 3; k++) atomicMin(&sh.fref[(t3 >> (8 * k)) & 0xff], t);
+        for (int j = 0; j < 3; j++) atomicMin(&sh.u.st.fref[(t3 >> (8 * j)) & 0xff], t);
     }
-    lds_sync();
+    lds_fence();
+    // a vertex whose opposite vertex across an edge lies on the vertex's
+    // fourth plane is degenerate: the edge has zero length (decided exactly)
     uint32_t zb = 0, ib = 0;
     for (int j = 0; j < 3 * S; j++) {
         int t = (j / 3) * G + gl, k = j % 3;
@@ -657,11 +828,11 @@ __device__ __forceinline__ int g_cell_run(const CellArgs &A, GLDS<G, S, MAXP> &s
                     uint32_t w3 = sh.u.st.tpl[sh.etab[b][a] & (G * S - 1)];
                     int d = (int)(w3 & 0xff) + (int)((w3 >> 8) & 0xff) + (int)((w3 >> 16) & 0xff) - a - b;
                     d = min(max(d, 0), MAXP - 1);
-                    int sg = exact_side3(gplane(sh, t3 & 0xff), gplane(sh, (t3 >> 8) & 0xff),
-                                         gplane(sh, (t3 >> 16) & 0xff), gplane(sh, d), ws);
+                    int sg = exact_side3(splane(sh, t3 & 0xff), splane(sh, (t3 >> 8) & 0xff),
+                                         splane(sh, (t3 >> 16) & 0xff), splane(sh, d), ws);
                     if (sg == 0) zb |= 1u << j;
                 }
-                if ((l / G) == (lane / G)) cnt[DC_EXACT]++;
+                if ((l / G) == (lane / G)) sh.gs.cnt[DC_EXACT]++;
             }
         }
     }
@@ -671,8 +842,8 @@ __device__ __forceinline__ int g_cell_run(const CellArgs &A, GLDS<G, S, MAXP> &s
         uint32_t t3 = sh.u.st.tpl[t];
         if (t3 == 0xffffffffu) continue;
         int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
-        if (!((zb >> j) & 1)) atomicAdd(&sh.forder[a], 1);
-        const double *r = sh.u.st.pos[sh.fref[a]];
+        if (!((zb >> j) & 1)) atomicAdd(&sh.u.st.forder[a], 1);
+        const double *r = sh.u.st.pos[sh.u.st.fref[a]];
         const double *w = sh.u.st.pos[sh.etab[b][a] & (G * S - 1)];
         const double *v = sh.u.st.pos[t];
         double det = r[0] * (w[1] * v[2] - w[2] * v[1]) - r[1] * (w[0] * v[2] - w[2] * v[0]) +
@@ -684,8 +855,10 @@ __device__ __forceinline__ int g_cell_run(const CellArgs &A, GLDS<G, S, MAXP> &s
     }
     int nvert = 0;
 #pragma unroll
-    for (int s = 0; s < S; s++) nvert += __popcll(c.live[s]);
-    if (gballot<G>(zb != 0, gb)) {
+    for (int s = 0; s < S; s++) nvert += __popc(c.live[s]);
+    if (gbal<G>(zb != 0, gb)) {
+        // merge the triangles of one geometric vertex (label propagation
+        // along zero-length edges)
         for (int it = 0; it < 4 * S * G; it++) {
             bool ch = false;
             for (int j = 0; j < 3 * S; j++) {
@@ -699,37 +872,41 @@ __device__ __forceinline__ int g_cell_run(const CellArgs &A, GLDS<G, S, MAXP> &s
                     ch = true;
                 }
             }
-            lds_sync();
-            if (!gballot<G>(ch, gb)) break;
+            lds_fence();
+            if (!gbal<G>(ch, gb)) break;
         }
         nvert = 0;
         for (int t0 = 0; t0 < S * G; t0 += G) {
             int t = t0 + gl;
-            nvert += __popcll(gballot<G>(sh.u.st.tpl[t] != 0xffffffffu && sh.u.st.lab[t] == t, gb));
+            nvert += __popc(gbal<G>(sh.u.st.tpl[t] != 0xffffffffu && sh.u.st.lab[t] == t, gb));
         }
     }
-    lds_sync();
+    lds_fence();
     int rk = 0, sumord = 0;
     for (int k0 = 0; k0 < MAXP; k0 += G) {
         int k = k0 + gl;
-        int ord = k < MAXP ? sh.forder[k] : 0;
+        int ord = k < MAXP ? sh.u.st.forder[k] : 0;
         bool real = ord >= 3;
-        unsigned long long rb = gballot<G>(real, gb);
-        int rank = rk + grank(rb, gl);
+        uint32_t rb = gbal<G>(real, gb);
+        int rank = rk + __popc(rb & below);
         if (real) {
-            if (ord < kFoLen) atomicAdd(&sh.fo[ord], 1);
+            if (ord < kFoLen) atomicAdd(&sh.u.st.fo[ord], 1);
             if ((A.mask & (16 | 32)) && A.nbr && rank < kMaxNbr) {
                 A.nbr[(int64_t)id * kMaxNbr + rank] = sh.plab[k];
                 A.nsh[(int64_t)id * kMaxNbr + rank] = sh.psh[k];
             }
         }
-        rk += __popcll(rb);
+        rk += __popc(rb);
         sumord += gisum<G>(real ? ord : 0);
     }
-    int nface = rk;
-    double vol6 = gsum<G>(v6);
-    double M0 = gsum<G>(m0), M1 = gsum<G>(m1), M2 = gsum<G>(m2);
-    lds_sync();
+    const int nface = rk;
+    const double vol6 = gsum<G>(v6);
+    const double M0 = gsum<G>(m0), M1 = gsum<G>(m1), M2 = gsum<G>(m2);
+    lds_fence();
+    if (nface > kMaxNbr) {
+        cell_fail<G, S, MAXP, F32>(A, sh, c, ST_CAP, gl);
+        return;
+    }
     if (gl == 0) {
         double vol = vol6 / 6.0;
         if (A.vol) A.vol[id] = vol;
@@ -741,67 +918,78 @@ __device__ __forceinline__ int g_cell_run(const CellArgs &A, GLDS<G, S, MAXP> &s
         if (A.nv) A.nv[id] = nvert;
         if (A.ne) A.ne[id] = sumord / 2;
         if (A.nf) A.nf[id] = nface;
+        A.status[id] = 0;
     }
     if (A.fo)
-        for (int k = gl; k < kFoLen; k += G) A.fo[(int64_t)id * kFoLen + k] = (uint8_t)min(sh.fo[k], 255);
-    return nface > kMaxNbr ? ST_CAP : ST_OK;
+        for (int k = gl; k < kFoLen; k += G) A.fo[(int64_t)id * kFoLen + k] = (uint8_t)min(sh.u.st.fo[k], 255);
+    lds_fence();
+    c.phase = PH_NEW;
 }
 
-// occupancy target of two waves per SIMD (the LDS of four cells allows about
-// two): the register allocator is held to that budget
+// candidates and tests are counted in registers, the rest in the group's LDS
+template <int G, int S, int MAXP>
+__device__ __forceinline__ void flush_counters(const CellArgs &A, SL<G, S, MAXP> &sh, uint32_t &ncand,
+                                               uint32_t &ntest, int gl)
+{
+    sh.gs.cnt[DC_CAND] += ncand;
+    sh.gs.cnt[DC_TESTS] += ntest;
+    ncand = ntest = 0;
+    lds_fence();
+    if (gl < DC_N) {
+        uint32_t v = sh.gs.cnt[gl];
+        if (v) atomicAdd(&A.diag[gl], (unsigned long long)v);
+    }
+    lds_fence();
+    if (gl < DC_N) sh.gs.cnt[gl] = 0;
+    lds_fence();
+}
+
+// occupancy target in waves per SIMD: the register allocator is held to that
+// budget
+#ifndef VC_SYNC_WAVES
+#define VC_SYNC_WAVES 3
+#endif
+template <int G>
+struct SyncWaves {
+    static constexpr int value = G == 32 ? VC_SYNC_WAVES : 2;
+};
+
 template <int G, int S, int MAXP, bool F32>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_cells_group(CellArgs A)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>::value))) void k_cells_sync(CellArgs A)
 {
     static_assert(((G * S) & (G * S - 1)) == 0 && G * S <= 256, "slot count must be a power of two");
-    __shared__ GLDS<G, S, MAXP> shv[Grp<G>::CPW];
+    static_assert(G == 16 || G == 32, "group width");
+    __shared__ SL<G, S, MAXP> shv[Gw<G>::CPW];
     const int lane = __lane_id();
     const int gl = lane % G, gb = lane - gl;
-    GLDS<G, S, MAXP> &sh = shv[lane / G];
+    const uint32_t below = (1u << gl) - 1u;
+    SL<G, S, MAXP> &sh = shv[lane / G];
     double *ws = A.xscratch + (size_t)blockIdx.x * A.xscratch_len;
-    unsigned long long cnt[DC_N];
-#pragma unroll
-    for (int k = 0; k < DC_N; k++) cnt[k] = 0;
+    uint32_t cnt[2] = {0, 0};  // candidates, vertex tests
     const int ncell = A.ncell;
+    SCell<S, F32> c;
+    c.phase = PH_NEW;
+    if (gl < DC_N) sh.gs.cnt[gl] = 0;
+    sh.gs.cell = 0;
+    sh.gs.cend = 0;
+    lds_fence();
     for (;;) {
-        int base = 0;
-        if (gl == 0) base = atomicAdd(A.queue, A.chunk);
-        base = __shfl(base, gb);
-        if (base >= ncell) break;
-        int end = min(base + A.chunk, ncell);
-        for (int ci = base; ci < end; ci++) {
-            int si = A.cell_list ? A.cell_list[ci] : ci;
-            int st = g_cell_run<G, S, MAXP, F32>(A, sh, si, ws, cnt, lane, gl, gb);
-            int id = A.part[si].id;
-            if (st != ST_OK && A.fo)
-                for (int k = gl; k < kFoLen; k += G) A.fo[(int64_t)id * kFoLen + k] = 0;
-            if (gl == 0) {
-                if (st != ST_OK) {
-                    if (A.vol) A.vol[id] = __builtin_nan("");
-                    if (A.cen) A.cen[3 * (int64_t)id] = A.cen[3 * (int64_t)id + 1] = A.cen[3 * (int64_t)id + 2] = __builtin_nan("");
-                    if (A.nv) A.nv[id] = 0;
-                    if (A.ne) A.ne[id] = 0;
-                    if (A.nf) A.nf[id] = 0;
-                }
-                if (st == ST_OK) {
-                    A.status[id] = 0;
-                } else if (st == ST_DUP) {
-                    A.status[id] = 3;
-                } else {
-                    A.status[id] = 1;
-                    int pos = atomicAdd(A.spill_count, 1);
-                    A.spill_list[pos] = si;
-                    cnt[DC_SPILL]++;
-                }
-            }
-            lds_sync();
+        if (c.phase == PH_NEW) {
+            if (cnt[1] > (1u << 30) || sh.gs.cnt[DC_NEWV] > (1u << 30)) flush_counters<G, S, MAXP>(A, sh, cnt[0], cnt[1], gl);
+            ph_new<G, S, MAXP, F32>(A, sh, c, ncell, gl, gb);
         }
+        if (!__ballot(c.phase != PH_DONE)) break;
+        if (c.phase == PH_GATHER) ph_gather<G, S, MAXP, F32>(A, sh, c, gl, gb, cnt);
+        if (c.phase == PH_BATCH) ph_batch<G, S, MAXP, F32>(A, sh, c, gl, gb, below);
+        while (c.phase == PH_TEST) ph_test<G, S, MAXP, F32>(A, sh, c, ws, cnt, lane, gl, gb);
+        // cuts and statistics wait until no group can advance without one
+        if (!__ballot(c.phase == PH_NEW || c.phase == PH_GATHER || c.phase == PH_BATCH || c.phase < 0)) {
+            if (c.phase == PH_CUT) ph_cut<G, S, MAXP, F32>(A, sh, c, cnt, gl, gb, below);
+            if (c.phase == PH_STATS) ph_stats<G, S, MAXP, F32>(A, sh, c, ws, cnt, lane, gl, gb, below);
+        }
+        if (c.phase < 0) cell_fail<G, S, MAXP, F32>(A, sh, c, -c.phase, gl);
     }
-    // counters: every group's leader adds its cell's totals
-    if (gl == 0) {
-#pragma unroll
-        for (int k = 0; k < DC_N; k++)
-            if (cnt[k]) atomicAdd(&A.diag[k], cnt[k]);
-    }
+    flush_counters<G, S, MAXP>(A, sh, cnt[0], cnt[1], gl);
 }
 
 }  // namespace
@@ -809,11 +997,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 hipError_t launch_cells_group(const CellArgs &a, int precision, int cpw, int waves, hipStream_t s)
 {
     if (cpw == 4) {
-        if (precision == 1) k_cells_group<16, 4, 32, true><<<waves, 64, 0, s>>>(a);
-        else k_cells_group<16, 4, 32, false><<<waves, 64, 0, s>>>(a);
+        if (precision == 1) k_cells_sync<16, 4, 32, true><<<waves, 64, 0, s>>>(a);
+        else k_cells_sync<16, 4, 32, false><<<waves, 64, 0, s>>>(a);
     } else if (cpw == 2) {
-        if (precision == 1) k_cells_group<32, 2, 40, true><<<waves, 64, 0, s>>>(a);
-        else k_cells_group<32, 2, 40, false><<<waves, 64, 0, s>>>(a);
+        if (precision == 1) k_cells_sync<32, 2, 40, true><<<waves, 64, 0, s>>>(a);
+        else k_cells_sync<32, 2, 40, false><<<waves, 64, 0, s>>>(a);
     } else {
         return hipErrorInvalidValue;
     }
