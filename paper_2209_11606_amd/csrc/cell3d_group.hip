@@ -162,7 +162,6 @@ struct SL {
             uint8_t ccode[G];
             uint16_t bedge[G * S + 8];
             union {
-                double npos[G][3];
                 unsigned long long key[G];
             } x;
         } w;
@@ -718,40 +717,30 @@ __device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP> &sh, SC
         take[s] = ((fr >> gl) & 1) && rk[s] < m;
         before += __popc(fr);
     }
-    // new vertices, G at a time, staged in LDS
-    for (int k0 = 0; k0 < m; k0 += G) {
-        int kk = k0 + gl;
-        if (kk < m) {
-            uint16_t e = sh.u.w.bedge[kk];
-            double x, y, z;
-            cramer(sh.pq[e & 0xff], sh.pq[e >> 8], sh.pq[p], x, y, z);
-            sh.u.w.x.npos[gl][0] = x;
-            sh.u.w.x.npos[gl][1] = y;
-            sh.u.w.x.npos[gl][2] = z;
-        }
-        lds_fence();
+    // each lane that takes a new triangle (a, b, p) computes its vertex
 #pragma unroll
-        for (int s = 0; s < S; s++) {
-            if (take[s] && rk[s] >= k0 && rk[s] < k0 + G) {
-                uint16_t e = sh.u.w.bedge[rk[s]];
-                int a = e & 0xff, b = e >> 8;
-                c.tp[s] = (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)p << 16);
-                c.vx[s] = sh.u.w.x.npos[rk[s] - k0][0];
-                c.vy[s] = sh.u.w.x.npos[rk[s] - k0][1];
-                c.vz[s] = sh.u.w.x.npos[rk[s] - k0][2];
-                if (F32) {
-                    c.fx[s] = (float)c.vx[s];
-                    c.fy[s] = (float)c.vy[s];
-                    c.fz[s] = (float)c.vz[s];
-                }
-                uint8_t t = (uint8_t)(s * G + gl);
-                sh.etab[a][b] = t;
-                sh.etab[b][p] = t;
-                sh.etab[p][a] = t;
+    for (int s = 0; s < S; s++) {
+        if (take[s]) {
+            uint16_t e = sh.u.w.bedge[rk[s]];
+            int a = e & 0xff, b = e >> 8;
+            double x, y, z;
+            cramer(sh.pq[a], sh.pq[b], sh.pq[p], x, y, z);
+            c.tp[s] = (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)p << 16);
+            c.vx[s] = x;
+            c.vy[s] = y;
+            c.vz[s] = z;
+            if (F32) {
+                c.fx[s] = (float)x;
+                c.fy[s] = (float)y;
+                c.fz[s] = (float)z;
             }
+            uint8_t t = (uint8_t)(s * G + gl);
+            sh.etab[a][b] = t;
+            sh.etab[b][p] = t;
+            sh.etab[p][a] = t;
         }
-        lds_fence();
     }
+    lds_fence();
 #pragma unroll
     for (int s = 0; s < S; s++) {
         c.live[s] = (c.live[s] & ~c.conf[s]) | gbal<G>(take[s], gb);
