@@ -30,6 +30,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+COUNTERS = os.path.join(ROOT, "profiles", "cells_periodic1M_counters.md")
+KERNEL_SOURCES = ["cell3d.hip", "cell3d_group.hip", "cell_common.h", "vc_internal.h"]
 FP64_VECTOR_PEAK = 78.6e12  # FLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FLOP_WEIGHTS = dict(candidates=9, vertex_tests=6, new_vertices=12, fan_triangles=28)
 
@@ -48,6 +50,41 @@ def parse():
                    choices=["periodic1m", "batch4096", "fcc10m", "periodic2d10m", "periodic102m"],
                    help="periodic1m: the metric's configuration (default); the others measure the remaining sets")
     return p.parse_args()
+
+
+def kernel_key(precision_name, tuned):
+    """Which cell kernel a variant ran: cells per wave and slots per lane."""
+    cpw = tuned["cells_per_wave"] if tuned else 1
+    slots = tuned["slots"] if tuned else 2
+    return f"{precision_name},cpw={cpw}" + (f",slots={slots}" if cpw == 1 else "")
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2209_11606_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(key):
+    """HBM bytes per launch of the cell kernel, from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each divided by what the
+    counter reads for a device copy of known size).  None when the summary
+    has no entry for this kernel or was taken on other kernel sources."""
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    i = text.find("```json")
+    if i < 0:
+        return None
+    data = json.loads(text[i + 7:text.index("```", i + 7)])
+    e = data.get("kernels", {}).get(key)
+    if not e or data.get("source_sha256") != sources_sha256():
+        return None
+    return e["traffic_bytes"]
 
 
 def _timed(torch, stream, steps, step_fn):
@@ -233,9 +270,12 @@ def main():
     roof = None
     if flops_per_cell is not None:
         achieved = n * flops_per_cell / (b["kernel_ms"] / 1e3)
+        key = kernel_key("fp64" if best.startswith("fp64") else "f32_filter", b.get("tuned"))
+        traffic = committed_traffic(key) if a.workload == "periodic1m" else None
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=FP64_VECTOR_PEAK / 1e12, unit="TFLOP/s",
-                    frac=achieved / FP64_VECTOR_PEAK, traffic=None, kernel="k_cells (cell construction)",
-                    flops_per_cell=flops_per_cell, kernel_ms=b["kernel_ms"])
+                    frac=achieved / FP64_VECTOR_PEAK, traffic=traffic,
+                    kernel="cell construction (" + key + ")", flops_per_cell=flops_per_cell,
+                    kernel_ms=b["kernel_ms"])
     out = {
         "metric": ("3D" if dim == 3 else "2D") + " Voronoi cells/s on 1 MI355X, FP32-filter vs FP64 plain; "
                   "oracle-exact topology",
