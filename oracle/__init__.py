@@ -27,7 +27,8 @@ FO_LEN = 32
 TAU = 2.0 ** -30  # FP64 band inside which the side test is decided exactly
 
 COUNTER_NAMES = ["candidates", "radius_rejects", "vertex_tests", "cuts",
-                 "new_vertices", "fan_triangles", "exact_decisions", "shells"]
+                 "new_vertices", "fan_triangles", "exact_decisions", "shells",
+                 "audited", "audit_disagreements"]
 
 
 def build(force=False):
@@ -56,6 +57,7 @@ def _load():
         lib.vo_cells.restype = ctypes.c_int
         lib.vo_cells.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                                  P, P, P, P, P, P, P, P, ctypes.c_int, P, P, P]
+        lib.vo_set_audit.argtypes = [ctypes.c_int]
         lib.vo_exact_side.restype = ctypes.c_int
         lib.vo_exact_side.argtypes = [ctypes.c_int, P]
         lib.vo_num_threads.restype = ctypes.c_int

@@ -53,7 +53,7 @@
 enum { VO_OK = 0, VO_ERR_CAP = -1, VO_ERR_TOPO = -2, VO_ERR_ARG = -3, VO_ERR_MEM = -4 };
 
 /* counters (per call, summed over cells) */
-enum { C_CAND = 0, C_RREJ, C_TESTS, C_CUTS, C_NEWV, C_TRIS, C_EXACT, C_SHELLS, C_NCOUNT };
+enum { C_CAND = 0, C_RREJ, C_TESTS, C_CUTS, C_NEWV, C_TRIS, C_EXACT, C_SHELLS, C_AUDIT, C_AUDIT_BAD, C_NCOUNT };
 
 /* ------------------------------------------------------------------------ */
 /* Exact arithmetic: dyadic rationals m * 2^e with a sign-magnitude big      */
@@ -297,6 +297,7 @@ static int exact_side(const oplane *pa, const oplane *pb, const oplane *pc, cons
 typedef struct {
     int dim;
     double tau;
+    int audit;            /* re-decide every test outside the band exactly */
     int np;
     oplane pl[VO_MAXP];
     int nv;
@@ -333,10 +334,18 @@ static int decide(ocell *c, int v, const oplane *p)
         m = fabs(t0) + fabs(t1) + fabs(p->h);
     }
     c->s[v] = s;
-    if (s > c->tau * m) return 1;
-    if (s < -c->tau * m) return -1;
-    c->cnt[C_EXACT]++;
     const int *d = c->vp[v];
+    if (s > c->tau * m || s < -c->tau * m) {
+        int sg = s > 0.0 ? 1 : -1;
+        if (c->audit) {
+            /* the decision outside the band must be the exact sign */
+            c->cnt[C_AUDIT]++;
+            if (exact_side(&c->pl[d[0]], &c->pl[d[1]], c->dim == 3 ? &c->pl[d[2]] : NULL, p, c->dim) != sg)
+                c->cnt[C_AUDIT_BAD]++;
+        }
+        return sg;
+    }
+    c->cnt[C_EXACT]++;
     return exact_side(&c->pl[d[0]], &c->pl[d[1]], c->dim == 3 ? &c->pl[d[2]] : NULL, p, c->dim);
 }
 
@@ -925,6 +934,16 @@ static void stats2(ocell *c, ostats *st, int32_t *nbr, int32_t *nsh, int maxnb)
     st->nf = n;
 }
 
+/* Exactness audit switch: while set, every side decision taken outside the
+ * band is also decided exactly, and disagreements are counted (test
+ * infrastructure; set it before vo_cells, not during). */
+static int g_audit = 0;
+
+void vo_set_audit(int on)
+{
+    g_audit = on ? 1 : 0;
+}
+
 /* Compute the cells of the m particles idx[0..m).  Outputs (each may be
  * NULL): vol[m], cen[3m], nv/ne/nf[m], fo[32m], nbr/nsh[maxnb*m] (one label
  * per face, unsorted), perim[m], status[m], counters[C_NCOUNT] (summed).
@@ -953,6 +972,7 @@ int vo_cells(const vo_handle *H, const int64_t *idx, int64_t m, int nthreads, do
         for (int64_t t = 0; t < m; t++) {
             if (!c || !cbuf) { err = VO_ERR_MEM; continue; }
             c->tau = tau;
+            c->audit = g_audit;
             int64_t i = idx[t];
             int rc = (i < 0 || i >= H->n) ? VO_ERR_ARG : compute_cell(H, i, c, &cbuf, &ccap);
             if (status) status[t] = rc;
@@ -1023,6 +1043,7 @@ int vo_cell_vertices(const vo_handle *H, int64_t i, double tau, double *out, int
     ocand *cbuf = (ocand *)malloc((size_t)ccap * sizeof(ocand));
     if (!c || !cbuf) { free(c); free(cbuf); return VO_ERR_MEM; }
     c->tau = tau;
+    c->audit = 0;
     int rc = compute_cell(H, i, c, &cbuf, &ccap);
     if (rc == VO_OK) {
         int n = H->dim == 3 ? c->nv : c->pn;

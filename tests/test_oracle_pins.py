@@ -302,6 +302,38 @@ def test_exact_predicate():
     assert oracle.exact_side(rows, 3) == _exact_sign(rows, 3) == -1
 
 
+def test_exactness_audit():
+    """Every side decision the oracle takes in FP64 outside the band agrees
+    with the exact sign (the decision rule of the paper's side test, Eq. 3,
+    with the band reading): the walled 1k set, 2,000 cells of the periodic 1M
+    set and 2,000 cells of a periodic 2D set.  The audit itself is checked on
+    an exact lattice with the band removed, where FP64 signs of exact zeros
+    must disagree."""
+    lib = oracle._load()
+    try:
+        lib.vo_set_audit(1)
+        w = W.walled_1k()
+        r = oracle.Oracle(w["xyz"], w["lo"], w["hi"], w["periodic"]).cells(nthreads=8, neighbors=False)
+        c = r["counters"]
+        assert c["audited"] > 100_000 and c["audit_disagreements"] == 0
+        w = W.periodic_1m()
+        r = oracle.Oracle(w["xyz"], w["lo"], w["hi"], w["periodic"]).cells(
+            np.arange(0, 1_000_000, 500), nthreads=8, neighbors=False)
+        c = r["counters"]
+        assert c["audited"] > 1_000_000 and c["audit_disagreements"] == 0
+        x = W.uniform(20_000, 2, 1.0, 9)
+        r = oracle.Oracle(x, [0, 0], [1, 1], [1, 1]).cells(np.arange(0, 20_000, 10), nthreads=8, neighbors=False)
+        c = r["counters"]
+        assert c["audited"] > 50_000 and c["audit_disagreements"] == 0
+        # planted: with no band, exact zeros on the simple-cubic lattice are
+        # decided by their FP64 sign, which the audit must catch
+        x, hi = W.sc(4, 1.0)
+        r = oracle.Oracle(x, [0, 0, 0], hi, [1, 1, 1]).cells(nthreads=8, tau=-1.0, neighbors=False)
+        assert r["counters"]["audit_disagreements"] > 0
+    finally:
+        lib.vo_set_audit(0)
+
+
 def test_grid_rule():
     """Section 2.1.4 block counts with the ceiling (text) rule."""
     assert oracle.grid_size(1000, [0] * 3, [1] * 3, 5.0) == [6, 6, 6]
