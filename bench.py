@@ -17,7 +17,11 @@ counts on a sample of the same workload, weighted (candidate distance 9,
 vertex side test 6, new vertex 12, fan tetrahedron 28), scaled to the cells of
 one launch -- over its HIP-event duration, against the FP64 vector peak.
 The cpu_baseline object times the oracle on the host cores on a bounded
-sample of the same workload.
+sample of the same workload; cpu_serial times it on one thread.
+binning_roofline is the rebin alone (HIP events) against the HBM peak, with
+212 algorithmic bytes per particle; end_to_end is one pass from positions in
+pinned host memory to every result field in host memory (PCIe included),
+reported beside `value`, never as it.
 """
 import argparse
 import json
@@ -32,6 +36,11 @@ sys.path.insert(0, ROOT)
 
 COUNTERS = os.path.join(ROOT, "profiles", "cells_periodic1M_counters.md")
 KERNEL_SOURCES = ["cell3d.hip", "cell3d_group.hip", "cell_common.h", "vc_internal.h"]
+HBM_PEAK = 8.0e12  # B/s
+# rebin of one particle: device copy of the positions (24 B read + 24 B
+# written), block count (24 B read, 8 B written), scatter (24 + 12 B read,
+# 32 B written), in-block order (32 B read + 32 B written)
+BIN_BYTES_PER_PARTICLE = 212
 FP64_VECTOR_PEAK = 78.6e12  # FLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FLOP_WEIGHTS = dict(candidates=9, vertex_tests=6, new_vertices=12, fan_triangles=28)
 
@@ -42,6 +51,7 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--cpu-sample", type=int, default=200_000, help="oracle cells timed on the host")
+    p.add_argument("--cpu-serial-sample", type=int, default=100_000, help="oracle cells timed on one thread")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--calibration-copy-mib", type=int, default=0,
                    help="first copy a device buffer of this size (reference for HBM byte counters)")
@@ -123,6 +133,53 @@ def time_variant(v, torch, xt, w, precision, steps, warmup, mask):
     return out
 
 
+def time_binning(v, torch, xt, w, steps):
+    """Binning alone: vc_container_rebin on HBM-resident positions (copy,
+    count, scan, scatter, in-block order, range check), HIP events."""
+    stream = torch.cuda.current_stream()
+    o = v.vc_options_init(xt.shape[1], w["lo"], w["hi"], w["periodic"])
+    c = v.vc_container_create(xt, o, stream)
+    try:
+        ms = _timed(torch, stream, steps, lambda: v.vc_container_rebin(c, xt, stream))
+    finally:
+        v.vc_container_destroy(c)
+    n = xt.shape[0]
+    achieved = n * BIN_BYTES_PER_PARTICLE / (ms / 1e3)
+    return dict(ms=ms, bytes_per_particle=BIN_BYTES_PER_PARTICLE, achieved_GBps=achieved / 1e9,
+                peak_GBps=HBM_PEAK / 1e9, frac=achieved / HBM_PEAK, bound="hbm")
+
+
+def end_to_end(v, torch, xyz, w, precision, mask, reps=3):
+    """Positions in pinned host memory to results in host memory: rebin from
+    the host pointer (PCIe copy + binning), compute, copy every produced
+    field back.  The container and result exist beforehand."""
+    import time as _t
+    stream = torch.cuda.current_stream()
+    host = torch.from_numpy(xyz).pin_memory()
+    n, dim = xyz.shape
+    # the fastest plain form: two cells per wave in 3D
+    o = v.vc_options_init(dim, w["lo"], w["hi"], w["periodic"], precision=precision,
+                          cells_per_wave=2 if dim == 3 else 0)
+    c = v.vc_container_create(host, o, stream)
+    r = v.vc_result_create(c, mask)
+    try:
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = _t.perf_counter()
+            v.vc_container_rebin(c, host, stream)
+            v.vc_compute(c, r, stream)
+            v.fetch(r, mask, n, dim)
+            torch.cuda.synchronize()
+            ms = (_t.perf_counter() - t) * 1e3
+            best = ms if best is None else min(best, ms)
+    finally:
+        v.vc_result_destroy(r)
+        v.vc_container_destroy(c)
+    return dict(ms=best, cells_per_s=n / (best / 1e3),
+                includes="H2D of positions from pinned memory, binning, cells, compaction, D2H of every field")
+
+
 def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask):
     """Batched form: autotuned launch parameters, compute replayed from a
     hipGraph; step = rebin + graph launch.  The cell-kernel duration for the
@@ -186,6 +243,20 @@ def cpu_baseline(members, sample):
              + FLOP_WEIGHTS["fan_triangles"] * tot["fan_triangles"]) / done
     per_cell = {k: val / done for k, val in tot.items()}
     return dict(value=done / secs, unit="cells/s", cores=cores, kind="oracle", seconds=secs), flops, per_cell
+
+
+def cpu_serial(members, sample):
+    """The oracle on one host thread: the first `sample` cells of the first
+    member (the paper's serial timings are per cell, one core)."""
+    import oracle
+    m = members[0]
+    k = min(sample, len(m["xyz"]))
+    o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"])
+    t = time.perf_counter()
+    o.cells(np.arange(k, dtype=np.int64), nthreads=1, neighbors=False)
+    secs = time.perf_counter() - t
+    return dict(value=k / secs, unit="cells/s", cores=1, kind="oracle", seconds=secs,
+                sample=f"first {k} cells, one thread")
 
 
 def main():
@@ -255,6 +326,14 @@ def main():
             res[name] = time_variant(v, torch, xt, members[0], prec, a.steps, a.warmup, mask)
         print(f"# {name}: {res[name]['ms_per_step']:.3f} ms/step, cell kernel {res[name]['kernel_ms']:.3f} ms, "
               f"tuned {res[name].get('tuned')}, diag {res[name]['diag']}", file=sys.stderr, flush=True)
+    binning = e2e = None
+    if len(members) == 1:
+        binning = time_binning(v, torch, xt, members[0], a.steps)
+        if a.workload != "periodic102m":
+            e2e = end_to_end(v, torch, xyz, members[0], v.VC_FP64, mask)
+        print(f"# binning: {binning['ms']:.3f} ms, end-to-end: {e2e and round(e2e['ms'], 3)} ms",
+              file=sys.stderr, flush=True)
+    serial = None
     if a.no_cpu_baseline:
         cpu, flops_per_cell = None, None
     else:
@@ -264,6 +343,7 @@ def main():
         cpu["sample"] = sample_desc.format(min(a.cpu_sample, n)) + ", OpenMP dynamic,64 over cells"
         print(f"# oracle: {cpu['value']:.0f} cells/s on {cpu['cores']} cores; per cell {per_cell}",
               file=sys.stderr, flush=True)
+        serial = cpu_serial(members, a.cpu_serial_sample)
     best = max(res, key=lambda k: n / res[k]["ms_per_step"])
     b = res[best]
     value = n / (b["ms_per_step"] / 1e3)
@@ -296,7 +376,10 @@ def main():
                              diag=r["diag"])
                      for k, r in res.items()},
         "roofline": roof,
+        "binning_roofline": binning,
+        "end_to_end": e2e,
         "cpu_baseline": cpu,
+        "cpu_serial": serial,
     }
     print(json.dumps(out), flush=True)
 
