@@ -10,7 +10,8 @@ code with the GPU library and imports nothing from it.
 Per-cell results (section 2.1.2 and the topology discussion of section 4):
 volume, centroid relative to the particle, vertex / edge / face counts, the
 face-order vector fo[k] = number of faces with k edges, and one neighbour label
-(j, image code) per face.  Labels -1..-6 are the walls x-, x+, y-, y+, z-, z+;
+(j, image code) per face.  Labels -1..-6 are the walls x-, x+, y-, y+, z-, z+,
+-7..-12 the faces of the clip cube when cells are clipped (section 3.1.3);
 the image code of a periodic shift s is 25(s_z+2) + 5(s_y+2) + (s_x+2).
 """
 import ctypes
@@ -54,6 +55,7 @@ def _load():
         lib.vo_create.restype = P
         lib.vo_create.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, P, P]
         lib.vo_destroy.argtypes = [P]
+        lib.vo_set_clip.argtypes = [P, ctypes.c_double]
         lib.vo_cells.restype = ctypes.c_int
         lib.vo_cells.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                                  P, P, P, P, P, P, P, P, ctypes.c_int, P, P, P]
@@ -86,9 +88,11 @@ def exact_side(rows, dim=3):
 
 
 class Oracle:
-    """Serial FP64 cells of a container (box [lo, hi], per-axis periodicity)."""
+    """Serial FP64 cells of a container (box [lo, hi], per-axis periodicity).
+    clip > 0 clips every cell by the cube of that side centred on its
+    particle (section 3.1.3)."""
 
-    def __init__(self, xyz, lo, hi, periodic, grid=None, n_opt=5.0):
+    def __init__(self, xyz, lo, hi, periodic, grid=None, n_opt=5.0, clip=0.0):
         lib = _load()
         self.xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64))
         self.n, self.dim = self.xyz.shape
@@ -111,6 +115,8 @@ class Oracle:
                                 hi3.ctypes.data, per.ctypes.data, g.ctypes.data)
         if not self._h:
             raise ValueError("oracle: bad container arguments")
+        self.clip = float(clip)
+        lib.vo_set_clip(self._h, self.clip)
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -23,15 +23,27 @@ def _shift_code(s):
     return 25 * (s[2] + 2) + 5 * (s[1] + 2) + (s[0] + 2)
 
 
-def _planes(xyz, i, lo, hi, periodic):
+def _box_offset(p, lo, hi, periodic, d, side):
+    """The domain's plane on one side of axis d, as a positive offset in the
+    cell's frame (the FP64 value, as the inputs define it)."""
+    if periodic[d]:
+        return 0.5 * (float(hi[d]) - float(lo[d]))
+    return float(hi[d]) - p[d] if side else -(float(lo[d]) - p[d])
+
+
+def _planes(xyz, i, lo, hi, periodic, clip=0.0):
     dim = xyz.shape[1]
     p = xyz[i]
     planes = []  # (normal tuple of Fr, offset Fr, label, image code, float |q|^2)
-    # box planes: walls, or bisectors with own images at +-L e_d
+    # box planes: walls, or bisectors with own images at +-L e_d; with
+    # clipping, a clip wall at h/2 on every side where it lies strictly inside
     for d in range(dim):
         for side in (0, 1):
             n = [Fr(0)] * dim
-            if periodic[d]:
+            if clip > 0 and 0.5 * clip < _box_offset(p, lo, hi, periodic, d, side):
+                n[d] = Fr(1) if side else Fr(-1)
+                planes.append((tuple(n), Fr(clip) / 2, -(7 + 2 * d + side), _shift_code([0] * dim), 0.0))
+            elif periodic[d]:
                 L = float(hi[d]) - float(lo[d])
                 n[d] = Fr(L) if side else -Fr(L)
                 h = Fr(L) * Fr(L) / 2
@@ -61,21 +73,19 @@ def _planes(xyz, i, lo, hi, periodic):
     return planes
 
 
-def cell(xyz, i, lo, hi, periodic):
-    """Exact cell of particle i.  Returns dict(vol, cen, nv, ne, nf, fo, nbr)
-    with vol and cen as Fractions and nbr sorted (label, image) pairs."""
+def cell(xyz, i, lo, hi, periodic, clip=0.0):
+    """Exact cell of particle i (clipped by the cube of side `clip` centred
+    on the particle when clip > 0).  Returns dict(vol, cen, nv, ne, nf, fo,
+    nbr) with vol and cen as Fractions and nbr sorted (label, image) pairs."""
     xyz = np.asarray(xyz, dtype=np.float64)
     dim = xyz.shape[1]
     p = xyz[i]
-    planes = _planes(xyz, i, lo, hi, periodic)
-    # initial box: corners tight at one plane per axis
+    planes = _planes(xyz, i, lo, hi, periodic, clip)
+    # initial box: corners tight at one plane per axis (its offset along d)
     ext = []
     for d in range(dim):
-        if periodic[d]:
-            half = Fr(float(hi[d]) - float(lo[d])) / 2
-            ext.append((-half, half))
-        else:
-            ext.append((Fr(float(lo[d]) - p[d]), Fr(float(hi[d]) - p[d])))
+        lo_pl, hi_pl = planes[2 * d], planes[2 * d + 1]
+        ext.append((-lo_pl[1] / abs(lo_pl[0][d]), hi_pl[1] / abs(hi_pl[0][d])))
     verts = []
     for bits in product((0, 1), repeat=dim):
         pt = tuple(ext[d][bits[d]] for d in range(dim))

@@ -361,8 +361,22 @@ static double max_r2(const ocell *c)
 
 static int shift_code(const int s[3]) { return 25 * (s[2] + 2) + 5 * (s[1] + 2) + (s[0] + 2); }
 
-/* the two bounding planes of axis d: index 2d (low side), 2d+1 (high side) */
-static void box_planes(ocell *c, const double *p, const double *lo, const double *hi, const int *per, int self)
+/* Offset of the domain's bounding plane on one side of axis d, in the
+ * cell's frame (positive): half the period on a periodic axis (the bisector
+ * with the particle's own image), else the distance to the wall. */
+static double domain_offset(const double *p, const double *lo, const double *hi, const int *per, int d, int side)
+{
+    if (per[d]) return 0.5 * (hi[d] - lo[d]);
+    return side ? (hi[d] - p[d]) : -(lo[d] - p[d]);
+}
+
+/* the two bounding planes of axis d: index 2d (low side), 2d+1 (high side).
+ * With clipping (section 3.1.3: the cell starts from a cube of side h
+ * centred on the particle), a side whose half-side h/2 is strictly inside
+ * the domain's plane becomes an axis-aligned clip wall, labelled -7..-12
+ * (x-, x+, y-, y+, z-, z+); ext receives the corner offsets. */
+static void box_planes(ocell *c, const double *p, const double *lo, const double *hi, const int *per, int self,
+                       double clip, double ext[3][2])
 {
     c->np = 0;
     for (int d = 0; d < c->dim; d++) {
@@ -370,7 +384,16 @@ static void box_planes(ocell *c, const double *p, const double *lo, const double
             oplane *q = &c->pl[c->np++];
             memset(q, 0, sizeof(*q));
             double sgn = side ? 1.0 : -1.0;
-            if (per[d]) {
+            double off = domain_offset(p, lo, hi, per, d, side);
+            double half = 0.5 * clip;
+            if (clip > 0.0 && half < off) {
+                q->wall = 1;
+                q->n[d] = sgn;
+                q->h = half;
+                q->label = -(7 + 2 * d + side);
+                q->shift = shift_code((int[3]){0, 0, 0});
+                ext[d][side] = side ? half : -half;
+            } else if (per[d]) {
                 /* bisector with own image at sgn*L: n = sgn*L e_d, h = L^2/2 */
                 double L = hi[d] - lo[d];
                 q->wall = 0;
@@ -380,28 +403,26 @@ static void box_planes(ocell *c, const double *p, const double *lo, const double
                 int sh[3] = {0, 0, 0};
                 sh[d] = side ? 1 : -1;
                 q->shift = shift_code(sh);
+                ext[d][side] = side ? off : -off;
             } else {
                 /* wall: r_d >= a_d - p_d  or  r_d <= b_d - p_d */
                 q->wall = 1;
                 q->n[d] = sgn;
-                q->h = side ? (hi[d] - p[d]) : -(lo[d] - p[d]);
+                q->h = off;
                 q->label = -(2 * d + side + 1);
                 q->shift = shift_code((int[3]){0, 0, 0});
+                ext[d][side] = side ? (hi[d] - p[d]) : (lo[d] - p[d]);
             }
         }
     }
 }
 
-/* Initial cell = box (Eq. 1-2). */
-static void cell_init(ocell *c, const double *p, const double *lo, const double *hi, const int *per, int self)
+/* Initial cell = box (Eq. 1-2), or the clip cube inside it. */
+static void cell_init(ocell *c, const double *p, const double *lo, const double *hi, const int *per, int self,
+                      double clip)
 {
-    box_planes(c, p, lo, hi, per, self);
     double ext[3][2];
-    for (int d = 0; d < c->dim; d++) {
-        /* corner coordinates are the plane offsets along the axis */
-        ext[d][0] = per[d] ? -(0.5 * (hi[d] - lo[d])) : (lo[d] - p[d]);
-        ext[d][1] = per[d] ? (0.5 * (hi[d] - lo[d])) : (hi[d] - p[d]);
-    }
+    box_planes(c, p, lo, hi, per, self, clip, ext);
     if (c->dim == 3) {
         c->nv = 8;
         for (int k = 0; k < 8; k++) {
@@ -681,6 +702,7 @@ typedef struct vo_handle {
     int64_t *ids;    /* particle ids sorted by block */
     double *xyz;     /* n x 3 (z = 0 in 2D) */
     int *blk;        /* block index per particle */
+    double clip;     /* side of the clip cube, 0: none */
 } vo_handle;
 
 static int block_coord(const vo_handle *H, double x, int d)
@@ -737,6 +759,12 @@ vo_handle *vo_create(int dim, const double *xyz, int64_t n, const double *lo, co
     return H;
 }
 
+/* Clip every cell by the cube of side h centred on its particle (0: none). */
+void vo_set_clip(vo_handle *H, double h)
+{
+    if (H) H->clip = h > 0.0 ? h : 0.0;
+}
+
 void vo_destroy(vo_handle *H)
 {
     if (!H) return;
@@ -763,7 +791,7 @@ static int compute_cell(const vo_handle *H, int64_t i, ocell *c, ocand **cbuf, i
     const int dim = H->dim;
     const double *p = &H->xyz[3 * i];
     c->dim = dim;
-    cell_init(c, p, H->lo, H->hi, H->per, (int32_t)i);
+    cell_init(c, p, H->lo, H->hi, H->per, (int32_t)i, H->clip);
     double r2 = max_r2(c);
     int b[3], own = H->blk[i];
     b[0] = own % H->g[0];

@@ -81,6 +81,46 @@ def test_brute_force_nonunit_box():
         _same_cell(r, i, brute.cell(x, i, lo, hi, per))
 
 
+@pytest.mark.parametrize("dim,per,clip", [(3, [0, 0, 0], 0.55), (3, [1, 1, 1], 0.45), (3, [1, 0, 1], 0.6),
+                                          (2, [0, 0], 0.3), (2, [1, 1], 0.25)])
+def test_brute_force_clipped(dim, per, clip):
+    """Cells clipped by the cube (square) of side h centred on the particle
+    (section 3.1.3) against the exact brute force: some cells keep every
+    face, some are cut by the clip walls (labels -7..-12)."""
+    n = 24 if dim == 3 else 40
+    x = W.uniform(n, dim, 1.0, 17 + dim)
+    r = oracle.Oracle(x, [0] * dim, [1] * dim, per, clip=clip).cells()
+    clipped = 0
+    for i in range(n):
+        b = brute.cell(x, i, [0] * dim, [1] * dim, per, clip)
+        _same_cell(r, i, b)
+        clipped += any(lab <= -7 for lab, _ in b["nbr"])
+    assert 0 < clipped < n
+
+
+def test_clip_closed_forms():
+    """Simple-cubic lattice (a = 1, periodic): a clip cube of side 0.8 is the
+    whole cell (volume 0.512, six clip faces); side 1.0 puts the clip walls
+    exactly on the neighbours' bisectors, which touch without cutting (the
+    unit cube, six clip faces); side 1.6 leaves the lattice cell (the unit
+    cube, six neighbours).  One particle in a walled box: the cell is the
+    clip cube cut by the walls."""
+    x, hi = W.sc(4, 1.0)
+    clip_labels = [-12, -11, -10, -9, -8, -7]
+    for h, vol in ((0.8, 0.8 ** 3), (1.0, 1.0)):
+        r = oracle.Oracle(x, [0] * 3, hi, [1, 1, 1], clip=h).cells()
+        assert np.all(r["vol"] == vol) and np.all(r["nf"] == 6) and np.all(r["fo"][:, 4] == 6)
+        assert all(sorted(int(t) for t in l[:, 0]) == clip_labels for l in r["nbr"])
+    r = oracle.Oracle(x, [0] * 3, hi, [1, 1, 1], clip=1.6).cells()
+    assert np.all(r["vol"] == 1.0) and np.all(r["nf"] == 6)
+    assert all(np.all(l[:, 0] >= 0) for l in r["nbr"])
+    p = np.array([[0.1, 0.5, 0.7]])
+    r = oracle.Oracle(p, [0] * 3, [1] * 3, [0] * 3, clip=0.5).cells()
+    # x: [0, 0.35] (wall x- at 0.1 below), y: [0.25, 0.75], z: [0.45, 0.95]
+    assert r["vol"][0] == pytest.approx(0.35 * 0.5 * 0.5, rel=1e-15)
+    assert sorted(int(t) for t in r["nbr"][0][:, 0]) == [-12, -11, -10, -9, -8, -1]
+
+
 def test_single_and_two_particles():
     """One particle: the cell is the box (Eq. 1-2).  Two particles: the box
     split by the bisector (volumes by hand)."""
