@@ -106,6 +106,10 @@ typedef struct {
     int waves;           /* resident cell waves launched; 0: auto */
     int chunk;           /* cells taken per work-queue grab; 0: auto */
     int cells_per_wave;  /* cells sharing one wavefront: 1, 2 or 4; 0: 1 */
+    double clip;         /* > 0: every cell starts as the cube (square) of this side
+                            centred on its particle, cut to the box (section 3.1.3:
+                            clipped cells); faces of the clip cube are labelled
+                            -7..-12 (x-, x+, y-, y+, z-, z+); 0: the whole box */
 } vc_options;
 
 typedef struct vc_container vc_container;

@@ -95,8 +95,14 @@ std::vector<Offset> build_offsets(int dim)
         if (a.dy != b.dy) return a.dy < b.dy;
         return a.dx < b.dx;
     });
+    // The search stops at the first entry whose gap bound reaches 2R.  Blocks
+    // outside the list (Chebyshev radius kOffRadius + 1 and beyond) have a gap
+    // of at least kOffRadius block sides, so the bound stored with each entry
+    // is capped there: stopping at an entry then also covers every block
+    // beyond the list, and a cell reaching farther searches the whole list and
+    // goes on shell by shell.  The cap keeps the list sorted.
     std::vector<Offset> out;
-    for (auto &e : v) out.push_back(Offset{e.dx, e.dy, e.dz, e.m});
+    for (auto &e : v) out.push_back(Offset{e.dx, e.dy, e.dz, std::min(e.m, kOffRadius * kOffRadius)});
     return out;
 }
 
@@ -115,6 +121,7 @@ vc_status check_options(const vc_options *o)
     if (o->waves < 0 || o->chunk < 0) return fail(VC_E_ARG, "options: negative waves or chunk");
     if (o->cells_per_wave != 0 && o->cells_per_wave != 1 && o->cells_per_wave != 2 && o->cells_per_wave != 4)
         return fail(VC_E_ARG, "options: cells_per_wave must be 0, 1, 2 or 4");
+    if (!std::isfinite(o->clip) || o->clip < 0.0) return fail(VC_E_ARG, "options: clip must be finite and >= 0");
     return VC_OK;
 }
 
@@ -301,6 +308,7 @@ vc_status create_common(vc_container *c, const double *xyz, const int64_t *offse
         double bmin = T.G.bs[0];
         for (int d = 1; d < dim; d++) bmin = std::min(bmin, T.G.bs[d]);
         T.bsmin2 = bmin * bmin;
+        T.clip_half = opts[t].clip > 0.0 ? 0.5 * opts[t].clip : 0.0;
         nb += T.G.nb;
         if (nb > (int64_t)INT32_MAX / 2) return fail(VC_E_ARG, "too many blocks (%lld)", (long long)nb);
     }

@@ -421,29 +421,16 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
         mrg[d] = fmin(p[d] - blo, blo + Gr.bs[d] - p[d]);
     }
     Poly<S, F32> c;
-    // box lines (Eq. 1-2): walls, or bisectors with the own images at +-L
+    // box lines (Eq. 1-2, clipped as in section 3.1.3)
     if (gl < 4) {
-        int d = gl >> 1, side = gl & 1;
-        double sg = side ? 1.0 : -1.0;
-        double n[2] = {0.0, 0.0};
-        double h;
-        if (Gr.per[d]) {
-            double L = Gr.L[d];
-            n[d] = sg * L;
-            h = 0.5 * (L * L);
-            sh.lwall[gl] = 0;
-            sh.llab[gl] = id;
-            sh.lsh[gl] = (uint8_t)(kNoShift + (side ? 1 : -1) * (d == 0 ? 1 : 5));
-        } else {
-            n[d] = sg;
-            h = side ? (Gr.hi[d] - p[d]) : -(Gr.lo[d] - p[d]);
-            sh.lwall[gl] = 1;
-            sh.llab[gl] = -(2 * d + side + 1);
-            sh.lsh[gl] = kNoShift;
-        }
-        sh.lq[gl][0] = n[0];
-        sh.lq[gl][1] = n[1];
-        sh.lq[gl][2] = h;
+        const int d = gl >> 1, side = gl & 1;
+        const BoxSide b = box_side(T, d == 0 ? p[0] : p[1], d, side, id);
+        sh.lwall[gl] = (uint8_t)b.wall;
+        sh.llab[gl] = b.lab;
+        sh.lsh[gl] = b.code;
+        sh.lq[gl][0] = d == 0 ? b.nd : 0.0;
+        sh.lq[gl][1] = d == 1 ? b.nd : 0.0;
+        sh.lq[gl][2] = b.h;
     }
 #pragma unroll
     for (int s = 0; s < S; s++) {
@@ -459,10 +446,10 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
         const int cx[4] = {0, 1, 1, 0}, cy[4] = {0, 0, 1, 1};
         const int lin[4] = {0, 2, 1, 3}, lout[4] = {2, 1, 3, 0};
         double ex[2], ey[2];
-        ex[0] = Gr.per[0] ? -(0.5 * Gr.L[0]) : (Gr.lo[0] - p[0]);
-        ex[1] = Gr.per[0] ? 0.5 * Gr.L[0] : (Gr.hi[0] - p[0]);
-        ey[0] = Gr.per[1] ? -(0.5 * Gr.L[1]) : (Gr.lo[1] - p[1]);
-        ey[1] = Gr.per[1] ? 0.5 * Gr.L[1] : (Gr.hi[1] - p[1]);
+        ex[0] = -box_side(T, p[0], 0, 0, id).off;
+        ex[1] = box_side(T, p[0], 0, 1, id).off;
+        ey[0] = -box_side(T, p[1], 1, 0, id).off;
+        ey[1] = box_side(T, p[1], 1, 1, id).off;
         c.tp[0] = (uint32_t)lin[gl] | ((uint32_t)lout[gl] << 8);
         c.vx[0] = ex[cx[gl]];
         c.vy[0] = ey[cy[gl]];

@@ -438,30 +438,19 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         mrg[d] = fmin(p[d] - blo, blo + G.bs[d] - p[d]);
     }
     Cell<S, MAXP, F32> c;
-    // box planes (Eq. 1-2): walls, or bisectors with the own images at +-L
+    // box planes (Eq. 1-2, clipped as in section 3.1.3); no register array
+    // is indexed by d
     if (lane < 6) {
-        int d = lane >> 1, side = lane & 1;
-        double sg = side ? 1.0 : -1.0;
-        double n[3] = {0.0, 0.0, 0.0};
-        double h;
-        if (G.per[d]) {
-            double L = G.L[d];
-            n[d] = sg * L;
-            h = 0.5 * (L * L);
-            sh.pwall[lane] = 0;
-            sh.plab[lane] = id;
-            sh.psh[lane] = (uint8_t)(kNoShift + (side ? 1 : -1) * (d == 0 ? 1 : (d == 1 ? 5 : 25)));
-        } else {
-            n[d] = sg;
-            h = side ? (G.hi[d] - p[d]) : -(G.lo[d] - p[d]);
-            sh.pwall[lane] = 1;
-            sh.plab[lane] = -(2 * d + side + 1);
-            sh.psh[lane] = kNoShift;
-        }
-        sh.pq[lane][0] = n[0];
-        sh.pq[lane][1] = n[1];
-        sh.pq[lane][2] = n[2];
-        sh.pq[lane][3] = h;
+        const int d = lane >> 1, side = lane & 1;
+        const double pd = d == 0 ? p[0] : (d == 1 ? p[1] : p[2]);
+        const BoxSide b = box_side(T, pd, d, side, id);
+        sh.pwall[lane] = (uint8_t)b.wall;
+        sh.plab[lane] = b.lab;
+        sh.psh[lane] = b.code;
+        sh.pq[lane][0] = d == 0 ? b.nd : 0.0;
+        sh.pq[lane][1] = d == 1 ? b.nd : 0.0;
+        sh.pq[lane][2] = d == 2 ? b.nd : 0.0;
+        sh.pq[lane][3] = b.h;
     }
     // corners: triangle (X, Y, Z) counter-clockwise when det(nX, nY, nZ) > 0
 #pragma unroll
@@ -480,9 +469,9 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         double e[3];
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            int b = (lane >> d) & 1;
-            if (G.per[d]) e[d] = b ? 0.5 * G.L[d] : -(0.5 * G.L[d]);
-            else e[d] = b ? (G.hi[d] - p[d]) : (G.lo[d] - p[d]);
+            const int b = (lane >> d) & 1;
+            const double o = box_side(T, p[d], d, b, id).off;
+            e[d] = b ? o : -o;
         }
         c.vx[0] = e[0];
         c.vy[0] = e[1];

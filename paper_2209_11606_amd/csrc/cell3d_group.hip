@@ -292,29 +292,17 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP> &sh, SC
 #pragma unroll
     for (int d = 0; d < 3; d++) sh.gs.bc[d] = block_coord(G3, sh.gs.p[d], d);
     if (gl < 6) {
-        // face 2d + side of the box; no register array is indexed by d
+        // face 2d + side of the box (Eq. 1-2, clipped as in section 3.1.3)
         const int d = gl >> 1, side = gl & 1;
-        const double sg = side ? 1.0 : -1.0;
         const double pd = d == 0 ? sh.gs.p[0] : (d == 1 ? sh.gs.p[1] : sh.gs.p[2]);
-        double nn, h;
-        if (G3.per[d]) {
-            double L = G3.L[d];
-            nn = sg * L;
-            h = 0.5 * (L * L);
-            sh.pwall[gl] = 0;
-            sh.plab[gl] = sh.gs.id;
-            sh.psh[gl] = (uint8_t)(kNoShift + (side ? 1 : -1) * (d == 0 ? 1 : (d == 1 ? 5 : 25)));
-        } else {
-            nn = sg;
-            h = side ? (G3.hi[d] - pd) : -(G3.lo[d] - pd);
-            sh.pwall[gl] = 1;
-            sh.plab[gl] = -(2 * d + side + 1);
-            sh.psh[gl] = kNoShift;
-        }
-        sh.pq[gl][0] = d == 0 ? nn : 0.0;
-        sh.pq[gl][1] = d == 1 ? nn : 0.0;
-        sh.pq[gl][2] = d == 2 ? nn : 0.0;
-        sh.pq[gl][3] = h;
+        const BoxSide b = box_side(sh.T, pd, d, side, sh.gs.id);
+        sh.pwall[gl] = (uint8_t)b.wall;
+        sh.plab[gl] = b.lab;
+        sh.psh[gl] = b.code;
+        sh.pq[gl][0] = d == 0 ? b.nd : 0.0;
+        sh.pq[gl][1] = d == 1 ? b.nd : 0.0;
+        sh.pq[gl][2] = d == 2 ? b.nd : 0.0;
+        sh.pq[gl][3] = b.h;
     }
 #pragma unroll
     for (int s = 0; s < S; s++) {
@@ -333,9 +321,9 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP> &sh, SC
         double e[3];
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            int b = (gl >> d) & 1;
-            if (G3.per[d]) e[d] = b ? 0.5 * G3.L[d] : -(0.5 * G3.L[d]);
-            else e[d] = b ? (G3.hi[d] - sh.gs.p[d]) : (G3.lo[d] - sh.gs.p[d]);
+            const int b = (gl >> d) & 1;
+            const double o = box_side(sh.T, sh.gs.p[d], d, b, sh.gs.id).off;
+            e[d] = b ? o : -o;
         }
         c.vx[0] = e[0];
         c.vy[0] = e[1];

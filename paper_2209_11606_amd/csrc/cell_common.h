@@ -347,6 +347,49 @@ __device__ __forceinline__ void cramer(const double *A, const double *B, const d
     z = (A[3] * bc2 + B[3] * ca2 + C[3] * ab2) * inv;
 }
 
+// The initial plane on one side of axis d (Eq. 1-2): the wall, or on a
+// periodic axis the bisector with the particle's own image at +-L; with
+// clipping (section 3.1.3) the clip wall at half the cube's side, where that
+// lies strictly inside.  `off` is the corner coordinate's magnitude.
+struct BoxSide {
+    double nd, h, off;  // normal along d, offset, corner offset
+    int wall;
+    int32_t lab;
+    uint8_t code;
+};
+
+__device__ __forceinline__ BoxSide box_side(const Tess &T, double pd, int d, int side, int32_t self)
+{
+    const Grid &G = T.G;
+    const double sg = side ? 1.0 : -1.0;
+    const double off = G.per[d] ? 0.5 * G.L[d] : (side ? (G.hi[d] - pd) : -(G.lo[d] - pd));
+    BoxSide b;
+    if (T.clip_half > 0.0 && T.clip_half < off) {
+        b.nd = sg;
+        b.h = T.clip_half;
+        b.off = T.clip_half;
+        b.wall = 1;
+        b.lab = -(7 + 2 * d + side);
+        b.code = kNoShift;
+    } else if (G.per[d]) {
+        const double L = G.L[d];
+        b.nd = sg * L;
+        b.h = 0.5 * (L * L);
+        b.off = off;
+        b.wall = 0;
+        b.lab = self;
+        b.code = (uint8_t)(kNoShift + (side ? 1 : -1) * (d == 0 ? 1 : (d == 1 ? 5 : 25)));
+    } else {
+        b.nd = sg;
+        b.h = off;
+        b.off = off;
+        b.wall = 1;
+        b.lab = -(2 * d + side + 1);
+        b.code = kNoShift;
+    }
+    return b;
+}
+
 enum { ST_OK = 0, ST_CAP = 1, ST_DUP = 3 };
 enum { DC_CAND, DC_TESTS, DC_CUTS, DC_NEWV, DC_EXACT, DC_RECHECK, DC_SPILL, DC_BLOCKS, DC_FALLBACK, DC_N };
 

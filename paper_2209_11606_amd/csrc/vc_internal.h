@@ -50,12 +50,14 @@ struct Tess {
     int32_t bbase;   // first block in the shared block arrays
     int32_t pad;
     double bsmin2;   // squared smallest block side
+    double clip_half; // half the side of the clip cube (section 3.1.3), 0: none
 };
 
 // Block offset relative to a particle's own block.  m = sum over axes of
-// max(|d|-1, 0)^2: the squared gap to that block in units of the block side,
-// so m * bsmin2 bounds the distance from any point of the own block from
-// below.  The list is sorted by m (nearest first).
+// max(|d|-1, 0)^2 is the squared gap to that block in units of the block
+// side, so m * bsmin2 bounds the distance from any point of the own block
+// from below; it is stored capped at kOffRadius^2, the smallest such bound of
+// any block outside the list.  The list is sorted by m (nearest first).
 struct Offset {
     int dx, dy, dz, m;
 };

@@ -32,7 +32,7 @@ class vc_options(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("periodic", ctypes.c_int * 3), ("n_opt", ctypes.c_double), ("grid", ctypes.c_int * 3),
                 ("precision", ctypes.c_int), ("slots", ctypes.c_int), ("waves", ctypes.c_int),
-                ("chunk", ctypes.c_int), ("cells_per_wave", ctypes.c_int)]
+                ("chunk", ctypes.c_int), ("cells_per_wave", ctypes.c_int), ("clip", ctypes.c_double)]
 
 
 class vc_tuning(ctypes.Structure):

@@ -106,6 +106,36 @@ def periodic_102m(seed=5, n=102_400_000):
                 periodic=[1, 1, 1])
 
 
+def localized(n_prime=10_000_000, dim=3, seed=6):
+    """Localized case of section 3.1: n_prime uniform points in the walled unit
+    box, keeping those inside the central cube (square) of volume (area) 0.1,
+    about n_prime / 10 points.  The grid follows the paper's table for this
+    case (N_opt 49 in 3D, 30 in 2D; n = floor((n_prime / N_opt)^(1/dim)),
+    126^3 and 1825^2 for n_prime = 10^8), and clip is the side of the cube
+    the paper clips each cell with in 3D, h = 1.5 sqrt(3) d0 with
+    d0 = n_prime^(-1/3) (section 3.1.3)."""
+    x = uniform(n_prime, dim, 1.0, seed)
+    half = 0.5 * 0.1 ** (1.0 / dim)
+    x = x[np.all(np.abs(x - 0.5) <= half, axis=1)]
+    n_opt = 49.0 if dim == 3 else 30.0
+    g = int(math.floor((n_prime / n_opt) ** (1.0 / dim)))
+    clip = 1.5 * math.sqrt(3.0) * n_prime ** (-1.0 / 3.0) if dim == 3 else 0.0
+    return dict(name=f"localized_{dim}d_{n_prime}", xyz=np.ascontiguousarray(x), lo=[0.0] * dim, hi=[1.0] * dim,
+                periodic=[0] * dim, grid=[g] * dim, n_opt=n_opt, clip=clip)
+
+
+def clustered(n=1_000_000, dim=3, seed=7):
+    """Extreme clustering of section 3.1: each coordinate is 1/2 + 4 (X - 1/2)^3
+    with X uniform on [0, 1), in the walled unit box, so points crowd the
+    planes x = 1/2 (and y, z = 1/2).  N_opt = 0.5 as in the paper's table:
+    n = floor((n / 0.5)^(1/dim)) blocks per axis (584 in 3D for 10^8)."""
+    X = rng(seed).random((n, dim))
+    x = 0.5 + 4.0 * (X - 0.5) ** 3
+    g = int(math.floor((n / 0.5) ** (1.0 / dim)))
+    return dict(name=f"clustered_{dim}d_{n}", xyz=x, lo=[0.0] * dim, hi=[1.0] * dim, periodic=[0] * dim,
+                grid=[g] * dim, n_opt=0.5, clip=0.0)
+
+
 def batch_sizes(count=4096, lo=100, hi=100_000, seed=1000):
     """Log-uniform tessellation sizes round(exp(U[ln lo, ln hi]))."""
     u = rng(seed).random(count)

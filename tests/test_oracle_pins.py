@@ -227,6 +227,48 @@ def test_invariants_periodic_and_2d():
     assert int(r["nf"].sum()) == 6 * len(x)  # torus, all vertices of degree 3
 
 
+def test_imbalanced_workloads():
+    """The localized and extreme-clustering sets of section 3.1, scaled down:
+    the cells tile the walled box, Euler and neighbour symmetry hold, and
+    cells of a small clustered set (centre and periphery) match the exact
+    brute force."""
+    for w in (W.localized(60_000), W.clustered(20_000)):
+        x = w["xyz"]
+        r = oracle.Oracle(x, w["lo"], w["hi"], w["periodic"], grid=w["grid"]).cells(nthreads=8)
+        _invariants(x, w["lo"], w["hi"], w["periodic"], r)
+    w = W.clustered(150, seed=8)
+    r = oracle.Oracle(w["xyz"], w["lo"], w["hi"], w["periodic"], grid=w["grid"]).cells()
+    for i in range(0, 150, 10):
+        _same_cell(r, i, brute.cell(w["xyz"], i, w["lo"], w["hi"], w["periodic"]))
+
+
+def test_clipping_changes_only_cells_that_reach_the_cube():
+    """Clipping (section 3.1.3) on the localized set with the paper's side
+    h = 1.5 sqrt(3) d0: every clipped cell lies in its cube, a cell with no
+    clip face is the unclipped cell, and the clipped cells include the
+    extended ones on the cluster's surface."""
+    w = W.localized(60_000)
+    x, h = w["xyz"], w["clip"]
+    o1 = oracle.Oracle(x, w["lo"], w["hi"], w["periodic"], grid=w["grid"])
+    o2 = oracle.Oracle(x, w["lo"], w["hi"], w["periodic"], grid=w["grid"], clip=h)
+    r1 = o1.cells(nthreads=8)
+    r2 = o2.cells(nthreads=8)
+    assert np.all(r2["vol"] <= h ** 3 * (1 + 1e-12))
+    assert np.all(r2["vol"] <= r1["vol"] * (1 + 1e-12))
+    has_clip = np.array([bool(np.any(l[:, 0] <= -7)) for l in r2["nbr"]])
+    assert 0 < has_clip.sum() < len(x)
+    assert np.all(r1["vol"][has_clip] > r2["vol"][has_clip])
+    big = r1["vol"] > h ** 3
+    assert np.all(has_clip[big])  # an unclipped cell larger than the cube must be clipped
+    for i in np.flatnonzero(~has_clip):
+        for k in ("nv", "ne", "nf", "fo"):
+            assert np.array_equal(r1[k][i], r2[k][i])
+        assert abs(r1["vol"][i] - r2["vol"][i]) <= 1e-12 * r1["vol"][i]
+    for i in np.flatnonzero(has_clip)[:50]:
+        v = o2.vertices(i)
+        assert np.all(np.abs(v) <= 0.5 * h * (1 + 1e-15))
+
+
 def test_empty_sphere_certificate():
     """Termination: for every vertex v of cell i no particle (or image) lies
     strictly inside the sphere of radius |v| about p_i + v; equivalently no
