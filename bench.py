@@ -19,12 +19,13 @@ one launch -- over its HIP-event duration, against the FP64 vector peak.
 The cpu_baseline object times the oracle on the host cores on a bounded
 sample of the same workload; cpu_serial times it on one thread.
 binning_roofline is the rebin alone (HIP events) against the HBM peak, with
-212 algorithmic bytes per particle; end_to_end is one pass from positions in
+188 algorithmic bytes per particle; end_to_end is one pass from positions in
 pinned host memory to every result field in host memory (PCIe included),
 reported beside `value`, never as it.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -38,9 +39,10 @@ COUNTERS = os.path.join(ROOT, "profiles", "cells_periodic1M_counters.md")
 KERNEL_SOURCES = ["cell3d.hip", "cell3d_group.hip", "cell_common.h", "vc_internal.h"]
 HBM_PEAK = 8.0e12  # B/s
 # rebin of one particle: device copy of the positions (24 B read + 24 B
-# written), block count (24 B read, 8 B written), scatter (24 + 12 B read,
-# 32 B written), in-block order (32 B read + 32 B written)
-BIN_BYTES_PER_PARTICLE = 212
+# written), block count (24 B read, 8 B written), provisional slot (12 B read,
+# 4 B written), rank by id and final scatter (24 B of position, 16 B of
+# index, block and range, ~20 B of the block's ids read; 32 B written)
+BIN_BYTES_PER_PARTICLE = 188
 FP64_VECTOR_PEAK = 78.6e12  # FLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FLOP_WEIGHTS = dict(candidates=9, vertex_tests=6, new_vertices=12, fan_triangles=28)
 
@@ -57,7 +59,8 @@ def parse():
                    help="first copy a device buffer of this size (reference for HBM byte counters)")
     p.add_argument("--variants", default="all", help="comma list of variants to run (default all)")
     p.add_argument("--workload", default="periodic1m",
-                   choices=["periodic1m", "batch4096", "fcc10m", "periodic2d10m", "periodic102m"],
+                   choices=["periodic1m", "batch4096", "fcc10m", "periodic2d10m", "periodic102m",
+                            "localized10m", "clustered10m"],
                    help="periodic1m: the metric's configuration (default); the others measure the remaining sets")
     return p.parse_args()
 
@@ -109,10 +112,21 @@ def _timed(torch, stream, steps, step_fn):
     return t0.elapsed_time(t1) / steps
 
 
+def options(v, w, **kw):
+    """vc_options of a workload: its box, and its grid and clip side if set."""
+    extra = {}
+    if w.get("grid"):
+        extra["grid"] = w["grid"]
+    if w.get("clip"):
+        extra["clip"] = w["clip"]
+    extra.update(kw)
+    return v.vc_options_init(len(w["lo"]), w["lo"], w["hi"], w["periodic"], **extra)
+
+
 def time_variant(v, torch, xt, w, precision, steps, warmup, mask):
     """Plain form: one container; step = rebin + compute."""
     stream = torch.cuda.current_stream()
-    o = v.vc_options_init(xt.shape[1], w["lo"], w["hi"], w["periodic"], precision=precision)
+    o = options(v, w, precision=precision)
     c = v.vc_container_create(xt, o, stream)
     r = v.vc_result_create(c, mask)
     kms = []
@@ -137,7 +151,7 @@ def time_binning(v, torch, xt, w, steps):
     """Binning alone: vc_container_rebin on HBM-resident positions (copy,
     count, scan, scatter, in-block order, range check), HIP events."""
     stream = torch.cuda.current_stream()
-    o = v.vc_options_init(xt.shape[1], w["lo"], w["hi"], w["periodic"])
+    o = options(v, w)
     c = v.vc_container_create(xt, o, stream)
     try:
         ms = _timed(torch, stream, steps, lambda: v.vc_container_rebin(c, xt, stream))
@@ -158,8 +172,7 @@ def end_to_end(v, torch, xyz, w, precision, mask, reps=3):
     host = torch.from_numpy(xyz).pin_memory()
     n, dim = xyz.shape
     # the fastest plain form: two cells per wave in 3D
-    o = v.vc_options_init(dim, w["lo"], w["hi"], w["periodic"], precision=precision,
-                          cells_per_wave=2 if dim == 3 else 0)
+    o = options(v, w, precision=precision, cells_per_wave=2 if dim == 3 else 0)
     c = v.vc_container_create(host, o, stream)
     r = v.vc_result_create(c, mask)
     try:
@@ -228,7 +241,7 @@ def cpu_baseline(members, sample):
     for m in members:
         if done >= sample:
             break
-        o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"])
+        o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"], grid=m.get("grid"), clip=m.get("clip", 0.0))
         k = min(sample - done, len(m["xyz"]))
         idx = np.arange(k, dtype=np.int64)
         t = time.perf_counter()
@@ -251,7 +264,7 @@ def cpu_serial(members, sample):
     import oracle
     m = members[0]
     k = min(sample, len(m["xyz"]))
-    o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"])
+    o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"], grid=m.get("grid"), clip=m.get("clip", 0.0))
     t = time.perf_counter()
     o.cells(np.arange(k, dtype=np.int64), nthreads=1, neighbors=False)
     secs = time.perf_counter() - t
@@ -290,6 +303,20 @@ def main():
         desc = ("periodic_uniform_102M: 102,400,000 uniform particles, periodic unit cube, "
                 "face-order vector and neighbour count only")
         sample_desc = "first {} cells of the 102.4M set"
+    elif a.workload == "localized10m":
+        w = W.localized(100_000_000)
+        # N_opt 5 over the occupied central cube (volume 0.1)
+        w["grid"] = [int(math.ceil((len(w["xyz"]) / (5.0 * 0.1)) ** (1.0 / 3.0)))] * 3
+        members = [w]
+        desc = ("localized_clipped_10M: 10^8 uniform points in the walled unit cube, the ~10^7 inside the "
+                "central cube of volume 0.1 kept, each cell clipped by the cube of side 1.5*sqrt(3)*1e-8^(1/3) "
+                "(section 3.1.3), full statistics")
+        sample_desc = "first {} cells of the localized set"
+    elif a.workload == "clustered10m":
+        members = [W.clustered(10_000_000)]
+        desc = ("extreme_clustering_10M: 10^7 points with coordinates 1/2 + 4 (X - 1/2)^3, walled unit cube, "
+                "N_opt 0.5 grid (section 3.1), full statistics")
+        sample_desc = "first {} cells of the clustered set"
     else:
         members = W.batch(4096)
         desc = ("batch_4096: 4,096 independent 3D tessellations, sizes log-uniform in [100, 100000], "
@@ -320,7 +347,7 @@ def main():
         variants = [x for x in variants if x[0] in keep]
     for name, prec, batched in variants:
         if batched:
-            opts = [v.vc_options_init(3, m["lo"], m["hi"], m["periodic"], precision=prec) for m in members]
+            opts = [options(v, m, precision=prec) for m in members]
             res[name] = time_batched(v, torch, xt, offsets, opts, a.steps, a.warmup, mask)
         else:
             res[name] = time_variant(v, torch, xt, members[0], prec, a.steps, a.warmup, mask)

@@ -178,6 +178,7 @@ struct vc_container {
     int32_t *count = nullptr;    // nb
     int32_t *blk = nullptr;      // n
     int32_t *rank = nullptr;     // n
+    int32_t *sid = nullptr;      // n: input index at each provisional slot
     int32_t *err = nullptr;      // range-error flag
     int32_t *scan_tmp = nullptr;
     Offset *offs = nullptr;
@@ -235,7 +236,7 @@ void free_container(vc_container *c)
 {
     if (!c) return;
     release_graph(c);
-    void *ps[] = {c->tess, c->ptess, c->xyz, c->part, c->start, c->count, c->blk, c->rank, c->err, c->scan_tmp,
+    void *ps[] = {c->tess, c->ptess, c->xyz, c->part, c->start, c->count, c->blk, c->rank, c->sid, c->err, c->scan_tmp,
                   c->offs, c->queue, c->spill_list, c->sample_list, c->xscratch};
     for (void *p : ps)
         if (p) (void)hipFree(p);
@@ -260,8 +261,7 @@ vc_status bin(vc_container *c, hipStream_t s)
     HIP_TRY(launch_fill_i32(c->err, 1, 0, s));
     HIP_TRY(launch_bin_count(c->xyz, c->n, c->dim, c->tess, c->ptess, c->blk, c->rank, c->count, c->err, s));
     HIP_TRY(launch_scan(c->count, c->start, c->nb, c->scan_tmp, s));
-    HIP_TRY(launch_scatter(c->xyz, c->n, c->dim, c->ptess, c->blk, c->rank, c->start, c->part, s));
-    HIP_TRY(launch_block_order(c->part, c->start, c->nb, s));
+    HIP_TRY(launch_scatter(c->xyz, c->n, c->dim, c->ptess, c->blk, c->rank, c->start, c->sid, c->part, s));
     return VC_OK;
 }
 
@@ -330,6 +330,7 @@ vc_status create_common(vc_container *c, const double *xyz, const int64_t *offse
     TRY(dalloc(&c->count, (size_t)nb));
     TRY(dalloc(&c->blk, (size_t)c->n));
     TRY(dalloc(&c->rank, (size_t)c->n));
+    TRY(dalloc(&c->sid, (size_t)c->n));
     TRY(dalloc(&c->err, 1));
     TRY(dalloc(&c->scan_tmp, (size_t)ntiles * 2));
     TRY(dalloc(&c->offs, offs.size()));

@@ -1,12 +1,13 @@
 // binning.hip -- container construction on the GPU: block index per
-// particle, per-block counts, exclusive scan, scatter into a block-sorted
-// particle array, and a deterministic in-block order (by input id).
+// particle, per-block counts, exclusive scan, and a scatter into a
+// block-sorted particle array in a deterministic in-block order (by input id).
 //
 // This replaces the serial put() and the atomic slot capture of the paper's
 // parallel insertion (section 2.2.5): the atomic counter gives each particle
-// a slot, and an exact prefix sum over the counts sizes every block, so no
-// overflow buffer is needed.  Sorting each block by id removes the run-to-run
-// order dependence that the paper notes for parallel insertion.
+// a provisional slot, and an exact prefix sum over the counts sizes every
+// block, so no overflow buffer is needed.  The final slot is the particle's
+// rank by id inside its block, which removes the run-to-run order dependence
+// that the paper notes for parallel insertion.
 #include "vc_internal.h"
 
 namespace vc {
@@ -123,37 +124,44 @@ __global__ void k_store_total(const T *__restrict__ total, T *__restrict__ dst)
     *dst = *total;
 }
 
-__global__ __launch_bounds__(kTB) void k_scatter(const double *__restrict__ xyz, int64_t n, int dim,
-                                                 const int32_t *__restrict__ ptess, const int32_t *__restrict__ blk,
-                                                 const int32_t *__restrict__ rank, const int32_t *__restrict__ start,
-                                                 Particle *__restrict__ part)
+// provisional slots: the input index of each particle at its atomic slot
+__global__ __launch_bounds__(kTB) void k_scatter_ids(int64_t n, const int32_t *__restrict__ blk,
+                                                     const int32_t *__restrict__ rank, const int32_t *__restrict__ start,
+                                                     int32_t *__restrict__ sid)
 {
-    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
-        Particle p;
-        p.x = xyz[i * dim];
-        p.y = xyz[i * dim + 1];
-        p.z = dim == 3 ? xyz[i * dim + 2] : 0.0;
-        p.id = (int32_t)i;
-        p.tess = ptess ? ptess[i] : 0;
-        part[start[blk[i]] + rank[i]] = p;
-    }
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+        sid[start[blk[i]] + rank[i]] = (int32_t)i;
 }
 
-// one thread per block: insertion sort of the block's particles by id
-__global__ __launch_bounds__(kTB) void k_block_order(Particle *__restrict__ part, const int32_t *__restrict__ start,
-                                                     int64_t nb)
+// final slots: one thread per provisional slot counts the smaller input
+// indices of its block (the threads of a wave share a block and read the
+// same ids), and writes the particle record there.  Linear in the block's
+// size per particle, parallel over the block's particles.
+__global__ __launch_bounds__(kTB) void k_rank_scatter(const double *__restrict__ xyz, int64_t n, int dim,
+                                                      const int32_t *__restrict__ ptess, const int32_t *__restrict__ blk,
+                                                      const int32_t *__restrict__ start, const int32_t *__restrict__ sid,
+                                                      Particle *__restrict__ part)
 {
-    for (int64_t b = (int64_t)blockIdx.x * kTB + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kTB) {
-        int s = start[b], e = start[b + 1];
-        for (int i = s + 1; i < e; i++) {
-            Particle v = part[i];
-            int j = i - 1;
-            while (j >= s && part[j].id > v.id) {
-                part[j + 1] = part[j];
-                j--;
-            }
-            part[j + 1] = v;
+    for (int64_t t = (int64_t)blockIdx.x * kTB + threadIdx.x; t < n; t += (int64_t)gridDim.x * kTB) {
+        const int32_t i = sid[t];
+        const int32_t b = blk[i];
+        const int s = start[b], e = start[b + 1];
+        int r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+        int u = s;
+        for (; u + 3 < e; u += 4) {
+            r0 += sid[u] < i;
+            r1 += sid[u + 1] < i;
+            r2 += sid[u + 2] < i;
+            r3 += sid[u + 3] < i;
         }
+        for (; u < e; u++) r0 += sid[u] < i;
+        Particle p;
+        p.x = xyz[(int64_t)i * dim];
+        p.y = xyz[(int64_t)i * dim + 1];
+        p.z = dim == 3 ? xyz[(int64_t)i * dim + 2] : 0.0;
+        p.id = i;
+        p.tess = ptess ? ptess[i] : 0;
+        part[s + r0 + r1 + r2 + r3] = p;
     }
 }
 
@@ -228,15 +236,10 @@ hipError_t launch_scan(const int32_t *count, int32_t *start, int64_t nb, int32_t
 }
 
 hipError_t launch_scatter(const double *xyz, int64_t n, int dim, const int32_t *ptess, const int32_t *blk,
-                          const int32_t *rank, const int32_t *start, Particle *part, hipStream_t s)
+                          const int32_t *rank, const int32_t *start, int32_t *sid, Particle *part, hipStream_t s)
 {
-    k_scatter<<<grid_for(n), kTB, 0, s>>>(xyz, n, dim, ptess, blk, rank, start, part);
-    return hipGetLastError();
-}
-
-hipError_t launch_block_order(Particle *part, const int32_t *start, int64_t nb, hipStream_t s)
-{
-    k_block_order<<<grid_for(nb), kTB, 0, s>>>(part, start, nb);
+    k_scatter_ids<<<grid_for(n), kTB, 0, s>>>(n, blk, rank, start, sid);
+    k_rank_scatter<<<grid_for(n), kTB, 0, s>>>(xyz, n, dim, ptess, blk, start, sid, part);
     return hipGetLastError();
 }
 
