@@ -80,7 +80,8 @@ enum {
 #define VC_DIAG_LEN 16
 
 /* per-cell status (VC_F_STATUS) */
-enum { VC_CELL_OK = 0, VC_CELL_SPILLED = 1, VC_CELL_CAPACITY = 2, VC_CELL_DUPLICATE = 3 };
+enum { VC_CELL_OK = 0, VC_CELL_SPILLED = 1, VC_CELL_CAPACITY = 2, VC_CELL_DUPLICATE = 3,
+       VC_CELL_SKIPPED = 4 /* not in the list of vc_compute_subset */ };
 
 /* diagnostic counters (VC_F_DIAG) */
 enum {
@@ -158,6 +159,18 @@ vc_status vc_result_create(const vc_container *c, uint32_t mask, vc_result **out
  * start, nearest-first bisector cuts, radius-bound termination, statistics).
  * Asynchronous on `stream`. */
 vc_status vc_compute(vc_container *c, vc_result *r, void *stream);
+
+/* Compute the cells of a subset of the particles (the paper's subset and
+ * ordered iterators, section 2.2.2): ids holds m input indices (0 <= m <= n,
+ * each in [0, n); host or device int64 array, detected as for positions),
+ * taken through the same work queue.  Only the listed cells' fields are
+ * written; every other cell gets status VC_CELL_SKIPPED, face count 0 and an
+ * empty neighbour list, and its other fields are left as they were.  A
+ * listed cell is bitwise the cell vc_compute gives.  An index out of range
+ * is VC_E_RANGE (checked before any cell is computed; a device list is
+ * checked on the device, and the call then waits for that check).  A repeated
+ * index computes its cell twice. */
+vc_status vc_compute_subset(vc_container *c, vc_result *r, const int64_t *ids, int64_t m, void *stream);
 
 /* Elapsed time in milliseconds of the main cell kernel of the last
  * vc_compute on r (HIP events recorded around that launch on its stream).

@@ -179,6 +179,9 @@ struct vc_container {
     int32_t *blk = nullptr;      // n
     int32_t *rank = nullptr;     // n
     int32_t *sid = nullptr;      // n: input index at each provisional slot
+    int32_t *inv = nullptr;      // n: sorted slot of each input index
+    int32_t *subset = nullptr;   // n: sorted slots of a subset (vc_compute_subset), on first use
+    int64_t *subset_ids = nullptr; // n: the subset's input indices copied from the host, on first use
     int32_t *err = nullptr;      // range-error flag
     int32_t *scan_tmp = nullptr;
     Offset *offs = nullptr;
@@ -236,7 +239,7 @@ void free_container(vc_container *c)
 {
     if (!c) return;
     release_graph(c);
-    void *ps[] = {c->tess, c->ptess, c->xyz, c->part, c->start, c->count, c->blk, c->rank, c->sid, c->err, c->scan_tmp,
+    void *ps[] = {c->tess, c->ptess, c->xyz, c->part, c->start, c->count, c->blk, c->rank, c->sid, c->inv, c->subset, c->subset_ids, c->err, c->scan_tmp,
                   c->offs, c->queue, c->spill_list, c->sample_list, c->xscratch};
     for (void *p : ps)
         if (p) (void)hipFree(p);
@@ -261,7 +264,7 @@ vc_status bin(vc_container *c, hipStream_t s)
     HIP_TRY(launch_fill_i32(c->err, 1, 0, s));
     HIP_TRY(launch_bin_count(c->xyz, c->n, c->dim, c->tess, c->ptess, c->blk, c->rank, c->count, c->err, s));
     HIP_TRY(launch_scan(c->count, c->start, c->nb, c->scan_tmp, s));
-    HIP_TRY(launch_scatter(c->xyz, c->n, c->dim, c->ptess, c->blk, c->rank, c->start, c->sid, c->part, s));
+    HIP_TRY(launch_scatter(c->xyz, c->n, c->dim, c->ptess, c->blk, c->rank, c->start, c->sid, c->part, c->inv, s));
     return VC_OK;
 }
 
@@ -331,6 +334,7 @@ vc_status create_common(vc_container *c, const double *xyz, const int64_t *offse
     TRY(dalloc(&c->blk, (size_t)c->n));
     TRY(dalloc(&c->rank, (size_t)c->n));
     TRY(dalloc(&c->sid, (size_t)c->n));
+    TRY(dalloc(&c->inv, (size_t)c->n));
     TRY(dalloc(&c->err, 1));
     TRY(dalloc(&c->scan_tmp, (size_t)ntiles * 2));
     TRY(dalloc(&c->offs, offs.size()));
@@ -388,7 +392,7 @@ CellArgs cell_args(const vc_container *c, const vc_result *r)
 // The launch sequence of one compute (graph-capturable: fill kernels, no
 // memset; events only when `events` is set).
 vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool events, const Launch &L,
-                          const int32_t *cell_list = nullptr, int ncell = -1)
+                          const int32_t *cell_list = nullptr, int ncell = -1, bool compact_subset = false)
 {
     CellArgs A = cell_args(c, r);
     A.chunk = L.chunk;
@@ -413,7 +417,7 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
     B.chunk = 1;
     if (c->dim == 2) HIP_TRY(launch_cells2d_spill(B, std::min(c->max_waves, 1024), s));
     else HIP_TRY(launch_cells_spill(B, std::min(c->max_waves, 1024), s));
-    if ((r->mask & VC_NEIGHBORS) && !cell_list) {
+    if ((r->mask & VC_NEIGHBORS) && (!cell_list || compact_subset)) {
         // CSR offsets by a scan of the face counts, then each cell's sorted
         // labels copied to its offset (capacity n * kMaxNbr always suffices)
         HIP_TRY(launch_nbr_offsets(r->nf, r->n, r->off, r->scan_tmp, s));
@@ -557,6 +561,44 @@ vc_status vc_compute(vc_container *c, vc_result *r, void *stream)
     if (!c || !r) return fail(VC_E_ARG, "vc_compute: null handle");
     if (r->c != c) return fail(VC_E_STATE, "vc_compute: result was created for another container");
     return enqueue_compute(c, r, (hipStream_t)stream, true, c->launch);
+}
+
+vc_status vc_compute_subset(vc_container *c, vc_result *r, const int64_t *ids, int64_t m, void *stream)
+{
+    if (!c || !r || (m > 0 && !ids)) return fail(VC_E_ARG, "vc_compute_subset: null argument");
+    if (r->c != c) return fail(VC_E_STATE, "vc_compute_subset: result was created for another container");
+    if (m < 0 || m > c->n) return fail(VC_E_ARG, "vc_compute_subset: need 0 <= m <= n (m = %lld)", (long long)m);
+    hipStream_t s = (hipStream_t)stream;
+    vc_status st;
+#define TRY(x)              \
+    do {                    \
+        st = (x);           \
+        if (st) return st;  \
+    } while (0)
+    if (!c->subset) TRY(dalloc(&c->subset, (size_t)c->n));
+    const int64_t *dids = ids;
+    if (m > 0 && !is_device_ptr(ids)) {
+        for (int64_t k = 0; k < m; k++)
+            if (ids[k] < 0 || ids[k] >= c->n)
+                return fail(VC_E_RANGE, "vc_compute_subset: index %lld outside [0, n)", (long long)ids[k]);
+        if (!c->subset_ids) TRY(dalloc(&c->subset_ids, (size_t)c->n));
+        HIP_TRY(hipMemcpyAsync(c->subset_ids, ids, (size_t)m * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        dids = c->subset_ids;
+    }
+#undef TRY
+    // the listed cells' sorted slots; a device list is range-checked here
+    HIP_TRY(launch_fill_i32(c->err, 1, 0, s));
+    HIP_TRY(launch_subset_list(dids, m, c->n, c->inv, c->subset, c->err, s));
+    if (m > 0 && is_device_ptr(ids)) {
+        int32_t herr = 0;
+        HIP_TRY(hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (herr) return fail(VC_E_RANGE, "vc_compute_subset: an index lies outside [0, n)");
+    }
+    // cells not listed: status VC_CELL_SKIPPED, no faces (empty neighbour lists)
+    HIP_TRY(launch_fill_u8(r->status, r->n, VC_CELL_SKIPPED, s));
+    if (r->nf) HIP_TRY(launch_fill_i32(r->nf, r->n, 0, s));
+    return enqueue_compute(c, r, s, true, c->launch, c->subset, (int)m, true);
 }
 
 vc_status vc_result_kernel_ms(vc_result *r, float *ms)

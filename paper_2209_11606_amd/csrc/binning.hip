@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kTB) void k_scatter_ids(int64_t n, const int32_t *_
 __global__ __launch_bounds__(kTB) void k_rank_scatter(const double *__restrict__ xyz, int64_t n, int dim,
                                                       const int32_t *__restrict__ ptess, const int32_t *__restrict__ blk,
                                                       const int32_t *__restrict__ start, const int32_t *__restrict__ sid,
-                                                      Particle *__restrict__ part)
+                                                      Particle *__restrict__ part, int32_t *__restrict__ inv)
 {
     for (int64_t t = (int64_t)blockIdx.x * kTB + threadIdx.x; t < n; t += (int64_t)gridDim.x * kTB) {
         const int32_t i = sid[t];
@@ -161,8 +161,32 @@ __global__ __launch_bounds__(kTB) void k_rank_scatter(const double *__restrict__
         p.z = dim == 3 ? xyz[(int64_t)i * dim + 2] : 0.0;
         p.id = i;
         p.tess = ptess ? ptess[i] : 0;
-        part[s + r0 + r1 + r2 + r3] = p;
+        const int slot = s + r0 + r1 + r2 + r3;
+        part[slot] = p;
+        inv[i] = slot;
     }
+}
+
+// sorted slots of a list of input indices (a subset of the cells); an index
+// outside [0, n) sets the error flag
+__global__ __launch_bounds__(kTB) void k_subset_list(const int64_t *__restrict__ ids, int64_t m, int64_t n,
+                                                     const int32_t *__restrict__ inv, int32_t *__restrict__ out,
+                                                     int32_t *__restrict__ err)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kTB + threadIdx.x; k < m; k += (int64_t)gridDim.x * kTB) {
+        const int64_t i = ids[k];
+        if (i < 0 || i >= n) {
+            atomicOr(err, 1);
+            out[k] = 0;
+        } else {
+            out[k] = inv[i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kTB) void k_fill_u8(uint8_t *p, int64_t n, uint8_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) p[i] = v;
 }
 
 __global__ __launch_bounds__(kTB) void k_fill(int32_t *p, int64_t n, int32_t v)
@@ -236,10 +260,24 @@ hipError_t launch_scan(const int32_t *count, int32_t *start, int64_t nb, int32_t
 }
 
 hipError_t launch_scatter(const double *xyz, int64_t n, int dim, const int32_t *ptess, const int32_t *blk,
-                          const int32_t *rank, const int32_t *start, int32_t *sid, Particle *part, hipStream_t s)
+                          const int32_t *rank, const int32_t *start, int32_t *sid, Particle *part, int32_t *inv,
+                          hipStream_t s)
 {
     k_scatter_ids<<<grid_for(n), kTB, 0, s>>>(n, blk, rank, start, sid);
-    k_rank_scatter<<<grid_for(n), kTB, 0, s>>>(xyz, n, dim, ptess, blk, start, sid, part);
+    k_rank_scatter<<<grid_for(n), kTB, 0, s>>>(xyz, n, dim, ptess, blk, start, sid, part, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_subset_list(const int64_t *ids, int64_t m, int64_t n, const int32_t *inv, int32_t *out,
+                              int32_t *err, hipStream_t s)
+{
+    if (m > 0) k_subset_list<<<grid_for(m), kTB, 0, s>>>(ids, m, n, inv, out, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s)
+{
+    if (n > 0) k_fill_u8<<<grid_for(n), kTB, 0, s>>>(p, n, v);
     return hipGetLastError();
 }
 

@@ -99,7 +99,11 @@ hipError_t launch_bin_count(const double *xyz, int64_t n, int dim, const Tess *t
                             int32_t *blk, int32_t *rank, int32_t *count, int32_t *err, hipStream_t s);
 hipError_t launch_scan(const int32_t *count, int32_t *start, int64_t nb, int32_t *tmp, hipStream_t s);
 hipError_t launch_scatter(const double *xyz, int64_t n, int dim, const int32_t *ptess, const int32_t *blk,
-                          const int32_t *rank, const int32_t *start, int32_t *sid, Particle *part, hipStream_t s);
+                          const int32_t *rank, const int32_t *start, int32_t *sid, Particle *part, int32_t *inv,
+                          hipStream_t s);
+hipError_t launch_subset_list(const int64_t *ids, int64_t m, int64_t n, const int32_t *inv, int32_t *out,
+                              int32_t *err, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_cells(const CellArgs &a, int precision, int slots, int waves, hipStream_t s);
 hipError_t launch_cells_spill(const CellArgs &a, int waves, hipStream_t s);

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvorohip.so")
 
 VC_OK, VC_E_ARG, VC_E_RANGE, VC_E_DUPLICATE, VC_E_NOMEM, VC_E_HIP, VC_E_CAPACITY, VC_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+VC_CELL_OK, VC_CELL_SPILLED, VC_CELL_CAPACITY, VC_CELL_DUPLICATE, VC_CELL_SKIPPED = 0, 1, 2, 3, 4
 VC_FP64, VC_F32_FILTER = 0, 1
 VC_VOLUME, VC_CENTROID, VC_COUNTS, VC_FACE_ORDERS, VC_NEIGHBORS, VC_NEIGHBOR_COUNT, VC_DIAG = 1, 2, 4, 8, 16, 32, 64
 VC_ALL = 127
@@ -60,6 +61,7 @@ def _load():
         "vc_grid_size": (I32, [P, I64, P]),
         "vc_container_blocks": (I32, [P, P, P, P]),
         "vc_compute": (I32, [P, P, P]),
+        "vc_compute_subset": (I32, [P, P, P, I64, P]),
         "vc_result_get": (I32, [P, I32, P, P]),
         "vc_result_copy": (I32, [P, I32, P, I64]),
         "vc_result_destroy": (None, [P]),
@@ -83,7 +85,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_grid_size", "vc_container_blocks",
-            "vc_result_create", "vc_compute",
+            "vc_result_create", "vc_compute", "vc_compute_subset",
             "vc_result_get", "vc_result_copy", "vc_result_kernel_ms", "vc_result_destroy", "vc_container_destroy", "vc_batch_create",
             "vc_batch_rebin", "vc_batch_result_create", "vc_batch_compute", "vc_batch_tune", "vc_batch_destroy",
             "vc_last_error", "vc_version"]
@@ -167,6 +169,19 @@ def vc_result_create(c, mask):
 
 def vc_compute(c, r, stream=None):
     _check(_lib.vc_compute(c, r, ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def vc_compute_subset(c, r, ids, stream=None):
+    """ids: int64 input indices, a numpy array (host) or a torch tensor
+    (host or device)."""
+    if hasattr(ids, "data_ptr"):
+        if ids.dtype != __import__("torch").int64 or not ids.is_contiguous():
+            raise ValueError("vc_compute_subset: ids must be a contiguous int64 tensor")
+        ptr, m = ids.data_ptr(), ids.numel()
+    else:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        ptr, m = ids.ctypes.data, ids.size
+    _check(_lib.vc_compute_subset(c, r, ctypes.c_void_p(ptr), int(m), ctypes.c_void_p(_stream_ptr(stream))))
 
 
 def vc_result_get(r, field):

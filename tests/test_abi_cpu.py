@@ -57,6 +57,11 @@ def test_argument_validation_without_gpu():
     assert L.vc_container_create(x.ctypes.data, 4, ctypes.byref(bad), None, ctypes.byref(h)) == v.VC_E_ARG
     assert L.vc_result_create(None, v.VC_ALL, ctypes.byref(h)) == v.VC_E_ARG
     assert L.vc_compute(None, None, None) == v.VC_E_ARG
+    assert L.vc_compute_subset(None, None, None, 0, None) == v.VC_E_ARG
+    bad = v.vc_options_init(3, [0, 0, 0], [1, 1, 1], [0, 0, 0])
+    bad.clip = -1.0
+    assert L.vc_container_create(x.ctypes.data, 4, ctypes.byref(bad), None, ctypes.byref(h)) == v.VC_E_ARG
+    assert "clip" in v.vc_last_error()
     assert L.vc_result_get(None, 0, None, None) == v.VC_E_ARG
     assert L.vc_result_kernel_ms(None, None) == v.VC_E_ARG
     assert v.vc_version().startswith("vorohip")

@@ -95,3 +95,45 @@ def test_clip_argument_errors(v):
         with pytest.raises(v.VcError) as e:
             v.tessellate(xt, [0] * 3, [1] * 3, [0, 0, 0], clip=bad)
         assert e.value.code == v.VC_E_ARG
+
+
+def test_subset_compute(v):
+    """vc_compute_subset (the subset and ordered iterators of section 2.2.2):
+    listed cells are bitwise the full computation's, in any order and from a
+    host or device list; the others are VC_CELL_SKIPPED with empty neighbour
+    lists; out-of-range indices are rejected before anything runs."""
+    x = W.uniform(20_000, 3, 20_000 ** (1 / 3), 81)
+    hi = [20_000 ** (1 / 3)] * 3
+    xt = torch.from_numpy(x).to("cuda:0")
+    full = v.tessellate(xt, [0] * 3, hi, [1, 1, 1], v.VC_ALL, cells_per_wave=2)
+    ids = np.random.default_rng(3).permutation(20_000)[:2_500].astype(np.int64)
+    o = v.vc_options_init(3, [0] * 3, hi, [1, 1, 1], cells_per_wave=2)
+    c = v.vc_container_create(xt, o)
+    r = v.vc_result_create(c, v.VC_ALL)
+    try:
+        for lst in (ids, torch.from_numpy(ids[::-1].copy()).to("cuda:0")):
+            v.vc_compute_subset(c, r, lst)
+            torch.cuda.synchronize()
+            g = v.fetch(r, v.VC_ALL, 20_000)
+            for k in ("vol", "cen", "nv", "ne", "nf", "fo", "status"):
+                assert np.array_equal(g[k][ids], full[k][ids]), k
+            skipped = np.ones(20_000, bool)
+            skipped[ids] = False
+            assert np.all(g["status"][skipped] == v.VC_CELL_SKIPPED)
+            assert np.all(g["nf"][skipped] == 0)
+            gl, fl = v.neighbor_lists(g), v.neighbor_lists(full)
+            for i in ids[:200]:
+                assert np.array_equal(gl[i], fl[i])
+            assert all(len(gl[i]) == 0 for i in np.flatnonzero(skipped)[:200])
+        v.vc_compute_subset(c, r, np.zeros(0, np.int64))
+        assert np.all(v.fetch(r, v.VC_ALL, 20_000)["status"] == v.VC_CELL_SKIPPED)
+        for bad in (np.array([5, 20_000]), torch.tensor([3, -1], dtype=torch.int64, device="cuda:0")):
+            with pytest.raises(v.VcError) as e:
+                v.vc_compute_subset(c, r, bad)
+            assert e.value.code == v.VC_E_RANGE
+        with pytest.raises(v.VcError) as e:
+            v.vc_compute_subset(c, r, np.arange(20_001))
+        assert e.value.code == v.VC_E_ARG
+    finally:
+        v.vc_result_destroy(r)
+        v.vc_container_destroy(c)
