@@ -56,6 +56,8 @@ def _load():
         lib.vo_create.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, P, P]
         lib.vo_destroy.argtypes = [P]
         lib.vo_set_clip.argtypes = [P, ctypes.c_double]
+        lib.vo_set_radii.restype = ctypes.c_int
+        lib.vo_set_radii.argtypes = [P, P]
         lib.vo_cells.restype = ctypes.c_int
         lib.vo_cells.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                                  P, P, P, P, P, P, P, P, ctypes.c_int, P, P, P]
@@ -90,9 +92,13 @@ def exact_side(rows, dim=3):
 class Oracle:
     """Serial FP64 cells of a container (box [lo, hi], per-axis periodicity).
     clip > 0 clips every cell by the cube of that side centred on its
-    particle (section 3.1.3)."""
+    particle (section 3.1.3).  radii (n values) makes it the radical
+    tessellation of the polydisperse container (section 2.1.1); a cell that
+    comes out empty has status 1 (EMPTY) and zero volume, counts and faces."""
 
-    def __init__(self, xyz, lo, hi, periodic, grid=None, n_opt=5.0, clip=0.0):
+    EMPTY = 1
+
+    def __init__(self, xyz, lo, hi, periodic, grid=None, n_opt=5.0, clip=0.0, radii=None):
         lib = _load()
         self.xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64))
         self.n, self.dim = self.xyz.shape
@@ -117,6 +123,11 @@ class Oracle:
             raise ValueError("oracle: bad container arguments")
         self.clip = float(clip)
         lib.vo_set_clip(self._h, self.clip)
+        self.radii = None
+        if radii is not None:
+            self.radii = np.ascontiguousarray(np.asarray(radii, dtype=np.float64))
+            if self.radii.shape != (self.n,) or lib.vo_set_radii(self._h, self.radii.ctypes.data) != 0:
+                raise ValueError("oracle: radii must be n finite values >= 0")
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -31,9 +31,11 @@ def _box_offset(p, lo, hi, periodic, d, side):
     return float(hi[d]) - p[d] if side else -(float(lo[d]) - p[d])
 
 
-def _planes(xyz, i, lo, hi, periodic, clip=0.0):
+def _planes(xyz, i, lo, hi, periodic, clip=0.0, radii=None):
     dim = xyz.shape[1]
     p = xyz[i]
+    # radical planes: |x|^2 - ri^2 <= |x - q|^2 - rj^2, i.e. x.q <= (q.q + ri^2 - rj^2) / 2
+    rr = None if radii is None else [Fr(float(r)) * Fr(float(r)) for r in radii]
     planes = []  # (normal tuple of Fr, offset Fr, label, image code, float |q|^2)
     # box planes: walls, or bisectors with own images at +-L e_d; with
     # clipping, a clip wall at h/2 on every side where it lies strictly inside
@@ -69,18 +71,21 @@ def _planes(xyz, i, lo, hi, periodic, clip=0.0):
                 q.append(v)
             qf = [Fr(v) for v in q]
             h = sum(v * v for v in qf) / 2
+            if rr is not None:
+                h += (rr[i] - rr[j]) / 2
             planes.append((tuple(qf), h, j, _shift_code(s), float(sum(v * v for v in q))))
     return planes
 
 
-def cell(xyz, i, lo, hi, periodic, clip=0.0):
+def cell(xyz, i, lo, hi, periodic, clip=0.0, radii=None):
     """Exact cell of particle i (clipped by the cube of side `clip` centred
-    on the particle when clip > 0).  Returns dict(vol, cen, nv, ne, nf, fo,
-    nbr) with vol and cen as Fractions and nbr sorted (label, image) pairs."""
+    on the particle when clip > 0; the radical cell when radii are given).
+    Returns dict(vol, cen, nv, ne, nf, fo, nbr, empty) with vol and cen as
+    Fractions and nbr sorted (label, image) pairs."""
     xyz = np.asarray(xyz, dtype=np.float64)
     dim = xyz.shape[1]
     p = xyz[i]
-    planes = _planes(xyz, i, lo, hi, periodic, clip)
+    planes = _planes(xyz, i, lo, hi, periodic, clip, radii)
     # initial box: corners tight at one plane per axis (its offset along d)
     ext = []
     for d in range(dim):
@@ -109,6 +114,10 @@ def cell(xyz, i, lo, hi, periodic, clip=0.0):
         if max(ss) <= 0:
             verts = [(pt, tg | {k}) if s == 0 else (pt, tg) for (pt, tg), s in zip(verts, ss)]
             continue
+        if min(ss) >= 0:
+            # no vertex strictly inside: nothing with volume is left
+            return dict(vol=Fr(0), cen=tuple(Fr(0) for _ in range(dim)), nv=0, ne=0, nf=0, fo=[0] * 32,
+                        nbr=[], empty=True)
         new = []
         for (pt, tg), s in zip(verts, ss):
             if s < 0:
@@ -149,29 +158,39 @@ def _stats(verts, planes, dim):
     fo = [0] * 32
     for k, vs in faces.items():
         pts = [verts[v][0] for v in vs]
+        # signed pieces (origin, face): the particle need not lie inside its
+        # cell (radical cells), so each face is oriented by its outward normal
+        n = planes[k][0]
         if dim == 3:
-            ring = _ring(pts, planes[k][0])
+            ring = _ring(pts, n)
             if len(pts) < 32:
                 fo[len(pts)] += 1
             a = ring[0]
+            u = [ring[1][d] - a[d] for d in range(3)]
+            w = [ring[2][d] - a[d] for d in range(3)]
+            tn = (u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0])
+            sgn = 1 if sum(tn[d] * n[d] for d in range(3)) > 0 else -1
             for t in range(1, len(ring) - 1):
                 b, c = ring[t], ring[t + 1]
                 det = (a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0])
                        + a[2] * (b[0] * c[1] - b[1] * c[0]))
-                tv = abs(det) / 6
+                tv = sgn * det / 6
                 vol += tv
                 for d in range(3):
                     cen[d] += tv * (a[d] + b[d] + c[d]) / 4
         else:
             a, b = pts
-            tri = abs(a[0] * b[1] - a[1] * b[0]) / 2
+            # traverse the edge so that its outward normal is on the right
+            if (b[1] - a[1]) * n[0] - (b[0] - a[0]) * n[1] < 0:
+                a, b = b, a
+            tri = (a[0] * b[1] - a[1] * b[0]) / 2
             vol += tri
             for d in range(2):
                 cen[d] += tri * (a[d] + b[d]) / 3
     cen = [c / vol for c in cen]
     nbr = sorted((planes[k][2], planes[k][3]) for k in faces)
     ne = len(edges)
-    return dict(vol=vol, cen=cen, nv=nv, ne=ne if dim == 3 else nv, nf=len(faces), fo=fo, nbr=nbr)
+    return dict(vol=vol, cen=cen, nv=nv, ne=ne if dim == 3 else nv, nf=len(faces), fo=fo, nbr=nbr, empty=False)
 
 
 def _ring(pts, normal):

@@ -50,7 +50,7 @@
 #define VO_MAXFV 128  /* vertices per face */
 #define VO_FO 32      /* length of the face-order vector */
 
-enum { VO_OK = 0, VO_ERR_CAP = -1, VO_ERR_TOPO = -2, VO_ERR_ARG = -3, VO_ERR_MEM = -4 };
+enum { VO_OK = 0, VO_EMPTY = 1, VO_ERR_CAP = -1, VO_ERR_TOPO = -2, VO_ERR_ARG = -3, VO_ERR_MEM = -4 };
 
 /* counters (per call, summed over cells) */
 enum { C_CAND = 0, C_RREJ, C_TESTS, C_CUTS, C_NEWV, C_TRIS, C_EXACT, C_SHELLS, C_AUDIT, C_AUDIT_BAD, C_NCOUNT };
@@ -231,10 +231,13 @@ typedef struct {
     double h;     /* kept side n.r <= h; FP64 value of q.q/2 for a bisector */
     int wall;     /* 1: axis-aligned wall with exact (n, h) */
     int32_t label;  /* neighbour id j, or -1..-6 for the walls x-,x+,y-,y+,z-,z+ */
+    int radical;    /* radical plane: h = (q.q + ri^2 - rj^2) / 2 */
+    double ri, rj;  /* radii of the cell's particle and of the neighbour */
     int32_t shift;  /* periodic image code 25(sz+2)+5(sy+2)+(sx+2) */
 } oplane;
 
-/* exact offset h of a plane: q.q/2 for a bisector, the stored value for a wall */
+/* exact offset h of a plane: q.q/2 for a bisector, (q.q + ri^2 - rj^2)/2 for
+ * a radical plane, the stored value for a wall */
 static void x_plane_h(const oplane *p, int dim, xnum *r)
 {
     static _Thread_local xnum a, sq, acc, t;
@@ -243,6 +246,17 @@ static void x_plane_h(const oplane *p, int dim, xnum *r)
     for (int d = 0; d < dim; d++) {
         x_from_double(&a, p->n[d]);
         x_mul(&a, &a, &sq);
+        x_add(&acc, &sq, &t);
+        acc = t;
+    }
+    if (p->radical) {
+        x_from_double(&a, p->ri);
+        x_mul(&a, &a, &sq);
+        x_add(&acc, &sq, &t);
+        acc = t;
+        x_from_double(&a, p->rj);
+        x_mul(&a, &a, &sq);
+        sq.sign = -sq.sign;
         x_add(&acc, &sq, &t);
         acc = t;
     }
@@ -510,13 +524,21 @@ static int solve2(const oplane *a, const oplane *b, double *out)
 /* Cut the 3D cell by plane *P.  Returns 1 if it cut, 0 if not, <0 on error. */
 static int cut3(ocell *c, const oplane *P)
 {
-    int any = 0;
+    int any = 0, inside = 0;
     for (int i = 0; i < c->nv; i++) {
         c->sg[i] = (signed char)decide(c, i, P);
         if (c->sg[i] > 0) any = 1;
+        if (c->sg[i] < 0) inside = 1;
     }
     c->cnt[C_TESTS] += c->nv;
     if (!any) return 0;
+    if (!inside) {
+        /* no vertex strictly inside: what is left has no volume (radical
+         * planes can remove a whole cell) */
+        c->nv = 0;
+        c->nf = 0;
+        return 2;
+    }
     if (c->np >= VO_MAXP) return VO_ERR_CAP;
     int pid = c->np++;
     c->pl[pid] = *P;
@@ -631,14 +653,20 @@ static int cut3(ocell *c, const oplane *P)
 /* Cut the 2D polygon by line *P. */
 static int cut2(ocell *c, const oplane *P)
 {
-    int any = 0;
+    int any = 0, inside = 0;
     for (int k = 0; k < c->pn; k++) {
         int v = c->pv[k];
         c->sg[v] = (signed char)decide(c, v, P);
         if (c->sg[v] > 0) any = 1;
+        if (c->sg[v] < 0) inside = 1;
     }
     c->cnt[C_TESTS] += c->pn;
     if (!any) return 0;
+    if (!inside) {
+        c->nv = 0;
+        c->pn = 0;
+        return 2;
+    }
     if (c->np >= VO_MAXP) return VO_ERR_CAP;
     int pid = c->np++;
     c->pl[pid] = *P;
@@ -703,6 +731,8 @@ typedef struct vo_handle {
     double *xyz;     /* n x 3 (z = 0 in 2D) */
     int *blk;        /* block index per particle */
     double clip;     /* side of the clip cube, 0: none */
+    double *rad;     /* radii (radical tessellation), NULL: Voronoi */
+    double rmax;     /* largest radius */
 } vo_handle;
 
 static int block_coord(const vo_handle *H, double x, int d)
@@ -765,9 +795,31 @@ void vo_set_clip(vo_handle *H, double h)
     if (H) H->clip = h > 0.0 ? h : 0.0;
 }
 
+/* Radical (power) tessellation: the cell of i is the set of points x with
+ * |x - p_i|^2 - r_i^2 <= |x - p_j|^2 - r_j^2 for every j (the radical Voronoi
+ * tessellation that the paper's polydisperse container computes, section
+ * 2.1.1).  r: n radii, or NULL for the plain Voronoi tessellation. */
+int vo_set_radii(vo_handle *H, const double *r)
+{
+    if (!H) return VO_ERR_ARG;
+    free(H->rad);
+    H->rad = NULL;
+    H->rmax = 0.0;
+    if (!r) return VO_OK;
+    H->rad = (double *)malloc((size_t)H->n * sizeof(double));
+    if (!H->rad) return VO_ERR_MEM;
+    for (int64_t i = 0; i < H->n; i++) {
+        if (!(r[i] >= 0.0) || !isfinite(r[i])) return VO_ERR_ARG;
+        H->rad[i] = r[i];
+        if (r[i] > H->rmax) H->rmax = r[i];
+    }
+    return VO_OK;
+}
+
 void vo_destroy(vo_handle *H)
 {
     if (!H) return;
+    free(H->rad);
     free(H->xyz);
     free(H->blk);
     free(H->start);
@@ -786,10 +838,22 @@ static int cand_cmp(const void *a, const void *b)
 }
 
 /* Compute the cell of particle i.  Returns VO_OK or an error code. */
+/* Squared search radius: a candidate at distance d can cut only if some
+ * vertex v (|v| <= R) has v.q > h, i.e. d^2 - 2Rd + ri^2 - rj^2 < 0, so d < R +
+ * sqrt(R^2 + rmax^2 - ri^2); without radii that is 2R. */
+static double search_r2(const vo_handle *H, double r2, double ri)
+{
+    if (!H->rad) return 4.0 * r2;
+    double t = r2 + H->rmax * H->rmax - ri * ri;
+    double l = sqrt(r2) + sqrt(t > 0.0 ? t : 0.0);
+    return l * l * (1.0 + 0x1p-40);
+}
+
 static int compute_cell(const vo_handle *H, int64_t i, ocell *c, ocand **cbuf, int64_t *ccap)
 {
     const int dim = H->dim;
     const double *p = &H->xyz[3 * i];
+    const double ri = H->rad ? H->rad[i] : 0.0;
     c->dim = dim;
     cell_init(c, p, H->lo, H->hi, H->per, (int32_t)i, H->clip);
     double r2 = max_r2(c);
@@ -815,7 +879,7 @@ static int compute_cell(const vo_handle *H, int64_t i, ocell *c, ocand **cbuf, i
                 if (H->per[d] || b[d] - r >= 0 || b[d] + r < H->g[d]) exists = 1;
             }
             if (!exists) break;
-            if (lb > 0 && lb * lb >= 4.0 * r2) break;
+            if (lb > 0 && lb * lb >= search_r2(H, r2, ri)) break;
         }
         c->cnt[C_SHELLS]++;
         int rz = dim == 3 ? r : 0;
@@ -870,18 +934,28 @@ static int compute_cell(const vo_handle *H, int64_t i, ocell *c, ocand **cbuf, i
             ocand *o = &(*cbuf)[t];
             c->cnt[C_CAND]++;
             if (o->d2 == 0.0) return VO_ERR_ARG; /* coincident particles */
-            if (o->d2 >= 4.0 * r2) { c->cnt[C_RREJ]++; continue; }
+            if (o->d2 >= search_r2(H, r2, ri)) { c->cnt[C_RREJ]++; continue; }
             oplane P;
             memset(&P, 0, sizeof(P));
             P.wall = 0;
             P.n[0] = o->q[0];
             P.n[1] = o->q[1];
             P.n[2] = o->q[2];
-            P.h = 0.5 * o->d2;
+            if (H->rad) {
+                /* radical plane: |x|^2 - ri^2 <= |x - q|^2 - rj^2 */
+                const double rj = H->rad[o->j];
+                P.radical = 1;
+                P.ri = ri;
+                P.rj = rj;
+                P.h = 0.5 * (o->d2 + (ri * ri - rj * rj));
+            } else {
+                P.h = 0.5 * o->d2;
+            }
             P.label = (int32_t)o->j;
             P.shift = o->shift;
             int rc = dim == 3 ? cut3(c, &P) : cut2(c, &P);
             if (rc < 0) return rc;
+            if (rc == 2) return VO_EMPTY;
             if (rc > 0) r2 = max_r2(c);
         }
     }
@@ -901,11 +975,23 @@ static void stats3(ocell *c, ostats *st, int32_t *nbr, int32_t *nsh, int maxnb)
     double vol = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
     int e2 = 0;
     memset(st->fo, 0, sizeof(st->fo));
+    /* tetrahedra (o, f0, fk, fk+1) from the particle (o = 0) when it lies
+     * strictly inside the cell (every face offset h > 0: always so for a
+     * Voronoi cell), else from one vertex of the cell, so that every term is
+     * >= 0 also for a radical cell that misses its particle */
+    static const double zero[3] = {0.0, 0.0, 0.0};
+    int inside = 1;
+    for (int f = 0; f < c->nf; f++)
+        if (!(c->pl[c->fplane[f]].h > 0.0)) inside = 0;
+    const double *o = inside ? zero : c->v[c->fv[0][0]];
     for (int f = 0; f < c->nf; f++) {
         int n = c->fn[f];
-        const double *a = c->v[c->fv[f][0]];
+        const double *a0 = c->v[c->fv[f][0]];
+        const double a[3] = {a0[0] - o[0], a0[1] - o[1], a0[2] - o[2]};
         for (int k = 1; k + 1 < n; k++) {
-            const double *b = c->v[c->fv[f][k]], *d = c->v[c->fv[f][k + 1]];
+            const double *b0 = c->v[c->fv[f][k]], *d0 = c->v[c->fv[f][k + 1]];
+            const double b[3] = {b0[0] - o[0], b0[1] - o[1], b0[2] - o[2]};
+            const double d[3] = {d0[0] - o[0], d0[1] - o[1], d0[2] - o[2]};
             double det = a[0] * (b[1] * d[2] - b[2] * d[1]) - a[1] * (b[0] * d[2] - b[2] * d[0]) +
                          a[2] * (b[0] * d[1] - b[1] * d[0]);
             double tv = det / 6.0;
@@ -923,9 +1009,9 @@ static void stats3(ocell *c, ostats *st, int32_t *nbr, int32_t *nsh, int maxnb)
         }
     }
     st->vol = vol;
-    st->cen[0] = cx / vol;
-    st->cen[1] = cy / vol;
-    st->cen[2] = cz / vol;
+    st->cen[0] = o[0] + cx / vol;
+    st->cen[1] = o[1] + cy / vol;
+    st->cen[2] = o[2] + cz / vol;
     st->nv = c->nv;
     st->ne = e2 / 2;
     st->nf = c->nf;
@@ -937,13 +1023,22 @@ static void stats2(ocell *c, ostats *st, int32_t *nbr, int32_t *nsh, int maxnb)
 {
     double area = 0.0, cx = 0.0, cy = 0.0, per = 0.0;
     int n = c->pn;
+    /* triangles (o, v_k, v_k+1) from the particle when it lies strictly
+     * inside the cell, else from the first vertex (a radical cell that misses
+     * its particle) */
+    static const double zero[3] = {0.0, 0.0, 0.0};
+    int inside = 1;
+    for (int k = 0; k < n; k++)
+        if (!(c->pl[c->pe[k]].h > 0.0)) inside = 0;
+    const double *o = inside ? zero : c->v[c->pv[0]];
     for (int k = 0; k < n; k++) {
-        const double *a = c->v[c->pv[k]], *b = c->v[c->pv[(k + 1) % n]];
+        const double *a0 = c->v[c->pv[k]], *b0 = c->v[c->pv[(k + 1) % n]];
+        const double a[2] = {a0[0] - o[0], a0[1] - o[1]}, b[2] = {b0[0] - o[0], b0[1] - o[1]};
         double cr = a[0] * b[1] - a[1] * b[0];
         area += cr / 2.0;
         cx += cr * (a[0] + b[0]) / 6.0;
         cy += cr * (a[1] + b[1]) / 6.0;
-        double dx = b[0] - a[0], dy = b[1] - a[1];
+        double dx = b0[0] - a0[0], dy = b0[1] - a0[1];
         per += sqrt(dx * dx + dy * dy);
         if (nbr && k < maxnb) {
             nbr[k] = c->pl[c->pe[k]].label;
@@ -953,8 +1048,8 @@ static void stats2(ocell *c, ostats *st, int32_t *nbr, int32_t *nsh, int maxnb)
     }
     memset(st->fo, 0, sizeof(st->fo));
     st->vol = area;
-    st->cen[0] = cx / area;
-    st->cen[1] = cy / area;
+    st->cen[0] = o[0] + cx / area;
+    st->cen[1] = o[1] + cy / area;
     st->cen[2] = 0.0;
     st->perim = per;
     st->nv = n;
@@ -1004,6 +1099,17 @@ int vo_cells(const vo_handle *H, const int64_t *idx, int64_t m, int nthreads, do
             int64_t i = idx[t];
             int rc = (i < 0 || i >= H->n) ? VO_ERR_ARG : compute_cell(H, i, c, &cbuf, &ccap);
             if (status) status[t] = rc;
+            if (rc == VO_EMPTY) {
+                /* an empty radical cell: zero volume, no faces */
+                if (vol) vol[t] = 0.0;
+                if (cen) cen[3 * t] = cen[3 * t + 1] = cen[3 * t + 2] = 0.0;
+                if (nv) nv[t] = 0;
+                if (ne) ne[t] = 0;
+                if (nf) nf[t] = 0;
+                if (fo) memset(fo + (size_t)t * VO_FO, 0, VO_FO * sizeof(int32_t));
+                if (perim) perim[t] = 0.0;
+                continue;
+            }
             if (rc != VO_OK) {
 #ifdef _OPENMP
 #pragma omp critical
@@ -1073,7 +1179,8 @@ int vo_cell_vertices(const vo_handle *H, int64_t i, double tau, double *out, int
     c->tau = tau;
     c->audit = 0;
     int rc = compute_cell(H, i, c, &cbuf, &ccap);
-    if (rc == VO_OK) {
+    if (rc == VO_EMPTY) rc = 0; /* no vertices */
+    else if (rc == VO_OK) {
         int n = H->dim == 3 ? c->nv : c->pn;
         for (int k = 0; k < n && k < maxv; k++) {
             int v = H->dim == 3 ? k : c->pv[k];

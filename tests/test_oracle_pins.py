@@ -21,18 +21,24 @@ from paper_2209_11606_amd import workloads as W
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _same_cell(r, i, b):
+def _same_cell(r, i, b, spacing=0.0):
+    """Topology identical; volume within 1e-13 and centroid within 1e-12 of
+    the cell's size.  spacing > 0 adds an absolute floor of 1e-14 spacing^d
+    (volume) and 1e-13 spacing (centroid): the rounding of FP64 vertices on a
+    sliver cell (radical cells can be arbitrarily thin) is relative to the
+    coordinates, not to the sliver's thickness."""
     assert b["nv"] == r["nv"][i]
     assert b["ne"] == r["ne"][i]
     assert b["nf"] == r["nf"][i]
-    if len(b["cen"]) == 3:
+    dim = len(b["cen"])
+    if dim == 3:
         assert list(b["fo"]) == list(r["fo"][i])
     assert [tuple(t) for t in r["nbr"][i].tolist()] == [tuple(t) for t in b["nbr"]]
     vol = float(b["vol"])
-    assert abs(r["vol"][i] - vol) <= 1e-13 * vol
-    scale = vol ** (1.0 / len(b["cen"]))
+    assert abs(r["vol"][i] - vol) <= 1e-13 * vol + 1e-14 * spacing ** dim
+    scale = vol ** (1.0 / dim)
     for d, c in enumerate(b["cen"]):
-        assert abs(r["cen"][i][d] - float(c)) <= 1e-12 * scale
+        assert abs(r["cen"][i][d] - float(c)) <= 1e-12 * scale + 1e-13 * spacing
 
 
 @pytest.mark.parametrize("n,per,seed", [(30, [0, 0, 0], 7), (24, [1, 1, 1], 8), (20, [1, 0, 1], 11)])
@@ -119,6 +125,50 @@ def test_clip_closed_forms():
     # x: [0, 0.35] (wall x- at 0.1 below), y: [0.25, 0.75], z: [0.45, 0.95]
     assert r["vol"][0] == pytest.approx(0.35 * 0.5 * 0.5, rel=1e-15)
     assert sorted(int(t) for t in r["nbr"][0][:, 0]) == [-12, -11, -10, -9, -8, -1]
+
+
+@pytest.mark.parametrize("dim,per", [(3, [1, 1, 1]), (3, [0, 0, 0]), (2, [1, 1]), (2, [0, 1])])
+def test_brute_force_radical(dim, per):
+    """Radical (power) cells, |x - p_i|^2 - r_i^2 <= |x - p_j|^2 - r_j^2 for
+    every j (the polydisperse container of section 2.1.1), against the exact
+    brute force on sets where some cells come out empty."""
+    n = 24 if dim == 3 else 40
+    x = W.uniform(n, dim, 1.0, 40 + dim)
+    rad = W.rng(41 + dim).random(n) * 1.2 * n ** (-1.0 / dim)
+    r = oracle.Oracle(x, [0] * dim, [1] * dim, per, radii=rad).cells()
+    empty = 0
+    for i in range(n):
+        b = brute.cell(x, i, [0] * dim, [1] * dim, per, radii=rad)
+        assert (r["status"][i] == oracle.Oracle.EMPTY) == b["empty"]
+        empty += b["empty"]
+        _same_cell(r, i, b, spacing=n ** (-1.0 / dim))
+    assert 0 < empty < n
+
+
+def test_radical_closed_forms():
+    """Two particles in the walled unit cube with radii 0.2 and 0.1: the
+    radical plane sits at x = 1/2 + (0.2^2 - 0.1^2) / (2 * 0.5) = 0.53.  Equal
+    radii give the Voronoi tessellation bit for bit, and the cells of a
+    random radical set tile the box."""
+    x = np.array([[0.25, 0.5, 0.5], [0.75, 0.5, 0.5]])
+    r = oracle.Oracle(x, [0] * 3, [1] * 3, [0] * 3, radii=[0.2, 0.1]).cells()
+    assert r["vol"][0] == pytest.approx(0.53, rel=1e-15) and r["vol"][1] == pytest.approx(0.47, rel=1e-15)
+    x = W.uniform(3000, 3, 1.0, 44)
+    v0 = oracle.Oracle(x, [0] * 3, [1] * 3, [1, 1, 1]).cells(nthreads=8)
+    v1 = oracle.Oracle(x, [0] * 3, [1] * 3, [1, 1, 1], radii=np.full(3000, 0.03)).cells(nthreads=8)
+    for k in ("vol", "cen", "nv", "ne", "nf", "fo"):
+        assert np.array_equal(v0[k], v1[k]), k
+    rad = W.rng(45).random(3000) * 0.06
+    rr = oracle.Oracle(x, [0] * 3, [1] * 3, [1, 1, 1], radii=rad).cells(nthreads=8)
+    ok = rr["status"] == 0
+    assert 0 < (~ok).sum() < 3000 and np.all(rr["vol"][~ok] == 0)
+    assert math.fsum(rr["vol"]) == pytest.approx(1.0, rel=1e-12)
+    assert np.all(rr["nv"][ok] - rr["ne"][ok] + rr["nf"][ok] == 2)
+    sets = [set(map(tuple, rr["nbr"][i].tolist())) for i in range(3000)]
+    for i in range(3000):
+        for j, c in sets[i]:
+            if j >= 0:
+                assert any(t[0] == i for t in sets[j])
 
 
 def test_single_and_two_particles():
