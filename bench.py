@@ -60,7 +60,7 @@ def parse():
     p.add_argument("--variants", default="all", help="comma list of variants to run (default all)")
     p.add_argument("--workload", default="periodic1m",
                    choices=["periodic1m", "batch4096", "fcc10m", "periodic2d10m", "periodic102m",
-                            "localized10m", "clustered10m"],
+                            "localized10m", "clustered10m", "polydisperse1m"],
                    help="periodic1m: the metric's configuration (default); the others measure the remaining sets")
     return p.parse_args()
 
@@ -128,6 +128,8 @@ def time_variant(v, torch, xt, w, precision, steps, warmup, mask):
     stream = torch.cuda.current_stream()
     o = options(v, w, precision=precision)
     c = v.vc_container_create(xt, o, stream)
+    if w.get("radii") is not None:
+        v.vc_container_set_radii(c, w["radii"], stream)
     r = v.vc_result_create(c, mask)
     kms = []
 
@@ -174,6 +176,8 @@ def end_to_end(v, torch, xyz, w, precision, mask, reps=3):
     # the fastest plain form: two cells per wave in 3D
     o = options(v, w, precision=precision, cells_per_wave=2 if dim == 3 else 0)
     c = v.vc_container_create(host, o, stream)
+    if w.get("radii") is not None:
+        v.vc_container_set_radii(c, w["radii"], stream)
     r = v.vc_result_create(c, mask)
     try:
         best = None
@@ -193,13 +197,15 @@ def end_to_end(v, torch, xyz, w, precision, mask, reps=3):
                 includes="H2D of positions from pinned memory, binning, cells, compaction, D2H of every field")
 
 
-def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask):
+def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask, radii=None):
     """Batched form: autotuned launch parameters, compute replayed from a
     hipGraph; step = rebin + graph launch.  The cell-kernel duration for the
     roofline comes from eager launches with the same parameters."""
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     b = v.vc_batch_create(xt, offsets, opts, stream)
+    if radii is not None:
+        v.vc_batch_set_radii(b, radii, stream)
     r = v.vc_batch_result_create(b, mask)
     try:
         tuned = v.vc_batch_tune(b, r, stream)
@@ -228,7 +234,9 @@ def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask):
 def _summary(v, r, ms, kernel_ms):
     status = v.vc_result_copy(r, v.VC_F_STATUS)
     diag = dict(zip(v.DIAG_NAMES, v.vc_result_copy(r, v.VC_F_DIAG)[:len(v.DIAG_NAMES)].tolist()))
-    return dict(ms_per_step=ms, kernel_ms=kernel_ms, status_ok=bool(np.all(status <= 1)), diag=diag)
+    ok = (status <= v.VC_CELL_SPILLED) | (status == v.VC_CELL_EMPTY)
+    return dict(ms_per_step=ms, kernel_ms=kernel_ms, status_ok=bool(np.all(ok)), diag=diag,
+                empty_cells=int(np.sum(status == v.VC_CELL_EMPTY)))
 
 
 def cpu_baseline(members, sample):
@@ -241,7 +249,8 @@ def cpu_baseline(members, sample):
     for m in members:
         if done >= sample:
             break
-        o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"], grid=m.get("grid"), clip=m.get("clip", 0.0))
+        o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"], grid=m.get("grid"), clip=m.get("clip", 0.0),
+                          radii=m.get("radii"))
         k = min(sample - done, len(m["xyz"]))
         idx = np.arange(k, dtype=np.int64)
         t = time.perf_counter()
@@ -264,7 +273,8 @@ def cpu_serial(members, sample):
     import oracle
     m = members[0]
     k = min(sample, len(m["xyz"]))
-    o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"], grid=m.get("grid"), clip=m.get("clip", 0.0))
+    o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"], grid=m.get("grid"), clip=m.get("clip", 0.0),
+                      radii=m.get("radii"))
     t = time.perf_counter()
     o.cells(np.arange(k, dtype=np.int64), nthreads=1, neighbors=False)
     secs = time.perf_counter() - t
@@ -317,6 +327,11 @@ def main():
         desc = ("extreme_clustering_10M: 10^7 points with coordinates 1/2 + 4 (X - 1/2)^3, walled unit cube, "
                 "N_opt 0.5 grid (section 3.1), full statistics")
         sample_desc = "first {} cells of the clustered set"
+    elif a.workload == "polydisperse1m":
+        members = [W.polydisperse(1_000_000, 3)]
+        desc = ("polydisperse_radical_1M: radical tessellation of 1,000,000 uniform particles in the periodic "
+                "unit cube, radii uniform on [0, 0.6 n^(-1/3)) (section 2.1.1), full statistics")
+        sample_desc = "first {} cells of the polydisperse set"
     else:
         members = W.batch(4096)
         desc = ("batch_4096: 4,096 independent 3D tessellations, sizes log-uniform in [100, 100000], "
@@ -348,7 +363,10 @@ def main():
     for name, prec, batched in variants:
         if batched:
             opts = [options(v, m, precision=prec) for m in members]
-            res[name] = time_batched(v, torch, xt, offsets, opts, a.steps, a.warmup, mask)
+            radii = None
+            if members[0].get("radii") is not None:
+                radii = np.concatenate([m["radii"] for m in members])
+            res[name] = time_batched(v, torch, xt, offsets, opts, a.steps, a.warmup, mask, radii)
         else:
             res[name] = time_variant(v, torch, xt, members[0], prec, a.steps, a.warmup, mask)
         print(f"# {name}: {res[name]['ms_per_step']:.3f} ms/step, cell kernel {res[name]['kernel_ms']:.3f} ms, "
@@ -384,7 +402,8 @@ def main():
                     kernel="cell construction (" + key + ")", flops_per_cell=flops_per_cell,
                     kernel_ms=b["kernel_ms"])
     out = {
-        "metric": ("3D" if dim == 3 else "2D") + " Voronoi cells/s on 1 MI355X, FP32-filter vs FP64 plain; "
+        "metric": ("3D" if dim == 3 else "2D") + (" radical" if members[0].get("radii") is not None else "")
+                  + " Voronoi cells/s on 1 MI355X, FP32-filter vs FP64 plain; "
                   "oracle-exact topology",
         "value": value,
         "unit": "cells/s",
@@ -399,7 +418,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "tessellations": len(members), "variant": best},
         "variants": {k: dict(cells_per_s=n / (r["ms_per_step"] / 1e3), ms_per_step=r["ms_per_step"],
-                             cell_kernel_ms=r["kernel_ms"], all_cells_ok=r["status_ok"], tuned=r.get("tuned"),
+                             cell_kernel_ms=r["kernel_ms"], all_cells_ok=r["status_ok"],
+                             empty_cells=r["empty_cells"], tuned=r.get("tuned"),
                              diag=r["diag"])
                      for k, r in res.items()},
         "roofline": roof,

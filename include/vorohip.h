@@ -81,7 +81,8 @@ enum {
 
 /* per-cell status (VC_F_STATUS) */
 enum { VC_CELL_OK = 0, VC_CELL_SPILLED = 1, VC_CELL_CAPACITY = 2, VC_CELL_DUPLICATE = 3,
-       VC_CELL_SKIPPED = 4 /* not in the list of vc_compute_subset */ };
+       VC_CELL_SKIPPED = 4, /* not in the list of vc_compute_subset */
+       VC_CELL_EMPTY = 5    /* radical tessellation: the cell has no volume */ };
 
 /* diagnostic counters (VC_F_DIAG) */
 enum {
@@ -137,6 +138,25 @@ vc_status vc_container_create(const double *xyz, int64_t n, const vc_options *op
  * range check.  On VC_E_RANGE the container holds the rejected positions and
  * must be re-binned before the next vc_compute. */
 vc_status vc_container_rebin(vc_container *c, const double *xyz, void *stream);
+
+/* Make the container's tessellation the radical (power) Voronoi tessellation
+ * of a polydisperse system (section 2.1.1): particle i, of radius r_i, owns
+ * the points x with |x - p_i|^2 - r_i^2 <= |x - p_j|^2 - r_j^2 for every j.
+ * Each bisector of Eq. 3 becomes the radical plane of the two particles,
+ * n.x <= (|q|^2 + r_i^2 - r_j^2) / 2 with q the neighbour's position relative
+ * to p_i, and the search radius of a cell whose farthest vertex lies at R
+ * grows from 2R to R + sqrt(R^2 + r_max^2 - r_i^2).  A cell can come out
+ * empty (a small particle inside the power range of larger neighbours): it
+ * gets status VC_CELL_EMPTY, zero volume, centroid and counts, and no faces.
+ * A cell that does not contain its particle has its centroid, as always,
+ * relative to the particle.
+ * radii: n doubles, finite and >= 0, by input index (host or device); the
+ * library copies them and keeps them across vc_container_rebin.  radii = NULL
+ * returns the container to the plain Voronoi tessellation.  Equal radii give
+ * the Voronoi cells.  Errors: VC_E_ARG (null container), VC_E_RANGE (a
+ * negative or non-finite radius; the container is then plain Voronoi),
+ * VC_E_NOMEM.  Synchronises `stream` once (to read the range check). */
+vc_status vc_container_set_radii(vc_container *c, const double *radii, void *stream);
 
 /* Block counts the library uses for n particles in the box of *opt
  * (section 2.1.4: lambda = (N/(N_opt V))^(1/d), n_d = ceil(lambda L_d),
@@ -205,6 +225,11 @@ vc_status vc_batch_create(const double *xyz_concat, const int64_t *offsets, int6
 
 /* Re-bin new positions (same counts) into a batch; as vc_container_rebin. */
 vc_status vc_batch_rebin(vc_batch *b, const double *xyz_concat, void *stream);
+
+/* Radii of every particle of a batch (n_total doubles in xyz_concat order),
+ * or NULL; as vc_container_set_radii, with r_max taken over the whole batch
+ * (a looser but valid search bound). */
+vc_status vc_batch_set_radii(vc_batch *b, const double *radii_concat, void *stream);
 
 /* Allocate a result for a batch (fields as for a container, over all
  * particles of the batch). */

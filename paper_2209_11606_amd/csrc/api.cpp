@@ -184,6 +184,12 @@ struct vc_container {
     int64_t *subset_ids = nullptr; // n: the subset's input indices copied from the host, on first use
     int32_t *err = nullptr;      // range-error flag
     int32_t *scan_tmp = nullptr;
+    // radical tessellation (vc_container_set_radii): radii by input index,
+    // by sorted slot (redone at every binning), and their maximum
+    bool radical = false;
+    double *rad_in = nullptr;
+    double *rad = nullptr;
+    double *rmax = nullptr;
     Offset *offs = nullptr;
     int noff = 0;
     int32_t *queue = nullptr;    // [0]: main queue head, [1]: spill queue head, [2]: spill count
@@ -191,7 +197,7 @@ struct vc_container {
     int32_t *sample_list = nullptr;  // tuning sample (batches)
     int nsample = 0;
     double *xscratch = nullptr;
-    int xscratch_len = 2048;
+    int xscratch_len = 3072;  // doubles: radical offsets make the expansions up to ~1.7x longer
     int max_waves = 0;
     Launch launch;
     // graph replay (batches)
@@ -240,7 +246,7 @@ void free_container(vc_container *c)
     if (!c) return;
     release_graph(c);
     void *ps[] = {c->tess, c->ptess, c->xyz, c->part, c->start, c->count, c->blk, c->rank, c->sid, c->inv, c->subset, c->subset_ids, c->err, c->scan_tmp,
-                  c->offs, c->queue, c->spill_list, c->sample_list, c->xscratch};
+                  c->rad_in, c->rad, c->rmax, c->offs, c->queue, c->spill_list, c->sample_list, c->xscratch};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete c;
@@ -265,6 +271,7 @@ vc_status bin(vc_container *c, hipStream_t s)
     HIP_TRY(launch_bin_count(c->xyz, c->n, c->dim, c->tess, c->ptess, c->blk, c->rank, c->count, c->err, s));
     HIP_TRY(launch_scan(c->count, c->start, c->nb, c->scan_tmp, s));
     HIP_TRY(launch_scatter(c->xyz, c->n, c->dim, c->ptess, c->blk, c->rank, c->start, c->sid, c->part, c->inv, s));
+    if (c->radical) HIP_TRY(launch_radii(c->rad_in, c->n, c->inv, c->rad, c->rmax, c->err, s));
     return VC_OK;
 }
 
@@ -285,6 +292,28 @@ vc_status copy_in_and_bin(vc_container *c, const double *xyz, hipStream_t s)
 
 // Build a container of one or more tessellations.  offsets: ntess + 1 particle
 // offsets (host); opts: ntess options.
+// Radii of the radical tessellation, or none (radii == NULL).
+vc_status set_radii(vc_container *c, const double *radii, hipStream_t s)
+{
+    release_graph(c);  // a captured graph holds the previous cell arguments
+    c->radical = false;
+    if (!radii) return VC_OK;
+    vc_status st;
+    if (!c->rad_in && (st = dalloc(&c->rad_in, (size_t)c->n))) return st;
+    if (!c->rad && (st = dalloc(&c->rad, (size_t)c->n))) return st;
+    if (!c->rmax && (st = dalloc(&c->rmax, 1))) return st;
+    HIP_TRY(hipMemcpyAsync(c->rad_in, radii, (size_t)c->n * sizeof(double),
+                           is_device_ptr(radii) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_i32(c->err, 1, 0, s));
+    HIP_TRY(launch_radii(c->rad_in, c->n, c->inv, c->rad, c->rmax, c->err, s));
+    int32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (herr) return fail(VC_E_RANGE, "a radius is negative or not finite");
+    c->radical = true;
+    return VC_OK;
+}
+
 vc_status create_common(vc_container *c, const double *xyz, const int64_t *offsets, int64_t ntess,
                         const vc_options *opts, hipStream_t s)
 {
@@ -386,6 +415,10 @@ CellArgs cell_args(const vc_container *c, const vc_result *r)
     A.diag = r->diag;
     A.xscratch = c->xscratch;
     A.xscratch_len = c->xscratch_len;
+    if (c->radical) {
+        A.rad = c->rad;
+        A.rmax = c->rmax;
+    }
     return A;
 }
 
@@ -523,6 +556,12 @@ vc_status vc_container_rebin(vc_container *c, const double *xyz, void *stream)
 {
     if (!c || !xyz) return fail(VC_E_ARG, "vc_container_rebin: null pointer");
     return copy_in_and_bin(c, xyz, (hipStream_t)stream);
+}
+
+vc_status vc_container_set_radii(vc_container *c, const double *radii, void *stream)
+{
+    if (!c) return fail(VC_E_ARG, "vc_container_set_radii: null container");
+    return set_radii(c, radii, (hipStream_t)stream);
 }
 
 vc_status vc_result_create(const vc_container *c, uint32_t mask, vc_result **out)
@@ -703,6 +742,12 @@ vc_status vc_batch_rebin(vc_batch *b, const double *xyz_concat, void *stream)
 {
     if (!b || !xyz_concat) return fail(VC_E_ARG, "vc_batch_rebin: null pointer");
     return copy_in_and_bin(b, xyz_concat, (hipStream_t)stream);
+}
+
+vc_status vc_batch_set_radii(vc_batch *b, const double *radii_concat, void *stream)
+{
+    if (!b) return fail(VC_E_ARG, "vc_batch_set_radii: null batch");
+    return set_radii(b, radii_concat, (hipStream_t)stream);
 }
 
 vc_status vc_batch_result_create(const vc_batch *b, uint32_t mask, vc_result **out)

@@ -100,6 +100,7 @@ __device__ __forceinline__ int g2scan(int v, int gl)
 template <int G, int S, int MAXL>
 struct L2 {
     double lq[MAXL][3];   // line normal (n0, n1) and offset h
+    double lrj[MAXL];     // radius of each line's neighbour (radical lines)
     int32_t llab[MAXL];
     uint8_t lsh[MAXL];
     uint8_t lwall[MAXL];
@@ -112,6 +113,8 @@ struct L2 {
         } st;
         struct {
             double cq[G][3];
+            double ch[G];     // line offsets h
+            double crj[G];    // neighbour radii
             int32_t cid[G];
             uint8_t ccode[G];
             double nv[2][2];
@@ -135,6 +138,12 @@ __device__ __forceinline__ PlaneD line_of(const L2<G, S, MAXL> &sh, int k)
     return p;
 }
 
+template <int G, int S, int MAXL>
+__device__ __forceinline__ PlaneR line_r(const L2<G, S, MAXL> &sh, int k, double ri)
+{
+    return PlaneR{line_of(sh, k), ri, sh.lrj[k]};
+}
+
 template <int S, bool F32>
 struct Poly {
     uint32_t tp[S];  // a | b << 8
@@ -143,10 +152,12 @@ struct Poly {
     unsigned long long live[S];
     unsigned long long used;
     double R2, R;
+    double lim;   // squared search radius
+    double ri;    // the particle's radius (radical tessellation), else 0
 };
 
 template <int G, int S, bool F32>
-__device__ __forceinline__ void p_radius(Poly<S, F32> &c, int gl)
+__device__ __forceinline__ void p_radius(Poly<S, F32> &c, int gl, const CellArgs &A)
 {
     double m = 0.0;
 #pragma unroll
@@ -154,20 +165,21 @@ __device__ __forceinline__ void p_radius(Poly<S, F32> &c, int gl)
         if ((c.live[s] >> gl) & 1) m = fmax(m, c.vx[s] * c.vx[s] + c.vy[s] * c.vy[s]);
     c.R2 = g2max<G>(m);
     c.R = sqrt(c.R2);
+    c.lim = search_lim(c.R2, c.R, A, c.ri);
 }
 
 template <int G, int S, int MAXL, bool F32>
 __device__ __forceinline__ int p_consider(const CellArgs &A, L2<G, S, MAXL> &sh, Poly<S, F32> &c, double q0,
-                                          double q1, double d2, int32_t lab, int code, double *ws,
+                                          double q1, double h, double rj, int32_t lab, int code, double *ws,
                                           unsigned long long *cnt, int lane, int gl, int gb)
 {
-    const double h = 0.5 * d2;
-    const double band = A.tau * ((fabs(q0) + fabs(q1)) * c.R + h);
+    const bool rad = A.rad != nullptr;
+    const double band = A.tau * ((fabs(q0) + fabs(q1)) * c.R + fabs(h));
     unsigned long long conf[S], inb[S];
     int ntest = 0;
     if (F32) {
         const float g0 = (float)q0, g1 = (float)q1, gh = (float)h;
-        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1)) * ((float)c.R * 1.0000001f) + gh);
+        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1)) * ((float)c.R * 1.0000001f) + fabsf(gh));
         unsigned long long uns = 0, unsr[S];
 #pragma unroll
         for (int s = 0; s < S; s++) {
@@ -200,20 +212,27 @@ __device__ __forceinline__ int p_consider(const CellArgs &A, L2<G, S, MAXL> &sh,
         }
     }
     cnt[DC_TESTS] += ntest;
+    unsigned long long zero[S];
 #pragma unroll
     for (int s = 0; s < S; s++) {
         unsigned long long wm = __ballot((inb[s] >> gl) & 1);
+        zero[s] = 0;
         while (wm) {
             int l = __builtin_ctzll(wm);
             wm &= wm - 1;
             int sg = 0;
             if (lane == l) {
-                PlaneD pp = {q0, q1, 0.0, h, 0};
-                sg = exact_side2(line_of(sh, c.tp[s] & 0xff), line_of(sh, (c.tp[s] >> 8) & 0xff), pp, ws);
+                const PlaneD pp = {q0, q1, 0.0, h, 0};
+                const int a = c.tp[s] & 0xff, b = (c.tp[s] >> 8) & 0xff;
+                if (rad)
+                    sg = exact_side2(line_r(sh, a, c.ri), line_r(sh, b, c.ri), PlaneR{pp, c.ri, rj}, ws);
+                else
+                    sg = exact_side2(line_of(sh, a), line_of(sh, b), pp, ws);
             }
             sg = __builtin_amdgcn_readlane(sg, l);
             if ((l / G) == (lane / G)) {
                 if (sg > 0) conf[s] |= 1ull << (l % G);
+                if (sg == 0) zero[s] |= 1ull << (l % G);
                 cnt[DC_EXACT]++;
             }
         }
@@ -222,6 +241,17 @@ __device__ __forceinline__ int p_consider(const CellArgs &A, L2<G, S, MAXL> &sh,
 #pragma unroll
     for (int s = 0; s < S; s++) anyc |= conf[s];
     if (!anyc) return ST_OK;
+    if (rad) {
+        // a radical line can leave no vertex strictly inside: empty cell
+        unsigned long long inside = 0;
+#pragma unroll
+        for (int s = 0; s < S; s++) inside |= c.live[s] & ~conf[s] & ~zero[s];
+        if (!inside) {
+#pragma unroll
+            for (int s = 0; s < S; s++) c.live[s] = 0;
+            return ST_EMPTY;
+        }
+    }
 
     // ---- cut ----
     constexpr unsigned long long valid = MAXL >= 64 ? ~0ull : ((1ull << MAXL) - 1ull);
@@ -279,6 +309,7 @@ __device__ __forceinline__ int p_consider(const CellArgs &A, L2<G, S, MAXL> &sh,
         sh.lq[p][0] = q0;
         sh.lq[p][1] = q1;
         sh.lq[p][2] = h;
+        if (A.rad) sh.lrj[p] = rj;
         sh.llab[p] = lab;
         sh.lsh[p] = (uint8_t)code;
         sh.lwall[p] = 0;
@@ -309,7 +340,7 @@ __device__ __forceinline__ int p_consider(const CellArgs &A, L2<G, S, MAXL> &sh,
     }
     c.used |= 1ull << p;
     lds_sync2();
-    p_radius<G, S, F32>(c, gl);
+    p_radius<G, S, F32>(c, gl, A);
     cnt[DC_CUTS]++;
     cnt[DC_NEWV] += 2;
     return c.R2 < 1e300 ? ST_OK : ST_CAP;
@@ -343,7 +374,7 @@ __device__ __forceinline__ int p_gather(const CellArgs &A, L2<G, S, MAXL> &sh, P
         double e = fmax(0.0, fmax(blo - p[d], p[d] - (blo + Gr.bs[d])));
         d2b += e * e;
     }
-    if (d2b >= 4.0 * c.R2 * kMargin) ok = false;
+    if (d2b >= c.lim) ok = false;
     int cntb = 0, beg = 0;
     if (ok) {
         int64_t blk = T.bbase + bb[0] + (int64_t)Gr.g[0] * bb[1];
@@ -376,11 +407,21 @@ __device__ __forceinline__ int p_gather(const CellArgs &A, L2<G, S, MAXL> &sh, P
             if (s0) a0 = a0 + s0 * Gr.L[0];
             if (s1) a1 = a1 + s1 * Gr.L[1];
             double d2 = a0 * a0 + a1 * a1;
+            double h = 0.5 * d2, rj = 0.0;
+            if (A.rad) {
+                // radical line (section 2.1.1): |x|^2 - ri^2 <= |x - q|^2 - rj^2
+                rj = A.rad[idx];
+                h = 0.5 * (d2 + radical_shift(c.ri, rj));
+            }
             bool self = (idx == si) && code == kNoShift;
-            if (!self && d2 < 4.0 * c.R2 * kMargin) key = __double_as_longlong(d2);
+            if (!self && d2 < c.lim) key = __double_as_longlong(d2);
             sh.u.gc.cq[gl][0] = a0;
             sh.u.gc.cq[gl][1] = a1;
             sh.u.gc.cq[gl][2] = d2;
+            if (A.rad) {
+                sh.u.gc.ch[gl] = h;
+                sh.u.gc.crj[gl] = rj;
+            }
             sh.u.gc.cid[gl] = q.id;
             sh.u.gc.ccode[gl] = (uint8_t)code;
         }
@@ -389,12 +430,13 @@ __device__ __forceinline__ int p_gather(const CellArgs &A, L2<G, S, MAXL> &sh, P
             unsigned long long mk = g2min_u64<G>(key);
             if (mk == ~0ull) break;
             double md2 = __longlong_as_double((long long)mk);
-            if (!(md2 < 4.0 * c.R2 * kMargin)) break;
+            if (!(md2 < c.lim)) break;
             int ol = __builtin_ctzll(gb2<G>(key == mk, gb));
             if (gl == ol) key = ~0ull;
             cnt[DC_CAND]++;
             if (md2 == 0.0) return ST_DUP;
-            int st = p_consider<G, S, MAXL, F32>(A, sh, c, sh.u.gc.cq[ol][0], sh.u.gc.cq[ol][1], md2,
+            int st = p_consider<G, S, MAXL, F32>(A, sh, c, sh.u.gc.cq[ol][0], sh.u.gc.cq[ol][1],
+                                                 A.rad ? sh.u.gc.ch[ol] : 0.5 * md2, A.rad ? sh.u.gc.crj[ol] : 0.0,
                                                  sh.u.gc.cid[ol], sh.u.gc.ccode[ol], ws, cnt, lane, gl, gb);
             if (st != ST_OK) return st;
         }
@@ -421,6 +463,7 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
         mrg[d] = fmin(p[d] - blo, blo + Gr.bs[d] - p[d]);
     }
     Poly<S, F32> c;
+    c.ri = A.rad ? A.rad[si] : 0.0;
     // box lines (Eq. 1-2, clipped as in section 3.1.3)
     if (gl < 4) {
         const int d = gl >> 1, side = gl & 1;
@@ -431,6 +474,7 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
         sh.lq[gl][0] = d == 0 ? b.nd : 0.0;
         sh.lq[gl][1] = d == 1 ? b.nd : 0.0;
         sh.lq[gl][2] = b.h;
+        sh.lrj[gl] = c.ri;  // the own images carry the own radius
     }
 #pragma unroll
     for (int s = 0; s < S; s++) {
@@ -460,11 +504,11 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
     }
     c.used = 0xfull;
     lds_sync2();
-    p_radius<G, S, F32>(c, gl);
+    p_radius<G, S, F32>(c, gl, A);
 
     bool finished = false;
     for (int o0 = 0; o0 < A.noff; o0 += G) {
-        if (A.offs[o0].m * T.bsmin2 >= 4.0 * c.R2 * kMargin) {
+        if (A.offs[o0].m * T.bsmin2 >= c.lim) {
             finished = true;
             break;
         }
@@ -486,7 +530,7 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
                 if (Gr.per[d] || bc[d] - r >= 0 || bc[d] + r < Gr.g[d]) exists = true;
             }
             if (!exists) break;
-            if (lb > 0.0 && lb * lb >= 4.0 * c.R2 * kMargin) break;
+            if (lb > 0.0 && lb * lb >= c.lim) break;
             int side = 2 * r + 1;
             int tot = side * side;
             for (int c0 = 0; c0 < tot; c0 += G) {
@@ -536,10 +580,32 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
                     int a = c.tp[s] & 0xff, b = (c.tp[s] >> 8) & 0xff;
                     uint32_t w2 = sh.u.st.tpl[sh.byin[b] & (G * S - 1)];
                     int cc = min((int)((w2 >> 8) & 0xff), MAXL - 1);
-                    if (exact_side2(line_of(sh, a), line_of(sh, b), line_of(sh, cc), ws) == 0) zb |= 1u << s;
+                    const int sg = A.rad ? exact_side2(line_r(sh, a, c.ri), line_r(sh, b, c.ri), line_r(sh, cc, c.ri), ws)
+                                         : exact_side2(line_of(sh, a), line_of(sh, b), line_of(sh, cc), ws);
+                    if (sg == 0) zb |= 1u << s;
                 }
                 if ((l / G) == (lane / G)) cnt[DC_EXACT]++;
             }
+        }
+    }
+    // triangles (apex, v, successor): the apex is the particle when it lies
+    // strictly inside the cell (every edge line has h > 0, always so for a
+    // Voronoi cell), else the cell's first live vertex, so that no term is
+    // negative for a radical cell that misses its particle
+    double o0 = 0.0, o1 = 0.0;
+    {
+        bool outside = false;
+        int first = -1;
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            bool lv = (c.live[s] >> gl) & 1;
+            if (lv && !(sh.lq[(c.tp[s] >> 8) & 0xff][2] > 0.0)) outside = true;
+            unsigned long long lm = gb2<G>(lv, gb);
+            if (first < 0 && lm) first = s * G + __builtin_ctzll(lm);
+        }
+        if (gb2<G>(outside, gb) && first >= 0) {
+            o0 = sh.u.st.pos[first][0];
+            o1 = sh.u.st.pos[first][1];
         }
     }
     double ar = 0.0, m0 = 0.0, m1 = 0.0, per = 0.0;
@@ -553,13 +619,14 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
         ne += __popcll(posmask[s]);
         if (lv) {
             int b = (c.tp[s] >> 8) & 0xff;
-            const double *w = sh.u.st.pos[sh.byin[b] & (G * S - 1)];
-            double x = c.vx[s], y = c.vy[s];
+            const double *w0 = sh.u.st.pos[sh.byin[b] & (G * S - 1)];
+            const double w[2] = {w0[0] - o0, w0[1] - o1};
+            double x = c.vx[s] - o0, y = c.vy[s] - o1;
             double cr = x * w[1] - y * w[0];
             ar += cr;
             m0 += cr * (x + w[0]);
             m1 += cr * (y + w[1]);
-            double dx = w[0] - x, dy = w[1] - y;
+            double dx = w0[0] - c.vx[s], dy = w0[1] - c.vy[s];
             per += sqrt(dx * dx + dy * dy);
         }
     }
@@ -583,8 +650,8 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
     if (gl == 0) {
         if (A.vol) A.vol[id] = 0.5 * area2;
         if (A.cen) {
-            A.cen[3 * (int64_t)id + 0] = M0 / (3.0 * area2);
-            A.cen[3 * (int64_t)id + 1] = M1 / (3.0 * area2);
+            A.cen[3 * (int64_t)id + 0] = o0 + M0 / (3.0 * area2);
+            A.cen[3 * (int64_t)id + 1] = o1 + M1 / (3.0 * area2);
             A.cen[3 * (int64_t)id + 2] = 0.0;
         }
         if (A.nv) A.nv[id] = ne;
@@ -597,9 +664,13 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
     return ne > kMaxNbr ? ST_CAP : ST_OK;
 }
 
-template <int G, int S, int MAXL, bool F32>
-__global__ __launch_bounds__(64) void k_cells2d(CellArgs A, int spill_mode)
+template <int G, int S, int MAXL, bool F32, bool RAD>
+__global__ __launch_bounds__(64) void k_cells2d(CellArgs Ain, int spill_mode)
 {
+    // the Voronoi instantiation carries no radical code: its rad pointer is
+    // a compile-time null
+    CellArgs A = Ain;
+    if (!RAD) A.rad = nullptr;
     static_assert(((G * S) & (G * S - 1)) == 0 && G * S <= 256, "slot count must be a power of two");
     __shared__ L2<G, S, MAXL> shv[64 / G];
     const int lane = __lane_id();
@@ -619,17 +690,23 @@ __global__ __launch_bounds__(64) void k_cells2d(CellArgs A, int spill_mode)
         for (int ci = base; ci < end; ci++) {
             int si = A.cell_list ? A.cell_list[ci] : ci;
             int st = poly_run<G, S, MAXL, F32>(A, sh, si, ws, cnt, lane, gl, gb);
+            if (st != ST_OK && A.fo)
+                for (int k = gl; k < kFoLen; k += G) A.fo[(int64_t)A.part[si].id * kFoLen + k] = 0;
             if (gl == 0) {
                 int id = A.part[si].id;
                 if (st != ST_OK) {
-                    if (A.vol) A.vol[id] = __builtin_nan("");
-                    if (A.cen) A.cen[3 * (int64_t)id] = A.cen[3 * (int64_t)id + 1] = __builtin_nan("");
+                    // an empty radical cell has zero area and perimeter
+                    const double f = st == ST_EMPTY ? 0.0 : __builtin_nan("");
+                    if (A.vol) A.vol[id] = f;
+                    if (A.cen) A.cen[3 * (int64_t)id] = A.cen[3 * (int64_t)id + 1] = f;
                     if (A.nv) A.nv[id] = 0;
                     if (A.ne) A.ne[id] = 0;
                     if (A.nf) A.nf[id] = 0;
-                    if (A.perim) A.perim[id] = __builtin_nan("");
+                    if (A.perim) A.perim[id] = f;
                 }
-                if (st == ST_OK) {
+                if (st == ST_EMPTY) {
+                    A.status[id] = (uint8_t)ST_EMPTY;
+                } else if (st == ST_OK) {
                     A.status[id] = spill_mode ? 1 : 0;
                 } else if (st == ST_DUP) {
                     A.status[id] = 3;
@@ -656,14 +733,20 @@ __global__ __launch_bounds__(64) void k_cells2d(CellArgs A, int spill_mode)
 
 hipError_t launch_cells2d(const CellArgs &a, int precision, int waves, hipStream_t s)
 {
-    if (precision == 1) k_cells2d<8, 2, 32, true><<<waves, 64, 0, s>>>(a, 0);
-    else k_cells2d<8, 2, 32, false><<<waves, 64, 0, s>>>(a, 0);
+    if (a.rad) {
+        if (precision == 1) k_cells2d<8, 2, 32, true, true><<<waves, 64, 0, s>>>(a, 0);
+        else k_cells2d<8, 2, 32, false, true><<<waves, 64, 0, s>>>(a, 0);
+    } else {
+        if (precision == 1) k_cells2d<8, 2, 32, true, false><<<waves, 64, 0, s>>>(a, 0);
+        else k_cells2d<8, 2, 32, false, false><<<waves, 64, 0, s>>>(a, 0);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_cells2d_spill(const CellArgs &a, int waves, hipStream_t s)
 {
-    k_cells2d<64, 4, 64, false><<<waves, 64, 0, s>>>(a, 1);
+    if (a.rad) k_cells2d<64, 4, 64, false, true><<<waves, 64, 0, s>>>(a, 1);
+    else k_cells2d<64, 4, 64, false, false><<<waves, 64, 0, s>>>(a, 1);
     return hipGetLastError();
 }
 

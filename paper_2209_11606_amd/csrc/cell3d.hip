@@ -35,6 +35,7 @@ namespace {
 template <int S, int MAXP, int K>
 struct CellLDS {
     double pq[MAXP][4];       // plane normal q (or wall normal) and offset h
+    double prj[MAXP];         // radius of each plane's neighbour (radical planes)
     int32_t plab[MAXP];       // neighbour id, or wall label
     uint8_t psh[MAXP];        // image code
     uint8_t pwall[MAXP];      // 1: wall plane (exact offset stored)
@@ -47,7 +48,9 @@ struct CellLDS {
         } st;
         struct {              // candidate sweep: the current batch sorted by
             double cq[64][4];               // distance (q, |q|^2), and the
-            int32_t cid[64];                // new vertices of a cut
+            double ch[64];                  // new vertices of a cut; plane
+            double crj[64];                 // offsets and radii
+            int32_t cid[64];
             uint8_t ccode[64];
             double npos[S * 64 + 8][3];
         } gc;
@@ -81,6 +84,12 @@ __device__ __forceinline__ PlaneD plane_of(const CellLDS<S, MAXP, K> &sh, int k)
     return p;
 }
 
+template <int S, int MAXP, int K>
+__device__ __forceinline__ PlaneR plane_r(const CellLDS<S, MAXP, K> &sh, int k, double ri)
+{
+    return PlaneR{plane_of(sh, k), ri, sh.prj[k]};
+}
+
 // State of one cell held by a wave (registers are per lane; masks uniform).
 template <int S, int MAXP, bool F32>
 struct Cell {
@@ -91,10 +100,12 @@ struct Cell {
     PlaneSet<MAXP> used;
     double R2;
     double R;
+    double lim;   // squared search radius
+    double ri;    // the particle's radius (radical tessellation), else 0
 };
 
 template <int S, int MAXP, bool F32>
-__device__ __forceinline__ void update_radius(Cell<S, MAXP, F32> &c, int lane)
+__device__ __forceinline__ void update_radius(Cell<S, MAXP, F32> &c, int lane, const CellArgs &A)
 {
     double m = 0.0;
 #pragma unroll
@@ -102,6 +113,7 @@ __device__ __forceinline__ void update_radius(Cell<S, MAXP, F32> &c, int lane)
         if ((c.live[s] >> lane) & 1) m = fmax(m, c.vx[s] * c.vx[s] + c.vy[s] * c.vy[s] + c.vz[s] * c.vz[s]);
     c.R2 = wave_max(m);
     c.R = sqrt(c.R2);
+    c.lim = search_lim(c.R2, c.R, A, c.ri);
 }
 
 template <int S, int MAXP, bool F32>
@@ -145,16 +157,17 @@ __device__ __forceinline__ int free_plane(Cell<S, MAXP, F32> &c)
 // Returns ST_OK or ST_CAP.
 template <int S, int MAXP, bool F32, int K>
 __device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &sh, Cell<S, MAXP, F32> &c, double q0, double q1,
-                        double q2, double d2, int32_t lab, int code, double *ws, unsigned long long *cnt, int lane)
+                        double q2, double h, double rj, int32_t lab, int code, double *ws, unsigned long long *cnt,
+                        int lane)
 {
-    const double h = 0.5 * d2;
-    const double Mub = (fabs(q0) + fabs(q1) + fabs(q2)) * c.R + h;
+    const bool rad = A.rad != nullptr;
+    const double Mub = (fabs(q0) + fabs(q1) + fabs(q2)) * c.R + fabs(h);
     const double band = A.tau * Mub;
     unsigned long long conf[S], inb[S];
     int ntest = 0;
     if (F32) {
         const float g0 = (float)q0, g1 = (float)q1, g2 = (float)q2, gh = (float)h;
-        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + gh);
+        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + fabsf(gh));
         unsigned long long uns = 0;
         unsigned long long unsr[S];
 #pragma unroll
@@ -190,20 +203,28 @@ __device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &
     }
     cnt[DC_TESTS] += ntest;
     // in-band vertices: exact decision, one lane at a time
+    unsigned long long zero[S];
 #pragma unroll
     for (int s = 0; s < S; s++) {
         unsigned long long m = inb[s];
+        zero[s] = 0;
         while (m) {
             int l = __builtin_ctzll(m);
             m &= m - 1;
             int sg = 0;
             if (lane == l) {
-                PlaneD pp = {q0, q1, q2, h, 0};
-                sg = exact_side3(plane_of(sh, c.tp[s] & 0xff), plane_of(sh, (c.tp[s] >> 8) & 0xff),
-                                 plane_of(sh, (c.tp[s] >> 16) & 0xff), pp, ws);
+                const PlaneD pp = {q0, q1, q2, h, 0};
+                const uint32_t t3 = c.tp[s];
+                if (rad)
+                    sg = exact_side3(plane_r(sh, t3 & 0xff, c.ri), plane_r(sh, (t3 >> 8) & 0xff, c.ri),
+                                     plane_r(sh, (t3 >> 16) & 0xff, c.ri), PlaneR{pp, c.ri, rj}, ws);
+                else
+                    sg = exact_side3(plane_of(sh, t3 & 0xff), plane_of(sh, (t3 >> 8) & 0xff),
+                                     plane_of(sh, (t3 >> 16) & 0xff), pp, ws);
             }
             sg = __builtin_amdgcn_readlane(sg, l);
             if (sg > 0) conf[s] |= 1ull << l;
+            if (sg == 0) zero[s] |= 1ull << l;
             cnt[DC_EXACT]++;
         }
     }
@@ -211,6 +232,17 @@ __device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &
 #pragma unroll
     for (int s = 0; s < S; s++) anyc |= conf[s];
     if (!anyc) return ST_OK;
+    if (rad) {
+        // a radical plane can leave no vertex strictly inside: empty cell
+        unsigned long long inside = 0;
+#pragma unroll
+        for (int s = 0; s < S; s++) inside |= c.live[s] & ~conf[s] & ~zero[s];
+        if (!inside) {
+#pragma unroll
+            for (int s = 0; s < S; s++) c.live[s] = 0;
+            return ST_EMPTY;
+        }
+    }
 
     // ---- cut ----
     int p = free_plane(c);
@@ -260,6 +292,7 @@ __device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &
         sh.pq[p][1] = q1;
         sh.pq[p][2] = q2;
         sh.pq[p][3] = h;
+        if (A.rad) sh.prj[p] = rj;
         sh.plab[p] = lab;
         sh.psh[p] = (uint8_t)code;
         sh.pwall[p] = 0;
@@ -305,7 +338,7 @@ __device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &
     }
     c.used.w[p >> 6] |= 1ull << (p & 63);
     __syncthreads();
-    update_radius(c, lane);
+    update_radius(c, lane, A);
     cnt[DC_CUTS]++;
     cnt[DC_NEWV] += m;
     return radius_ok(c) ? ST_OK : ST_CAP;
@@ -341,7 +374,7 @@ __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh
         double e = fmax(0.0, fmax(blo - p[d], p[d] - (blo + G.bs[d])));
         d2b += e * e;
     }
-    if (d2b >= 4.0 * c.R2 * kMargin) ok = false;
+    if (d2b >= c.lim) ok = false;
     int cntb = 0, beg = 0;
     if (ok) {
         int64_t blk = T.bbase + bb[0] + (int64_t)G.g[0] * (bb[1] + (int64_t)G.g[1] * bb[2]);
@@ -361,7 +394,7 @@ __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh
         // load one candidate per lane
         int ci = c0 + lane;
         unsigned long long key = ~0ull;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, d2 = 0.0;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, d2 = 0.0, h = 0.0, rj = 0.0;
         int32_t qid = 0;
         int code = kNoShift;
         if (ci < total) {
@@ -382,8 +415,15 @@ __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh
             if (s1) a1 = a1 + s1 * G.L[1];
             if (s2) a2 = a2 + s2 * G.L[2];
             d2 = a0 * a0 + a1 * a1 + a2 * a2;
+            if (A.rad) {
+                // radical plane (section 2.1.1): |x|^2 - ri^2 <= |x - q|^2 - rj^2
+                rj = A.rad[idx];
+                h = 0.5 * (d2 + radical_shift(c.ri, rj));
+            } else {
+                h = 0.5 * d2;
+            }
             bool self = (idx == si) && code == kNoShift;
-            if (!self && d2 < 4.0 * c.R2 * kMargin) key = __double_as_longlong(d2);
+            if (!self && d2 < c.lim) key = __double_as_longlong(d2);
             qid = q.id;
         }
         // rank the batch by (distance, lane) and store it sorted
@@ -402,6 +442,10 @@ __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh
             sh.u.gc.cq[rank][1] = a1;
             sh.u.gc.cq[rank][2] = a2;
             sh.u.gc.cq[rank][3] = d2;
+            if (A.rad) {
+                sh.u.gc.ch[rank] = h;
+                sh.u.gc.crj[rank] = rj;
+            }
             sh.u.gc.cid[rank] = qid;
             sh.u.gc.ccode[rank] = (uint8_t)code;
         }
@@ -409,11 +453,13 @@ __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh
         // nearest first; stop at the first candidate beyond 2R
         for (int k = 0; k < nval; k++) {
             double md2 = sh.u.gc.cq[k][3];
-            if (!(md2 < 4.0 * c.R2 * kMargin)) break;
+            if (!(md2 < c.lim)) break;
             cnt[DC_CAND]++;
             if (md2 == 0.0) return ST_DUP;
-            int st = consider<S, MAXP, F32, K>(A, sh, c, sh.u.gc.cq[k][0], sh.u.gc.cq[k][1], sh.u.gc.cq[k][2], md2,
-                                               sh.u.gc.cid[k], sh.u.gc.ccode[k], ws, cnt, lane);
+            int st = consider<S, MAXP, F32, K>(A, sh, c, sh.u.gc.cq[k][0], sh.u.gc.cq[k][1], sh.u.gc.cq[k][2],
+                                               A.rad ? sh.u.gc.ch[k] : 0.5 * md2, A.rad ? sh.u.gc.crj[k] : 0.0,
+                                               sh.u.gc.cid[k], sh.u.gc.ccode[k], ws,
+                                               cnt, lane);
             if (st != ST_OK) return st;
         }
     }
@@ -438,6 +484,8 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         mrg[d] = fmin(p[d] - blo, blo + G.bs[d] - p[d]);
     }
     Cell<S, MAXP, F32> c;
+    c.ri = A.rad ? A.rad[si] : 0.0;
+    const bool rad = A.rad != nullptr;
     // box planes (Eq. 1-2, clipped as in section 3.1.3); no register array
     // is indexed by d
     if (lane < 6) {
@@ -451,6 +499,7 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         sh.pq[lane][1] = d == 1 ? b.nd : 0.0;
         sh.pq[lane][2] = d == 2 ? b.nd : 0.0;
         sh.pq[lane][3] = b.h;
+        sh.prj[lane] = c.ri;  // the own images carry the own radius
     }
     // corners: triangle (X, Y, Z) counter-clockwise when det(nX, nY, nZ) > 0
 #pragma unroll
@@ -491,12 +540,12 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     c.used.w[0] = 0x3full;
     c.used.w[PlaneSet<MAXP>::W - 1] |= PlaneSet<MAXP>::pad;
     __syncthreads();
-    update_radius(c, lane);
+    update_radius(c, lane, A);
 
     // nearest-first sweep over the precomputed block offsets
     bool finished = false;
     for (int o0 = 0; o0 < A.noff; o0 += 64) {
-        if (A.offs[o0].m * T.bsmin2 >= 4.0 * c.R2 * kMargin) {
+        if (A.offs[o0].m * T.bsmin2 >= c.lim) {
             finished = true;
             break;
         }
@@ -519,7 +568,7 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
                 if (G.per[d] || bc[d] - r >= 0 || bc[d] + r < G.g[d]) exists = true;
             }
             if (!exists) break;
-            if (lb > 0.0 && lb * lb >= 4.0 * c.R2 * kMargin) break;
+            if (lb > 0.0 && lb * lb >= c.lim) break;
             int side = 2 * r + 1;
             int tot = side * side * side;
             for (int c0 = 0; c0 < tot; c0 += 64) {
@@ -589,8 +638,10 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
                     uint32_t w3 = sh.u.st.tpl[sh.etab[b][a] & (S * 64 - 1)];
                     int d = (int)(w3 & 0xff) + (int)((w3 >> 8) & 0xff) + (int)((w3 >> 16) & 0xff) - a - b;
                     d = min(max(d, 0), MAXP - 1);
-                    int sg = exact_side3(plane_of(sh, t3 & 0xff), plane_of(sh, (t3 >> 8) & 0xff),
-                                         plane_of(sh, (t3 >> 16) & 0xff), plane_of(sh, d), ws);
+                    int sg = rad ? exact_side3(plane_r(sh, t3 & 0xff, c.ri), plane_r(sh, (t3 >> 8) & 0xff, c.ri),
+                                               plane_r(sh, (t3 >> 16) & 0xff, c.ri), plane_r(sh, d, c.ri), ws)
+                                 : exact_side3(plane_of(sh, t3 & 0xff), plane_of(sh, (t3 >> 8) & 0xff),
+                                               plane_of(sh, (t3 >> 16) & 0xff), plane_of(sh, d), ws);
                     if (sg == 0) zb |= 1u << j;
                 }
                 cnt[DC_EXACT]++;
@@ -600,6 +651,26 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     // face orders and the fan over each face from its reference vertex:
     // tetrahedra (0, r_a, v_twin, v_t), the twin across a -> b being the
     // previous vertex of face a counter-clockwise
+    // The apex is the particle when it lies strictly inside the cell (every
+    // face offset h > 0, always so for a Voronoi cell), else one vertex.
+    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+    if (rad) {
+        bool in = true;
+#pragma unroll
+        for (int s = 0; s < S; s++)
+            if ((c.live[s] >> lane) & 1)
+#pragma unroll
+                for (int k = 0; k < 3; k++) in = in && sh.pq[(c.tp[s] >> (8 * k)) & 0xff][3] > 0.0;
+        if (__ballot(!in)) {
+            int t0 = 0;
+#pragma unroll
+            for (int s = S - 1; s >= 0; s--)
+                if (c.live[s]) t0 = s * 64 + __builtin_ctzll(c.live[s]);
+            o0 = sh.u.st.pos[t0][0];
+            o1 = sh.u.st.pos[t0][1];
+            o2 = sh.u.st.pos[t0][2];
+        }
+    }
     double v6 = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
     for (int j = 0; j < 3 * S; j++) {
         int t = (j / 3) * 64 + lane, k = j % 3;
@@ -607,9 +678,12 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         if (t3 == 0xffffffffu) continue;
         int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
         if (!((zb >> j) & 1)) atomicAdd(&sh.forder[a], 1);
-        const double *r = sh.u.st.pos[sh.fref[a]];
-        const double *w = sh.u.st.pos[sh.etab[b][a] & (S * 64 - 1)];
-        const double *v = sh.u.st.pos[t];
+        const double *r0 = sh.u.st.pos[sh.fref[a]];
+        const double *w0 = sh.u.st.pos[sh.etab[b][a] & (S * 64 - 1)];
+        const double *v0 = sh.u.st.pos[t];
+        const double r[3] = {r0[0] - o0, r0[1] - o1, r0[2] - o2};
+        const double w[3] = {w0[0] - o0, w0[1] - o1, w0[2] - o2};
+        const double v[3] = {v0[0] - o0, v0[1] - o1, v0[2] - o2};
         double det = r[0] * (w[1] * v[2] - w[2] * v[1]) - r[1] * (w[0] * v[2] - w[2] * v[0]) +
                      r[2] * (w[0] * v[1] - w[1] * v[0]);
         v6 += det;
@@ -675,9 +749,9 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         double vol = vol6 / 6.0;
         if (A.vol) A.vol[id] = vol;
         if (A.cen) {
-            A.cen[3 * (int64_t)id + 0] = M0 / (4.0 * vol6);
-            A.cen[3 * (int64_t)id + 1] = M1 / (4.0 * vol6);
-            A.cen[3 * (int64_t)id + 2] = M2 / (4.0 * vol6);
+            A.cen[3 * (int64_t)id + 0] = o0 + M0 / (4.0 * vol6);
+            A.cen[3 * (int64_t)id + 1] = o1 + M1 / (4.0 * vol6);
+            A.cen[3 * (int64_t)id + 2] = o2 + M2 / (4.0 * vol6);
         }
         if (A.nv) A.nv[id] = nvert;
         if (A.ne) A.ne[id] = sumord / 2;
@@ -687,9 +761,13 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     return capfail ? ST_CAP : ST_OK;
 }
 
-template <int S, int MAXP, bool F32, int K>
-__global__ __launch_bounds__(64) void k_cells(CellArgs A, int spill_mode)
+template <int S, int MAXP, bool F32, int K, bool RAD>
+__global__ __launch_bounds__(64) void k_cells(CellArgs Ain, int spill_mode)
 {
+    // the Voronoi instantiation carries no radical code: its rad pointer is
+    // a compile-time null
+    CellArgs A = Ain;
+    if (!RAD) A.rad = nullptr;
     __shared__ CellLDS<S, MAXP, K> sh;
     const int lane = __lane_id();
     double *ws = A.xscratch + (size_t)blockIdx.x * A.xscratch_len;
@@ -710,14 +788,18 @@ __global__ __launch_bounds__(64) void k_cells(CellArgs A, int spill_mode)
             if (lane == 0) {
                 int id = A.part[si].id;
                 if (st != ST_OK) {
-                    // no statistics for this cell (yet): empty outputs
-                    if (A.vol) A.vol[id] = __builtin_nan("");
-                    if (A.cen) A.cen[3 * (int64_t)id] = A.cen[3 * (int64_t)id + 1] = A.cen[3 * (int64_t)id + 2] = __builtin_nan("");
+                    // no statistics for this cell (yet): empty outputs; an
+                    // empty radical cell has zero volume
+                    const double f = st == ST_EMPTY ? 0.0 : __builtin_nan("");
+                    if (A.vol) A.vol[id] = f;
+                    if (A.cen) A.cen[3 * (int64_t)id] = A.cen[3 * (int64_t)id + 1] = A.cen[3 * (int64_t)id + 2] = f;
                     if (A.nv) A.nv[id] = 0;
                     if (A.ne) A.ne[id] = 0;
                     if (A.nf) A.nf[id] = 0;
                 }
-                if (st == ST_OK) {
+                if (st == ST_EMPTY) {
+                    A.status[id] = (uint8_t)ST_EMPTY;
+                } else if (st == ST_OK) {
                     A.status[id] = spill_mode ? 1 : 0;
                 } else if (st == ST_DUP) {
                     A.status[id] = 3;
@@ -748,19 +830,31 @@ __global__ __launch_bounds__(64) void k_cells(CellArgs A, int spill_mode)
 
 hipError_t launch_cells(const CellArgs &a, int precision, int slots, int waves, hipStream_t s)
 {
+    const bool rad = a.rad != nullptr;
     if (slots == 4) {
-        if (precision == 1) k_cells<4, 48, true, 1><<<waves, 64, 0, s>>>(a, 0);
-        else k_cells<4, 48, false, 1><<<waves, 64, 0, s>>>(a, 0);
+        if (rad) {
+            if (precision == 1) k_cells<4, 48, true, 1, true><<<waves, 64, 0, s>>>(a, 0);
+            else k_cells<4, 48, false, 1, true><<<waves, 64, 0, s>>>(a, 0);
+        } else {
+            if (precision == 1) k_cells<4, 48, true, 1, false><<<waves, 64, 0, s>>>(a, 0);
+            else k_cells<4, 48, false, 1, false><<<waves, 64, 0, s>>>(a, 0);
+        }
     } else {
-        if (precision == 1) k_cells<2, 48, true, 1><<<waves, 64, 0, s>>>(a, 0);
-        else k_cells<2, 48, false, 1><<<waves, 64, 0, s>>>(a, 0);
+        if (rad) {
+            if (precision == 1) k_cells<2, 48, true, 1, true><<<waves, 64, 0, s>>>(a, 0);
+            else k_cells<2, 48, false, 1, true><<<waves, 64, 0, s>>>(a, 0);
+        } else {
+            if (precision == 1) k_cells<2, 48, true, 1, false><<<waves, 64, 0, s>>>(a, 0);
+            else k_cells<2, 48, false, 1, false><<<waves, 64, 0, s>>>(a, 0);
+        }
     }
     return hipGetLastError();
 }
 
 hipError_t launch_cells_spill(const CellArgs &a, int waves, hipStream_t s)
 {
-    k_cells<4, 128, false, 1><<<waves, 64, 0, s>>>(a, 1);
+    if (a.rad) k_cells<4, 128, false, 1, true><<<waves, 64, 0, s>>>(a, 1);
+    else k_cells<4, 128, false, 1, false><<<waves, 64, 0, s>>>(a, 1);
     return hipGetLastError();
 }
 

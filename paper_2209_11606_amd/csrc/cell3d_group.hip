@@ -136,6 +136,7 @@ struct GState {
     double p[3];            // the particle
     int bc[3];              // its block
     int si, id;             // sorted index, input index
+    double ri;              // the particle's radius (radical tessellation), else 0
     int shell;              // 0: offset list; r > 0: Chebyshev shell r
     int cur;                // next offset index, or position in the shell
     int gtot, gc0;          // candidates of the gather, next batch start
@@ -148,6 +149,7 @@ struct SL {
     GState gs;
     Tess T;                 // the cell's tessellation
     double pq[MAXP][4];     // planes n.r = h (n = q for a bisector, h = |q|^2 / 2)
+    double prj[MAXP];       // radius of each plane's neighbour (radical planes)
     int32_t plab[MAXP];
     uint8_t psh[MAXP];
     uint8_t pwall[MAXP];
@@ -155,6 +157,8 @@ struct SL {
     union {
         struct {               // the search
             double cq[G][4];   // the batch's candidates, nearest first: q, |q|^2
+            double ch[G];      // their plane offsets h
+            double crj[G];     // their radii (radical planes)
             int32_t cid[G];
             int32_t cpre[G];   // the gather's blocks: candidates before, first particle, image code
             int32_t cbeg[G];
@@ -188,6 +192,21 @@ __device__ __forceinline__ PlaneD splane(const SL<G, S, MAXP> &sh, int k)
     return p;
 }
 
+template <int G, int S, int MAXP>
+__device__ __forceinline__ PlaneR splane_r(const SL<G, S, MAXP> &sh, int k)
+{
+    return PlaneR{splane(sh, k), sh.gs.ri, sh.prj[k]};
+}
+
+// exact side of plane p at the vertex of planes (a, b, c), radical or not
+template <int G, int S, int MAXP>
+__device__ __forceinline__ int sside3(const SL<G, S, MAXP> &sh, bool rad, uint32_t t3, int p, double *ws)
+{
+    const int a = t3 & 0xff, b = (t3 >> 8) & 0xff, c = (t3 >> 16) & 0xff;
+    if (rad) return exact_side3(splane_r(sh, a), splane_r(sh, b), splane_r(sh, c), splane_r(sh, p), ws);
+    return exact_side3(splane(sh, a), splane(sh, b), splane(sh, c), splane(sh, p), ws);
+}
+
 // one cell and its search state, held by a group (values are the same on
 // every lane of the group, apart from the per-lane slots)
 template <int S, bool F32>
@@ -198,7 +217,7 @@ struct SCell {
     uint32_t live[S];            // live slots (group bit fields)
     uint32_t conf[S];            // conflict slots of the pending cut
     unsigned long long used;     // plane slots in use
-    double R2, R;                // upper bounds of the squared / plain radius
+    double lim, R;               // squared search radius, radius bound (upper bounds)
     int nlive;                   // live slots (vertices) of the cell
     int phase;
     int bn, bk;                  // candidates of the batch, next one
@@ -214,10 +233,10 @@ __device__ __forceinline__ int free_plane(unsigned long long used)
 
 // Radius bound: the largest squared vertex norm, rounded up to 20 mantissa
 // bits (the high word of the double plus one unit), so the group maximum is
-// a 32-bit DPP reduction.  Both R2 and R are upper bounds, which is all the
+// a 32-bit DPP reduction.  R2, R and the search radius are upper bounds, which is all the
 // radius test and the error bands need.
 template <int G, int S, bool F32>
-__device__ __forceinline__ void update_radius(SCell<S, F32> &c, int gl)
+__device__ __forceinline__ void update_radius(SCell<S, F32> &c, int gl, const CellArgs &A, double ri)
 {
     uint32_t m = 0;
 #pragma unroll
@@ -227,11 +246,12 @@ __device__ __forceinline__ void update_radius(SCell<S, F32> &c, int gl)
         if ((c.live[s] >> gl) & 1) m = max(m, hw);
     }
     m = gmax_u32<G>(m);
-    c.R2 = __builtin_bit_cast(double, (unsigned long long)m << 32);
-    if (c.R2 > 1e-30 && c.R2 < 1e30)
-        c.R = (double)__builtin_amdgcn_sqrtf((float)c.R2) * (1.0 + 0x1p-18);
+    const double R2 = __builtin_bit_cast(double, (unsigned long long)m << 32);
+    if (R2 > 1e-30 && R2 < 1e30)
+        c.R = (double)__builtin_amdgcn_sqrtf((float)R2) * (1.0 + 0x1p-18);
     else
-        c.R = sqrt(c.R2) * (1.0 + 0x1p-40);
+        c.R = sqrt(R2) * (1.0 + 0x1p-40);
+    c.lim = search_lim(R2, c.R, A, ri);
 }
 
 template <int G, int S, int MAXP, bool F32>
@@ -279,6 +299,7 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP> &sh, SC
     const Particle me = A.part[si];
     sh.gs.si = si;
     sh.gs.id = me.id;
+    sh.gs.ri = A.rad ? A.rad[si] : 0.0;
     sh.gs.p[0] = me.x;
     sh.gs.p[1] = me.y;
     sh.gs.p[2] = me.z;
@@ -299,6 +320,7 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP> &sh, SC
         sh.pwall[gl] = (uint8_t)b.wall;
         sh.plab[gl] = b.lab;
         sh.psh[gl] = b.code;
+        sh.prj[gl] = sh.gs.ri;  // the own images carry the own radius
         sh.pq[gl][0] = d == 0 ? b.nd : 0.0;
         sh.pq[gl][1] = d == 1 ? b.nd : 0.0;
         sh.pq[gl][2] = d == 2 ? b.nd : 0.0;
@@ -341,7 +363,7 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP> &sh, SC
     c.used = 0x3full;
     c.nlive = 8;
     lds_fence();
-    update_radius<G, S, F32>(c, gl);
+    update_radius<G, S, F32>(c, gl, A, sh.gs.ri);
     sh.gs.shell = 0;
     sh.gs.cur = 0;
     c.phase = PH_GATHER;
@@ -354,7 +376,7 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
 {
     const Tess &T = sh.T;
     const Grid &G3 = T.G;
-    const double lim = 4.0 * c.R2 * kMargin;
+    const double lim = c.lim;
     int dd[3] = {0, 0, 0};
     bool v = false;
     if (sh.gs.shell == 0) {
@@ -378,7 +400,7 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
     if (sh.gs.shell > 0) {
         const int r = sh.gs.shell;
         if (sh.gs.cur == 0) {
-            if (r > kMaxShell || !(c.R2 < 1e300)) {
+            if (r > kMaxShell || !(c.lim < 1e300)) {
                 c.phase = -ST_CAP;
                 return;
             }
@@ -470,7 +492,7 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP> &sh, 
     const Grid &G3 = sh.T.G;
     const int ci = sh.gs.gc0 + gl;
     unsigned long long key = ~0ull;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, d2 = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, d2 = 0.0, h = 0.0, rj = 0.0;
     int pid = 0, code = 0;
     if (ci < sh.gs.gtot) {
         int lo = 0, hi = G - 1;
@@ -491,11 +513,19 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP> &sh, 
         if (s2) a2 = a2 + s2 * G3.L[2];
         d2 = a0 * a0 + a1 * a1 + a2 * a2;
         pid = q.id;
+        if (A.rad) {
+            // radical plane (section 2.1.1): |x|^2 - ri^2 <= |x - q|^2 - rj^2
+            const double ri = sh.gs.ri;
+            rj = A.rad[idx];
+            h = 0.5 * (d2 + radical_shift(ri, rj));
+        } else {
+            h = 0.5 * d2;
+        }
         bool self = (idx == sh.gs.si) && code == kNoShift;
         // unique keys: the distance with its low five bits replaced by the
         // lane; candidates closer than 32 ulps may swap, which the radius
         // margin (2^-30) absorbs when the batch is cut short
-        if (!self && d2 < 4.0 * c.R2 * kMargin)
+        if (!self && d2 < c.lim)
             key = (__builtin_bit_cast(unsigned long long, d2) & ~31ull) | (unsigned long long)gl;
     }
     // the valid keys, compacted; each counts the smaller ones
@@ -512,6 +542,10 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP> &sh, 
         sh.u.w.cq[rank][1] = a1;
         sh.u.w.cq[rank][2] = a2;
         sh.u.w.cq[rank][3] = d2;
+        if (A.rad) {
+            sh.u.w.ch[rank] = h;
+            sh.u.w.crj[rank] = rj;
+        }
         sh.u.w.cid[rank] = pid;
         sh.u.w.ccode[rank] = (uint8_t)code;
     }
@@ -536,7 +570,7 @@ __device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP> &sh, S
     }
     const int k = c.bk;
     const double q0 = sh.u.w.cq[k][0], q1 = sh.u.w.cq[k][1], q2 = sh.u.w.cq[k][2], d2 = sh.u.w.cq[k][3];
-    if (!(d2 < 4.0 * c.R2 * kMargin)) {
+    if (!(d2 < c.lim)) {
         c.phase = PH_BATCH;  // sorted: the rest of the batch is farther still
         return;
     }
@@ -545,12 +579,13 @@ __device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP> &sh, S
         c.phase = -ST_DUP;
         return;
     }
-    const double h = 0.5 * d2;
-    const double band = A.tau * ((fabs(q0) + fabs(q1) + fabs(q2)) * c.R + h);
-    unsigned long long wc[S], wi[S];
+    const bool rad = A.rad != nullptr;
+    const double h = rad ? sh.u.w.ch[k] : 0.5 * d2;
+    const double band = A.tau * ((fabs(q0) + fabs(q1) + fabs(q2)) * c.R + fabs(h));
+    unsigned long long wc[S], wi[S], wz[S];
     if (F32) {
         const float g0 = (float)q0, g1 = (float)q1, g2 = (float)q2, gh = (float)h;
-        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + gh);
+        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + fabsf(gh));
         unsigned long long wu[S], wun = 0;
 #pragma unroll
         for (int s = 0; s < S; s++) {
@@ -589,17 +624,24 @@ __device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP> &sh, S
 #pragma unroll
     for (int s = 0; s < S; s++) {
         unsigned long long wm = wi[s];
+        wz[s] = 0;
         while (wm) {
             int l = __builtin_ctzll(wm);
             wm &= wm - 1;
             int sg = 0;
             if (lane == l) {
-                PlaneD pp = {q0, q1, q2, h, 0};
-                sg = exact_side3(splane(sh, c.tp[s] & 0xff), splane(sh, (c.tp[s] >> 8) & 0xff),
-                                 splane(sh, (c.tp[s] >> 16) & 0xff), pp, ws);
+                const PlaneD pp = {q0, q1, q2, h, 0};
+                const uint32_t t3 = c.tp[s];
+                if (rad)
+                    sg = exact_side3(splane_r(sh, t3 & 0xff), splane_r(sh, (t3 >> 8) & 0xff),
+                                     splane_r(sh, (t3 >> 16) & 0xff), PlaneR{pp, sh.gs.ri, sh.u.w.crj[k]}, ws);
+                else
+                    sg = exact_side3(splane(sh, t3 & 0xff), splane(sh, (t3 >> 8) & 0xff), splane(sh, (t3 >> 16) & 0xff),
+                                     pp, ws);
             }
             sg = __builtin_amdgcn_readlane(sg, l);
             if (sg > 0) wc[s] |= 1ull << l;
+            if (sg == 0) wz[s] |= 1ull << l;
             if ((l / G) == (lane / G)) sh.gs.cnt[DC_EXACT]++;
         }
     }
@@ -609,6 +651,23 @@ __device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP> &sh, S
     if ((uint32_t)(wany >> gb) & Gw<G>::FULL) {
 #pragma unroll
         for (int s = 0; s < S; s++) c.conf[s] = (uint32_t)(wc[s] >> gb) & Gw<G>::FULL;
+        if (rad) {
+            // a radical plane can leave no vertex strictly inside: the cell
+            // is empty (a Voronoi cell always keeps its particle inside)
+            uint32_t inside = 0;
+#pragma unroll
+            for (int s = 0; s < S; s++) inside |= c.live[s] & ~c.conf[s] & ~((uint32_t)(wz[s] >> gb) & Gw<G>::FULL);
+            if (!inside) {
+#pragma unroll
+                for (int s = 0; s < S; s++) {
+                    c.live[s] = 0;
+                    c.conf[s] = 0;
+                }
+                c.nlive = 0;
+                c.phase = PH_STATS;
+                return;
+            }
+        }
         c.phase = PH_CUT;
     } else {
         c.bk++;
@@ -688,7 +747,12 @@ __device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP> &sh, SC
         sh.pq[p][0] = sh.u.w.cq[k][0];
         sh.pq[p][1] = sh.u.w.cq[k][1];
         sh.pq[p][2] = sh.u.w.cq[k][2];
-        sh.pq[p][3] = 0.5 * sh.u.w.cq[k][3];
+        if (A.rad) {
+            sh.pq[p][3] = sh.u.w.ch[k];
+            sh.prj[p] = sh.u.w.crj[k];
+        } else {
+            sh.pq[p][3] = 0.5 * sh.u.w.cq[k][3];
+        }
         sh.plab[p] = sh.u.w.cid[k];
         sh.psh[p] = sh.u.w.ccode[k];
         sh.pwall[p] = 0;
@@ -739,11 +803,11 @@ __device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP> &sh, SC
 #pragma unroll
     for (int s = 0; s < S; s++) nl += __popc(c.live[s]);
     c.nlive = nl;
-    update_radius<G, S, F32>(c, gl);
+    update_radius<G, S, F32>(c, gl, A, sh.gs.ri);
     sh.gs.cnt[DC_CUTS]++;
     sh.gs.cnt[DC_NEWV] += m;
     c.bk++;
-    c.phase = c.R2 < 1e300 ? PH_TEST : -ST_CAP;
+    c.phase = c.lim < 1e300 ? PH_TEST : -ST_CAP;
 }
 
 // ---- STATS: volume, centroid, V/E/F, face orders, neighbours ----
@@ -752,6 +816,21 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
                                          uint32_t *cnt, int lane, int gl, int gb, uint32_t below)
 {
     const int id = sh.gs.id;
+    if (c.nlive == 0) {
+        // an empty radical cell: zero volume, no vertices or faces
+        if (gl == 0) {
+            if (A.vol) A.vol[id] = 0.0;
+            if (A.cen) A.cen[3 * (int64_t)id] = A.cen[3 * (int64_t)id + 1] = A.cen[3 * (int64_t)id + 2] = 0.0;
+            if (A.nv) A.nv[id] = 0;
+            if (A.ne) A.ne[id] = 0;
+            if (A.nf) A.nf[id] = 0;
+            A.status[id] = (uint8_t)ST_EMPTY;
+        }
+        if (A.fo)
+            for (int k = gl; k < kFoLen; k += G) A.fo[(int64_t)id * kFoLen + k] = 0;
+        c.phase = PH_NEW;
+        return;
+    }
     lds_fence();
 #pragma unroll
     for (int s = 0; s < S; s++) {
@@ -775,6 +854,7 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
         for (int j = 0; j < 3; j++) atomicMin(&sh.u.st.fref[(t3 >> (8 * j)) & 0xff], t);
     }
     lds_fence();
+    const bool rad = A.rad != nullptr;
     // a vertex whose opposite vertex across an edge lies on the vertex's
     // fourth plane is degenerate: the edge has zero length (decided exactly)
     uint32_t zb = 0, ib = 0;
@@ -805,12 +885,31 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
                     uint32_t w3 = sh.u.st.tpl[sh.etab[b][a] & (G * S - 1)];
                     int d = (int)(w3 & 0xff) + (int)((w3 >> 8) & 0xff) + (int)((w3 >> 16) & 0xff) - a - b;
                     d = min(max(d, 0), MAXP - 1);
-                    int sg = exact_side3(splane(sh, t3 & 0xff), splane(sh, (t3 >> 8) & 0xff),
-                                         splane(sh, (t3 >> 16) & 0xff), splane(sh, d), ws);
+                    int sg = sside3(sh, rad, t3, d, ws);
                     if (sg == 0) zb |= 1u << j;
                 }
                 if ((l / G) == (lane / G)) sh.gs.cnt[DC_EXACT]++;
             }
+        }
+    }
+    // fan apex: the particle when it lies strictly inside the cell (every
+    // face offset h > 0, always so for a Voronoi cell), else one vertex
+    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+    if (A.rad) {
+        bool in = true;
+#pragma unroll
+        for (int s = 0; s < S; s++)
+            if ((c.live[s] >> gl) & 1)
+#pragma unroll
+                for (int j = 0; j < 3; j++) in = in && sh.pq[(c.tp[s] >> (8 * j)) & 0xff][3] > 0.0;
+        if (gbal<G>(!in, gb)) {
+            int t0 = 0;
+#pragma unroll
+            for (int s = S - 1; s >= 0; s--)
+                if (c.live[s]) t0 = s * G + __builtin_ctz(c.live[s]);
+            o0 = sh.u.st.pos[t0][0];
+            o1 = sh.u.st.pos[t0][1];
+            o2 = sh.u.st.pos[t0][2];
         }
     }
     double v6 = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
@@ -820,9 +919,12 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
         if (t3 == 0xffffffffu) continue;
         int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
         if (!((zb >> j) & 1)) atomicAdd(&sh.u.st.forder[a], 1);
-        const double *r = sh.u.st.pos[sh.u.st.fref[a]];
-        const double *w = sh.u.st.pos[sh.etab[b][a] & (G * S - 1)];
-        const double *v = sh.u.st.pos[t];
+        const double *r0 = sh.u.st.pos[sh.u.st.fref[a]];
+        const double *w0 = sh.u.st.pos[sh.etab[b][a] & (G * S - 1)];
+        const double *v0 = sh.u.st.pos[t];
+        const double r[3] = {r0[0] - o0, r0[1] - o1, r0[2] - o2};
+        const double w[3] = {w0[0] - o0, w0[1] - o1, w0[2] - o2};
+        const double v[3] = {v0[0] - o0, v0[1] - o1, v0[2] - o2};
         double det = r[0] * (w[1] * v[2] - w[2] * v[1]) - r[1] * (w[0] * v[2] - w[2] * v[0]) +
                      r[2] * (w[0] * v[1] - w[1] * v[0]);
         v6 += det;
@@ -888,9 +990,9 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
         double vol = vol6 / 6.0;
         if (A.vol) A.vol[id] = vol;
         if (A.cen) {
-            A.cen[3 * (int64_t)id + 0] = M0 / (4.0 * vol6);
-            A.cen[3 * (int64_t)id + 1] = M1 / (4.0 * vol6);
-            A.cen[3 * (int64_t)id + 2] = M2 / (4.0 * vol6);
+            A.cen[3 * (int64_t)id + 0] = o0 + M0 / (4.0 * vol6);
+            A.cen[3 * (int64_t)id + 1] = o1 + M1 / (4.0 * vol6);
+            A.cen[3 * (int64_t)id + 2] = o2 + M2 / (4.0 * vol6);
         }
         if (A.nv) A.nv[id] = nvert;
         if (A.ne) A.ne[id] = sumord / 2;
@@ -931,9 +1033,13 @@ struct SyncWaves {
     static constexpr int value = G == 32 ? VC_SYNC_WAVES : 2;
 };
 
-template <int G, int S, int MAXP, bool F32>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>::value))) void k_cells_sync(CellArgs A)
+template <int G, int S, int MAXP, bool F32, bool RAD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>::value))) void k_cells_sync(CellArgs Ain)
 {
+    // the Voronoi instantiation carries no radical code: its rad pointer is
+    // a compile-time null
+    CellArgs A = Ain;
+    if (!RAD) A.rad = nullptr;
     static_assert(((G * S) & (G * S - 1)) == 0 && G * S <= 256, "slot count must be a power of two");
     static_assert(G == 16 || G == 32, "group width");
     __shared__ SL<G, S, MAXP> shv[Gw<G>::CPW];
@@ -973,12 +1079,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
 
 hipError_t launch_cells_group(const CellArgs &a, int precision, int cpw, int waves, hipStream_t s)
 {
+    const bool rad = a.rad != nullptr;
     if (cpw == 4) {
-        if (precision == 1) k_cells_sync<16, 4, 32, true><<<waves, 64, 0, s>>>(a);
-        else k_cells_sync<16, 4, 32, false><<<waves, 64, 0, s>>>(a);
+        if (rad) {
+            if (precision == 1) k_cells_sync<16, 4, 32, true, true><<<waves, 64, 0, s>>>(a);
+            else k_cells_sync<16, 4, 32, false, true><<<waves, 64, 0, s>>>(a);
+        } else {
+            if (precision == 1) k_cells_sync<16, 4, 32, true, false><<<waves, 64, 0, s>>>(a);
+            else k_cells_sync<16, 4, 32, false, false><<<waves, 64, 0, s>>>(a);
+        }
     } else if (cpw == 2) {
-        if (precision == 1) k_cells_sync<32, 2, 40, true><<<waves, 64, 0, s>>>(a);
-        else k_cells_sync<32, 2, 40, false><<<waves, 64, 0, s>>>(a);
+        if (rad) {
+            if (precision == 1) k_cells_sync<32, 2, 40, true, true><<<waves, 64, 0, s>>>(a);
+            else k_cells_sync<32, 2, 40, false, true><<<waves, 64, 0, s>>>(a);
+        } else {
+            if (precision == 1) k_cells_sync<32, 2, 40, true, false><<<waves, 64, 0, s>>>(a);
+            else k_cells_sync<32, 2, 40, false, false><<<waves, 64, 0, s>>>(a);
+        }
     } else {
         return hipErrorInvalidValue;
     }

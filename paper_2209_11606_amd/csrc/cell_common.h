@@ -15,6 +15,19 @@ struct PlaneD {
     int wall;
 };
 
+// A plane of a radical cell: h = (q.q + ri^2 - rj^2) / 2 with ri the radius
+// of the cell's particle and rj that of the neighbour (a wall keeps its h).
+struct PlaneR {
+    PlaneD p;
+    double ri, rj;
+};
+
+template <class P>
+constexpr bool kRadicalPlane = sizeof(P) > sizeof(PlaneD);
+
+__device__ __forceinline__ const PlaneD &plane_base(const PlaneD &p) { return p; }
+__device__ __forceinline__ const PlaneD &plane_base(const PlaneR &p) { return p.p; }
+
 // ---------------------------------------------------------------------------
 // Exact sign with floating-point expansions (Shewchuk 1997): a list of
 // doubles, nonoverlapping and increasing in magnitude, whose exact sum is the
@@ -69,7 +82,21 @@ __device__ inline int xs_sign(const double *e, int n)
 }
 
 // The exact offset of a plane as a short list of doubles summing to it:
-// q.q/2 for a bisector (three exact squares, halved), h for a wall.
+// q.q/2 for a bisector (three exact squares, halved), (q.q + ri^2 - rj^2)/2
+// for a radical plane (five exact squares, halved), h for a wall.
+__device__ inline int xs_radical_terms(const PlaneR &p, double *out, int k)
+{
+    if (p.p.wall) return k;
+    double x, y;
+    xs_two_prod(p.ri, p.ri, x, y);
+    out[k++] = 0.5 * x;
+    out[k++] = 0.5 * y;
+    xs_two_prod(p.rj, p.rj, x, y);
+    out[k++] = -0.5 * x;
+    out[k++] = -0.5 * y;
+    return k;
+}
+
 __device__ inline int xs_offset(const PlaneD &p, double *out)
 {
     if (p.wall) {
@@ -85,6 +112,11 @@ __device__ inline int xs_offset(const PlaneD &p, double *out)
         out[k++] = 0.5 * y;
     }
     return k;
+}
+
+__device__ inline int xs_offset(const PlaneR &p, double *out)
+{
+    return xs_radical_terms(p, out, xs_offset(p.p, out));
 }
 
 // acc += sgn * h_list * det3(u, v, w) over the six permutation products.
@@ -113,17 +145,19 @@ __device__ int xs_acc_hdet(double *acc, int n, const double *hl, int nh, double 
 
 // Exact sign of n_p.v - h_p at v = planes a, b, c:
 //   s * D(a,b,c) = h_a D(b,c,p) - h_b D(a,c,p) + h_c D(a,b,p) - h_p D(a,b,c).
-__device__ __noinline__ int exact_side3(PlaneD a, PlaneD b, PlaneD c, PlaneD p, double *ws)
+// P is PlaneD (Voronoi) or PlaneR (radical).
+template <class P>
+__device__ __noinline__ int exact_side3(P a, P b, P c, P p, double *ws)
 {
-    const PlaneD *r[4] = {&a, &b, &c, &p};
+    const P *r[4] = {&a, &b, &c, &p};
     double nv[4][3];
     for (int i = 0; i < 4; i++) {
-        nv[i][0] = r[i]->n0;
-        nv[i][1] = r[i]->n1;
-        nv[i][2] = r[i]->n2;
+        nv[i][0] = plane_base(*r[i]).n0;
+        nv[i][1] = plane_base(*r[i]).n1;
+        nv[i][2] = plane_base(*r[i]).n2;
     }
     const int mi[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
-    double hl[6];
+    double hl[kRadicalPlane<P> ? 10 : 6];  // the plane offset's exact terms
     int n = 0;
     for (int i = 0; i < 4; i++) {
         int nh = xs_offset(*r[i], hl);
@@ -171,17 +205,23 @@ __device__ inline int xs_offset2(const PlaneD &p, double *out)
     return k;
 }
 
-__device__ __noinline__ int exact_side2(PlaneD a, PlaneD b, PlaneD p, double *ws)
+__device__ inline int xs_offset2(const PlaneR &p, double *out)
 {
-    const PlaneD *r[3] = {&a, &b, &p};
+    return xs_radical_terms(p, out, xs_offset2(p.p, out));
+}
+
+template <class P>
+__device__ __noinline__ int exact_side2(P a, P b, P p, double *ws)
+{
+    const P *r[3] = {&a, &b, &p};
     double nv[3][2];
     for (int i = 0; i < 3; i++) {
-        nv[i][0] = r[i]->n0;
-        nv[i][1] = r[i]->n1;
+        nv[i][0] = plane_base(*r[i]).n0;
+        nv[i][1] = plane_base(*r[i]).n1;
     }
     const int mi[3][2] = {{1, 2}, {0, 2}, {0, 1}};
     const double sg[3] = {-1.0, 1.0, -1.0};
-    double hl[4];
+    double hl[kRadicalPlane<P> ? 8 : 4];
     int n = 0;
     for (int i = 0; i < 3; i++) {
         int nh = xs_offset2(*r[i], hl);
@@ -192,6 +232,14 @@ __device__ __noinline__ int exact_side2(PlaneD a, PlaneD b, PlaneD p, double *ws
     int m = xs_acc_hdet2(ws, 0, &one, 1, 1.0, nv[0], nv[1]);
     int s2 = m ? xs_sign(ws, m) : 0;
     return s3 * s2;
+}
+
+// r_i^2 - r_j^2 of a radical plane (section 2.1.1) with each square rounded
+// on its own (no fused multiply-add): equal radii give exactly 0, and the
+// plane is then the bisector bit for bit
+__device__ __forceinline__ double radical_shift(double ri, double rj)
+{
+    return ri * ri - rj * rj;
 }
 
 #pragma clang fp contract(fast)
@@ -390,7 +438,21 @@ __device__ __forceinline__ BoxSide box_side(const Tess &T, double pd, int d, int
     return b;
 }
 
-enum { ST_OK = 0, ST_CAP = 1, ST_DUP = 3 };
+// Squared search radius from the radius bound R (an upper bound of the
+// vertex norms; R2 >= R^2 ... both upper bounds): a candidate at distance d
+// can cut only if d^2 - 2 R d + ri^2 - rj^2 < 0 for some vertex, i.e.
+// d < R + sqrt(R^2 + rmax^2 - ri^2); without radii that is 2R.  The result
+// carries the radius bound's safety factor.
+__device__ __forceinline__ double search_lim(double R2, double R, const CellArgs &A, double ri)
+{
+    if (!A.rad) return 4.0 * R2 * kMargin;
+    const double rm = *A.rmax;
+    const double t = fmax(R2 + (rm * rm - ri * ri), 0.0);
+    const double l = R + sqrt(t) * (1.0 + 0x1p-40);
+    return l * l * kMargin;
+}
+
+enum { ST_OK = 0, ST_CAP = 1, ST_DUP = 3, ST_EMPTY = 5 };
 enum { DC_CAND, DC_TESTS, DC_CUTS, DC_NEWV, DC_EXACT, DC_RECHECK, DC_SPILL, DC_BLOCKS, DC_FALLBACK, DC_N };
 
 }  // namespace

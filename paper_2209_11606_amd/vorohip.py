@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvorohip.so")
 
 VC_OK, VC_E_ARG, VC_E_RANGE, VC_E_DUPLICATE, VC_E_NOMEM, VC_E_HIP, VC_E_CAPACITY, VC_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
-VC_CELL_OK, VC_CELL_SPILLED, VC_CELL_CAPACITY, VC_CELL_DUPLICATE, VC_CELL_SKIPPED = 0, 1, 2, 3, 4
+VC_CELL_OK, VC_CELL_SPILLED, VC_CELL_CAPACITY, VC_CELL_DUPLICATE, VC_CELL_SKIPPED, VC_CELL_EMPTY = 0, 1, 2, 3, 4, 5
 VC_FP64, VC_F32_FILTER = 0, 1
 VC_VOLUME, VC_CENTROID, VC_COUNTS, VC_FACE_ORDERS, VC_NEIGHBORS, VC_NEIGHBOR_COUNT, VC_DIAG = 1, 2, 4, 8, 16, 32, 64
 VC_ALL = 127
@@ -57,6 +57,8 @@ def _load():
         "vc_options_init": (I32, [P, I32, P, P, P]),
         "vc_container_create": (I32, [P, I64, P, P, P]),
         "vc_container_rebin": (I32, [P, P, P]),
+        "vc_container_set_radii": (I32, [P, P, P]),
+        "vc_batch_set_radii": (I32, [P, P, P]),
         "vc_result_create": (I32, [P, U32, P]),
         "vc_grid_size": (I32, [P, I64, P]),
         "vc_container_blocks": (I32, [P, P, P, P]),
@@ -84,7 +86,8 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_grid_size", "vc_container_blocks",
+EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_container_set_radii",
+            "vc_batch_set_radii", "vc_grid_size", "vc_container_blocks",
             "vc_result_create", "vc_compute", "vc_compute_subset",
             "vc_result_get", "vc_result_copy", "vc_result_kernel_ms", "vc_result_destroy", "vc_container_destroy", "vc_batch_create",
             "vc_batch_rebin", "vc_batch_result_create", "vc_batch_compute", "vc_batch_tune", "vc_batch_destroy",
@@ -144,6 +147,32 @@ def vc_container_create(xyz, opts, stream=None):
 def vc_container_rebin(c, xyz, stream=None):
     ptr = xyz.data_ptr() if hasattr(xyz, "data_ptr") else xyz.ctypes.data
     _check(_lib.vc_container_rebin(c, ctypes.c_void_p(ptr), ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def _radii_ptr(radii):
+    if radii is None:
+        return None, None
+    if hasattr(radii, "data_ptr"):
+        import torch
+        if radii.dtype != torch.float64 or not radii.is_contiguous():
+            raise ValueError("radii must be a contiguous float64 tensor")
+        return radii, radii.data_ptr()
+    a = np.ascontiguousarray(radii, dtype=np.float64)
+    return a, a.ctypes.data
+
+
+def vc_container_set_radii(c, radii, stream=None):
+    """radii: n float64 values by input index (numpy array, or torch tensor on
+    the host or the GPU), or None for the plain Voronoi tessellation."""
+    keep, ptr = _radii_ptr(radii)
+    _check(_lib.vc_container_set_radii(c, ctypes.c_void_p(ptr), ctypes.c_void_p(_stream_ptr(stream))))
+    del keep
+
+
+def vc_batch_set_radii(b, radii, stream=None):
+    keep, ptr = _radii_ptr(radii)
+    _check(_lib.vc_batch_set_radii(b, ctypes.c_void_p(ptr), ctypes.c_void_p(_stream_ptr(stream))))
+    del keep
 
 
 def vc_grid_size(opts, n):
@@ -280,13 +309,16 @@ def neighbor_lists(res):
             for i in range(len(off) - 1)]
 
 
-def tessellate(xyz, lo, hi, periodic, mask=VC_ALL, stream=None, **opts):
+def tessellate(xyz, lo, hi, periodic, mask=VC_ALL, stream=None, radii=None, **opts):
     """Create a container from device positions, compute all cells, fetch the
-    results to the host, and free everything.  Convenience for tests."""
+    results to the host, and free everything.  Convenience for tests.
+    radii (n values) makes it the radical tessellation."""
     dim = xyz.shape[1]
     o = vc_options_init(dim, lo, hi, periodic, **opts)
     c = vc_container_create(xyz, o, stream)
     try:
+        if radii is not None:
+            vc_container_set_radii(c, radii, stream)
         r = vc_result_create(c, mask)
         try:
             vc_compute(c, r, stream)

@@ -136,6 +136,18 @@ def clustered(n=1_000_000, dim=3, seed=7):
                 grid=[g] * dim, n_opt=0.5, clip=0.0)
 
 
+def polydisperse(n=1_000_000, dim=3, seed=8, rmax_frac=0.6, periodic=True):
+    """Polydisperse container for the radical tessellation (section 2.1.1):
+    n uniform points in the unit box with radii uniform on [0, rmax_frac s),
+    s = n^(-1/dim) the mean spacing.  The points are random, not a packing,
+    so wide radii leave some small particles with empty cells: about 0.6%
+    in 3D and 3% in 2D at rmax_frac 0.6, 8% in 3D at 1.0."""
+    x = uniform(n, dim, 1.0, seed)
+    rad = rng(seed + 1).random(n) * (rmax_frac * n ** (-1.0 / dim))
+    per = [1 if periodic else 0] * dim
+    return dict(name=f"polydisperse_{dim}d_{n}", xyz=x, radii=rad, lo=[0.0] * dim, hi=[1.0] * dim, periodic=per)
+
+
 def batch_sizes(count=4096, lo=100, hi=100_000, seed=1000):
     """Log-uniform tessellation sizes round(exp(U[ln lo, ln hi]))."""
     u = rng(seed).random(count)
