@@ -271,7 +271,7 @@ vc_status bin(vc_container *c, hipStream_t s)
     HIP_TRY(launch_bin_count(c->xyz, c->n, c->dim, c->tess, c->ptess, c->blk, c->rank, c->count, c->err, s));
     HIP_TRY(launch_scan(c->count, c->start, c->nb, c->scan_tmp, s));
     HIP_TRY(launch_scatter(c->xyz, c->n, c->dim, c->ptess, c->blk, c->rank, c->start, c->sid, c->part, c->inv, s));
-    if (c->radical) HIP_TRY(launch_radii(c->rad_in, c->n, c->inv, c->rad, c->rmax, c->err, s));
+    if (c->radical) HIP_TRY(launch_radii(c->rad_in, c->n, c->inv, c->rad, s));
     return VC_OK;
 }
 
@@ -305,7 +305,8 @@ vc_status set_radii(vc_container *c, const double *radii, hipStream_t s)
     HIP_TRY(hipMemcpyAsync(c->rad_in, radii, (size_t)c->n * sizeof(double),
                            is_device_ptr(radii) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
     HIP_TRY(launch_fill_i32(c->err, 1, 0, s));
-    HIP_TRY(launch_radii(c->rad_in, c->n, c->inv, c->rad, c->rmax, c->err, s));
+    HIP_TRY(launch_radii_check(c->rad_in, c->n, c->rmax, c->err, s));
+    HIP_TRY(launch_radii(c->rad_in, c->n, c->inv, c->rad, s));
     int32_t herr = 0;
     HIP_TRY(hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -167,29 +167,39 @@ __global__ __launch_bounds__(kTB) void k_rank_scatter(const double *__restrict__
     }
 }
 
-// radii moved to sorted-slot order (radical tessellation) and their maximum,
-// kept as the bit pattern of a non-negative double (whose order is that of
-// the values); a radius that is negative or not finite sets the error flag
+// radii moved to sorted-slot order (radical tessellation)
 __global__ __launch_bounds__(kTB) void k_radii(const double *__restrict__ rin, int64_t n,
-                                               const int32_t *__restrict__ inv, double *__restrict__ rad,
-                                               unsigned long long *__restrict__ rmax_bits, int32_t *__restrict__ err)
+                                               const int32_t *__restrict__ inv, double *__restrict__ rad)
 {
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+        rad[inv[i]] = rin[i];
+}
+
+// check of the radii and their maximum, kept as the bit pattern of a
+// non-negative double (whose order is that of the values): a workgroup
+// reduction, then one atomic per workgroup.  A radius that is negative or
+// not finite sets the error flag.
+__global__ __launch_bounds__(kTB) void k_radii_check(const double *__restrict__ rin, int64_t n,
+                                                     unsigned long long *__restrict__ rmax_bits,
+                                                     int32_t *__restrict__ err)
+{
+    __shared__ unsigned long long wmax[kTB / 64];
     unsigned long long m = 0;
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
         double r = rin[i];
-        if (!(r >= 0.0 && r <= 1.7976931348623157e308)) {
-            bad = true;
-            r = 0.0;
-        }
-        if (r == 0.0) r = 0.0;  // -0 -> +0
-        rad[inv[i]] = r;
-        m = max(m, (unsigned long long)__double_as_longlong(r));
+        if (!(r >= 0.0 && r <= 1.7976931348623157e308)) bad = true;
+        else if (r > 0.0) m = max(m, (unsigned long long)__double_as_longlong(r));
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, o));
-    if (__lane_id() == 0 && m) atomicMax(rmax_bits, m);
+    if (__lane_id() == 0) wmax[threadIdx.x / 64] = m;
     if (bad) *err = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kTB / 64; w++) m = max(m, wmax[w]);
+        if (m) atomicMax(rmax_bits, m);
+    }
 }
 
 // sorted slots of a list of input indices (a subset of the cells); an index
@@ -300,11 +310,17 @@ hipError_t launch_subset_list(const int64_t *ids, int64_t m, int64_t n, const in
     return hipGetLastError();
 }
 
-hipError_t launch_radii(const double *rin, int64_t n, const int32_t *inv, double *rad, double *rmax, int32_t *err,
-                        hipStream_t s)
+hipError_t launch_radii(const double *rin, int64_t n, const int32_t *inv, double *rad, hipStream_t s)
+{
+    k_radii<<<grid_for(n), kTB, 0, s>>>(rin, n, inv, rad);
+    return hipGetLastError();
+}
+
+hipError_t launch_radii_check(const double *rin, int64_t n, double *rmax, int32_t *err, hipStream_t s)
 {
     k_fill<<<1, kTB, 0, s>>>(reinterpret_cast<int32_t *>(rmax), 2, 0);
-    k_radii<<<grid_for(n), kTB, 0, s>>>(rin, n, inv, rad, reinterpret_cast<unsigned long long *>(rmax), err);
+    const int g = std::min(grid_for(n), 1024);
+    k_radii_check<<<g, kTB, 0, s>>>(rin, n, reinterpret_cast<unsigned long long *>(rmax), err);
     return hipGetLastError();
 }
 

@@ -105,8 +105,8 @@ hipError_t launch_scatter(const double *xyz, int64_t n, int dim, const int32_t *
                           hipStream_t s);
 hipError_t launch_subset_list(const int64_t *ids, int64_t m, int64_t n, const int32_t *inv, int32_t *out,
                               int32_t *err, hipStream_t s);
-hipError_t launch_radii(const double *rin, int64_t n, const int32_t *inv, double *rad, double *rmax, int32_t *err,
-                        hipStream_t s);
+hipError_t launch_radii(const double *rin, int64_t n, const int32_t *inv, double *rad, hipStream_t s);
+hipError_t launch_radii_check(const double *rin, int64_t n, double *rmax, int32_t *err, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_cells(const CellArgs &a, int precision, int slots, int waves, hipStream_t s);
