@@ -13,6 +13,10 @@ face-order vector fo[k] = number of faces with k edges, and one neighbour label
 (j, image code) per face.  Labels -1..-6 are the walls x-, x+, y-, y+, z-, z+,
 -7..-12 the faces of the clip cube when cells are clipped (section 3.1.3);
 the image code of a periodic shift s is 25(s_z+2) + 5(s_y+2) + (s_x+2).
+
+Weinberg codes (the cell-topology code of VoroTop, section 5, after Weinberg
+1966): ``Oracle.weinberg`` walks every dart of the cell's edge graph from
+every start and in both orientations and keeps the smallest code.
 """
 import ctypes
 import math
@@ -67,6 +71,10 @@ def _load():
         lib.vo_num_threads.restype = ctypes.c_int
         lib.vo_cell_vertices.restype = ctypes.c_int
         lib.vo_cell_vertices.argtypes = [P, ctypes.c_int64, ctypes.c_double, P, ctypes.c_int]
+        lib.vo_weinberg.restype = ctypes.c_int
+        lib.vo_weinberg.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_double, P, ctypes.c_int, P, P, P]
+        lib.vo_cell_edges.restype = ctypes.c_int
+        lib.vo_cell_edges.argtypes = [P, ctypes.c_int64, ctypes.c_double, P, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -173,6 +181,35 @@ class Oracle:
         if rc != 0:
             raise RuntimeError(f"oracle: cell computation failed with code {rc}")
         return out
+
+    def weinberg(self, idx=None, nthreads=1, tau=TAU, maxlen=2048):
+        """Weinberg codes of the 3D cells of the particles idx (default: all):
+        the lexicographically smallest walk code over every starting dart and
+        both orientations (Weinberg 1966; the topology code of VoroTop).
+        Returns a dict: codes (list of uint8 arrays of length 2E; empty for an
+        empty cell), sym (the number of (dart, orientation) pairs giving the
+        code: the order of the graph's symmetry group), chiral (1 when only
+        one orientation gives it)."""
+        lib = _load()
+        idx = np.arange(self.n, dtype=np.int64) if idx is None else np.ascontiguousarray(idx, dtype=np.int64)
+        m = len(idx)
+        codes = np.zeros((m, maxlen), np.uint8)
+        ln = np.zeros(m, np.int32)
+        sym = np.zeros(m, np.int32)
+        ch = np.zeros(m, np.int32)
+        rc = lib.vo_weinberg(self._h, idx.ctypes.data, m, nthreads, tau, codes.ctypes.data, maxlen, ln.ctypes.data,
+                             sym.ctypes.data, ch.ctypes.data)
+        if rc != 0:
+            raise RuntimeError(f"oracle: Weinberg code failed with code {rc}")
+        return dict(codes=[codes[t, :ln[t]].copy() for t in range(m)], len=ln, sym=sym, chiral=ch)
+
+    def edges(self, i, tau=TAU):
+        """Undirected edges (u, w), u < w, of the 3D cell of particle i."""
+        buf = np.zeros((8192, 2), np.int32)
+        k = _load().vo_cell_edges(self._h, int(i), tau, buf.ctypes.data, 8192)
+        if k < 0:
+            raise RuntimeError(f"oracle: cell computation failed with code {k}")
+        return buf[:k].copy()
 
     def vertices(self, i, tau=TAU):
         """Vertices of the cell of particle i, relative to the particle."""

@@ -34,6 +34,11 @@
  *
  * The 2D form (section 2.1: "identical in both 2D and 3D") clips a polygon.
  *
+ * Weinberg codes (section 5, the topology code that VoroTop computes for each
+ * cell; after Weinberg 1966): the cell's edges as darts, one walk over every
+ * dart per starting dart and orientation under Weinberg's three turning
+ * rules, and the smallest resulting code.
+ *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -shared -fPIC.
  */
 #include <math.h>
@@ -1187,6 +1192,209 @@ int vo_cell_vertices(const vo_handle *H, int64_t i, double tau, double *out, int
             for (int d = 0; d < 3; d++) out[3 * k + d] = c->v[v][d];
         }
         rc = n;
+    }
+    free(c);
+    free(cbuf);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Weinberg codes (the topology code of VoroTop, section 5; Weinberg 1966)   */
+/* ------------------------------------------------------------------------ */
+
+/* The edge graph of a finished 3D cell as darts (directed edges).  Each face
+ * lists its vertices in one consistent rotational sense, so the dart u -> w
+ * taken along face f has f on one fixed side; every edge gives two darts,
+ * one in each of its two faces.  nxt: the next dart along the same face;
+ * prv: the previous one; rev: the opposite dart. */
+typedef struct {
+    int nd, nv;
+    int tail[2 * VO_MAXV], head[2 * VO_MAXV];
+    int nxt[2 * VO_MAXV], prv[2 * VO_MAXV], rev[2 * VO_MAXV];
+} odarts;
+
+static int cell_darts(const ocell *c, odarts *g)
+{
+    int nd = 0;
+    for (int f = 0; f < c->nf; f++) {
+        int n = c->fn[f];
+        if (nd + n > 2 * VO_MAXV) return VO_ERR_CAP;
+        for (int k = 0; k < n; k++) {
+            g->tail[nd + k] = c->fv[f][k];
+            g->head[nd + k] = c->fv[f][(k + 1) % n];
+            g->nxt[nd + k] = nd + (k + 1) % n;
+            g->prv[nd + k] = nd + (k + n - 1) % n;
+        }
+        nd += n;
+    }
+    g->nd = nd;
+    g->nv = c->nv;
+    for (int d = 0; d < nd; d++) {
+        g->rev[d] = -1;
+        for (int e = 0; e < nd; e++)
+            if (g->tail[e] == g->head[d] && g->head[e] == g->tail[d]) { g->rev[d] = e; break; }
+        if (g->rev[d] < 0) return VO_ERR_TOPO;
+    }
+    return VO_OK;
+}
+
+/* The outgoing dart after dart d (which leaves vertex v) in the rotation
+ * around v: orientation 0 turns one way, orientation 1 the other.  With f
+ * the face of d, the dart that enters v along f is prv(d), and the next
+ * dart around v is the one leaving v along the other face of that edge. */
+static int rot(const odarts *g, int d, int o)
+{
+    return o == 0 ? g->nxt[g->rev[d]] : g->rev[g->prv[d]];
+}
+
+/* One Weinberg walk from dart d0 in orientation o: every dart once.  The
+ * walk's vertices are numbered 1, 2, ... in the order they are first
+ * reached, and the code is the number of the vertex each dart leaves, in
+ * the order the darts are taken (2E numbers).  The rules: on reaching a
+ * vertex for the first time, leave by the next dart in the rotation after
+ * the one just arrived on (reversed); on reaching a vertex seen before,
+ * go back along the same edge unless that was already done; otherwise
+ * leave by the first unused dart in the rotation after the reversed
+ * arrival dart. */
+static int weinberg_walk(const odarts *g, int d0, int o, uint8_t *code, int *lab, unsigned char *used)
+{
+    for (int v = 0; v < g->nv; v++) lab[v] = 0;
+    for (int d = 0; d < g->nd; d++) used[d] = 0;
+    int nl = 1, d = d0;
+    lab[g->tail[d0]] = 1;
+    for (int k = 0; k < g->nd; k++) {
+        code[k] = (uint8_t)lab[g->tail[d]];
+        used[d] = 1;
+        if (k == g->nd - 1) break;
+        int v = g->head[d], r = g->rev[d];
+        if (lab[v] == 0) {
+            lab[v] = ++nl;
+            d = rot(g, r, o);
+        } else if (!used[r]) {
+            d = r;
+        } else {
+            int e = rot(g, r, o), guard = 0;
+            while (used[e]) {
+                e = rot(g, e, o);
+                if (++guard > g->nd) return VO_ERR_TOPO;
+            }
+            d = e;
+        }
+    }
+    return VO_OK;
+}
+
+/* The cell's Weinberg code: the lexicographically smallest walk code over
+ * every starting dart and both orientations.  sym = the number of (dart,
+ * orientation) pairs that give it (the order of the graph's symmetry
+ * group); chiral = 1 when only one orientation gives it.  Returns the code
+ * length 2E, or a negative error. */
+static int weinberg3(const ocell *c, uint8_t *best, int maxlen, int32_t *sym, int32_t *chiral)
+{
+    odarts *g = (odarts *)malloc(sizeof(odarts));
+    uint8_t *code = (uint8_t *)malloc(2 * VO_MAXV);
+    int *lab = (int *)malloc(VO_MAXV * sizeof(int));
+    unsigned char *used = (unsigned char *)malloc(2 * VO_MAXV);
+    int rc = (g && code && lab && used) ? cell_darts(c, g) : VO_ERR_MEM;
+    if (rc == VO_OK && (g->nd > maxlen || c->nv > 255)) rc = VO_ERR_CAP;
+    int count = 0, omask = 0;
+    for (int o = 0; o < 2 && rc == VO_OK; o++)
+        for (int d0 = 0; d0 < g->nd && rc == VO_OK; d0++) {
+            rc = weinberg_walk(g, d0, o, code, lab, used);
+            if (rc != VO_OK) break;
+            int cmp = count == 0 ? -1 : memcmp(code, best, (size_t)g->nd);
+            if (cmp < 0) {
+                memcpy(best, code, (size_t)g->nd);
+                count = 1;
+                omask = 1 << o;
+            } else if (cmp == 0) {
+                count++;
+                omask |= 1 << o;
+            }
+        }
+    if (rc == VO_OK) {
+        *sym = count;
+        *chiral = omask != 3;
+        rc = g->nd;
+    }
+    free(g);
+    free(code);
+    free(lab);
+    free(used);
+    return rc;
+}
+
+/* Weinberg codes of the 3D cells of the particles idx[0..m): code t in
+ * codes[t * maxlen ...], its length 2E in len[t] (0 for an empty cell),
+ * sym[t], chiral[t].  Returns 0 or the first per-cell error code. */
+int vo_weinberg(const vo_handle *H, const int64_t *idx, int64_t m, int nthreads, double tau, uint8_t *codes,
+                int maxlen, int32_t *len, int32_t *sym, int32_t *chiral)
+{
+    if (!H || H->dim != 3 || (m > 0 && (!idx || !codes || !len || !sym || !chiral))) return VO_ERR_ARG;
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        ocell *c = (ocell *)malloc(sizeof(ocell));
+        int64_t ccap = 256;
+        ocand *cbuf = (ocand *)malloc((size_t)ccap * sizeof(ocand));
+        if (c) memset(c->cnt, 0, sizeof(c->cnt));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t t = 0; t < m; t++) {
+            len[t] = sym[t] = chiral[t] = 0;
+            if (!c || !cbuf) { err = VO_ERR_MEM; continue; }
+            c->tau = tau;
+            c->audit = 0;
+            int64_t i = idx[t];
+            int rc = (i < 0 || i >= H->n) ? VO_ERR_ARG : compute_cell(H, i, c, &cbuf, &ccap);
+            if (rc == VO_EMPTY) continue;
+            if (rc == VO_OK) rc = weinberg3(c, codes + (size_t)t * maxlen, maxlen, &sym[t], &chiral[t]);
+            if (rc < 0) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+                if (!err) err = rc;
+                continue;
+            }
+            len[t] = rc;
+        }
+        free(c);
+        free(cbuf);
+    }
+    return err;
+}
+
+/* Undirected edges of the 3D cell of particle i as vertex pairs (u < w),
+ * for graph checks in tests.  Returns the edge count (up to maxe written),
+ * or a negative error. */
+int vo_cell_edges(const vo_handle *H, int64_t i, double tau, int32_t *out, int maxe)
+{
+    if (!H || H->dim != 3 || i < 0 || i >= H->n) return VO_ERR_ARG;
+    ocell *c = (ocell *)calloc(1, sizeof(ocell));
+    int64_t ccap = 256;
+    ocand *cbuf = (ocand *)malloc((size_t)ccap * sizeof(ocand));
+    if (!c || !cbuf) { free(c); free(cbuf); return VO_ERR_MEM; }
+    c->tau = tau;
+    int rc = compute_cell(H, i, c, &cbuf, &ccap);
+    if (rc == VO_EMPTY) rc = 0;
+    else if (rc == VO_OK) {
+        int ne = 0;
+        for (int f = 0; f < c->nf; f++)
+            for (int k = 0; k < c->fn[f]; k++) {
+                int u = c->fv[f][k], w = c->fv[f][(k + 1) % c->fn[f]];
+                if (u < w) {
+                    if (ne < maxe) {
+                        out[2 * ne] = u;
+                        out[2 * ne + 1] = w;
+                    }
+                    ne++;
+                }
+            }
+        rc = ne;
     }
     free(c);
     free(cbuf);

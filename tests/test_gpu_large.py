@@ -84,3 +84,36 @@ def test_uniform_102m_reduced_mask(v):
                                                                     neighbors=False)
     assert np.array_equal(nf[idx], ro["nf"])
     assert np.array_equal(fo[idx].astype(np.int32), ro["fo"])
+
+
+def test_polydisperse_1m_radical(v):
+    """The radical tessellation at the measured size (10^6 particles, radii
+    up to 0.6 spacings, the two-cells-per-wave form the bench times): the
+    volumes tile the box, the empty set and the sampled cells equal the
+    oracle, and so does every cell that went through the spill pass."""
+    w = W.polydisperse(1_000_000, 3)
+    x, rad = w["xyz"], w["radii"]
+    xt = torch.from_numpy(x).to("cuda:0")
+    a = v.tessellate(xt, w["lo"], w["hi"], w["periodic"], v.VC_ALL, radii=rad, cells_per_wave=2)
+    empty = a["status"] == v.VC_CELL_EMPTY
+    assert np.all((a["status"] <= 1) | empty)
+    assert 0.003 * len(x) < empty.sum() < 0.01 * len(x)
+    assert math.fsum(a["vol"]) == pytest.approx(1.0, rel=1e-12)
+    ok = ~empty
+    assert np.all(a["nv"][ok] - a["ne"][ok] + a["nf"][ok] == 2)
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([rng.choice(len(x), 1500, replace=False), np.nonzero(a["status"] == 1)[0],
+                                    np.nonzero(empty)[0][:200]]))
+    o = oracle.Oracle(x, w["lo"], w["hi"], w["periodic"], radii=rad)
+    r = o.cells(idx, nthreads=oracle.num_threads())
+    assert np.array_equal(a["status"][idx] == v.VC_CELL_EMPTY, r["status"] == oracle.Oracle.EMPTY)
+    nb = v.neighbor_lists(a)
+    for key in ("nv", "ne", "nf"):
+        assert np.array_equal(a[key][idx], r[key]), key
+    assert np.array_equal(a["fo"][idx], r["fo"])
+    for t, i in enumerate(idx):
+        assert np.array_equal(nb[i], r["nbr"][t]), i
+    s = len(x) ** (-1.0 / 3.0)
+    live = r["status"] != oracle.Oracle.EMPTY
+    dv = np.abs(a["vol"][idx][live] - r["vol"][live])
+    assert np.all(dv <= 1e-12 * r["vol"][live] + 1e-14 * s ** 3)

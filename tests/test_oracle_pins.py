@@ -472,3 +472,152 @@ def test_grid_rule():
     assert oracle.grid_size(1_000_000, [0] * 3, [100] * 3, 5.0) == [59, 59, 59]
     assert oracle.grid_size(10_000_000, [0] * 2, [1] * 2, 5.0) == [1415, 1415]
     assert oracle.grid_size(3, [0] * 3, [1] * 3, 5.0) == [1, 1, 1]
+
+
+# ---- Weinberg codes (the topology code of VoroTop, section 5) ----
+
+def _adjacency(edges, nv=None):
+    nv = int(edges.max()) + 1 if nv is None else nv
+    adj = [set() for _ in range(nv)]
+    for u, w in edges.tolist():
+        adj[u].add(w)
+        adj[w].add(u)
+    return adj
+
+
+def _isomorphisms(a1, a2, count_all=True):
+    """Number of vertex bijections G1 -> G2 that preserve adjacency, by
+    plain backtracking over a breadth-first order of G1 (each vertex after
+    the first is adjacent to an earlier one, so its image is a neighbour of
+    that one's image).  With count_all False, stops at the first."""
+    n = len(a1)
+    if n != len(a2) or sorted(map(len, a1)) != sorted(map(len, a2)):
+        return 0
+    order, parent, seen = [0], {0: None}, {0}
+    for v in order:
+        for w in sorted(a1[v]):
+            if w not in seen:
+                seen.add(w)
+                parent[w] = v
+                order.append(w)
+    assert len(order) == n  # connected
+    f, used = {}, set()
+    found = 0
+
+    def place(k):
+        nonlocal found
+        if k == n:
+            found += 1
+            return not count_all
+        v = order[k]
+        cands = range(n) if parent[v] is None else a2[f[parent[v]]]
+        for c in cands:
+            if c in used or len(a2[c]) != len(a1[v]):
+                continue
+            if any((u in a1[v]) != (f[u] in a2[c]) for u in f):
+                continue
+            f[v] = c
+            used.add(c)
+            stop = place(k + 1)
+            del f[v]
+            used.discard(c)
+            if stop:
+                return True
+        return False
+
+    place(0)
+    return found
+
+
+def _check_code_shape(code, edges):
+    """A walk code takes each dart once: length 2E, starts at vertex 1,
+    numbers vertices in order of first appearance, and leaves each vertex
+    once per incident edge."""
+    nv = int(edges.max()) + 1
+    assert len(code) == 2 * len(edges)
+    assert code[0] == 1
+    top = 0
+    for x in code.tolist():
+        assert 1 <= x <= top + 1
+        top = max(top, x)
+    assert top == nv
+    deg = np.bincount(edges.ravel(), minlength=nv)
+    assert sorted(np.bincount(code, minlength=nv + 1)[1:].tolist()) == sorted(deg.tolist())
+
+
+def test_weinberg_lattice_closed_forms():
+    """Cube (simple cubic), truncated octahedron (BCC) and rhombic
+    dodecahedron (FCC, six four-valent vertices): E = 12, 36, 24; each graph
+    has the 48 symmetries of the octahedral group, is not chiral, and its
+    symmetry count equals the automorphism count found by backtracking."""
+    for (x, hi), e in ((W.sc(4, 1.0), 12), (W.bcc(3, 1.0), 36), (W.fcc((3, 3, 3), 1.0), 24)):
+        o = oracle.Oracle(x, [0] * 3, hi, [1, 1, 1])
+        r = o.weinberg(np.arange(4))
+        assert np.all(r["len"] == 2 * e) and np.all(r["sym"] == 48) and np.all(r["chiral"] == 0)
+        assert all(np.array_equal(c, r["codes"][0]) for c in r["codes"])
+        ed = o.edges(0)
+        _check_code_shape(r["codes"][0], ed)
+        adj = _adjacency(ed)
+        assert _isomorphisms(adj, adj) == 48
+
+
+def test_weinberg_symmetry_is_automorphism_count():
+    """On random cells (periodic uniform) the number of (dart, orientation)
+    pairs giving the minimal code equals the order of the graph's
+    automorphism group counted by backtracking; a cell is chiral exactly
+    when no orientation-reversing pair gives it."""
+    x = W.uniform(3000, 3, 1.0, 51)
+    o = oracle.Oracle(x, [0] * 3, [1] * 3, [1, 1, 1])
+    idx = np.arange(0, 3000, 10)
+    r = o.weinberg(idx, nthreads=8)
+    assert np.any(r["sym"] > 1)
+    for t, i in enumerate(idx):
+        ed = o.edges(i)
+        _check_code_shape(r["codes"][t], ed)
+        adj = _adjacency(ed)
+        assert _isomorphisms(adj, adj) == r["sym"][t], i
+
+
+def test_weinberg_code_decides_isomorphism():
+    """Two cells have the same code exactly when their edge graphs are
+    isomorphic (3-connected planar graphs: Whitney), checked by backtracking
+    on every pair of cells with equal vertex and edge counts and face
+    orders in a sample, both ways."""
+    x = W.uniform(4000, 3, 1.0, 52)
+    o = oracle.Oracle(x, [0] * 3, [1] * 3, [1, 1, 1])
+    idx = np.arange(0, 4000, 4)
+    r = o.weinberg(idx, nthreads=8)
+    c = o.cells(idx, nthreads=8, neighbors=False)
+    groups = {}
+    for t in range(len(idx)):
+        if c["nf"][t] <= 12:
+            groups.setdefault((int(c["nv"][t]), tuple(c["fo"][t].tolist())), []).append(t)
+    same = diff = 0
+    for ts in groups.values():
+        for a_ in range(len(ts)):
+            for b_ in range(a_ + 1, min(len(ts), a_ + 6)):
+                ta, tb = ts[a_], ts[b_]
+                iso = _isomorphisms(_adjacency(o.edges(idx[ta])), _adjacency(o.edges(idx[tb])), False) > 0
+                eq = np.array_equal(r["codes"][ta], r["codes"][tb])
+                assert iso == eq, (idx[ta], idx[tb])
+                same += eq
+                diff += not eq
+    assert same > 20 and diff > 20
+
+
+def test_weinberg_invariant_under_mirror_and_axis_swap():
+    """Relabelling the particles, permuting the axes and mirroring the set
+    (x -> 1 - x, periodic) leave every cell's code, symmetry count and
+    chirality unchanged: the code is taken over both orientations."""
+    n = 1500
+    x = W.uniform(n, 3, 1.0, 53)
+    r0 = oracle.Oracle(x, [0] * 3, [1] * 3, [1, 1, 1]).weinberg(nthreads=8)
+    perm = W.rng(54).permutation(n)
+    y = x[perm][:, [2, 0, 1]].copy()
+    y[:, 1] = 1.0 - y[:, 1]
+    y[y >= 1.0] -= 1.0
+    r1 = oracle.Oracle(y, [0] * 3, [1] * 3, [1, 1, 1]).weinberg(nthreads=8)
+    for t in range(n):
+        i = perm[t]
+        assert np.array_equal(r1["codes"][t], r0["codes"][i])
+        assert r1["sym"][t] == r0["sym"][i] and r1["chiral"][t] == r0["chiral"][i]
