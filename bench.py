@@ -60,7 +60,7 @@ def parse():
     p.add_argument("--variants", default="all", help="comma list of variants to run (default all)")
     p.add_argument("--workload", default="periodic1m",
                    choices=["periodic1m", "batch4096", "fcc10m", "periodic2d10m", "periodic102m",
-                            "localized10m", "clustered10m", "polydisperse1m"],
+                            "localized10m", "clustered10m", "polydisperse1m", "vorotop1m"],
                    help="periodic1m: the metric's configuration (default); the others measure the remaining sets")
     return p.parse_args()
 
@@ -253,9 +253,17 @@ def cpu_baseline(members, sample):
                           radii=m.get("radii"))
         k = min(sample - done, len(m["xyz"]))
         idx = np.arange(k, dtype=np.int64)
-        t = time.perf_counter()
-        r = o.cells(idx, nthreads=cores, neighbors=False)
-        secs += time.perf_counter() - t
+        if m.get("weinberg"):
+            # cells and their Weinberg codes (the VoroTop pipeline); the
+            # statistics pass runs untimed, for the operation counts
+            t = time.perf_counter()
+            o.weinberg(idx, nthreads=cores)
+            secs += time.perf_counter() - t
+            r = o.cells(idx, nthreads=cores, neighbors=False)
+        else:
+            t = time.perf_counter()
+            r = o.cells(idx, nthreads=cores, neighbors=False)
+            secs += time.perf_counter() - t
         done += k
         for key, val in r["counters"].items():
             tot[key] = tot.get(key, 0) + val
@@ -327,6 +335,11 @@ def main():
         desc = ("extreme_clustering_10M: 10^7 points with coordinates 1/2 + 4 (X - 1/2)^3, walled unit cube, "
                 "N_opt 0.5 grid (section 3.1), full statistics")
         sample_desc = "first {} cells of the clustered set"
+    elif a.workload == "vorotop1m":
+        members = [W.vorotop(1_000_000)]
+        desc = ("vorotop_1M: 1,000,000 uniform particles in the periodic unit cube, full statistics and every "
+                "cell's Weinberg code (the VoroTop workload of section 5)")
+        sample_desc = "first {} cells and Weinberg codes of the same set"
     elif a.workload == "polydisperse1m":
         members = [W.polydisperse(1_000_000, 3)]
         desc = ("polydisperse_radical_1M: radical tessellation of 1,000,000 uniform particles in the periodic "
@@ -353,6 +366,8 @@ def main():
     variants = []
     dim = xyz.shape[1]
     mask = v.VC_FACE_ORDERS | v.VC_NEIGHBOR_COUNT if a.workload == "periodic102m" else v.VC_ALL
+    if members[0].get("weinberg"):
+        mask |= v.VC_WEINBERG
     if len(members) == 1:
         variants += [("fp64", v.VC_FP64, False), ("f32_filter", v.VC_F32_FILTER, False)]
     if dim == 3:

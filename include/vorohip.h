@@ -56,7 +56,10 @@ enum {
     VC_NEIGHBOR_COUNT = 32, /* number of neighbours (faces) only */
     VC_DIAG = 64,           /* run counters (exact decisions, rechecks, spills, ...) */
     VC_ALL = 127,           /* every field above */
-    VC_PERIMETER = 128      /* 2D only: cell perimeter */
+    VC_PERIMETER = 128,     /* 2D only: cell perimeter */
+    VC_WEINBERG = 256       /* 3D only: Weinberg code of each cell (VoroTop's
+                               topology code, section 5; Weinberg 1966), its
+                               symmetry count and chirality */
 };
 
 /* result fields for vc_result_get / vc_result_copy */
@@ -74,8 +77,31 @@ enum {
                              25(s_z+2) + 5(s_y+2) + (s_x+2), 62 = no shift */
     VC_F_STATUS = 9,      /* uint8[n]: VC_CELL_* */
     VC_F_DIAG = 10,       /* int64[VC_DIAG_LEN] */
-    VC_F_PERIMETER = 11   /* double[n], 2D */
+    VC_F_PERIMETER = 11,  /* double[n], 2D */
+    VC_F_WB_OFFSETS = 12, /* int64[n + 1] CSR offsets into the Weinberg codes */
+    VC_F_WB_CODES = 13,   /* uint8[total]: each cell's code, 2E vertex numbers;
+                             none (length 0) for an empty or failed cell and
+                             for a cell whose edge graph exceeds the record
+                             (3 + V + 2E > 384 bytes) */
+    VC_F_WB_SYM = 14,     /* int32[n]: the number of (starting dart, sense)
+                             pairs that give the code = the order of the edge
+                             graph's symmetry group; 0: no code */
+    VC_F_WB_CHIRAL = 15   /* uint8[n]: 1 when only one rotational sense gives
+                             the code (the cell has no mirror symmetry) */
 };
+/* The Weinberg code (VC_WEINBERG).  The edges of a 3D cell, each taken as
+ * two darts (directed edges), are walked once each: from a starting dart,
+ * on reaching a vertex for the first time leave by the next dart in the
+ * rotation around that vertex after the one just arrived on; on reaching a
+ * vertex seen before, go back along the same edge unless that was done
+ * already, and else leave by the first unused dart in the rotation after the
+ * one just arrived on.  Vertices are numbered 1, 2, ... as first reached and
+ * the walk's code is the number of the vertex each dart leaves (2E numbers,
+ * starting with 1).  The cell's code is the lexicographically smallest walk
+ * code over all 2E starting darts and both rotational senses: two cells have
+ * the same code exactly when their edge graphs are isomorphic.  Vertices
+ * where more than three faces meet (zero-length edges merged) are single
+ * vertices of higher degree. */
 #define VC_FO_LEN 32
 #define VC_DIAG_LEN 16
 

@@ -225,6 +225,14 @@ struct vc_result {
     uint8_t *shifts = nullptr;
     int32_t *scan_tmp = nullptr;
     uint8_t *status = nullptr;
+    // Weinberg codes: edge-graph records (n x kWbStride), code lengths, CSR
+    // offsets and codes, symmetry counts, chirality
+    uint8_t *wbg = nullptr;
+    int32_t *wbl = nullptr;
+    int64_t *wb_off = nullptr;
+    uint8_t *wb_codes = nullptr;
+    int32_t *wb_sym = nullptr;
+    uint8_t *wb_chiral = nullptr;
     unsigned long long *diag = nullptr;
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the main cell kernel
@@ -256,7 +264,7 @@ void free_result(vc_result *r)
 {
     if (!r) return;
     void *ps[] = {r->vol, r->cen, r->perim, r->nv, r->ne, r->nf, r->fo, r->nbr, r->nsh, r->off, r->ids, r->shifts,
-                  r->scan_tmp, r->status, r->diag};
+                  r->scan_tmp, r->status, r->diag, r->wbg, r->wbl, r->wb_off, r->wb_codes, r->wb_sym, r->wb_chiral};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     if (r->ev0) (void)hipEventDestroy(r->ev0);
@@ -416,6 +424,8 @@ CellArgs cell_args(const vc_container *c, const vc_result *r)
     A.diag = r->diag;
     A.xscratch = c->xscratch;
     A.xscratch_len = c->xscratch_len;
+    A.wbg = r->wbg;
+    A.wbl = r->wbl;
     if (c->radical) {
         A.rad = c->rad;
         A.rmax = c->rmax;
@@ -451,6 +461,12 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
     B.chunk = 1;
     if (c->dim == 2) HIP_TRY(launch_cells2d_spill(B, std::min(c->max_waves, 1024), s));
     else HIP_TRY(launch_cells_spill(B, std::min(c->max_waves, 1024), s));
+    if (r->mask & VC_WEINBERG) {
+        // codes of every cell with a record, written at the scan of their lengths
+        HIP_TRY(launch_nbr_offsets(r->wbl, r->n, r->wb_off, r->scan_tmp, s));
+        HIP_TRY(launch_weinberg(r->wbg, r->wbl, r->wb_off, r->n, r->wb_codes, r->wb_sym, r->wb_chiral, c->queue + 3,
+                                (int)std::min<int64_t>(c->max_waves, r->n), s));
+    }
     if ((r->mask & VC_NEIGHBORS) && (!cell_list || compact_subset)) {
         // CSR offsets by a scan of the face counts, then each cell's sorted
         // labels copied to its offset (capacity n * kMaxNbr always suffices)
@@ -466,8 +482,10 @@ vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
     if (!out) return fail(VC_E_ARG, "result_create: out is null");
     *out = nullptr;
     if (!c) return fail(VC_E_ARG, "result_create: container is null");
-    if (mask & ~(uint32_t)(VC_ALL | VC_PERIMETER)) return fail(VC_E_ARG, "result_create: unknown mask bits 0x%x", mask);
+    if (mask & ~(uint32_t)(VC_ALL | VC_PERIMETER | VC_WEINBERG))
+        return fail(VC_E_ARG, "result_create: unknown mask bits 0x%x", mask);
     if ((mask & VC_PERIMETER) && c->dim != 2) return fail(VC_E_ARG, "result_create: the perimeter is a 2D field");
+    if ((mask & VC_WEINBERG) && c->dim != 3) return fail(VC_E_ARG, "result_create: Weinberg codes are a 3D field");
     vc_result *r = new (std::nothrow) vc_result();
     if (!r) return fail(VC_E_NOMEM, "host allocation failed");
     r->c = c;
@@ -499,8 +517,16 @@ vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
         TRY(dalloc(&r->off, (size_t)n + 1));
         TRY(dalloc(&r->ids, (size_t)n * kMaxNbr));
         TRY(dalloc(&r->shifts, (size_t)n * kMaxNbr));
-        TRY(dalloc(&r->scan_tmp, (size_t)((n + 2047) / 2048 + 2) * 2));
     }
+    if (mask & VC_WEINBERG) {
+        TRY(dalloc(&r->wbg, (size_t)n * kWbStride));
+        TRY(dalloc(&r->wbl, n));
+        TRY(dalloc(&r->wb_off, (size_t)n + 1));
+        TRY(dalloc(&r->wb_codes, (size_t)n * kWbMaxD));
+        TRY(dalloc(&r->wb_sym, n));
+        TRY(dalloc(&r->wb_chiral, n));
+    }
+    if (mask & (VC_NEIGHBORS | VC_WEINBERG)) TRY(dalloc(&r->scan_tmp, (size_t)((n + 2047) / 2048 + 2) * 2));
     TRY(dalloc(&r->status, n));
     TRY(dalloc(&r->diag, VC_DIAG_LEN));
 #undef TRY
@@ -638,6 +664,7 @@ vc_status vc_compute_subset(vc_container *c, vc_result *r, const int64_t *ids, i
     // cells not listed: status VC_CELL_SKIPPED, no faces (empty neighbour lists)
     HIP_TRY(launch_fill_u8(r->status, r->n, VC_CELL_SKIPPED, s));
     if (r->nf) HIP_TRY(launch_fill_i32(r->nf, r->n, 0, s));
+    if (r->wbl) HIP_TRY(launch_fill_i32(r->wbl, r->n, 0, s));
     return enqueue_compute(c, r, s, true, c->launch, c->subset, (int)m, true);
 }
 
@@ -674,6 +701,16 @@ vc_status vc_result_get(vc_result *r, int field, void **dev_ptr, int64_t *count)
     case VC_F_STATUS: p = r->status; k = n; break;
     case VC_F_DIAG: p = r->diag; k = VC_DIAG_LEN; break;
     case VC_F_PERIMETER: p = r->perim; k = n; break;
+    case VC_F_WB_OFFSETS: p = r->wb_off; k = n + 1; break;
+    case VC_F_WB_CODES: {
+        if (!(r->mask & VC_WEINBERG)) return fail(VC_E_STATE, "Weinberg codes were not requested in the mask");
+        HIP_TRY(hipStreamSynchronize(r->last_stream));
+        HIP_TRY(hipMemcpy(&k, r->wb_off + n, sizeof(int64_t), hipMemcpyDeviceToHost));
+        p = r->wb_codes;
+        break;
+    }
+    case VC_F_WB_SYM: p = r->wb_sym; k = n; break;
+    case VC_F_WB_CHIRAL: p = r->wb_chiral; k = n; break;
     default: return fail(VC_E_ARG, "vc_result_get: unknown field %d", field);
     }
     if (!p) return fail(VC_E_STATE, "field %d was not requested in the statistics mask", field);
@@ -689,7 +726,7 @@ vc_status vc_result_copy(vc_result *r, int field, void *host_dst, int64_t bytes)
     int64_t k;
     vc_status st = vc_result_get(r, field, &p, &k);
     if (st) return st;
-    static const int esz[] = {8, 8, 4, 4, 4, 1, 8, 4, 1, 1, 8, 8};
+    static const int esz[] = {8, 8, 4, 4, 4, 1, 8, 4, 1, 1, 8, 8, 8, 1, 4, 1};
     int64_t need = k * esz[field];
     if (bytes < need) return fail(VC_E_ARG, "vc_result_copy: need %lld bytes, got %lld", (long long)need, (long long)bytes);
     HIP_TRY(hipStreamSynchronize(r->last_stream));

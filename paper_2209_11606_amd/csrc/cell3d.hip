@@ -745,6 +745,14 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     double vol6 = wave_sum(v6);
     double M0 = wave_sum(m0), M1 = wave_sum(m1), M2 = wave_sum(m2);
     __syncthreads();
+    if (A.wbg && !capfail) {
+        // the vertex positions are no longer needed: their LDS holds the
+        // record's scratch (zero-length edge bits, vertex numbers, degrees)
+        uint8_t *wsc = reinterpret_cast<uint8_t *>(&sh.u.st.pos[0][0]);
+        const int wl = wb_record<64, S, MAXP>(A.wbg + (int64_t)id * kWbStride, sumord, sh.u.st.tpl, sh.u.st.lab,
+                                              sh.etab, wsc, wsc + 64 * S, wsc + 128 * S, zb, lane, 0);
+        if (lane == 0) A.wbl[id] = wl;
+    }
     if (lane == 0) {
         double vol = vol6 / 6.0;
         if (A.vol) A.vol[id] = vol;
@@ -761,13 +769,18 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     return capfail ? ST_CAP : ST_OK;
 }
 
-template <int S, int MAXP, bool F32, int K, bool RAD>
+template <int S, int MAXP, bool F32, int K, bool RAD, bool WB>
 __global__ __launch_bounds__(64) void k_cells(CellArgs Ain, int spill_mode)
 {
-    // the Voronoi instantiation carries no radical code: its rad pointer is
-    // a compile-time null
+    // the Voronoi instantiation carries no radical code, and one without
+    // Weinberg records none of their code: those pointers are compile-time
+    // nulls
     CellArgs A = Ain;
     if (!RAD) A.rad = nullptr;
+    if (!WB) {
+        A.wbg = nullptr;
+        A.wbl = nullptr;
+    }
     __shared__ CellLDS<S, MAXP, K> sh;
     const int lane = __lane_id();
     double *ws = A.xscratch + (size_t)blockIdx.x * A.xscratch_len;
@@ -796,6 +809,7 @@ __global__ __launch_bounds__(64) void k_cells(CellArgs Ain, int spill_mode)
                     if (A.nv) A.nv[id] = 0;
                     if (A.ne) A.ne[id] = 0;
                     if (A.nf) A.nf[id] = 0;
+                    if (A.wbl) A.wbl[id] = 0;
                 }
                 if (st == ST_EMPTY) {
                     A.status[id] = (uint8_t)ST_EMPTY;
@@ -830,31 +844,43 @@ __global__ __launch_bounds__(64) void k_cells(CellArgs Ain, int spill_mode)
 
 hipError_t launch_cells(const CellArgs &a, int precision, int slots, int waves, hipStream_t s)
 {
-    const bool rad = a.rad != nullptr;
-    if (slots == 4) {
-        if (rad) {
-            if (precision == 1) k_cells<4, 48, true, 1, true><<<waves, 64, 0, s>>>(a, 0);
-            else k_cells<4, 48, false, 1, true><<<waves, 64, 0, s>>>(a, 0);
-        } else {
-            if (precision == 1) k_cells<4, 48, true, 1, false><<<waves, 64, 0, s>>>(a, 0);
-            else k_cells<4, 48, false, 1, false><<<waves, 64, 0, s>>>(a, 0);
-        }
-    } else {
-        if (rad) {
-            if (precision == 1) k_cells<2, 48, true, 1, true><<<waves, 64, 0, s>>>(a, 0);
-            else k_cells<2, 48, false, 1, true><<<waves, 64, 0, s>>>(a, 0);
-        } else {
-            if (precision == 1) k_cells<2, 48, true, 1, false><<<waves, 64, 0, s>>>(a, 0);
-            else k_cells<2, 48, false, 1, false><<<waves, 64, 0, s>>>(a, 0);
-        }
-    }
+    const bool rad = a.rad != nullptr, wb = a.wbg != nullptr, f32 = precision == 1;
+#define VC_CELLS(S)                                                                              \
+    do {                                                                                         \
+        if (rad) {                                                                               \
+            if (wb) {                                                                            \
+                if (f32) k_cells<S, 48, true, 1, true, true><<<waves, 64, 0, s>>>(a, 0);         \
+                else k_cells<S, 48, false, 1, true, true><<<waves, 64, 0, s>>>(a, 0);            \
+            } else {                                                                             \
+                if (f32) k_cells<S, 48, true, 1, true, false><<<waves, 64, 0, s>>>(a, 0);        \
+                else k_cells<S, 48, false, 1, true, false><<<waves, 64, 0, s>>>(a, 0);           \
+            }                                                                                    \
+        } else {                                                                                 \
+            if (wb) {                                                                            \
+                if (f32) k_cells<S, 48, true, 1, false, true><<<waves, 64, 0, s>>>(a, 0);        \
+                else k_cells<S, 48, false, 1, false, true><<<waves, 64, 0, s>>>(a, 0);           \
+            } else {                                                                             \
+                if (f32) k_cells<S, 48, true, 1, false, false><<<waves, 64, 0, s>>>(a, 0);       \
+                else k_cells<S, 48, false, 1, false, false><<<waves, 64, 0, s>>>(a, 0);          \
+            }                                                                                    \
+        }                                                                                        \
+    } while (0)
+    if (slots == 4) VC_CELLS(4);
+    else VC_CELLS(2);
+#undef VC_CELLS
     return hipGetLastError();
 }
 
 hipError_t launch_cells_spill(const CellArgs &a, int waves, hipStream_t s)
 {
-    if (a.rad) k_cells<4, 128, false, 1, true><<<waves, 64, 0, s>>>(a, 1);
-    else k_cells<4, 128, false, 1, false><<<waves, 64, 0, s>>>(a, 1);
+    const bool rad = a.rad != nullptr, wb = a.wbg != nullptr;
+    if (rad) {
+        if (wb) k_cells<4, 128, false, 1, true, true><<<waves, 64, 0, s>>>(a, 1);
+        else k_cells<4, 128, false, 1, true, false><<<waves, 64, 0, s>>>(a, 1);
+    } else {
+        if (wb) k_cells<4, 128, false, 1, false, true><<<waves, 64, 0, s>>>(a, 1);
+        else k_cells<4, 128, false, 1, false, false><<<waves, 64, 0, s>>>(a, 1);
+    }
     return hipGetLastError();
 }
 

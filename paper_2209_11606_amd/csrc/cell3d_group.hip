@@ -266,6 +266,7 @@ __device__ __forceinline__ void cell_fail(const CellArgs &A, SL<G, S, MAXP> &sh,
         if (A.nv) A.nv[id] = 0;
         if (A.ne) A.ne[id] = 0;
         if (A.nf) A.nf[id] = 0;
+        if (A.wbl) A.wbl[id] = 0;
         if (st == ST_DUP) {
             A.status[id] = 3;
         } else {
@@ -824,6 +825,7 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
             if (A.nv) A.nv[id] = 0;
             if (A.ne) A.ne[id] = 0;
             if (A.nf) A.nf[id] = 0;
+            if (A.wbl) A.wbl[id] = 0;
             A.status[id] = (uint8_t)ST_EMPTY;
         }
         if (A.fo)
@@ -986,7 +988,16 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
         cell_fail<G, S, MAXP, F32>(A, sh, c, ST_CAP, gl);
         return;
     }
+    int wl = 0;
+    if (A.wbg) {
+        // the vertex positions are no longer needed: their LDS holds the
+        // record's scratch (zero-length edge bits, vertex numbers, degrees)
+        uint8_t *wsc = reinterpret_cast<uint8_t *>(&sh.u.st.pos[0][0]);
+        wl = wb_record<G, S, MAXP>(A.wbg + (int64_t)id * kWbStride, sumord, sh.u.st.tpl, sh.u.st.lab, sh.etab, wsc,
+                                   wsc + G * S, wsc + 2 * G * S, zb, gl, gb);
+    }
     if (gl == 0) {
+        if (A.wbl) A.wbl[id] = wl;
         double vol = vol6 / 6.0;
         if (A.vol) A.vol[id] = vol;
         if (A.cen) {
@@ -1033,13 +1044,18 @@ struct SyncWaves {
     static constexpr int value = G == 32 ? VC_SYNC_WAVES : 2;
 };
 
-template <int G, int S, int MAXP, bool F32, bool RAD>
+template <int G, int S, int MAXP, bool F32, bool RAD, bool WB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>::value))) void k_cells_sync(CellArgs Ain)
 {
-    // the Voronoi instantiation carries no radical code: its rad pointer is
-    // a compile-time null
+    // the Voronoi instantiation carries no radical code, and one without
+    // Weinberg records none of their code: those pointers are compile-time
+    // nulls
     CellArgs A = Ain;
     if (!RAD) A.rad = nullptr;
+    if (!WB) {
+        A.wbg = nullptr;
+        A.wbl = nullptr;
+    }
     static_assert(((G * S) & (G * S - 1)) == 0 && G * S <= 256, "slot count must be a power of two");
     static_assert(G == 16 || G == 32, "group width");
     __shared__ SL<G, S, MAXP> shv[Gw<G>::CPW];
@@ -1079,26 +1095,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
 
 hipError_t launch_cells_group(const CellArgs &a, int precision, int cpw, int waves, hipStream_t s)
 {
-    const bool rad = a.rad != nullptr;
-    if (cpw == 4) {
-        if (rad) {
-            if (precision == 1) k_cells_sync<16, 4, 32, true, true><<<waves, 64, 0, s>>>(a);
-            else k_cells_sync<16, 4, 32, false, true><<<waves, 64, 0, s>>>(a);
-        } else {
-            if (precision == 1) k_cells_sync<16, 4, 32, true, false><<<waves, 64, 0, s>>>(a);
-            else k_cells_sync<16, 4, 32, false, false><<<waves, 64, 0, s>>>(a);
-        }
-    } else if (cpw == 2) {
-        if (rad) {
-            if (precision == 1) k_cells_sync<32, 2, 40, true, true><<<waves, 64, 0, s>>>(a);
-            else k_cells_sync<32, 2, 40, false, true><<<waves, 64, 0, s>>>(a);
-        } else {
-            if (precision == 1) k_cells_sync<32, 2, 40, true, false><<<waves, 64, 0, s>>>(a);
-            else k_cells_sync<32, 2, 40, false, false><<<waves, 64, 0, s>>>(a);
-        }
-    } else {
-        return hipErrorInvalidValue;
-    }
+    const bool rad = a.rad != nullptr, wb = a.wbg != nullptr, f32 = precision == 1;
+#define VC_GROUP(G, S, P)                                                                        \
+    do {                                                                                         \
+        if (rad) {                                                                               \
+            if (wb) {                                                                            \
+                if (f32) k_cells_sync<G, S, P, true, true, true><<<waves, 64, 0, s>>>(a);        \
+                else k_cells_sync<G, S, P, false, true, true><<<waves, 64, 0, s>>>(a);           \
+            } else {                                                                             \
+                if (f32) k_cells_sync<G, S, P, true, true, false><<<waves, 64, 0, s>>>(a);       \
+                else k_cells_sync<G, S, P, false, true, false><<<waves, 64, 0, s>>>(a);          \
+            }                                                                                    \
+        } else {                                                                                 \
+            if (wb) {                                                                            \
+                if (f32) k_cells_sync<G, S, P, true, false, true><<<waves, 64, 0, s>>>(a);       \
+                else k_cells_sync<G, S, P, false, false, true><<<waves, 64, 0, s>>>(a);          \
+            } else {                                                                             \
+                if (f32) k_cells_sync<G, S, P, true, false, false><<<waves, 64, 0, s>>>(a);      \
+                else k_cells_sync<G, S, P, false, false, false><<<waves, 64, 0, s>>>(a);         \
+            }                                                                                    \
+        }                                                                                        \
+    } while (0)
+    if (cpw == 4) VC_GROUP(16, 4, 32);
+    else if (cpw == 2) VC_GROUP(32, 2, 40);
+    else return hipErrorInvalidValue;
+#undef VC_GROUP
     return hipGetLastError();
 }
 

@@ -453,6 +453,171 @@ __device__ __forceinline__ double search_lim(double R2, double R, const CellArgs
 }
 
 enum { ST_OK = 0, ST_CAP = 1, ST_DUP = 3, ST_EMPTY = 5 };
+
+// ---------------------------------------------------------------------------
+// Edge-graph records for the Weinberg codes (the cell-topology code of
+// VoroTop; section 5).  A cell's vertex is a class of triangles joined by
+// zero-length edges; around it, its edges come in the order of the
+// triangles' planes (a, b, c), so every vertex sees its edges in one common
+// rotational sense.  The record lists the vertices in slot order of their
+// first triangle.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wb_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int GW>
+__device__ __forceinline__ unsigned long long grp_ballot(bool p, int gb)
+{
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(p);
+    return GW == 64 ? m : (m >> gb) & ((1ull << GW) - 1ull);
+}
+
+template <int GW>
+__device__ __forceinline__ int grp_isum(int v)
+{
+#pragma unroll
+    for (int m = 1; m < GW; m <<= 1) v += __shfl_xor(v, m, GW);
+    return v;
+}
+
+// slot of the triangle across edge k (planes k, k+1) of slot s
+template <int NT, int MAXP>
+__device__ __forceinline__ int wb_twin(const uint32_t *tpl, const uint8_t (*etab)[MAXP], int s, int k)
+{
+    const uint32_t t3 = tpl[s];
+    const int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * (k == 2 ? 0 : k + 1))) & 0xff;
+    return etab[b][a] & (NT - 1);
+}
+
+// Once around the vertex that slot r belongs to, starting at r's first
+// edge of positive length.  A zero-length edge is stepped through into the
+// next triangle of the same vertex, continuing after the shared edge.  The
+// positive edges give the neighbours w_0 .. w_{m-1} in rotation order (as
+// vertex numbers); a face that degenerated to a segment between two real
+// faces (a plane that only touches the cell along an edge) makes the same
+// neighbour appear twice in a row, so each run of equal neighbours counts
+// once: emit(j, w_i) for every i with w_i != w_{i+1} (cyclically).  An edge
+// back into the vertex itself is not an edge of the cell.  Returns the
+// degree, or -1 for an inconsistent graph (or no positive edge at r).
+template <int NT, int MAXP, class F>
+__device__ __forceinline__ int wb_walk(const uint32_t *tpl, const uint8_t (*etab)[MAXP], const uint8_t *zbt,
+                                       const uint8_t *vid, int r, F emit)
+{
+    int k0 = 0;
+    while (k0 < 3 && ((zbt[r] >> k0) & 1)) k0++;
+    if (k0 == 3) return -1;
+    const int self = vid[r];
+    int s = r, k = k0, n = 0, nraw = 0, first = -1, pend = -1;
+    do {
+        const int w = vid[wb_twin<NT, MAXP>(tpl, etab, s, k)];
+        if (w != self) {
+            if (nraw == 0) {
+                first = w;
+            } else if (w != pend) {
+                emit(n, pend);
+                n++;
+            }
+            pend = w;
+            if (++nraw > 255) return -1;
+        }
+        k = k == 2 ? 0 : k + 1;
+        int guard = 0;
+        while ((zbt[s] >> k) & 1) {
+            const int b = (tpl[s] >> (8 * (k == 2 ? 0 : k + 1))) & 0xff;
+            const int s2 = wb_twin<NT, MAXP>(tpl, etab, s, k);
+            const uint32_t u3 = tpl[s2];
+            int k2 = 0;
+            while (k2 < 3 && (int)((u3 >> (8 * k2)) & 0xff) != b) k2++;
+            if (k2 == 3 || ++guard > NT) return -1;
+            s = s2;
+            k = k2 == 2 ? 0 : k2 + 1;
+        }
+    } while (s != r || k != k0);
+    if (nraw > 0 && pend != first) {
+        emit(n, pend);
+        n++;
+    }
+    return n;
+}
+
+// Write the record of a finished cell: [V][D low][D high], the degree of
+// each vertex, each vertex's neighbours in rotation order.  GW lanes hold
+// the cell, slot t = s * GW + gl; bit 3s + k of zb: edge k of the lane's
+// slot s has zero length; lab[t]: first slot of t's vertex.  zbt, vid and
+// degs are LDS scratch of GW * S bytes.  Returns (in every lane) the code
+// length D = 2E, or 0 when the record does not fit or the graph is found
+// inconsistent: no code for the cell.
+template <int GW, int S, int MAXP>
+__device__ __noinline__ int wb_record(uint8_t *rec, int D, const uint32_t *tpl, const int32_t *lab, const uint8_t (*etab)[MAXP],
+                         uint8_t *zbt, uint8_t *vid, uint8_t *degs, uint32_t zb, int gl, int gb)
+{
+    constexpr int NT = GW * S;
+    int V = 0;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        const int t = s * GW + gl;
+        zbt[t] = (uint8_t)((zb >> (3 * s)) & 7);
+        const bool rep = tpl[t] != 0xffffffffu && lab[t] == t;
+        const unsigned long long m = grp_ballot<GW>(rep, gb);
+        if (rep) vid[t] = (uint8_t)min(V + __popcll(m & ((1ull << gl) - 1ull)), 255);
+        V += __popcll(m);
+    }
+    if (V > kWbMaxV || D > kWbMaxD || 3 + V + D > kWbStride) return 0;
+    wb_fence();
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        const int t = s * GW + gl;
+        if (tpl[t] != 0xffffffffu && lab[t] != t) vid[t] = vid[lab[t] & (NT - 1)];
+    }
+    wb_fence();
+    // a vertex's walk starts at its first triangle with a positive edge
+    int start[S];
+    int sum = 0;
+    bool bad = false;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        const int t = s * GW + gl;
+        start[s] = -1;
+        if (tpl[t] == 0xffffffffu || lab[t] != t) continue;
+        int r = t;
+        if (zbt[t] == 7)
+            for (int u = 0; u < NT; u++)
+                if (tpl[u] != 0xffffffffu && lab[u] == t && zbt[u] != 7) {
+                    r = u;
+                    break;
+                }
+        const int dg = wb_walk<NT, MAXP>(tpl, etab, zbt, vid, r, [](int, int) {});
+        if (dg < 3) {
+            bad = true;
+            continue;
+        }
+        start[s] = r;
+        degs[vid[t]] = (uint8_t)dg;
+        sum += dg;
+    }
+    sum = grp_isum<GW>(sum);
+    if (grp_ballot<GW>(bad, gb) || sum != D) return 0;
+    wb_fence();
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        if (start[s] < 0) continue;
+        const int v = vid[s * GW + gl];
+        int off = 0;
+        for (int u = 0; u < v; u++) off += degs[u];
+        rec[3 + v] = degs[v];
+        uint8_t *out = rec + 3 + V + off;
+        wb_walk<NT, MAXP>(tpl, etab, zbt, vid, start[s], [&](int j, int w) { out[j] = (uint8_t)w; });
+    }
+    if (gl == 0) {
+        rec[0] = (uint8_t)V;
+        rec[1] = (uint8_t)(D & 0xff);
+        rec[2] = (uint8_t)(D >> 8);
+    }
+    return D;
+}
 enum { DC_CAND, DC_TESTS, DC_CUTS, DC_NEWV, DC_EXACT, DC_RECHECK, DC_SPILL, DC_BLOCKS, DC_FALLBACK, DC_N };
 
 }  // namespace

@@ -11,6 +11,13 @@ constexpr int kFoLen = 32;      // face-order vector length
 constexpr int kMaxNbr = 64;     // neighbour slots per cell in the fixed-stride scratch
 constexpr int kOffRadius = 4;   // Chebyshev radius of the precomputed block-offset list
 constexpr int kNoShift = 62;    // image code of the zero shift: 25*2 + 5*2 + 2
+// Edge-graph record of one cell for the Weinberg codes: [V][D low][D high],
+// the degree of each vertex, then each vertex's neighbours in rotation
+// order (3 + V + D bytes, D = 2E).  A cell whose record does not fit has no
+// code.  Every vertex has degree >= 3, so V <= (kWbStride - 3) / 4.
+constexpr int kWbStride = 384;
+constexpr int kWbMaxD = kWbStride - 3;
+constexpr int kWbMaxV = (kWbStride - 3) / 4;
 
 // One particle in the block-sorted array (32 bytes: one aligned pair of
 // 16-byte loads per lane).
@@ -94,6 +101,8 @@ struct CellArgs {
     unsigned long long *diag;  // VC_DIAG_LEN counters
     double *xscratch;          // per-wave workspace of the exact predicate
     int xscratch_len;          // doubles per wave
+    uint8_t *wbg;              // Weinberg codes requested: edge-graph records, id * kWbStride
+    int32_t *wbl;              // code length 2E of each record, 0: no code
 };
 
 // Launchers (defined in the .hip translation unit).
@@ -114,6 +123,8 @@ hipError_t launch_cells_spill(const CellArgs &a, int waves, hipStream_t s);
 hipError_t launch_cells_group(const CellArgs &a, int precision, int cells_per_wave, int waves, hipStream_t s);
 hipError_t launch_cells2d(const CellArgs &a, int precision, int waves, hipStream_t s);
 hipError_t launch_cells2d_spill(const CellArgs &a, int waves, hipStream_t s);
+hipError_t launch_weinberg(const uint8_t *wbg, const int32_t *wbl, const int64_t *off, int64_t n, uint8_t *codes,
+                           int32_t *sym, uint8_t *chiral, int32_t *queue, int waves, hipStream_t s);
 hipError_t launch_nbr_compact(const int32_t *nf, int64_t n, const int32_t *nbr, const uint8_t *nsh,
                               int64_t *offsets, int32_t *ids, uint8_t *shifts, int32_t *tmp, hipStream_t s);
 hipError_t launch_nbr_offsets(const int32_t *nf, int64_t n, int64_t *offsets, int32_t *tmp, hipStream_t s);

@@ -19,14 +19,17 @@ VC_FP64, VC_F32_FILTER = 0, 1
 VC_VOLUME, VC_CENTROID, VC_COUNTS, VC_FACE_ORDERS, VC_NEIGHBORS, VC_NEIGHBOR_COUNT, VC_DIAG = 1, 2, 4, 8, 16, 32, 64
 VC_ALL = 127
 VC_PERIMETER = 128
+VC_WEINBERG = 256
 (VC_F_VOLUME, VC_F_CENTROID, VC_F_NV, VC_F_NE, VC_F_NF, VC_F_FACE_ORDERS, VC_F_NBR_OFFSETS, VC_F_NBR_IDS,
- VC_F_NBR_SHIFTS, VC_F_STATUS, VC_F_DIAG, VC_F_PERIMETER) = range(12)
+ VC_F_NBR_SHIFTS, VC_F_STATUS, VC_F_DIAG, VC_F_PERIMETER, VC_F_WB_OFFSETS, VC_F_WB_CODES, VC_F_WB_SYM,
+ VC_F_WB_CHIRAL) = range(16)
 VC_FO_LEN = 32
 VC_DIAG_LEN = 16
 DIAG_NAMES = ["candidates", "tests", "cuts", "new_vertices", "exact", "recheck", "spilled", "blocks", "fallback"]
 _FIELD_DTYPE = {VC_F_VOLUME: np.float64, VC_F_CENTROID: np.float64, VC_F_NV: np.int32, VC_F_NE: np.int32,
                 VC_F_NF: np.int32, VC_F_FACE_ORDERS: np.uint8, VC_F_NBR_OFFSETS: np.int64, VC_F_NBR_IDS: np.int32,
-                VC_F_NBR_SHIFTS: np.uint8, VC_F_STATUS: np.uint8, VC_F_DIAG: np.uint64, VC_F_PERIMETER: np.float64}
+                VC_F_NBR_SHIFTS: np.uint8, VC_F_STATUS: np.uint8, VC_F_DIAG: np.uint64, VC_F_PERIMETER: np.float64,
+                VC_F_WB_OFFSETS: np.int64, VC_F_WB_CODES: np.uint8, VC_F_WB_SYM: np.int32, VC_F_WB_CHIRAL: np.uint8}
 
 
 class vc_options(ctypes.Structure):
@@ -297,9 +300,20 @@ def fetch(r, mask, n, dim=3):
         ids = vc_result_copy(r, VC_F_NBR_IDS)
         sh = vc_result_copy(r, VC_F_NBR_SHIFTS)
         out["nbr_off"], out["nbr_ids"], out["nbr_sh"] = off, ids, sh
+    if mask & VC_WEINBERG:
+        out["wb_off"] = vc_result_copy(r, VC_F_WB_OFFSETS)
+        out["wb_codes"] = vc_result_copy(r, VC_F_WB_CODES)
+        out["wb_sym"] = vc_result_copy(r, VC_F_WB_SYM)
+        out["wb_chiral"] = vc_result_copy(r, VC_F_WB_CHIRAL)
     d = vc_result_copy(r, VC_F_DIAG)
     out["diag"] = dict(zip(DIAG_NAMES, d[:len(DIAG_NAMES)].tolist()))
     return out
+
+
+def weinberg_codes(res):
+    """Per-cell Weinberg codes (uint8 arrays) from the CSR fields of fetch()."""
+    off, codes = res["wb_off"], res["wb_codes"]
+    return [codes[off[i]:off[i + 1]] for i in range(len(off) - 1)]
 
 
 def neighbor_lists(res):

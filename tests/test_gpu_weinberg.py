@@ -1,0 +1,163 @@
+"""Weinberg codes (the cell-topology code of VoroTop, section 5) on the GPU,
+through the C ABI (VC_WEINBERG), against the oracle: every cell's code, its
+symmetry count and its chirality identical (integer results, bit-exact)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_11606_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def v():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_11606_amd import vorohip
+    return vorohip
+
+
+def run(v, x, lo, hi, per, radii=None, **opt):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+    out = v.tessellate(xt, lo, hi, per, v.VC_ALL | v.VC_WEINBERG, radii=radii, **opt)
+    out["codes"] = v.weinberg_codes(out)
+    return out
+
+
+def fits(nv, ne):
+    """The edge-graph record of a cell holds 3 + V + 2E <= 384 bytes."""
+    return 3 + nv + 2 * ne <= 384
+
+
+def assert_codes(g, r, idx=None, ne=None, nv=None):
+    idx = np.arange(len(g["codes"])) if idx is None else np.asarray(idx)
+    for t, i in enumerate(idx):
+        if nv is not None and not fits(nv[t], ne[t]):
+            assert g["wb_sym"][i] == 0 and len(g["codes"][i]) == 0, i
+            continue
+        assert np.array_equal(g["codes"][i], r["codes"][t]), (i, g["codes"][i][:20], r["codes"][t][:20])
+        assert g["wb_sym"][i] == r["sym"][t], (i, g["wb_sym"][i], r["sym"][t])
+        assert g["wb_chiral"][i] == r["chiral"][t], i
+
+
+@pytest.mark.parametrize("per", [[1, 1, 1], [0, 0, 0], [1, 0, 1]])
+def test_weinberg_all_forms(v, per):
+    """Every launch form and the FP32 filter on 4000 uniform points."""
+    x = W.uniform(4000, 3, 1.0, 91)
+    r = oracle.Oracle(x, [0] * 3, [1] * 3, per).weinberg(nthreads=8)
+    assert np.any(r["sym"] > 1) and np.any(r["chiral"] == 1)
+    for cpw in (1, 2, 4):
+        for prec in (v.VC_FP64, v.VC_F32_FILTER):
+            g = run(v, x, [0] * 3, [1] * 3, per, cells_per_wave=cpw, precision=prec)
+            assert np.array_equal(g["wb_off"][1:] - g["wb_off"][:-1], 2 * g["ne"])
+            assert_codes(g, r)
+
+
+@pytest.mark.parametrize("lat", ["sc", "bcc", "fcc"])
+def test_weinberg_lattices(v, lat):
+    """Cube, truncated octahedron and rhombic dodecahedron (four-valent
+    vertices made of two triangles joined by a zero-length edge): the
+    oracle's codes, 48 symmetries, not chiral."""
+    x, hi = {"sc": lambda: W.sc(5, 1.0), "bcc": lambda: W.bcc(4, 1.0), "fcc": lambda: W.fcc((4, 4, 4), 1.0)}[lat]()
+    r = oracle.Oracle(x, [0] * 3, hi, [1, 1, 1]).weinberg(np.arange(3))
+    for cpw in (1, 2):
+        g = run(v, x, [0] * 3, hi, [1, 1, 1], cells_per_wave=cpw)
+        assert np.all(g["wb_sym"] == 48) and np.all(g["wb_chiral"] == 0)
+        assert all(np.array_equal(c, r["codes"][0]) for c in g["codes"])
+
+
+def test_weinberg_perturbed_fcc(v):
+    """Perturbed FCC (sigma = 1e-3 a: cells near the degenerate rhombic
+    dodecahedron, many exact decisions)."""
+    x, hi = W.fcc((6, 6, 6), 1.0, sigma=1e-3, seed=92)
+    r = oracle.Oracle(x, [0] * 3, hi, [1, 1, 1]).weinberg(nthreads=8)
+    for cpw in (1, 2):
+        assert_codes(run(v, x, [0] * 3, hi, [1, 1, 1], cells_per_wave=cpw), r)
+
+
+def test_weinberg_clipped(v):
+    """Clipped cells (section 3.1.3): faces of the clip cube."""
+    x = W.uniform(3000, 3, 1.0, 93)
+    h = 1.9 * 3000 ** (-1.0 / 3.0)
+    r = oracle.Oracle(x, [0] * 3, [1] * 3, [0, 0, 0], clip=h).weinberg(nthreads=8)
+    assert_codes(run(v, x, [0] * 3, [1] * 3, [0, 0, 0], clip=h, cells_per_wave=2), r)
+
+
+def test_weinberg_radical(v):
+    """Radical cells, some empty (no code, length 0)."""
+    w = W.polydisperse(3000, 3, seed=94, rmax_frac=1.0)
+    r = oracle.Oracle(w["xyz"], w["lo"], w["hi"], w["periodic"], radii=w["radii"]).weinberg(nthreads=8)
+    assert np.any(r["len"] == 0)
+    for cpw in (1, 2):
+        g = run(v, w["xyz"], w["lo"], w["hi"], w["periodic"], radii=w["radii"], cells_per_wave=cpw)
+        assert np.array_equal(g["wb_sym"] == 0, r["len"] == 0)
+        assert_codes(g, r)
+
+
+def test_weinberg_large_cells(v):
+    """The extreme-clustering set: cells far from the cluster have many
+    faces; those whose record exceeds 384 bytes get no code (symmetry 0),
+    every other cell equals the oracle."""
+    w = W.clustered(20_000)
+    g = run(v, w["xyz"], w["lo"], w["hi"], w["periodic"], grid=w["grid"])
+    idx = np.arange(0, 20_000, 7)
+    o = oracle.Oracle(w["xyz"], w["lo"], w["hi"], w["periodic"], grid=w["grid"])
+    r = o.weinberg(idx, nthreads=8)
+    c = o.cells(idx, nthreads=8, neighbors=False)
+    assert_codes(g, r, idx, ne=c["ne"], nv=c["nv"])
+
+
+def test_weinberg_subset_and_batch(v):
+    """vc_compute_subset: the listed cells' codes equal the full run's, the
+    others have none.  A batch, replayed from a hipGraph: each member's
+    codes equal its oracle's."""
+    x = W.uniform(3000, 3, 1.0, 95)
+    xt = torch.from_numpy(x).to("cuda:0")
+    full = run(v, x, [0] * 3, [1] * 3, [1, 1, 1])
+    ids = np.sort(W.rng(96).choice(3000, 500, replace=False)).astype(np.int64)
+    o = v.vc_options_init(3, [0] * 3, [1] * 3, [1, 1, 1])
+    c = v.vc_container_create(xt, o)
+    try:
+        rr = v.vc_result_create(c, v.VC_ALL | v.VC_WEINBERG)
+        try:
+            v.vc_compute_subset(c, rr, ids)
+            g = v.fetch(rr, v.VC_ALL | v.VC_WEINBERG, 3000, 3)
+        finally:
+            v.vc_result_destroy(rr)
+    finally:
+        v.vc_container_destroy(c)
+    codes = v.weinberg_codes(g)
+    listed = np.zeros(3000, bool)
+    listed[ids] = True
+    for i in range(3000):
+        if listed[i]:
+            assert np.array_equal(codes[i], full["codes"][i]) and g["wb_sym"][i] == full["wb_sym"][i]
+        else:
+            assert len(codes[i]) == 0 and g["wb_sym"][i] == 0
+    members = [W.batch_member(t, n) for t, n in enumerate([400, 1500, 700, 2500])]
+    xyz = np.concatenate([m["xyz"] for m in members])
+    offs = np.cumsum([0] + [len(m["xyz"]) for m in members]).astype(np.int64)
+    opts = [v.vc_options_init(3, m["lo"], m["hi"], m["periodic"]) for m in members]
+    st = torch.cuda.Stream()
+    xb = torch.from_numpy(xyz).to("cuda:0")
+    torch.cuda.synchronize()
+    b = v.vc_batch_create(xb, offs, opts, st)
+    try:
+        rb = v.vc_batch_result_create(b, v.VC_ALL | v.VC_WEINBERG)
+        try:
+            v.vc_batch_compute(b, rb, True, st)
+            v.vc_batch_compute(b, rb, True, st)
+            st.synchronize()
+            gb = v.fetch(rb, v.VC_ALL | v.VC_WEINBERG, len(xyz), 3)
+        finally:
+            v.vc_result_destroy(rb)
+    finally:
+        v.vc_batch_destroy(b)
+    bc = v.weinberg_codes(gb)
+    for t, m in enumerate(members):
+        r = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"]).weinberg(nthreads=8)
+        for k in range(len(m["xyz"])):
+            i = offs[t] + k
+            assert np.array_equal(bc[i], r["codes"][k]) and gb["wb_sym"][i] == r["sym"][k], (t, k)
