@@ -192,7 +192,8 @@ struct vc_container {
     double *rmax = nullptr;
     Offset *offs = nullptr;
     int noff = 0;
-    int32_t *queue = nullptr;    // [0]: main queue head, [1]: spill queue head, [2]: spill count
+    int32_t *queue = nullptr;    // [0]: main queue head, [1]: spill queue head, [2]: spill count,
+                                 // [3..5]: the Weinberg code kernels' heads and list count
     int32_t *spill_list = nullptr;
     int32_t *sample_list = nullptr;  // tuning sample (batches)
     int nsample = 0;
@@ -376,7 +377,7 @@ vc_status create_common(vc_container *c, const double *xyz, const int64_t *offse
     TRY(dalloc(&c->err, 1));
     TRY(dalloc(&c->scan_tmp, (size_t)ntiles * 2));
     TRY(dalloc(&c->offs, offs.size()));
-    TRY(dalloc(&c->queue, 4));
+    TRY(dalloc(&c->queue, 8));
     TRY(dalloc(&c->spill_list, (size_t)c->n));
     TRY(dalloc(&c->xscratch, (size_t)c->max_waves * c->xscratch_len));
 #undef TRY
@@ -444,7 +445,7 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
         A.cell_list = cell_list;
         A.ncell = ncell;
     }
-    HIP_TRY(launch_fill_i32(c->queue, 4, 0, s));
+    HIP_TRY(launch_fill_i32(c->queue, 8, 0, s));
     HIP_TRY(launch_fill_i32((int32_t *)r->diag, VC_DIAG_LEN * 2, 0, s));
     if (events) HIP_TRY(hipEventRecord(r->ev0, s));
     if (c->dim == 2) HIP_TRY(launch_cells2d(A, c->precision, std::min(L.waves, c->max_waves), s));
@@ -464,8 +465,9 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
     if (r->mask & VC_WEINBERG) {
         // codes of every cell with a record, written at the scan of their lengths
         HIP_TRY(launch_nbr_offsets(r->wbl, r->n, r->wb_off, r->scan_tmp, s));
+        // (the spill list is free again: its pass has run)
         HIP_TRY(launch_weinberg(r->wbg, r->wbl, r->wb_off, r->n, r->wb_codes, r->wb_sym, r->wb_chiral, c->queue + 3,
-                                (int)std::min<int64_t>(c->max_waves, r->n), s));
+                                c->spill_list, (int)std::min<int64_t>(c->max_waves, r->n), s));
     }
     if ((r->mask & VC_NEIGHBORS) && (!cell_list || compact_subset)) {
         // CSR offsets by a scan of the face counts, then each cell's sorted

@@ -123,8 +123,10 @@ hipError_t launch_cells_spill(const CellArgs &a, int waves, hipStream_t s);
 hipError_t launch_cells_group(const CellArgs &a, int precision, int cells_per_wave, int waves, hipStream_t s);
 hipError_t launch_cells2d(const CellArgs &a, int precision, int waves, hipStream_t s);
 hipError_t launch_cells2d_spill(const CellArgs &a, int waves, hipStream_t s);
+// queue: three zeroed counters; big: n ints of scratch (cells for the
+// general kernel)
 hipError_t launch_weinberg(const uint8_t *wbg, const int32_t *wbl, const int64_t *off, int64_t n, uint8_t *codes,
-                           int32_t *sym, uint8_t *chiral, int32_t *queue, int waves, hipStream_t s);
+                           int32_t *sym, uint8_t *chiral, int32_t *queue, int32_t *big, int waves, hipStream_t s);
 hipError_t launch_nbr_compact(const int32_t *nf, int64_t n, const int32_t *nbr, const uint8_t *nsh,
                               int64_t *offsets, int32_t *ids, uint8_t *shifts, int32_t *tmp, hipStream_t s);
 hipError_t launch_nbr_offsets(const int32_t *nf, int64_t n, int64_t *offsets, int32_t *tmp, hipStream_t s);

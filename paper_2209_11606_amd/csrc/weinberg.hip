@@ -18,6 +18,12 @@
 // prefix, the smallest next number is kept and every lane with a larger one
 // drops out; a round whose prefix exceeds the best code so far stops.  The
 // first round runs all 2E steps; later rounds usually stop within a few.
+//
+// Two kernels: k_weinberg_small takes the cells of up to 64 vertices and 192
+// darts (all but a few in practice) with each lane's walk state in
+// registers (vertices seen: a 64-bit mask; darts taken: three) and every
+// turn a table lookup, so a step costs one or two LDS round trips; the
+// general kernel takes the rest.
 #include "cell_common.h"
 
 namespace vc {
@@ -60,27 +66,270 @@ __device__ __forceinline__ bool wb_used(const WbLDS &sh, int d, int lane)
     return (sh.used[d >> 5][lane] >> (d & 31)) & 1u;
 }
 
+constexpr int kSmV = 64, kSmD = 192;  // the small-cell kernel's limits
+
+struct WbSmall {
+    uint8_t head[kSmD];      // vertex each dart enters
+    uint8_t tailv[kSmD];     // vertex each dart leaves
+    uint8_t rev[kSmD];       // the opposite dart
+    uint8_t rot[2][kSmD];    // next dart leaving the same vertex, in sense 0 / 1
+    uint8_t turn[2][kSmD];   // rot(rev(d)): the way on after arriving by d
+    uint8_t deg[kSmV];
+    uint8_t base[kSmV + 1];  // first dart of each vertex
+    uint8_t best[kSmD];      // smallest code so far
+    uint8_t cur[kSmD];       // the current round's code
+    uint16_t cand[2 * kSmD]; // candidate starts: 2 x dart + sense
+    uint8_t lbl[kSmV][64];   // per lane: each vertex's number, written on its first visit
+};
+
+// OR of a small value over the wave
+__device__ __forceinline__ int grp_or64(int v)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v |= __shfl_xor(v, m);
+    return v;
+}
+
+__device__ __forceinline__ bool bit3(uint64_t u0, uint64_t u1, uint64_t u2, int d)
+{
+    const uint64_t w = d < 64 ? u0 : (d < 128 ? u1 : u2);
+    return (w >> (d & 63)) & 1ull;
+}
+
+__device__ __forceinline__ void set3(uint64_t &u0, uint64_t &u1, uint64_t &u2, int d)
+{
+    const uint64_t b = 1ull << (d & 63);
+    u0 |= d < 64 ? b : 0ull;
+    u1 |= (d >= 64 && d < 128) ? b : 0ull;
+    u2 |= d >= 128 ? b : 0ull;
+}
+
+constexpr int kWbChunk = 8;  // cells per work-queue grab of the small kernel
+
+// The cells whose record has at most kSmV vertices and kSmD darts (and the
+// cells without a record: symmetry 0).  The others are listed in big (their
+// count in queue[2]) for the general kernel.
+__global__ __launch_bounds__(64) void k_weinberg_small(const uint8_t *__restrict__ wbg,
+                                                       const int32_t *__restrict__ wbl,
+                                                       const int64_t *__restrict__ off, int64_t n,
+                                                       uint8_t *__restrict__ codes, int32_t *__restrict__ sym,
+                                                       uint8_t *__restrict__ chiral, int32_t *__restrict__ queue,
+                                                       int32_t *__restrict__ big)
+{
+    __shared__ WbSmall sh;
+    const int lane = __lane_id();
+    for (;;) {
+        int first = 0;
+        if (lane == 0) first = atomicAdd(queue, kWbChunk);
+        first = __builtin_amdgcn_readfirstlane(first);
+        if (first >= n) break;
+        const int last = (int)min((int64_t)first + kWbChunk, n);
+        for (int cell = first; cell < last; cell++) {
+            const int64_t id = cell;
+            const uint8_t *rec = wbg + id * kWbStride;
+            const int D = __builtin_amdgcn_readfirstlane(wbl[id]);
+            const int V = D > 0 ? __builtin_amdgcn_readfirstlane((int)rec[0]) : 0;
+            const int Drec = D > 0 ? __builtin_amdgcn_readfirstlane((int)(rec[1] | (rec[2] << 8))) : 0;
+            const bool mine = D <= 0 || (V <= kSmV && D <= kSmD);
+            bool ok = mine && D > 0 && V >= 4 && Drec == D;
+            int count = 0, senses = 0;
+            if (ok) {
+                // degrees, first darts (a wave scan), dart ends, opposites, turns
+                const int dg = lane < V ? rec[3 + lane] : 0;
+                int inc = dg;
+    #pragma unroll
+                for (int m = 1; m < 64; m <<= 1) {
+                    const int y = __shfl_up(inc, m);
+                    if (lane >= m) inc += y;
+                }
+                const int b0 = inc - dg;
+                if (lane < V) {
+                    sh.deg[lane] = (uint8_t)dg;
+                    sh.base[lane] = (uint8_t)min(b0, 255);
+                    for (int j = 0; j < dg && b0 + j < kSmD; j++) sh.tailv[b0 + j] = (uint8_t)lane;
+                }
+                const int total = __builtin_amdgcn_readlane(inc, 63);
+                ok = total == D;
+                for (int d = lane; d < D; d += 64) sh.head[d] = rec[3 + V + d];
+                wb_fence();
+                bool bad = false;
+                if (ok) {
+                    for (int d = lane; d < D; d += 64) {
+                        const int v = sh.tailv[d], w = sh.head[d];
+                        int r = -1;
+                        if (w < V)
+                            for (int e = sh.base[w]; e < sh.base[w] + sh.deg[w]; e++)
+                                if (sh.head[e] == v) r = e;
+                        bad |= r < 0;
+                        sh.rev[d] = (uint8_t)max(r, 0);
+                        const int b = sh.base[v], nv = sh.deg[v];
+                        sh.rot[0][d] = (uint8_t)(d + 1 == b + nv ? b : d + 1);
+                        sh.rot[1][d] = (uint8_t)(d == b ? b + nv - 1 : d - 1);
+                    }
+                    wb_fence();
+                    for (int d = lane; d < D; d += 64) {
+                        const int r = sh.rev[d];
+                        sh.turn[0][d] = sh.rot[0][r];
+                        sh.turn[1][d] = sh.rot[1][r];
+                    }
+                    wb_fence();
+                }
+                ok = ok && __builtin_amdgcn_ballot_w64(bad) == 0;
+            }
+            int nc = 0;
+            if (ok) {
+                // A walk's code starts 1, 2, ..., p, 1 where p is the size of the
+                // face on its turning side (it turns that way at every new
+                // vertex until it closes that face), so only the starts on a
+                // smallest face can give the smallest code: the candidates.
+                int fs[2 * ((kSmD + 63) / 64)];
+                int pmin = 0x7fffffff;
+    #pragma unroll
+                for (int j = 0; j < (kSmD + 63) / 64; j++) {
+                    const int d = lane + 64 * j;
+    #pragma unroll
+                    for (int o = 0; o < 2; o++) {
+                        int len = 0x7fffffff;
+                        if (d < D) {
+                            int e = d;
+                            len = 0;
+                            do {
+                                e = sh.turn[o][e];
+                                len++;
+                            } while (e != d && len < 64);
+                        }
+                        fs[2 * j + o] = len;
+                        pmin = min(pmin, len);
+                    }
+                }
+                pmin = wave_imin(pmin);
+    #pragma unroll
+                for (int j = 0; j < (kSmD + 63) / 64; j++)
+    #pragma unroll
+                    for (int o = 0; o < 2; o++) {
+                        const bool is = fs[2 * j + o] == pmin;
+                        const unsigned long long b = __builtin_amdgcn_ballot_w64(is);
+                        if (is) sh.cand[nc + lane_rank(b)] = (uint16_t)(2 * (lane + 64 * j) + o);
+                        nc += __popcll(b);
+                    }
+                wb_fence();
+            }
+            if (ok) {
+                // the candidate walks, 64 per round, one per lane
+                bool have = false;
+                for (int c0 = 0; c0 < nc; c0 += 64) {
+                    bool alive = c0 + lane < nc;
+                    const int cd = alive ? sh.cand[c0 + lane] : 0;
+                    const int o = cd & 1;
+                    int dcur = cd >> 1;
+                    uint64_t vis = 0, u0 = 0, u1 = 0, u2 = 0;
+                    int nl = 1, lab = 1;
+                    if (alive) {
+                        const int t = sh.tailv[dcur];
+                        vis = 1ull << t;
+                        sh.lbl[t][lane] = 1;
+                    }
+                    bool eq = have, better = !have, done = false;
+                    for (int k = 0; k < D; k++) {
+                        const int m = wave_imin(alive ? lab : 0x7fffffff);
+                        if (m == 0x7fffffff) break;
+                        if (eq) {
+                            const int bk = __builtin_amdgcn_readfirstlane((int)sh.best[k]);
+                            if (m > bk) break;
+                            if (m < bk) {
+                                eq = false;
+                                better = true;
+                            }
+                        }
+                        alive = alive && lab == m;
+                        if (lane == 0) sh.cur[k] = (uint8_t)m;
+                        if (k == D - 1) {
+                            done = true;
+                            break;
+                        }
+                        if (alive) {
+                            set3(u0, u1, u2, dcur);
+                            const int v = sh.head[dcur];
+                            if (!((vis >> v) & 1ull)) {
+                                vis |= 1ull << v;
+                                lab = ++nl;
+                                sh.lbl[v][lane] = (uint8_t)nl;
+                                dcur = sh.turn[o][dcur];
+                            } else {
+                                lab = sh.lbl[v][lane];
+                                const int r = sh.rev[dcur];
+                                if (!bit3(u0, u1, u2, r)) {
+                                    dcur = r;
+                                } else {
+                                    int e = sh.turn[o][dcur];
+                                    for (int g = 0; g < 64 && bit3(u0, u1, u2, e); g++) e = sh.rot[o][e];
+                                    dcur = e;
+                                }
+                            }
+                        }
+                    }
+                    wb_fence();
+                    if (done) {
+                        const unsigned long long am = __builtin_amdgcn_ballot_w64(alive);
+                        int sm = 0;
+                        if (alive) sm = 1 << o;
+                        sm = grp_or64(sm);
+                        if (better) {
+                            for (int k = lane; k < D; k += 64) sh.best[k] = sh.cur[k];
+                            count = __popcll(am);
+                            senses = sm;
+                            have = true;
+                        } else if (eq) {
+                            count += __popcll(am);
+                            senses |= sm;
+                        }
+                    }
+                    wb_fence();
+                }
+                uint8_t *out = codes + off[id];
+                for (int k = lane; k < D; k += 64) out[k] = sh.best[k];
+            } else if (mine && D > 0 && D <= kWbMaxD) {
+                uint8_t *out = codes + off[id];
+                for (int k = lane; k < D; k += 64) out[k] = 0;
+            }
+            if (lane == 0) {
+                if (mine) {
+                    sym[id] = ok ? count : 0;
+                    chiral[id] = ok && senses != 3;
+                } else {
+                    // beyond this kernel's limits: listed for the general kernel
+                    big[atomicAdd(queue + 2, 1)] = cell;
+                }
+            }
+            wb_fence();
+        }
+    }
+}
+
+// The cells listed by the small kernel (their count in queue[2]).
 __global__ __launch_bounds__(64) void k_weinberg(const uint8_t *__restrict__ wbg, const int32_t *__restrict__ wbl,
-                                                 const int64_t *__restrict__ off, int64_t n,
+                                                 const int64_t *__restrict__ off, const int32_t *__restrict__ big,
                                                  uint8_t *__restrict__ codes, int32_t *__restrict__ sym,
                                                  uint8_t *__restrict__ chiral, int32_t *__restrict__ queue)
 {
     __shared__ WbLDS sh;
     const int lane = __lane_id();
+    const int nbig = __builtin_amdgcn_readfirstlane(queue[2]);
     // Every branch below is taken by the whole wave (its condition is made
     // wave-uniform), and the loop body has no early exit: the next cell is
     // claimed only once the wave has reconverged.
     for (;;) {
-        int cell = 0;
-        if (lane == 0) cell = atomicAdd(queue, 1);
-        cell = __builtin_amdgcn_readfirstlane(cell);
-        if (cell >= n) break;
-        const int64_t id = cell;
+        int item = 0;
+        if (lane == 0) item = atomicAdd(queue + 1, 1);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= nbig) break;
+        const int64_t id = __builtin_amdgcn_readfirstlane(big[item]);
         const uint8_t *rec = wbg + id * kWbStride;
         const int D = __builtin_amdgcn_readfirstlane(wbl[id]);
         const int V = D > 0 ? __builtin_amdgcn_readfirstlane((int)rec[0]) : 0;
         const int Drec = D > 0 ? __builtin_amdgcn_readfirstlane((int)(rec[1] | (rec[2] << 8))) : 0;
-        bool ok = D > 0 && D <= kWbMaxD && V >= 4 && V <= kWbMaxV && Drec == D;
+        const bool mine = D > 0;
+        bool ok = mine && D <= kWbMaxD && V >= 4 && V <= kWbMaxV && Drec == D;
         int count = 0, senses = 0;
         if (ok) {
             // vertex degrees, first darts (a wave scan), dart ends and opposites
@@ -193,12 +442,12 @@ __global__ __launch_bounds__(64) void k_weinberg(const uint8_t *__restrict__ wbg
             }
             uint8_t *out = codes + off[id];
             for (int k = lane; k < D; k += 64) out[k] = sh.best[k];
-        } else if (D > 0 && D <= kWbMaxD) {
+        } else if (mine && D <= kWbMaxD) {
             // an inconsistent record: its slot of the codes is zeroed
             uint8_t *out = codes + off[id];
             for (int k = lane; k < D; k += 64) out[k] = 0;
         }
-        if (lane == 0) {
+        if (mine && lane == 0) {
             sym[id] = ok ? count : 0;
             chiral[id] = ok && senses != 3;
         }
@@ -209,9 +458,12 @@ __global__ __launch_bounds__(64) void k_weinberg(const uint8_t *__restrict__ wbg
 }  // namespace
 
 hipError_t launch_weinberg(const uint8_t *wbg, const int32_t *wbl, const int64_t *off, int64_t n, uint8_t *codes,
-                           int32_t *sym, uint8_t *chiral, int32_t *queue, int waves, hipStream_t s)
+                           int32_t *sym, uint8_t *chiral, int32_t *queue, int32_t *big, int waves, hipStream_t s)
 {
-    if (n > 0) k_weinberg<<<waves, 64, 0, s>>>(wbg, wbl, off, n, codes, sym, chiral, queue);
+    if (n > 0) {
+        k_weinberg_small<<<waves, 64, 0, s>>>(wbg, wbl, off, n, codes, sym, chiral, queue, big);
+        k_weinberg<<<std::max(1, waves / 16), 64, 0, s>>>(wbg, wbl, off, big, codes, sym, chiral, queue);
+    }
     return hipGetLastError();
 }
 
