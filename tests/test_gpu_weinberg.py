@@ -161,3 +161,24 @@ def test_weinberg_subset_and_batch(v):
         for k in range(len(m["xyz"])):
             i = offs[t] + k
             assert np.array_equal(bc[i], r["codes"][k]) and gb["wb_sym"][i] == r["sym"][k], (t, k)
+
+
+@pytest.mark.parametrize("shell", [40, 60])
+def test_weinberg_many_faces(v, shell):
+    """A particle inside a shell of `shell` neighbours: its cell has about
+    `shell` faces.  At 40 (76 vertices, 228 darts) the code comes from the
+    general kernel; at 60 the record exceeds 384 bytes and the cell has no
+    code.  Every other cell equals the oracle."""
+    rng = W.rng(97 + shell)
+    u = rng.normal(size=(shell, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    bg = rng.random((3000, 3))
+    bg = bg[np.linalg.norm(bg - 0.5, axis=1) > 0.25]
+    x = np.concatenate([[[0.5, 0.5, 0.5]], 0.5 + 0.1 * u, bg])
+    g = run(v, x, [0] * 3, [1] * 3, [0, 0, 0], cells_per_wave=2)
+    o = oracle.Oracle(x, [0] * 3, [1] * 3, [0, 0, 0])
+    r = o.weinberg(nthreads=8)
+    c = o.cells(nthreads=8, neighbors=False)
+    assert c["nf"][0] >= shell - 2 and c["nv"][0] > 64
+    assert fits(c["nv"][0], c["ne"][0]) == (shell == 40)
+    assert_codes(g, r, np.arange(len(x)), ne=c["ne"], nv=c["nv"])
