@@ -148,7 +148,7 @@ def polydisperse(n=1_000_000, dim=3, seed=8, rmax_frac=0.6, periodic=True):
     return dict(name=f"polydisperse_{dim}d_{n}", xyz=x, radii=rad, lo=[0.0] * dim, hi=[1.0] * dim, periodic=per)
 
 
-def vorotop(n=1_000_000, seed=9):
+def vorotop(n=1_000_000, seed=10):
     """The VoroTop systems of section 5: n uniform points in the periodic unit
     cube, every cell with its Weinberg code."""
     return dict(name=f"vorotop_{n}", xyz=uniform(n, 3, 1.0, seed), lo=[0.0] * 3, hi=[1.0] * 3, periodic=[1, 1, 1],
