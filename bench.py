@@ -52,7 +52,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--cpu-sample", type=int, default=200_000, help="oracle cells timed on the host")
+    p.add_argument("--cpu-sample", type=int, default=500_000,
+                   help="oracle cells timed on the host (about 20 s of core time for the 1M set)")
     p.add_argument("--cpu-serial-sample", type=int, default=100_000, help="oracle cells timed on one thread")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--calibration-copy-mib", type=int, default=0,
