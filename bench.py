@@ -16,6 +16,9 @@ cell kernel): its algorithmic FP64 flops per launch -- the oracle's operation
 counts on a sample of the same workload, weighted (candidate distance 9,
 vertex side test 6, new vertex 12, fan tetrahedron 28), scaled to the cells of
 one launch -- over its HIP-event duration, against the FP64 vector peak.
+Each entry of `variants` carries the same fraction for its own cell
+kernel (roofline_frac), so the plain FP64 and the FP32-filter forms are
+both placed against the peak.
 The cpu_baseline object times the oracle on the host cores on a bounded
 sample of the same workload; cpu_serial times it on one thread.
 binning_roofline is the rebin alone (HIP events) against the HBM peak, with
@@ -436,6 +439,8 @@ def main():
         "variants": {k: dict(cells_per_s=n / (r["ms_per_step"] / 1e3), ms_per_step=r["ms_per_step"],
                              cell_kernel_ms=r["kernel_ms"], all_cells_ok=r["status_ok"],
                              empty_cells=r["empty_cells"], tuned=r.get("tuned"),
+                             roofline_frac=(None if flops_per_cell is None else
+                                            n * flops_per_cell / (r["kernel_ms"] / 1e3) / FP64_VECTOR_PEAK),
                              diag=r["diag"])
                      for k, r in res.items()},
         "roofline": roof,
