@@ -119,8 +119,10 @@ enum {
     VC_D_EXACT = 4,       /* side decisions taken exactly */
     VC_D_RECHECK = 5,     /* FP32 tests re-done in FP64 (VC_F32_FILTER) */
     VC_D_SPILLED = 6,     /* cells re-run in the large-capacity kernel */
-    VC_D_BLOCKS = 7,      /* blocks visited */
-    VC_D_FALLBACK = 8     /* cells that searched beyond the precomputed offsets */
+    VC_D_BLOCKS = 7,      /* blocks whose particles were loaded */
+    VC_D_FALLBACK = 8,    /* cells that searched beyond the precomputed offsets */
+    VC_D_SHELLS = 9       /* Chebyshev shells of blocks searched beyond them
+                             (section 2.1.3: the block bound ends the search) */
 };
 
 typedef struct {

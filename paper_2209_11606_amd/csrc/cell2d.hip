@@ -106,7 +106,7 @@ struct L2 {
     uint8_t lwall[MAXL];
     uint8_t byin[MAXL];   // slot of the vertex whose entering edge lies on line l
     uint8_t byout[MAXL];  // slot of the vertex whose leaving edge lies on line l
-    union {
+    union alignas(16) {
         struct {
             double pos[G * S][2];
             uint32_t tpl[G * S];
@@ -518,8 +518,15 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
         int st = p_gather<G, S, MAXL, F32>(A, sh, c, T, si, p, bc, of.dx, of.dy, v, ws, cnt, lane, gl, gb);
         if (st != ST_OK) return st;
     }
+    // beyond the list: whole Chebyshev rings, until the radius bound holds or
+    // no block of a ring meets the bounding box of the discs of the block
+    // bound (section 2.1.3)
     if (!finished) {
         cnt[DC_FALLBACK]++;
+        static_assert(sizeof(sh.u) >= sizeof(float4) * G * S, "ball list does not fit");
+        float4 *bbl = reinterpret_cast<float4 *>(&sh.u);
+        const double extra = A.rad ? fmax(*A.rmax * *A.rmax - c.ri * c.ri, 0.0) : 0.0;
+        const double pad = bb_pad(Gr, p, 2);
         for (int r = A.off_radius + 1;; r++) {
             if (r > kMaxShell || !(c.R2 < 1e300)) return ST_CAP;
             double lb = 1e300;
@@ -531,16 +538,49 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
             }
             if (!exists) break;
             if (lb > 0.0 && lb * lb >= c.lim) break;
+            cnt[DC_SHELLS]++;
             int side = 2 * r + 1;
             int tot = side * side;
+            bool met = false;
             for (int c0 = 0; c0 < tot; c0 += G) {
                 int ix = c0 + gl;
                 int dx = ix % side - r, dy = ix / side - r;
                 bool v = ix < tot && max(abs(dx), abs(dy)) == r;
                 if (!gb2<G>(v, gb)) continue;
+                // the bounding box of the discs, then the discs for the
+                // non-empty blocks
+                double ext[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < S; s++)
+                    if ((c.live[s] >> gl) & 1) bb_ext_add(ext, c.vx[s], c.vy[s], 0.0, extra);
+#pragma unroll
+                for (int k = 0; k < 6; k++) ext[k] = g2max<G>(ext[k]);
+                const int t[3] = {bc[0] + dx, bc[1] + dy, 0};
+                double blo[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int d = 0; d < 2; d++) {
+                    if (!Gr.per[d] && (t[d] < 0 || t[d] >= Gr.g[d])) v = false;
+                    blo[d] = Gr.lo[d] + t[d] * Gr.bs[d] - p[d];
+                }
+                v = v && bb_in_ext(ext, blo, Gr.bs, pad, 2);
+                if (!gb2<G>(v, gb)) continue;
+                met = true;
+                v = v && bb_block_count<2>(A.start, T, t) > 0;
+                if (!gb2<G>(v, gb)) continue;
+                int nv = 0;
+#pragma unroll
+                for (int s = 0; s < S; s++) {
+                    const unsigned long long m = c.live[s];
+                    if ((m >> gl) & 1) bb_put(bbl, nv + __popcll(m & ((1ull << gl) - 1ull)), c.vx[s], c.vy[s], 0.0, extra);
+                    nv += __popcll(m);
+                }
+                lds_sync2();
+                v = v && bb_meets(bbl, nv, blo, Gr.bs, pad, 2);
+                if (!gb2<G>(v, gb)) continue;
                 int st = p_gather<G, S, MAXL, F32>(A, sh, c, T, si, p, bc, dx, dy, v, ws, cnt, lane, gl, gb);
                 if (st != ST_OK) return st;
             }
+            if (!met) break;
         }
     }
 

@@ -25,7 +25,11 @@
 // nearest-first order; the particles of up to 64 blocks are loaded at once
 // and taken in increasing distance.  A candidate at distance >= 2R (R the
 // largest vertex distance) is skipped and the sweep stops when the next block
-// is farther than 2R (the radius bound of section 2.1.3).
+// is farther than 2R (the radius bound of section 2.1.3).  Past the list the
+// search runs Chebyshev shells of blocks under the block bound of the same
+// section: blocks and candidates outside the balls B(v, |v|) of the vertices
+// are skipped, and the search ends at the first shell that misses their
+// bounding box.
 #include "cell_common.h"
 
 namespace vc {
@@ -40,7 +44,7 @@ struct CellLDS {
     uint8_t psh[MAXP];        // image code
     uint8_t pwall[MAXP];      // 1: wall plane (exact offset stored)
     uint8_t etab[MAXP][MAXP]; // slot of the triangle holding directed edge a -> b
-    union {
+    union alignas(16) {
         struct {              // statistics
             double pos[S * 64][3];
             uint32_t tpl[S * 64];
@@ -344,11 +348,35 @@ __device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &
     return radius_ok(c) ? ST_OK : ST_CAP;
 }
 
+// The cell's vertices as the ball list of the block bound, in the
+// new-vertex buffer (unused outside cuts); returns their number.
+template <int S, int MAXP, bool F32, int K>
+__device__ __forceinline__ int bb_list(CellLDS<S, MAXP, K> &sh, const Cell<S, MAXP, F32> &c, int lane, double extra)
+{
+    static_assert(sizeof(sh.u.gc.npos) >= sizeof(float4) * S * 64, "ball list does not fit");
+    float4 *list = reinterpret_cast<float4 *>(&sh.u.gc.npos[0][0]);
+    int n = 0;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        const unsigned long long m = c.live[s];
+        if ((m >> lane) & 1) bb_put(list, n + lane_rank(m), c.vx[s], c.vy[s], c.vz[s], extra);
+        n += __popcll(m);
+    }
+    __syncthreads();
+    return n;
+}
+
 // Load the particles of up to 64 blocks (one per lane: offset dx,dy,dz,
 // valid) and feed them to the cell in increasing distance.
+// A batch with at least bbmin candidates inside the radius bound is first
+// tested against the balls of the block bound, one candidate per lane: a
+// candidate outside every ball cannot cut (section 2.1.3), and this costs
+// one pass over the vertex list instead of a side test of every vertex.
 template <int S, int MAXP, bool F32, int K>
 __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh, Cell<S, MAXP, F32> &c, int si, const double *p,
-                      const int *bc, int dx, int dy, int dz, bool valid, double *ws, unsigned long long *cnt, int lane)
+                      const int *bc, int dx, int dy, int dz, bool valid, double *ws, unsigned long long *cnt, int lane,
+                      int bbmin, double extra, double pad)
 {
     const Tess &T = A.tess[A.part[si].tess];
     const Grid &G = T.G;
@@ -425,6 +453,12 @@ __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh
             bool self = (idx == si) && code == kNoShift;
             if (!self && d2 < c.lim) key = __double_as_longlong(d2);
             qid = q.id;
+        }
+        if (__popcll(__ballot(key != ~0ull)) >= bbmin) {
+            const int nv = bb_list(sh, c, lane, extra);
+            const double q[3] = {a0, a1, a2}, zero[3] = {0.0, 0.0, 0.0};
+            if (key != ~0ull && !bb_meets(reinterpret_cast<const float4 *>(&sh.u.gc.npos[0][0]), nv, q, zero, pad, 3))
+                key = ~0ull;
         }
         // rank the batch by (distance, lane) and store it sorted
         unsigned long long vm = __ballot(key != ~0ull);
@@ -542,6 +576,9 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     __syncthreads();
     update_radius(c, lane, A);
 
+    // the balls of the block bound: radical widening and rounding allowance
+    const double extra = rad ? fmax(*A.rmax * *A.rmax - c.ri * c.ri, 0.0) : 0.0;
+    const double pad = bb_pad(G, p, 3);
     // nearest-first sweep over the precomputed block offsets
     bool finished = false;
     for (int o0 = 0; o0 < A.noff; o0 += 64) {
@@ -552,12 +589,15 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         int o = o0 + lane;
         bool v = o < A.noff;
         Offset of = v ? A.offs[o] : Offset{0, 0, 0, 0};
-        int st = gather<S, MAXP, F32, K>(A, sh, c, si, p, bc, of.dx, of.dy, of.dz, v, ws, cnt, lane);
+        int st = gather<S, MAXP, F32, K>(A, sh, c, si, p, bc, of.dx, of.dy, of.dz, v, ws, cnt, lane, kBbMinList, extra,
+                                         pad);
         if (st != ST_OK) return st;
     }
-    // beyond the list: whole Chebyshev shells until the radius bound holds
+    // beyond the list: whole Chebyshev shells, until the radius bound holds
+    // or no block of a shell meets the bounding box of the block bound
     if (!finished) {
         cnt[DC_FALLBACK]++;
+        const float4 *bbl = reinterpret_cast<const float4 *>(&sh.u.gc.npos[0][0]);
         for (int r = A.off_radius + 1;; r++) {
             if (r > kMaxShell || !radius_ok(c)) return ST_CAP;
             double lb = 1e300;
@@ -569,17 +609,43 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
             }
             if (!exists) break;
             if (lb > 0.0 && lb * lb >= c.lim) break;
+            cnt[DC_SHELLS]++;
             int side = 2 * r + 1;
             int tot = side * side * side;
+            bool met = false;
             for (int c0 = 0; c0 < tot; c0 += 64) {
                 int ix = c0 + lane;
                 int dx = ix % side - r, dy = (ix / side) % side - r, dz = ix / (side * side) - r;
                 int ch = max(abs(dx), max(abs(dy), abs(dz)));
                 bool v = ix < tot && ch == r;
                 if (!__ballot(v)) continue;
-                int st = gather<S, MAXP, F32, K>(A, sh, c, si, p, bc, dx, dy, dz, v, ws, cnt, lane);
+                // block bound (section 2.1.3): the bounding box of the balls,
+                // then the balls for the non-empty blocks
+                double ext[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < S; s++)
+                    if ((c.live[s] >> lane) & 1) bb_ext_add(ext, c.vx[s], c.vy[s], c.vz[s], extra);
+#pragma unroll
+                for (int k = 0; k < 6; k++) ext[k] = wave_max(ext[k]);
+                const int t[3] = {bc[0] + dx, bc[1] + dy, bc[2] + dz};
+                double blo[3];
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    if (!G.per[d] && (t[d] < 0 || t[d] >= G.g[d])) v = false;
+                    blo[d] = G.lo[d] + t[d] * G.bs[d] - p[d];
+                }
+                v = v && bb_in_ext(ext, blo, G.bs, pad, 3);
+                if (!__ballot(v)) continue;
+                met = true;
+                v = v && bb_block_count<3>(A.start, T, t) > 0;
+                if (!__ballot(v)) continue;
+                const int nv = bb_list(sh, c, lane, extra);
+                v = v && bb_meets(bbl, nv, blo, G.bs, pad, 3);
+                if (!__ballot(v)) continue;
+                int st = gather<S, MAXP, F32, K>(A, sh, c, si, p, bc, dx, dy, dz, v, ws, cnt, lane, 1, extra, pad);
                 if (st != ST_OK) return st;
             }
+            if (!met) break;
         }
     }
 

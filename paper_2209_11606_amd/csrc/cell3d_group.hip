@@ -75,6 +75,21 @@ __device__ __forceinline__ uint32_t gmax_u32(uint32_t v)
 }
 
 template <int G>
+__device__ __forceinline__ double gmax_f64(double v)
+{
+    v = fmax(v, dpp_f64<DPP_QUAD_1032, 0xf>(v, v));
+    v = fmax(v, dpp_f64<DPP_QUAD_2301, 0xf>(v, v));
+    v = fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR, 0xf>(v, v));
+    v = fmax(v, dpp_f64<DPP_ROW_MIRROR, 0xf>(v, v));
+    if (G >= 32) {
+        unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        unsigned lo = (unsigned)swz16((int)(unsigned)u), hi = (unsigned)swz16((int)(unsigned)(u >> 32));
+        v = fmax(v, __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo));
+    }
+    return v;
+}
+
+template <int G>
 __device__ __forceinline__ int gisum(int v)
 {
     v = v + dpp_i32<DPP_QUAD_1032, 0xf>(0, v);
@@ -139,6 +154,7 @@ struct GState {
     double ri;              // the particle's radius (radical tessellation), else 0
     int shell;              // 0: offset list; r > 0: Chebyshev shell r
     int cur;                // next offset index, or position in the shell
+    int bbhit;              // a block of the current shell met the bounding box of the block bound
     int gtot, gc0;          // candidates of the gather, next batch start
     int cell, cend;         // claimed range of the work queue
     uint32_t cnt[DC_N];     // counters other than candidates and tests
@@ -154,7 +170,7 @@ struct SL {
     uint8_t psh[MAXP];
     uint8_t pwall[MAXP];
     uint8_t etab[MAXP][MAXP];  // slot of the triangle holding directed edge a->b
-    union {
+    union alignas(16) {
         struct {               // the search
             double cq[G][4];   // the batch's candidates, nearest first: q, |q|^2
             double ch[G];      // their plane offsets h
@@ -418,6 +434,8 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
                 c.phase = PH_STATS;
                 return;
             }
+            sh.gs.bbhit = 0;
+            sh.gs.cnt[DC_SHELLS]++;
         }
         const int side = 2 * r + 1;
         const int tot = side * side * side;
@@ -427,14 +445,41 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
         dd[2] = ix / (side * side) - r;
         int ch = max(abs(dd[0]), max(abs(dd[1]), abs(dd[2])));
         v = ix < tot && ch == r;
+        // block bound (section 2.1.3): blocks outside a wall and blocks
+        // that miss the bounding box of the balls are skipped, and a shell
+        // in which every block misses it ends the search
+        {
+            const double extra = A.rad ? fmax(*A.rmax * *A.rmax - sh.gs.ri * sh.gs.ri, 0.0) : 0.0;
+            double ext[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < S; s++)
+                if ((c.live[s] >> gl) & 1) bb_ext_add(ext, c.vx[s], c.vy[s], c.vz[s], extra);
+#pragma unroll
+            for (int k = 0; k < 6; k++) ext[k] = gmax_f64<G>(ext[k]);
+            double blo[3];
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                const int t = sh.gs.bc[d] + dd[d];
+                if (!G3.per[d] && (t < 0 || t >= G3.g[d])) v = false;
+                blo[d] = G3.lo[d] + t * G3.bs[d] - sh.gs.p[d];
+            }
+            v = v && bb_in_ext(ext, blo, G3.bs, bb_pad(G3, sh.gs.p, 3), 3);
+        }
+        const int hit = sh.gs.bbhit | (gbal<G>(v, gb) != 0u);
+        sh.gs.bbhit = hit;
         sh.gs.cur += G;
         if (sh.gs.cur >= tot) {
+            if (!hit) {
+                c.phase = PH_STATS;
+                return;
+            }
             sh.gs.shell++;
             sh.gs.cur = 0;
         }
     }
     // the blocks: periodic wrap by whole periods (at most two each way), walls
     int bb[3], sv[3];
+    double rel[3];
     bool ok = v;
     double d2b = 0.0;
 #pragma unroll
@@ -460,6 +505,7 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
         double blo = G3.lo[d] + t * G3.bs[d];
         double e = fmax(0.0, fmax(blo - sh.gs.p[d], sh.gs.p[d] - (blo + G3.bs[d])));
         d2b += e * e;
+        rel[d] = blo - sh.gs.p[d];
     }
     if (d2b >= lim) ok = false;
     int cntb = 0, beg = 0;
@@ -467,6 +513,26 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
         int blk = T.bbase + bb[0] + G3.g[0] * (bb[1] + G3.g[1] * bb[2]);
         beg = A.start[blk];
         cntb = A.start[blk + 1] - beg;
+    }
+    if (sh.gs.shell > 0) {
+        // shell blocks: only non-empty blocks that meet the balls (the ball
+        // list sits in the search buffers, free between batches)
+        ok = ok && cntb > 0;
+        if (gbal<G>(ok, gb)) {
+            static_assert(sizeof(sh.u) >= sizeof(float4) * G * S, "ball list does not fit");
+            float4 *bbl = reinterpret_cast<float4 *>(&sh.u);
+            const double extra = A.rad ? fmax(*A.rmax * *A.rmax - sh.gs.ri * sh.gs.ri, 0.0) : 0.0;
+            int nv = 0;
+#pragma unroll
+            for (int s = 0; s < S; s++) {
+                const uint32_t m = c.live[s];
+                if ((m >> gl) & 1) bb_put(bbl, nv + __popc(m & ((1u << gl) - 1u)), c.vx[s], c.vy[s], c.vz[s], extra);
+                nv += __popc(m);
+            }
+            lds_fence();
+            ok = ok && bb_meets(bbl, nv, rel, G3.bs, bb_pad(G3, sh.gs.p, 3), 3);
+        }
+        if (!ok) cntb = 0;
     }
     sh.gs.cnt[DC_BLOCKS] += __popc(gbal<G>(ok, gb));
     int incl = gscan_incl<G>(cntb);

@@ -8,6 +8,7 @@ namespace vc {
 namespace {
 
 constexpr double kMargin = 1.0 + 0x1p-30;  // radius-bound safety factor on squared distances
+constexpr int kBbMinList = 16;             // candidates of a batch that turn on the ball test in the offset list
 constexpr int kMaxShell = 64;              // largest Chebyshev shell searched; beyond it the cell fails
 
 struct PlaneD {
@@ -455,6 +456,119 @@ __device__ __forceinline__ double search_lim(double R2, double R, const CellArgs
 enum { ST_OK = 0, ST_CAP = 1, ST_DUP = 3, ST_EMPTY = 5 };
 
 // ---------------------------------------------------------------------------
+// Block bound (section 2.1.3).  A particle at q (relative to the cell's
+// particle) cuts the cell only if some vertex v lies strictly beyond its
+// plane, v.q > |q|^2 / 2, that is |q - v| < |v|: q lies in the union U of the
+// balls B(v, |v|).  A block whose box meets none of them holds no particle
+// that can cut.  U only shrinks as the cell is cut.
+//
+// The shell search tests every block of a Chebyshev shell against the
+// axis-aligned bounding box of U (six numbers, cheap per block); once no
+// block of a shell meets that box, the box lies inside the shell and every
+// block farther out misses it, so the search is complete.  A non-empty
+// block that meets the box is then tested against the balls themselves
+// before its particles are loaded.
+// ---------------------------------------------------------------------------
+
+// One vertex's part of the bounding box of U: ext[d] >= v_d + rho and
+// ext[3 + d] >= rho - v_d, rho the ball radius widened as in the ball list.
+__device__ __forceinline__ void bb_ext_add(double ext[6], double x, double y, double z, double extra)
+{
+    const double rho = sqrt((x * x + y * y + z * z + extra) * (1.0 + 0x1p-8)) * (1.0 + 0x1p-40);
+    ext[0] = fmax(ext[0], x + rho);
+    ext[1] = fmax(ext[1], y + rho);
+    ext[2] = fmax(ext[2], z + rho);
+    ext[3] = fmax(ext[3], rho - x);
+    ext[4] = fmax(ext[4], rho - y);
+    ext[5] = fmax(ext[5], rho - z);
+}
+
+// Does the box [lo - pad, lo + bs + pad] meet the bounding box of U?
+__device__ __forceinline__ bool bb_in_ext(const double ext[6], const double lo[3], const double bs[3], double pad,
+                                          int dim)
+{
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+        if (d < dim) in = in && lo[d] - pad < ext[d] && lo[d] + bs[d] + pad > -ext[3 + d];
+    return in;
+}
+
+// Particle count of the block at unfolded block coordinates t (t[2] = 0 in
+// 2D); 0 for a block outside a wall or more than two periods away, which the
+// gathers skip as well.
+template <int DIM>
+__device__ __forceinline__ int bb_block_count(const int32_t *start, const Tess &T, const int t[3])
+{
+    const Grid &G = T.G;
+    int bb[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+        const int g = G.g[d];
+        if (G.per[d]) {
+            const int w = ((t[d] % g) + g) % g;
+            const int sv = (t[d] - w) / g;
+            if (sv > 2 || sv < -2) return 0;
+            bb[d] = w;
+        } else {
+            if (t[d] < 0 || t[d] >= g) return 0;
+            bb[d] = t[d];
+        }
+    }
+    const int64_t blk = T.bbase + bb[0] + (int64_t)G.g[0] * (bb[1] + (DIM == 3 ? (int64_t)G.g[1] * bb[2] : 0));
+    return start[blk + 1] - start[blk];
+}
+
+// For a radical cell the plane of a particle of radius rj is
+// v.q > (|q|^2 + ri^2 - rj^2) / 2, so the ball grows to the squared radius
+// |v|^2 + rmax^2 - ri^2 (extra = max(rmax^2 - ri^2, 0): the balls still
+// hold the particle, and U stays star-shaped about it).
+//
+// The list of a cell's vertices for the test: x, y, z and the squared ball
+// radius as floats, the latter widened by 2^-8 so that the float rounding
+// of the coordinates can only keep a block, never drop one that the FP64
+// cell would need.
+// Rounding allowance of the block boxes: far above the error of a block
+// bound or of a relative particle position (a few units in the last place of
+// the container's coordinates), far below a block side.
+__device__ __forceinline__ double bb_pad(const Grid &G, const double *p, int dim)
+{
+    double m = 0.0;
+    for (int d = 0; d < dim; d++) m = fmax(m, fabs(p[d]) + fabs(G.lo[d]) + 3.0 * G.L[d]);
+    return m * 0x1p-40;
+}
+
+__device__ __forceinline__ void bb_put(float4 *list, int j, double x, double y, double z, double extra)
+{
+    list[j] = make_float4((float)x, (float)y, (float)z,
+                          (float)(x * x + y * y + z * z + extra) * (1.0f + 0x1p-8f));
+}
+
+// Does the box [lo, lo + bs] (relative coordinates, z ignored in 2D) meet a
+// ball of the list?  The box is widened by pad, which covers the rounding of
+// block bounds and particle positions relative to the cell's particle, and
+// its corners are rounded outward to float.
+__device__ __forceinline__ bool bb_meets(const float4 *list, int nv, const double lo[3], const double bs[3], double pad,
+                                         int dim)
+{
+    float l[3], h[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const double lo_d = d < dim ? lo[d] - pad : 0.0, hi_d = d < dim ? lo[d] + bs[d] + pad : 0.0;
+        l[d] = __double2float_rd(lo_d);
+        h[d] = __double2float_ru(hi_d);
+    }
+    for (int j = 0; j < nv; j++) {
+        const float4 v = list[j];
+        const float e0 = fmaxf(0.0f, fmaxf(l[0] - v.x, v.x - h[0]));
+        const float e1 = fmaxf(0.0f, fmaxf(l[1] - v.y, v.y - h[1]));
+        const float e2 = fmaxf(0.0f, fmaxf(l[2] - v.z, v.z - h[2]));
+        if (e0 * e0 + e1 * e1 + e2 * e2 < v.w) return true;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
 // Edge-graph records for the Weinberg codes (the cell-topology code of
 // VoroTop; section 5).  A cell's vertex is a class of triangles joined by
 // zero-length edges; around it, its edges come in the order of the
@@ -618,7 +732,7 @@ __device__ __noinline__ int wb_record(uint8_t *rec, int D, const uint32_t *tpl, 
     }
     return D;
 }
-enum { DC_CAND, DC_TESTS, DC_CUTS, DC_NEWV, DC_EXACT, DC_RECHECK, DC_SPILL, DC_BLOCKS, DC_FALLBACK, DC_N };
+enum { DC_CAND, DC_TESTS, DC_CUTS, DC_NEWV, DC_EXACT, DC_RECHECK, DC_SPILL, DC_BLOCKS, DC_FALLBACK, DC_SHELLS, DC_N };
 
 }  // namespace
 }  // namespace vc
