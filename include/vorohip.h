@@ -121,8 +121,10 @@ enum {
     VC_D_SPILLED = 6,     /* cells re-run in the large-capacity kernel */
     VC_D_BLOCKS = 7,      /* blocks whose particles were loaded */
     VC_D_FALLBACK = 8,    /* cells that searched beyond the precomputed offsets */
-    VC_D_SHELLS = 9       /* Chebyshev shells of blocks searched beyond them
+    VC_D_SHELLS = 9,      /* Chebyshev shells of blocks searched beyond them
                              (section 2.1.3: the block bound ends the search) */
+    VC_D_LOADED = 10      /* particles loaded from the blocks (before the radius
+                             and ball tests) */
 };
 
 typedef struct {

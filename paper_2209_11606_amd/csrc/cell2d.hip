@@ -384,6 +384,7 @@ __device__ __forceinline__ int p_gather(const CellArgs &A, L2<G, S, MAXL> &sh, P
     cnt[DC_BLOCKS] += __popcll(gb2<G>(ok, gb));
     int incl = g2scan<G>(cntb, gl);
     int total = __shfl(incl, gb + G - 1);
+    cnt[DC_LOADED] += total;
     if (total == 0) return ST_OK;
     lds_sync2();
     sh.cpre[gl] = incl - cntb;

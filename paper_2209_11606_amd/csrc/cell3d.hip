@@ -412,6 +412,7 @@ __device__ __forceinline__ int gather(const CellArgs &A, CellLDS<S, MAXP, K> &sh
     cnt[DC_BLOCKS] += __popcll(__ballot(ok));
     int incl = wave_incl_scan(cntb);
     int total = __builtin_amdgcn_readlane(incl, 63);
+    cnt[DC_LOADED] += total;
     if (total == 0) return ST_OK;
     __syncthreads();
     sh.cpre[lane] = incl - cntb;

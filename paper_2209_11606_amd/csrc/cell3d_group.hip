@@ -537,6 +537,7 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
     sh.gs.cnt[DC_BLOCKS] += __popc(gbal<G>(ok, gb));
     int incl = gscan_incl<G>(cntb);
     int total = __shfl(incl, gb + G - 1);
+    sh.gs.cnt[DC_LOADED] += total;
     if (total == 0) return;  // stay in GATHER: next blocks
     sh.u.w.cpre[gl] = incl - cntb;
     sh.u.w.cbeg[gl] = beg;
@@ -1140,7 +1141,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
     lds_fence();
     for (;;) {
         if (c.phase == PH_NEW) {
-            if (cnt[1] > (1u << 30) || sh.gs.cnt[DC_NEWV] > (1u << 30)) flush_counters<G, S, MAXP>(A, sh, cnt[0], cnt[1], gl);
+            if (cnt[1] > (1u << 30) || sh.gs.cnt[DC_NEWV] > (1u << 30) || sh.gs.cnt[DC_LOADED] > (1u << 30))
+                flush_counters<G, S, MAXP>(A, sh, cnt[0], cnt[1], gl);
             ph_new<G, S, MAXP, F32>(A, sh, c, ncell, gl, gb);
         }
         if (!__ballot(c.phase != PH_DONE)) break;

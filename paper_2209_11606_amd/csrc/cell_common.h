@@ -732,7 +732,7 @@ __device__ __noinline__ int wb_record(uint8_t *rec, int D, const uint32_t *tpl, 
     }
     return D;
 }
-enum { DC_CAND, DC_TESTS, DC_CUTS, DC_NEWV, DC_EXACT, DC_RECHECK, DC_SPILL, DC_BLOCKS, DC_FALLBACK, DC_SHELLS, DC_N };
+enum { DC_CAND, DC_TESTS, DC_CUTS, DC_NEWV, DC_EXACT, DC_RECHECK, DC_SPILL, DC_BLOCKS, DC_FALLBACK, DC_SHELLS, DC_LOADED, DC_N };
 
 }  // namespace
 }  // namespace vc

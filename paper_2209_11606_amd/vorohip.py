@@ -26,7 +26,7 @@ VC_WEINBERG = 256
 VC_FO_LEN = 32
 VC_DIAG_LEN = 16
 DIAG_NAMES = ["candidates", "tests", "cuts", "new_vertices", "exact", "recheck", "spilled", "blocks", "fallback",
-              "shells"]
+              "shells", "loaded"]
 _FIELD_DTYPE = {VC_F_VOLUME: np.float64, VC_F_CENTROID: np.float64, VC_F_NV: np.int32, VC_F_NE: np.int32,
                 VC_F_NF: np.int32, VC_F_FACE_ORDERS: np.uint8, VC_F_NBR_OFFSETS: np.int64, VC_F_NBR_IDS: np.int32,
                 VC_F_NBR_SHIFTS: np.uint8, VC_F_STATUS: np.uint8, VC_F_DIAG: np.uint64, VC_F_PERIMETER: np.float64,

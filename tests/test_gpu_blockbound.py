@@ -86,6 +86,8 @@ def test_sc_lattice_fine_grid(v, cpw):
     # box), then only the non-empty blocks that meet the balls, among those
     # of the 26 nearest sites
     assert n * (9 ** 3 + 6) <= d["blocks"] <= n * (9 ** 3 + 26)
+    # particles loaded: the cell's own, then those of the blocks loaded
+    assert n * 7 <= d["loaded"] <= n * 27
 
 
 @pytest.mark.parametrize("radical", [False, True])
