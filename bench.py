@@ -424,10 +424,12 @@ def main():
         achieved = n * flops_per_cell / (b["kernel_ms"] / 1e3)
         key = kernel_key("fp64" if best.startswith("fp64") else "f32_filter", b.get("tuned"))
         traffic = committed_traffic(key) if a.workload == "periodic1m" else None
+        # the published peak, confirmed on this device by an FMA microbenchmark
+        measured = {"fp64": v.vc_device_fma_rate(v.VC_FP64), "fp32_unpacked": v.vc_device_fma_rate(v.VC_F32_FILTER)}
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=FP64_VECTOR_PEAK / 1e12, unit="TFLOP/s",
                     frac=achieved / FP64_VECTOR_PEAK, traffic=traffic,
                     kernel="cell construction (" + key + ")", flops_per_cell=flops_per_cell,
-                    kernel_ms=b["kernel_ms"])
+                    kernel_ms=b["kernel_ms"], measured_fma_peak=measured)
     out = {
         "metric": ("3D" if dim == 3 else "2D") + (" radical" if members[0].get("radii") is not None else "")
                   + " Voronoi cells/s on 1 MI355X, FP32-filter vs FP64 plain; "

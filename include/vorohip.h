@@ -290,6 +290,17 @@ vc_status vc_batch_tune(vc_batch *b, vc_result *r, void *stream, vc_tuning *best
 
 void vc_batch_destroy(vc_batch *b);
 
+/* Measured vector FMA rate of the current device: the compute roof of the
+ * cell kernels, which are bound by FP64 vector arithmetic.  precision:
+ * VC_FP64, or VC_F32_FILTER for FP32 lanes (unpacked: the library is built
+ * without packed FP32 instructions).
+ * Runs one untimed and `reps` timed launches of eight independent FMA
+ * chains per lane on every compute unit, on `stream`, and returns the best
+ * rate in *tflops (10^12 flops/s, an FMA counted as 2).  Allocates and frees
+ * its own device buffer; synchronous.  VC_E_ARG for a null tflops, reps < 1
+ * or another precision. */
+vc_status vc_device_fma_rate(int precision, int reps, void *stream, double *tflops);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *vc_last_error(void);
 

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvorohip.so")
-SOURCES = ["binning.hip", "cell3d.hip", "cell3d_group.hip", "cell2d.hip", "weinberg.hip", "api.cpp"]
+SOURCES = ["binning.hip", "cell3d.hip", "cell3d_group.hip", "cell2d.hip", "weinberg.hip", "peak.hip", "api.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed FP32 instructions anywhere in the library
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

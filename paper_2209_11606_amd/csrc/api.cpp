@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/vorohip.h"
+#include "peak.h"
 #include "vc_internal.h"
 
 using namespace vc;
@@ -870,6 +871,36 @@ vc_status vc_batch_tune(vc_batch *b, vc_result *r, void *stream, vc_tuning *best
 }
 
 void vc_batch_destroy(vc_batch *b) { free_container(b); }
+
+vc_status vc_device_fma_rate(int precision, int reps, void *stream, double *tflops)
+{
+    if (!tflops || reps < 1 || (precision != VC_FP64 && precision != VC_F32_FILTER))
+        return fail(VC_E_ARG, "vc_device_fma_rate: null tflops, reps < 1 or unknown precision");
+    hipStream_t s = (hipStream_t)stream;
+    const int blocks = device_cu_count() * 32, steps = 4096;
+    double *out = nullptr;
+    vc_status st = dalloc(&out, (size_t)blocks * 256);
+    if (st) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = 1e30f;
+    for (int r = 0; r <= reps && e == hipSuccess; r++) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch_fma_rate(out, precision == VC_FP64, blocks, steps, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && r > 0 && ms < best) best = ms;  // the first launch is untimed
+    }
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipFree(out);
+    if (e != hipSuccess) return fail(VC_E_HIP, "vc_device_fma_rate: %s", hipGetErrorString(e));
+    *tflops = (double)blocks * 256.0 * 8.0 * steps * 2.0 / (best * 1e-3) / 1e12;
+    return VC_OK;
+}
 
 const char *vc_last_error(void) { return g_err.c_str(); }
 

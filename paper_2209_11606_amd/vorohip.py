@@ -81,6 +81,7 @@ def _load():
         "vc_result_kernel_ms": (I32, [P, P]),
         "vc_last_error": (ctypes.c_char_p, []),
         "vc_version": (ctypes.c_char_p, []),
+        "vc_device_fma_rate": (I32, [I32, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -95,7 +96,7 @@ EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_
             "vc_result_create", "vc_compute", "vc_compute_subset",
             "vc_result_get", "vc_result_copy", "vc_result_kernel_ms", "vc_result_destroy", "vc_container_destroy", "vc_batch_create",
             "vc_batch_rebin", "vc_batch_result_create", "vc_batch_compute", "vc_batch_tune", "vc_batch_destroy",
-            "vc_last_error", "vc_version"]
+            "vc_last_error", "vc_version", "vc_device_fma_rate"]
 
 
 def lib():
@@ -113,6 +114,14 @@ def vc_version():
 def _check(code):
     if code != VC_OK:
         raise VcError(code, vc_last_error())
+
+
+def vc_device_fma_rate(precision=VC_FP64, reps=3, stream=None):
+    """Measured vector FMA rate of the current device in TFLOP/s (an FMA
+    counts as 2): FP64 for VC_FP64, unpacked FP32 for VC_F32_FILTER."""
+    out = ctypes.c_double(0.0)
+    _check(_lib.vc_device_fma_rate(precision, reps, _stream_ptr(stream), ctypes.byref(out)))
+    return out.value
 
 
 def vc_options_init(dim, lo, hi, periodic, **kw):

@@ -64,6 +64,10 @@ def test_argument_validation_without_gpu():
     assert "clip" in v.vc_last_error()
     assert L.vc_result_get(None, 0, None, None) == v.VC_E_ARG
     assert L.vc_result_kernel_ms(None, None) == v.VC_E_ARG
+    t = ctypes.c_double()
+    assert L.vc_device_fma_rate(v.VC_FP64, 3, None, None) == v.VC_E_ARG
+    assert L.vc_device_fma_rate(v.VC_FP64, 0, None, ctypes.byref(t)) == v.VC_E_ARG
+    assert L.vc_device_fma_rate(5, 3, None, ctypes.byref(t)) == v.VC_E_ARG
     assert v.vc_version().startswith("vorohip")
 
 
