@@ -64,7 +64,7 @@ def parse():
     p.add_argument("--variants", default="all", help="comma list of variants to run (default all)")
     p.add_argument("--workload", default="periodic1m",
                    choices=["periodic1m", "batch4096", "fcc10m", "periodic2d10m", "periodic102m",
-                            "localized10m", "localized100k_unclipped", "clustered10m", "polydisperse1m", "vorotop1m"],
+                            "localized10m", "localized10m_unclipped", "localized100k_unclipped", "clustered10m", "polydisperse1m", "vorotop1m"],
                    help="periodic1m: the metric's configuration (default); the others measure the remaining sets")
     return p.parse_args()
 
@@ -333,6 +333,14 @@ def main():
         desc = ("localized_clipped_10M: 10^8 uniform points in the walled unit cube, the ~10^7 inside the "
                 "central cube of volume 0.1 kept, each cell clipped by the cube of side 1.5*sqrt(3)*1e-8^(1/3) "
                 "(section 3.1.3), full statistics")
+        sample_desc = "first {} cells of the localized set"
+    elif a.workload == "localized10m_unclipped":
+        w = W.localized(100_000_000)
+        w["clip"] = 0.0
+        members = [w]
+        desc = ("localized_unclipped_10M: 10^8 uniform points in the walled unit cube, the ~10^7 inside the "
+                "central cube of volume 0.1 kept, no clipping, the paper's N_opt 49 grid (126^3; section 3.1), "
+                "full statistics")
         sample_desc = "first {} cells of the localized set"
     elif a.workload == "localized100k_unclipped":
         w = W.localized(1_000_000)
