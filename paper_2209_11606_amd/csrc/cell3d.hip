@@ -369,6 +369,38 @@ __device__ __forceinline__ int bb_list(CellLDS<S, MAXP, K> &sh, const Cell<S, MA
 
 // Load the particles of up to 64 blocks (one per lane: offset dx,dy,dz,
 // valid) and feed them to the cell in increasing distance.
+// Block bound (section 2.1.3) of one block per lane, at unfolded block
+// coordinates t: false for a block outside a wall or one that misses the
+// bounding box of the vertices' balls (met is set when some lane's block
+// meets that box), then for an empty block, then for one that misses the
+// balls themselves.
+template <int S, int MAXP, bool F32, int K>
+__device__ __forceinline__ bool bb_block(const CellArgs &A, CellLDS<S, MAXP, K> &sh, const Cell<S, MAXP, F32> &c,
+                                         const Tess &T, const double *p, const int t[3], bool v, double extra,
+                                         double pad, int lane, bool &met)
+{
+    const Grid &G = T.G;
+    double ext[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < S; s++)
+        if ((c.live[s] >> lane) & 1) bb_ext_add(ext, c.vx[s], c.vy[s], c.vz[s], extra);
+#pragma unroll
+    for (int k = 0; k < 6; k++) ext[k] = wave_max(ext[k]);
+    double blo[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        if (!G.per[d] && (t[d] < 0 || t[d] >= G.g[d])) v = false;
+        blo[d] = G.lo[d] + t[d] * G.bs[d] - p[d];
+    }
+    v = v && bb_in_ext(ext, blo, G.bs, pad, 3);
+    if (!__ballot(v)) return false;
+    met = true;
+    v = v && bb_block_count<3>(A.start, T, t) > 0;
+    if (!__ballot(v)) return false;
+    const int nv = bb_list(sh, c, lane, extra);
+    return v && bb_meets(reinterpret_cast<const float4 *>(&sh.u.gc.npos[0][0]), nv, blo, G.bs, pad, 3);
+}
+
 // A batch with at least bbmin candidates inside the radius bound is first
 // tested against the balls of the block bound, one candidate per lane: a
 // candidate outside every ball cannot cut (section 2.1.3), and this costs
@@ -580,7 +612,9 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     // the balls of the block bound: radical widening and rounding allowance
     const double extra = rad ? fmax(*A.rmax * *A.rmax - c.ri * c.ri, 0.0) : 0.0;
     const double pad = bb_pad(G, p, 3);
-    // nearest-first sweep over the precomputed block offsets
+    // nearest-first sweep over the precomputed block offsets; once the cell
+    // is extended (2R beyond three block sides, past the first chunk), its
+    // blocks go through the block bound too
     bool finished = false;
     for (int o0 = 0; o0 < A.noff; o0 += 64) {
         if (A.offs[o0].m * T.bsmin2 >= c.lim) {
@@ -590,6 +624,12 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         int o = o0 + lane;
         bool v = o < A.noff;
         Offset of = v ? A.offs[o] : Offset{0, 0, 0, 0};
+        if (o0 > 0 && c.lim > kBbExtended * T.bsmin2) {
+            bool met = false;
+            const int t[3] = {bc[0] + of.dx, bc[1] + of.dy, bc[2] + of.dz};
+            v = bb_block(A, sh, c, T, p, t, v, extra, pad, lane, met);
+            if (!__ballot(v)) continue;
+        }
         int st = gather<S, MAXP, F32, K>(A, sh, c, si, p, bc, of.dx, of.dy, of.dz, v, ws, cnt, lane, kBbMinList, extra,
                                          pad);
         if (st != ST_OK) return st;
@@ -598,7 +638,6 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     // or no block of a shell meets the bounding box of the block bound
     if (!finished) {
         cnt[DC_FALLBACK]++;
-        const float4 *bbl = reinterpret_cast<const float4 *>(&sh.u.gc.npos[0][0]);
         for (int r = A.off_radius + 1;; r++) {
             if (r > kMaxShell || !radius_ok(c)) return ST_CAP;
             double lb = 1e300;
@@ -620,28 +659,8 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
                 int ch = max(abs(dx), max(abs(dy), abs(dz)));
                 bool v = ix < tot && ch == r;
                 if (!__ballot(v)) continue;
-                // block bound (section 2.1.3): the bounding box of the balls,
-                // then the balls for the non-empty blocks
-                double ext[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s = 0; s < S; s++)
-                    if ((c.live[s] >> lane) & 1) bb_ext_add(ext, c.vx[s], c.vy[s], c.vz[s], extra);
-#pragma unroll
-                for (int k = 0; k < 6; k++) ext[k] = wave_max(ext[k]);
                 const int t[3] = {bc[0] + dx, bc[1] + dy, bc[2] + dz};
-                double blo[3];
-#pragma unroll
-                for (int d = 0; d < 3; d++) {
-                    if (!G.per[d] && (t[d] < 0 || t[d] >= G.g[d])) v = false;
-                    blo[d] = G.lo[d] + t[d] * G.bs[d] - p[d];
-                }
-                v = v && bb_in_ext(ext, blo, G.bs, pad, 3);
-                if (!__ballot(v)) continue;
-                met = true;
-                v = v && bb_block_count<3>(A.start, T, t) > 0;
-                if (!__ballot(v)) continue;
-                const int nv = bb_list(sh, c, lane, extra);
-                v = v && bb_meets(bbl, nv, blo, G.bs, pad, 3);
+                v = bb_block(A, sh, c, T, p, t, v, extra, pad, lane, met);
                 if (!__ballot(v)) continue;
                 int st = gather<S, MAXP, F32, K>(A, sh, c, si, p, bc, dx, dy, dz, v, ws, cnt, lane, 1, extra, pad);
                 if (st != ST_OK) return st;
@@ -836,8 +855,11 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     return capfail ? ST_CAP : ST_OK;
 }
 
+// two waves per SIMD for the main kernels (the register allocator is held
+// to that budget); the spill kernel's LDS allows one
 template <int S, int MAXP, bool F32, int K, bool RAD, bool WB>
-__global__ __launch_bounds__(64) void k_cells(CellArgs Ain, int spill_mode)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MAXP == 48 ? 2 : 1))) void k_cells(CellArgs Ain,
+                                                                                                     int spill_mode)
 {
     // the Voronoi instantiation carries no radical code, and one without
     // Weinberg records none of their code: those pointers are compile-time

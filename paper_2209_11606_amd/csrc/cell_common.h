@@ -9,6 +9,7 @@ namespace {
 
 constexpr double kMargin = 1.0 + 0x1p-30;  // radius-bound safety factor on squared distances
 constexpr int kBbMinList = 16;             // candidates of a batch that turn on the ball test in the offset list
+constexpr double kBbExtended = 9.0;        // (2R / smallest block side)^2 above which the offset list's blocks are tested
 constexpr int kMaxShell = 64;              // largest Chebyshev shell searched; beyond it the cell fails
 
 struct PlaneD {

@@ -82,10 +82,14 @@ def test_sc_lattice_fine_grid(v, cpw):
     assert counts == {(21, 17)}
     d = out["diag"]
     assert d["fallback"] == n and d["shells"] == 17 * n
-    # blocks loaded: the offset list (all 9^3: the first cell is the whole
-    # box), then only the non-empty blocks that meet the balls, among those
-    # of the 26 nearest sites
-    assert n * (9 ** 3 + 6) <= d["blocks"] <= n * (9 ** 3 + 26)
+    # blocks loaded: in the offset list every block of the first chunk of 64
+    # (the first cell is the whole box), then the rest of the list (all 9^3
+    # blocks in the grouped form; in the one-cell form, which applies the
+    # block bound to the list once the cell is extended, only non-empty
+    # blocks that meet the balls: none), then, in the shells, the non-empty
+    # blocks that meet the balls, among those of the 26 nearest sites
+    near = 64 if cpw == 1 else 9 ** 3
+    assert n * (near + 6) <= d["blocks"] <= n * (near + 26)
     # particles loaded: the cell's own, then those of the blocks loaded
     assert n * 7 <= d["loaded"] <= n * 27
 
