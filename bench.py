@@ -64,7 +64,8 @@ def parse():
     p.add_argument("--variants", default="all", help="comma list of variants to run (default all)")
     p.add_argument("--workload", default="periodic1m",
                    choices=["periodic1m", "batch4096", "fcc10m", "periodic2d10m", "periodic102m",
-                            "localized10m", "localized10m_unclipped", "localized100k_unclipped", "clustered10m", "polydisperse1m", "vorotop1m"],
+                            "localized10m", "localized10m_unclipped", "localized100k_unclipped", "localized2d10m", "clustered10m",
+                            "clustered2d100m", "polydisperse1m", "vorotop1m"],
                    help="periodic1m: the metric's configuration (default); the others measure the remaining sets")
     return p.parse_args()
 
@@ -350,6 +351,16 @@ def main():
                 "central cube of volume 0.1 kept, no clipping, the paper's N_opt 49 grid (27^3; section 3.1), "
                 "full statistics")
         sample_desc = "first {} cells of the localized set"
+    elif a.workload == "localized2d10m":
+        members = [W.localized(100_000_000, dim=2)]
+        desc = ("localized_2d_10M: 10^8 uniform points in the walled unit square, the ~10^7 inside the central "
+                "square of area 0.1 kept, the paper's N_opt 30 grid (1825^2; section 3.1), full statistics")
+        sample_desc = "first {} cells of the 2D localized set"
+    elif a.workload == "clustered2d100m":
+        members = [W.clustered(100_000_000, dim=2)]
+        desc = ("extreme_clustering_2d_100M: 10^8 points with coordinates 1/2 + 4 (X - 1/2)^3, walled unit "
+                "square, N_opt 0.5 grid (14142^2; section 3.1), full statistics")
+        sample_desc = "first {} cells of the 2D clustered set"
     elif a.workload == "clustered10m":
         members = [W.clustered(10_000_000)]
         desc = ("extreme_clustering_10M: 10^7 points with coordinates 1/2 + 4 (X - 1/2)^3, walled unit cube, "

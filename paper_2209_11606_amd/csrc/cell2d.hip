@@ -529,7 +529,9 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
         const double extra = A.rad ? fmax(*A.rmax * *A.rmax - c.ri * c.ri, 0.0) : 0.0;
         const double pad = bb_pad(Gr, p, 2);
         for (int r = A.off_radius + 1;; r++) {
-            if (r > kMaxShell || !(c.R2 < 1e300)) return ST_CAP;
+            // a group of 8 lanes scans a ring 8 blocks at a time: a cell that
+            // searches far goes to the spill pass, where 64 lanes scan it
+            if (r > (G < 64 ? kRingSpill2 : kMaxShell) || !(c.R2 < 1e300)) return ST_CAP;
             double lb = 1e300;
             bool exists = false;
 #pragma unroll
@@ -540,14 +542,13 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
             if (!exists) break;
             if (lb > 0.0 && lb * lb >= c.lim) break;
             cnt[DC_SHELLS]++;
-            int side = 2 * r + 1;
-            int tot = side * side;
+            const int tot = 8 * r;
             bool met = false;
             for (int c0 = 0; c0 < tot; c0 += G) {
-                int ix = c0 + gl;
-                int dx = ix % side - r, dy = ix / side - r;
-                bool v = ix < tot && max(abs(dx), abs(dy)) == r;
-                if (!gb2<G>(v, gb)) continue;
+                const int ix = c0 + gl;
+                int dx = 0, dy = 0;
+                bool v = ix < tot;
+                if (v) ring_block2(r, ix, dx, dy);
                 // the bounding box of the discs, then the discs for the
                 // non-empty blocks
                 double ext[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};

@@ -650,15 +650,13 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
             if (!exists) break;
             if (lb > 0.0 && lb * lb >= c.lim) break;
             cnt[DC_SHELLS]++;
-            int side = 2 * r + 1;
-            int tot = side * side * side;
+            const int tot = shell_size3(r);
             bool met = false;
             for (int c0 = 0; c0 < tot; c0 += 64) {
-                int ix = c0 + lane;
-                int dx = ix % side - r, dy = (ix / side) % side - r, dz = ix / (side * side) - r;
-                int ch = max(abs(dx), max(abs(dy), abs(dz)));
-                bool v = ix < tot && ch == r;
-                if (!__ballot(v)) continue;
+                const int ix = c0 + lane;
+                int dx = 0, dy = 0, dz = 0;
+                bool v = ix < tot;
+                if (v) shell_block3(r, ix, dx, dy, dz);
                 const int t[3] = {bc[0] + dx, bc[1] + dy, bc[2] + dz};
                 v = bb_block(A, sh, c, T, p, t, v, extra, pad, lane, met);
                 if (!__ballot(v)) continue;

@@ -437,14 +437,10 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
             sh.gs.bbhit = 0;
             sh.gs.cnt[DC_SHELLS]++;
         }
-        const int side = 2 * r + 1;
-        const int tot = side * side * side;
-        int ix = sh.gs.cur + gl;
-        dd[0] = ix % side - r;
-        dd[1] = (ix / side) % side - r;
-        dd[2] = ix / (side * side) - r;
-        int ch = max(abs(dd[0]), max(abs(dd[1]), abs(dd[2])));
-        v = ix < tot && ch == r;
+        const int tot = shell_size3(r);
+        const int ix = sh.gs.cur + gl;
+        v = ix < tot;
+        if (v) shell_block3(r, ix, dd[0], dd[1], dd[2]);
         // block bound (section 2.1.3): blocks outside a wall and blocks
         // that miss the bounding box of the balls are skipped, and a shell
         // in which every block misses it ends the search

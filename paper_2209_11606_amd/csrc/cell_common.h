@@ -10,7 +10,8 @@ namespace {
 constexpr double kMargin = 1.0 + 0x1p-30;  // radius-bound safety factor on squared distances
 constexpr int kBbMinList = 16;             // candidates of a batch that turn on the ball test in the offset list
 constexpr double kBbExtended = 9.0;        // (2R / smallest block side)^2 above which the offset list's blocks are tested
-constexpr int kMaxShell = 64;              // largest Chebyshev shell searched; beyond it the cell fails
+constexpr int kMaxShell = 1024;            // largest Chebyshev shell searched; beyond it the cell fails
+constexpr int kRingSpill2 = 32;            // 2D: rings searched by a narrow group before the cell is spilled
 
 struct PlaneD {
     double n0, n1, n2, h;
@@ -493,6 +494,57 @@ __device__ __forceinline__ bool bb_in_ext(const double ext[6], const double lo[3
     for (int d = 0; d < 3; d++)
         if (d < dim) in = in && lo[d] - pad < ext[d] && lo[d] + bs[d] + pad > -ext[3 + d];
     return in;
+}
+
+// Chebyshev shell r >= 1 of blocks, enumerated directly (24 r^2 + 2 blocks
+// in 3D, 8 r in 2D): block k of the shell at offset (dx, dy, dz).  3D: the
+// faces z = -r and z = r whole, then y = -r and y = r without their z
+// edges, then x = -r and x = r inside both.
+__device__ __forceinline__ int shell_size3(int r) { return 24 * r * r + 2; }
+
+__device__ __forceinline__ void shell_block3(int r, int k, int &dx, int &dy, int &dz)
+{
+    const int a = 2 * r + 1, b = 2 * r - 1;
+    if (k < 2 * a * a) {
+        const int f = k / (a * a), m = k - f * a * a;
+        dz = f ? r : -r;
+        dx = m % a - r;
+        dy = m / a - r;
+        return;
+    }
+    k -= 2 * a * a;
+    if (k < 2 * a * b) {
+        const int f = k / (a * b), m = k - f * a * b;
+        dy = f ? r : -r;
+        dx = m % a - r;
+        dz = m / a - (r - 1);
+        return;
+    }
+    k -= 2 * a * b;
+    const int f = k / (b * b), m = k - f * b * b;
+    dx = f ? r : -r;
+    dy = m % b - (r - 1);
+    dz = m / b - (r - 1);
+}
+
+// 2D ring: the four sides in turn, 2 r blocks each, counter-clockwise from
+// the corner (-r, -r).
+__device__ __forceinline__ void ring_block2(int r, int k, int &dx, int &dy)
+{
+    const int side = k / (2 * r), m = k - side * 2 * r;
+    if (side == 0) {
+        dx = -r + m;
+        dy = -r;
+    } else if (side == 1) {
+        dx = r;
+        dy = -r + m;
+    } else if (side == 2) {
+        dx = r - m;
+        dy = r;
+    } else {
+        dx = -r;
+        dy = r - m;
+    }
 }
 
 // Particle count of the block at unfolded block coordinates t (t[2] = 0 in
