@@ -117,3 +117,35 @@ def test_polydisperse_1m_radical(v):
     live = r["status"] != oracle.Oracle.EMPTY
     dv = np.abs(a["vol"][idx][live] - r["vol"][live])
     assert np.all(dv <= 1e-12 * r["vol"][live] + 1e-14 * s ** 3)
+
+
+def test_localized_1m_unclipped(v):
+    """The unclipped localized set at 10^7 points (998,307 cells in the
+    central cube, the paper's N_opt 49 grid 58^3): the surface cells reach
+    the walls and are finished by the block bound's shell search.  Every
+    cell finished, volumes tiling the box, Euler's formula, the one-cell and
+    grouped forms equal, and sampled cells, the 20 largest among them,
+    against the oracle."""
+    w = W.localized(10_000_000)
+    x = w["xyz"]
+    n = len(x)
+    xt = torch.from_numpy(x).to("cuda:0")
+    a = v.tessellate(xt, w["lo"], w["hi"], w["periodic"], v.VC_ALL, grid=w["grid"], cells_per_wave=1)
+    assert np.all(a["status"] == 0)
+    assert a["diag"]["fallback"] > 5000
+    assert math.fsum(a["vol"]) == pytest.approx(1.0, rel=1e-12)
+    assert np.all(a["nv"] - a["ne"] + a["nf"] == 2)
+    b = v.tessellate(xt, w["lo"], w["hi"], w["periodic"], v.VC_ALL, grid=w["grid"], cells_per_wave=2)
+    assert np.all(b["status"] <= 1)
+    for k in ("nv", "ne", "nf", "fo", "nbr_off", "nbr_ids", "nbr_sh"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.max(np.abs(a["vol"] - b["vol"]) / a["vol"]) <= 1e-12
+    big = np.argsort(a["vol"])[-20:]
+    idx = np.concatenate([big, np.random.default_rng(4).choice(n, 200, replace=False)])
+    r = oracle.Oracle(x, w["lo"], w["hi"], w["periodic"], grid=w["grid"]).cells(idx, nthreads=oracle.num_threads())
+    nb = v.neighbor_lists(a)
+    assert np.array_equal(a["nf"][idx], r["nf"]) and np.array_equal(a["nv"][idx], r["nv"])
+    assert np.array_equal(a["fo"][idx], r["fo"])
+    for t, i in enumerate(idx):
+        assert np.array_equal(nb[i], r["nbr"][t]), i
+    assert np.max(np.abs(a["vol"][idx] - r["vol"]) / r["vol"]) <= 1e-12
