@@ -52,7 +52,7 @@ def gpu_bins(v, x, lo, hi, per, **opt):
     return g, start, ids
 
 
-@pytest.mark.parametrize("case", ["walled1k", "periodic1m", "2d", "box"])
+@pytest.mark.parametrize("case", ["walled1k", "periodic1m", "2d", "box", "clustered"])
 def test_binning_equals_counting_sort(v, case):
     if case == "walled1k":
         w = W.walled_1k()
@@ -60,16 +60,23 @@ def test_binning_equals_counting_sort(v, case):
         w = W.periodic_1m()
     elif case == "2d":
         w = dict(xyz=W.uniform(300_000, 2, 1.0, 5), lo=[0, 0], hi=[1, 1], periodic=[1, 1])
+    elif case == "clustered":
+        # blocks of thousands of particles (the in-block rank is linear in
+        # the block's size per particle)
+        w = W.clustered(200_000)
     else:
         lo, hi = [-1.5, 2.0, 0.25], [0.5, 2.75, 1.75]
         x = np.array(lo) + W.uniform(50_000, 3, 1.0, 6) * (np.array(hi) - np.array(lo))
         x[:10] = np.array(hi)  # points on the upper walls go to the last block
         w = dict(xyz=x, lo=lo, hi=hi, periodic=[0, 0, 0])
     x = w["xyz"]
-    g, start, ids = gpu_bins(v, x, w["lo"], w["hi"], w["periodic"])
+    opt = {"grid": w["grid"]} if "grid" in w else {}
+    g, start, ids = gpu_bins(v, x, w["lo"], w["hi"], w["periodic"], **opt)
     rs, rid = reference_bins(x, w["lo"], w["hi"], g[:x.shape[1]])
     assert np.array_equal(start, rs)
     assert np.array_equal(ids, rid)
+    if case == "clustered":
+        assert np.diff(start).max() > 1000
 
 
 def test_block_occupancy_matches_paper(v):
