@@ -298,8 +298,8 @@ def cpu_serial(members, sample):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md and not launched.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {a.gpus}); "
+              "sharding over several GPUs is designed but not launched.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2209_11606_amd import build as hipbuild
