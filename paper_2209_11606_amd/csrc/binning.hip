@@ -8,6 +8,8 @@
 // block, so no overflow buffer is needed.  The final slot is the particle's
 // rank by id inside its block, which removes the run-to-run order dependence
 // that the paper notes for parallel insertion.
+#include <algorithm>
+
 #include "vc_internal.h"
 
 namespace vc {
@@ -230,32 +232,54 @@ __global__ __launch_bounds__(kTB) void k_fill(int32_t *p, int64_t n, int32_t v)
 }
 
 // neighbour lists: per cell, sort the labels (id, image) and copy them into
-// the CSR arrays at the cell's offset
+// the CSR arrays at the cell's offset.  A group of 16 lanes takes a cell:
+// lane l loads labels l, l + 16, l + 32, l + 48 (coalesced), the keys go to
+// the group's LDS row, and each label's place is the number of the cell's
+// keys below it (ties, which do not occur, by position).  The groups of a
+// wave only share the wave's in-order LDS stream, so no barrier spans them.
+constexpr int kNbrLanes = 16;
+constexpr int kNbrGroups = kTB / kNbrLanes;
+
 __global__ __launch_bounds__(kTB) void k_nbr_compact(const int32_t *__restrict__ nf, int64_t n,
                                                      const int32_t *__restrict__ nbr, const uint8_t *__restrict__ nsh,
                                                      const int64_t *__restrict__ off, int32_t *__restrict__ ids,
                                                      uint8_t *__restrict__ shifts)
 {
-    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+    static_assert(kMaxNbr == 4 * kNbrLanes, "four labels per lane");
+    __shared__ long long keys[kNbrGroups][kMaxNbr];
+    const int g = threadIdx.x / kNbrLanes, l = threadIdx.x % kNbrLanes;
+    for (int64_t i = (int64_t)blockIdx.x * kNbrGroups + g; i < n; i += (int64_t)gridDim.x * kNbrGroups) {
         int k = nf[i];
         if (k > kMaxNbr) k = kMaxNbr;
-        int64_t key[kMaxNbr];
-        for (int t = 0; t < k; t++)
-            key[t] = ((int64_t)nbr[i * kMaxNbr + t] << 8) | (int64_t)nsh[i * kMaxNbr + t];
-        for (int t = 1; t < k; t++) {
-            int64_t v = key[t];
-            int u = t - 1;
-            while (u >= 0 && key[u] > v) {
-                key[u + 1] = key[u];
-                u--;
+        long long mine[4];
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int t = l + s * kNbrLanes;
+            mine[s] = 0;
+            if (t < k) {
+                mine[s] = ((long long)nbr[i * kMaxNbr + t] << 8) | (long long)nsh[i * kMaxNbr + t];
+                keys[g][t] = mine[s];
             }
-            key[u + 1] = v;
         }
-        int64_t o = off[i];
-        for (int t = 0; t < k; t++) {
-            ids[o + t] = (int32_t)(key[t] >> 8);
-            shifts[o + t] = (uint8_t)(key[t] & 0xff);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        const int64_t o = off[i];
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int t = l + s * kNbrLanes;
+            if (t < k) {
+                int r = 0;
+                for (int j = 0; j < k; j++) {
+                    const long long kj = keys[g][j];
+                    r += kj < mine[s] || (kj == mine[s] && j < t);
+                }
+                ids[o + r] = (int32_t)(mine[s] >> 8);
+                shifts[o + r] = (uint8_t)(mine[s] & 0xff);
+            }
         }
+        // the row is rewritten by the group's next cell
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -345,7 +369,9 @@ hipError_t launch_nbr_compact(const int32_t *nf, int64_t n, const int32_t *nbr, 
                               int32_t *ids, uint8_t *shifts, int32_t *tmp, hipStream_t s)
 {
     (void)tmp;
-    k_nbr_compact<<<grid_for(n), kTB, 0, s>>>(nf, n, nbr, nsh, offsets, ids, shifts);
+    const int64_t groups = (n + kNbrGroups - 1) / kNbrGroups;
+    const int blocks = (int)std::min<int64_t>(std::max<int64_t>(groups, 1), 65536);
+    k_nbr_compact<<<blocks, kTB, 0, s>>>(nf, n, nbr, nsh, offsets, ids, shifts);
     return hipGetLastError();
 }
 
