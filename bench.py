@@ -170,16 +170,21 @@ def time_binning(v, torch, xt, w, steps):
                 peak_GBps=HBM_PEAK / 1e9, frac=achieved / HBM_PEAK, bound="hbm")
 
 
-def end_to_end(v, torch, xyz, w, precision, mask, reps=3):
+def end_to_end(v, torch, xyz, w, precision, mask, reps=3, launch=None):
     """Positions in pinned host memory to results in host memory: rebin from
     the host pointer (PCIe copy + binning), compute, copy every produced
-    field back.  The container and result exist beforehand."""
+    field back.  The container and result exist beforehand.  launch: the
+    tuner's choice for this set (cells per wave, slots, waves, chunk), else
+    two cells per wave in 3D."""
     import time as _t
     stream = torch.cuda.current_stream()
     host = torch.from_numpy(xyz).pin_memory()
     n, dim = xyz.shape
-    # the fastest plain form: two cells per wave in 3D
-    o = options(v, w, precision=precision, cells_per_wave=2 if dim == 3 else 0)
+    if launch:
+        form = {k: int(launch[k]) for k in ("cells_per_wave", "slots", "waves", "chunk")}
+    else:
+        form = dict(cells_per_wave=2 if dim == 3 else 0)
+    o = options(v, w, precision=precision, **form)
     c = v.vc_container_create(host, o, stream)
     if w.get("radii") is not None:
         v.vc_container_set_radii(c, w["radii"], stream)
@@ -421,7 +426,8 @@ def main():
     if len(members) == 1:
         binning = time_binning(v, torch, xt, members[0], a.steps)
         if a.workload != "periodic102m":
-            e2e = end_to_end(v, torch, xyz, members[0], v.VC_FP64, mask)
+            tuned = res.get("fp64_batched", {}).get("tuned") if dim == 3 else None
+            e2e = end_to_end(v, torch, xyz, members[0], v.VC_FP64, mask, launch=tuned)
         print(f"# binning: {binning['ms']:.3f} ms, end-to-end: {e2e and round(e2e['ms'], 3)} ms",
               file=sys.stderr, flush=True)
     serial = None
