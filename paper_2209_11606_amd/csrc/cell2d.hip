@@ -544,11 +544,10 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
             cnt[DC_SHELLS]++;
             const int tot = 8 * r;
             bool met = false;
-            for (int c0 = 0; c0 < tot; c0 += G) {
-                const int ix = c0 + gl;
-                int dx = 0, dy = 0;
-                bool v = ix < tot;
-                if (v) ring_block2(r, ix, dx, dy);
+            // the spill kernel's lanes take four blocks each per step, so the
+            // particle counts of a far ring are loaded four at a time
+            constexpr int U = G == 64 ? 4 : 1;
+            for (int c0 = 0; c0 < tot; c0 += U * G) {
                 // the bounding box of the discs, then the discs for the
                 // non-empty blocks
                 double ext[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -557,30 +556,56 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
                     if ((c.live[s] >> gl) & 1) bb_ext_add(ext, c.vx[s], c.vy[s], 0.0, extra);
 #pragma unroll
                 for (int k = 0; k < 6; k++) ext[k] = g2max<G>(ext[k]);
-                const int t[3] = {bc[0] + dx, bc[1] + dy, 0};
-                double blo[3] = {0.0, 0.0, 0.0};
+                int qdx[U], qdy[U], qn[U];
+                bool any = false;
 #pragma unroll
-                for (int d = 0; d < 2; d++) {
-                    if (!Gr.per[d] && (t[d] < 0 || t[d] >= Gr.g[d])) v = false;
-                    blo[d] = Gr.lo[d] + t[d] * Gr.bs[d] - p[d];
+                for (int u = 0; u < U; u++) {
+                    const int ix = c0 + u * G + gl;
+                    int dx = 0, dy = 0;
+                    bool v = ix < tot;
+                    if (v) ring_block2(r, ix, dx, dy);
+                    const int t[3] = {bc[0] + dx, bc[1] + dy, 0};
+                    double blo[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int d = 0; d < 2; d++) {
+                        if (!Gr.per[d] && (t[d] < 0 || t[d] >= Gr.g[d])) v = false;
+                        blo[d] = Gr.lo[d] + t[d] * Gr.bs[d] - p[d];
+                    }
+                    v = v && bb_in_ext(ext, blo, Gr.bs, pad, 2);
+                    any = any || gb2<G>(v, gb);
+                    qdx[u] = dx;
+                    qdy[u] = dy;
+                    qn[u] = v ? 1 : 0;
                 }
-                v = v && bb_in_ext(ext, blo, Gr.bs, pad, 2);
-                if (!gb2<G>(v, gb)) continue;
+                if (!any) continue;
                 met = true;
-                v = v && bb_block_count<2>(A.start, T, t) > 0;
-                if (!gb2<G>(v, gb)) continue;
-                int nv = 0;
 #pragma unroll
-                for (int s = 0; s < S; s++) {
-                    const unsigned long long m = c.live[s];
-                    if ((m >> gl) & 1) bb_put(bbl, nv + __popcll(m & ((1ull << gl) - 1ull)), c.vx[s], c.vy[s], 0.0, extra);
-                    nv += __popcll(m);
+                for (int u = 0; u < U; u++) {
+                    if (qn[u]) {
+                        const int t[3] = {bc[0] + qdx[u], bc[1] + qdy[u], 0};
+                        qn[u] = bb_block_count<2>(A.start, T, t);
+                    }
                 }
-                lds_sync2();
-                v = v && bb_meets(bbl, nv, blo, Gr.bs, pad, 2);
-                if (!gb2<G>(v, gb)) continue;
-                int st = p_gather<G, S, MAXL, F32>(A, sh, c, T, si, p, bc, dx, dy, v, ws, cnt, lane, gl, gb);
-                if (st != ST_OK) return st;
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    bool v = qn[u] > 0;
+                    if (!gb2<G>(v, gb)) continue;
+                    int nv = 0;
+#pragma unroll
+                    for (int s = 0; s < S; s++) {
+                        const unsigned long long m = c.live[s];
+                        if ((m >> gl) & 1)
+                            bb_put(bbl, nv + __popcll(m & ((1ull << gl) - 1ull)), c.vx[s], c.vy[s], 0.0, extra);
+                        nv += __popcll(m);
+                    }
+                    lds_sync2();
+                    const double blo[3] = {Gr.lo[0] + (bc[0] + qdx[u]) * Gr.bs[0] - p[0],
+                                           Gr.lo[1] + (bc[1] + qdy[u]) * Gr.bs[1] - p[1], 0.0};
+                    v = v && bb_meets(bbl, nv, blo, Gr.bs, pad, 2);
+                    if (!gb2<G>(v, gb)) continue;
+                    int st = p_gather<G, S, MAXL, F32>(A, sh, c, T, si, p, bc, qdx[u], qdy[u], v, ws, cnt, lane, gl, gb);
+                    if (st != ST_OK) return st;
+                }
             }
             if (!met) break;
         }
@@ -706,8 +731,10 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
     return ne > kMaxNbr ? ST_CAP : ST_OK;
 }
 
+// two waves per SIMD (the register allocator is held to that budget): the
+// spill kernel's far ring searches need the waves more than the registers
 template <int G, int S, int MAXL, bool F32, bool RAD>
-__global__ __launch_bounds__(64) void k_cells2d(CellArgs Ain, int spill_mode)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_cells2d(CellArgs Ain, int spill_mode)
 {
     // the Voronoi instantiation carries no radical code: its rad pointer is
     // a compile-time null
