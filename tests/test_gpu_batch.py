@@ -128,3 +128,28 @@ def test_batch_argument_errors(v):
     with pytest.raises(v.VcError) as e:
         v.vc_batch_create(xyz, bad, opts)
     assert e.value.code == v.VC_E_ARG
+
+
+def test_full_size_periodic_1m_bench_path(v):
+    """The benchmark's own launch path on its workload: the 1M periodic set
+    as a one-member batch, tuned, computed eagerly and by two graph
+    replays, in both precisions.  Every replay equals the eager result bit
+    for bit; sampled cells equal the oracle; the volumes tile the box."""
+    import math
+    from test_gpu_parity import assert_parity
+    w = W.periodic_1m()
+    x = np.ascontiguousarray(w["xyz"])
+    n = len(x)
+    offsets = np.array([0, n], np.int64)
+    idx = np.random.default_rng(11).choice(n, 1000, replace=False)
+    r = oracle.Oracle(x, w["lo"], w["hi"], w["periodic"]).cells(idx, nthreads=oracle.num_threads())
+    for precision in (v.VC_FP64, v.VC_F32_FILTER):
+        eager, replays, tuned = batch_run(v, [w], offsets, x, graph_replays=2, tune=True, precision=precision)
+        print("bench path", precision, tuned, flush=True)
+        for res in replays:
+            for k in ("vol", "cen", "nv", "ne", "nf", "fo", "status", "nbr_off", "nbr_ids", "nbr_sh"):
+                assert np.array_equal(res[k], eager[k]), k
+        assert np.all(eager["status"] == 0)
+        assert math.fsum(eager["vol"]) == pytest.approx(100.0 ** 3, rel=1e-12)
+        eager["nbr"] = v.neighbor_lists(eager)
+        assert_parity(eager, r, idx)

@@ -175,8 +175,10 @@ def test_grouped_forms_on_hard_inputs(v, cpw):
 
 
 def test_full_size_periodic_1m(v):
-    """The 1M-particle periodic workload in the benchmark's launch
-    configuration: sampled cells against the oracle, invariants over all."""
+    """The 1M-particle periodic workload of the benchmark in a plain
+    container (two cells per wave): sampled cells against the oracle,
+    invariants over all (the batched, tuned path of the benchmark is tested
+    in test_gpu_batch.py)."""
     w = W.periodic_1m()
     x = w["xyz"]
     g = run(v, x, w["lo"], w["hi"], w["periodic"])
