@@ -86,11 +86,10 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def committed_traffic(key):
-    """HBM bytes per launch of the cell kernel, from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE, each divided by what the
-    counter reads for a device copy of known size).  None when the summary
-    has no entry for this kernel or was taken on other kernel sources."""
+def committed_counters(key):
+    """The committed counter summary's entry for this kernel (traffic, VALU
+    busy fraction, waiting fraction), or None when it has none or was taken
+    on other kernel sources."""
     try:
         text = open(COUNTERS).read()
     except OSError:
@@ -102,7 +101,16 @@ def committed_traffic(key):
     e = data.get("kernels", {}).get(key)
     if not e or data.get("source_sha256") != sources_sha256():
         return None
-    return e["traffic_bytes"]
+    return e
+
+
+def committed_traffic(key):
+    """HBM bytes per launch of the cell kernel, from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each divided by what the
+    counter reads for a device copy of known size).  None when the summary
+    has no entry for this kernel or was taken on other kernel sources."""
+    e = committed_counters(key)
+    return e["traffic_bytes"] if e else None
 
 
 def _timed(torch, stream, steps, step_fn):
@@ -449,12 +457,16 @@ def main():
         achieved = n * flops_per_cell / (b["kernel_ms"] / 1e3)
         key = kernel_key("fp64" if best.startswith("fp64") else "f32_filter", b.get("tuned"))
         traffic = committed_traffic(key) if a.workload == "periodic1m" else None
+        ctr = committed_counters(key) if a.workload == "periodic1m" else None
         # the published peak, confirmed on this device by an FMA microbenchmark
         measured = {"fp64": v.vc_device_fma_rate(v.VC_FP64), "fp32_unpacked": v.vc_device_fma_rate(v.VC_F32_FILTER)}
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=FP64_VECTOR_PEAK / 1e12, unit="TFLOP/s",
                     frac=achieved / FP64_VECTOR_PEAK, traffic=traffic,
                     kernel="cell construction (" + key + ")", flops_per_cell=flops_per_cell,
-                    kernel_ms=b["kernel_ms"], measured_fma_peak=measured)
+                    kernel_ms=b["kernel_ms"], measured_fma_peak=measured,
+                    # issue-side utilisation from the same counter runs: the
+                    # kernel is bound by instruction issue and latency
+                    valu_busy=ctr and ctr.get("valu_busy"), wait_frac=ctr and ctr.get("wait_frac"))
     out = {
         "metric": ("3D" if dim == 3 else "2D") + (" radical" if members[0].get("radii") is not None else "")
                   + " Voronoi cells/s on 1 MI355X, FP32-filter vs FP64 plain; "
