@@ -652,16 +652,62 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
             cnt[DC_SHELLS]++;
             const int tot = shell_size3(r);
             bool met = false;
-            for (int c0 = 0; c0 < tot; c0 += 64) {
-                const int ix = c0 + lane;
-                int dx = 0, dy = 0, dz = 0;
-                bool v = ix < tot;
-                if (v) shell_block3(r, ix, dx, dy, dz);
-                const int t[3] = {bc[0] + dx, bc[1] + dy, bc[2] + dz};
-                v = bb_block(A, sh, c, T, p, t, v, extra, pad, lane, met);
-                if (!__ballot(v)) continue;
-                int st = gather<S, MAXP, F32, K>(A, sh, c, si, p, bc, dx, dy, dz, v, ws, cnt, lane, 1, extra, pad);
-                if (st != ST_OK) return st;
+            // four chunks of 64 blocks per step: the bounding box of the
+            // balls once, then the four blocks' particle counts loaded
+            // together, then the balls and the gather chunk by chunk
+            constexpr int U = 4;
+            for (int c0 = 0; c0 < tot; c0 += U * 64) {
+                double ext[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < S; s++)
+                    if ((c.live[s] >> lane) & 1) bb_ext_add(ext, c.vx[s], c.vy[s], c.vz[s], extra);
+#pragma unroll
+                for (int k = 0; k < 6; k++) ext[k] = wave_max(ext[k]);
+                int qk[U], qn[U];
+                bool any = false;
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const int ix = c0 + u * 64 + lane;
+                    int dx = 0, dy = 0, dz = 0;
+                    bool v = ix < tot;
+                    if (v) shell_block3(r, ix, dx, dy, dz);
+                    const int t[3] = {bc[0] + dx, bc[1] + dy, bc[2] + dz};
+                    double blo[3];
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        if (!G.per[d] && (t[d] < 0 || t[d] >= G.g[d])) v = false;
+                        blo[d] = G.lo[d] + t[d] * G.bs[d] - p[d];
+                    }
+                    v = v && bb_in_ext(ext, blo, G.bs, pad, 3);
+                    any = any || __ballot(v);
+                    qk[u] = ix;
+                    qn[u] = v ? 1 : 0;
+                }
+                if (!any) continue;
+                met = true;
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    if (qn[u]) {
+                        int dx, dy, dz;
+                        shell_block3(r, qk[u], dx, dy, dz);
+                        const int t[3] = {bc[0] + dx, bc[1] + dy, bc[2] + dz};
+                        qn[u] = bb_block_count<3>(A.start, T, t);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    bool v = qn[u] > 0;
+                    if (!__ballot(v)) continue;
+                    int dx = 0, dy = 0, dz = 0;
+                    if (qk[u] < tot) shell_block3(r, qk[u], dx, dy, dz);
+                    const int nv = bb_list(sh, c, lane, extra);
+                    const double blo[3] = {G.lo[0] + (bc[0] + dx) * G.bs[0] - p[0], G.lo[1] + (bc[1] + dy) * G.bs[1] - p[1],
+                                           G.lo[2] + (bc[2] + dz) * G.bs[2] - p[2]};
+                    v = v && bb_meets(reinterpret_cast<const float4 *>(&sh.u.gc.npos[0][0]), nv, blo, G.bs, pad, 3);
+                    if (!__ballot(v)) continue;
+                    int st = gather<S, MAXP, F32, K>(A, sh, c, si, p, bc, dx, dy, dz, v, ws, cnt, lane, 1, extra, pad);
+                    if (st != ST_OK) return st;
+                }
             }
             if (!met) break;
         }
