@@ -66,6 +66,7 @@ def _load():
         lib.vo_cells.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                                  P, P, P, P, P, P, P, P, ctypes.c_int, P, P, P]
         lib.vo_set_audit.argtypes = [ctypes.c_int]
+        lib.vo_set_wb_rule.argtypes = [ctypes.c_int]
         lib.vo_exact_side.restype = ctypes.c_int
         lib.vo_exact_side.argtypes = [ctypes.c_int, P]
         lib.vo_num_threads.restype = ctypes.c_int
@@ -218,6 +219,13 @@ class Oracle:
         if k < 0:
             raise RuntimeError(f"oracle: cell computation failed with code {k}")
         return buf[:k, :self.dim].copy()
+
+
+def set_weinberg_rule(rule):
+    """Test-only: 0 restores Weinberg's walk rules; 1 plants the other
+    rotational sense at revisited vertices, 2 drops the return along the
+    arrival edge (for checks that the pins catch such mistakes)."""
+    _load().vo_set_wb_rule(int(rule))
 
 
 def num_threads():

@@ -1256,6 +1256,17 @@ static int rot(const odarts *g, int d, int o)
  * go back along the same edge unless that was already done; otherwise
  * leave by the first unused dart in the rotation after the reversed
  * arrival dart. */
+/* Test-only planted mistakes (vo_set_wb_rule): 0 = Weinberg's rules; 1 =
+ * the other rotational sense at a vertex seen before; 2 = no return along the
+ * arrival edge; 3 = the code lists the vertex each dart enters instead of the
+ * one it leaves.  The pins of the hand-derived codes must fail under each. */
+static int g_wb_rule = 0;
+
+void vo_set_wb_rule(int rule)
+{
+    g_wb_rule = rule;
+}
+
 static int weinberg_walk(const odarts *g, int d0, int o, uint8_t *code, int *lab, unsigned char *used)
 {
     for (int v = 0; v < g->nv; v++) lab[v] = 0;
@@ -1263,19 +1274,20 @@ static int weinberg_walk(const odarts *g, int d0, int o, uint8_t *code, int *lab
     int nl = 1, d = d0;
     lab[g->tail[d0]] = 1;
     for (int k = 0; k < g->nd; k++) {
-        code[k] = (uint8_t)lab[g->tail[d]];
         used[d] = 1;
+        const int v = g->head[d], r = g->rev[d], first = lab[v] == 0;
+        if (first) lab[v] = ++nl;
+        code[k] = (uint8_t)(g_wb_rule == 3 ? lab[v] : lab[g->tail[d]]);
         if (k == g->nd - 1) break;
-        int v = g->head[d], r = g->rev[d];
-        if (lab[v] == 0) {
-            lab[v] = ++nl;
+        if (first) {
             d = rot(g, r, o);
-        } else if (!used[r]) {
+        } else if (!used[r] && g_wb_rule != 2) {
             d = r;
         } else {
-            int e = rot(g, r, o), guard = 0;
+            const int so = g_wb_rule == 1 ? 1 - o : o;
+            int e = rot(g, r, so), guard = 0;
             while (used[e]) {
-                e = rot(g, e, o);
+                e = rot(g, e, so);
                 if (++guard > g->nd) return VO_ERR_TOPO;
             }
             d = e;

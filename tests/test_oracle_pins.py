@@ -621,3 +621,92 @@ def test_weinberg_invariant_under_mirror_and_axis_swap():
         i = perm[t]
         assert np.array_equal(r1["codes"][t], r0["codes"][i])
         assert r1["sym"][t] == r0["sym"][i] and r1["chiral"][t] == r0["chiral"][i]
+
+
+# Weinberg codes derived by hand (Weinberg 1966, section 5's VoroTop code).
+# Notation: a face-tracing rotation system; succ_v(u) is the neighbour that
+# follows u around v in the sense that, taken at every new vertex, walks
+# around one face.  A dart is written u>w with walk labels (vertices are
+# numbered in order of first visit); the code lists the label each dart
+# leaves (2E numbers, the final return to 1 not repeated).
+#
+# Tetrahedron (faces 123, 214, 324, 134 traced by succ): start 1>2, new 2
+# -> succ_2(1) = 3: 2>3; new 3 -> succ_3(2) = 1: 3>1; 1 seen, 1>3 unused ->
+# back 1>3; 3 seen, 3>1 used -> first unused after 1 at 3 is 4: 3>4; new 4
+# -> succ_4(3) = 1: 4>1; back 1>4; at 4 after 1: 2: 4>2; back 2>4; at 4
+# after 2: 3: 4>3; at 3 (3>4 used) after 4: 2: 3>2; at 2 (2>3 used) after
+# 3: 4 used, then 1: 2>1.  Tails: 1 2 3 1 3 4 1 4 2 4 3 2.  Every one of
+# the 12 darts in both senses gives it (24 = the tetrahedral group).
+WB_TETRA = [1, 2, 3, 1, 3, 4, 1, 4, 2, 4, 3, 2]
+# Cube (bottom a1..a4 traced a1>a2>a3>a4, top b_i above a_i; at a_i the
+# rotation is a_(i-1), a_(i+1), b_i; at b_i it is a_i, b_(i+1), b_(i-1)):
+# 1>2>3>4 around the bottom (all new), 4>1; back 1>4; at 4 after 1: b4 = 5;
+# new 5 -> b1 = 6; new 6 -> a1: 6>1; back 1>6; at 6 after 1: b2 = 7; new 7
+# -> a2: 7>2; back 2>7; at 7 after 2: b3 = 8; new 8 -> a3: 8>3; back 3>8;
+# at 8 after 3: b4 (5): 8>5; back 5>8; at 8 after 5: 7: 8>7; at 7 after 8:
+# 6: 7>6; at 6 after 7: 5: 6>5; at 5 after 6: 8 used, then a4: 5>4; at 4
+# after 5: 3: 4>3; at 3 after 4: 8 used, then 2: 3>2; at 2 after 3: 7
+# used, then 1: 2>1.  48 (dart, sense) pairs give it.
+WB_CUBE = [1, 2, 3, 4, 1, 4, 5, 6, 1, 6, 7, 2, 7, 8, 3, 8, 5, 8, 7, 6, 5, 4, 3, 2]
+# Triangular prism (triangles a1a2a3 and b1b2b3, rotations as for the cube
+# with indices mod 3).  The 36 (dart, sense) pairs fall into three orbits
+# of 12 under its symmetry group:
+#  start on a triangle, tracing it: 1>2>3>1; back 1>3; at 3 after 1: b3 = 4;
+#    new 4 -> b1 = 5; new 5 -> a1: 5>1; back 1>5; at 5 after 1: b2 = 6; new
+#    6 -> a2: 6>2; back 2>6; at 6 after 2: 4: 6>4; back 4>6; at 6 after 4:
+#    5: 6>5; at 5 after 6: 4: 5>4; at 4 after 5: 6 used, then 3: 4>3; at 3
+#    after 4: 2: 3>2; at 2 after 3: 6 used, then 1: 2>1.
+#    -> 1 2 3 1 3 4 5 1 5 6 2 6 4 6 5 4 3 2
+#  start on a triangle edge, tracing a square: 1 2 3 4 1 4 5 6 1 6 2 6 5 3 5 4 3 2
+#  start on a vertical edge:                   1 2 3 4 1 4 5 1 5 6 2 6 3 6 5 4 3 2
+# The smallest is the first; sym = 12.
+WB_PRISM = [1, 2, 3, 1, 3, 4, 5, 1, 5, 6, 2, 6, 4, 6, 5, 4, 3, 2]
+
+
+def _wb_shapes():
+    """Cells of exactly these shapes in a walled unit cube: a lone particle
+    (the cube), a particle at (0.1, 0.1, 0.5) cut by the bisector x + y = 0.4
+    (a triangular prism) and one at (0.1, 0.1, 0.1) cut by x + y + z = 0.6
+    (a tetrahedron)."""
+    cube = np.array([[0.5, 0.5, 0.5]])
+    prism = np.array([[0.1, 0.1, 0.5], [0.3, 0.3, 0.5]])
+    tetra = np.array([[0.1, 0.1, 0.1], [0.3, 0.3, 0.3]])
+    return [(tetra, 12, WB_TETRA, 24), (prism, 18, WB_PRISM, 12), (cube, 24, WB_CUBE, 48)]
+
+
+def test_weinberg_hand_derived_codes():
+    """The oracle's codes of the tetrahedron, triangular prism and cube are
+    the codes derived by hand from Weinberg's rules above, with symmetry
+    counts 24, 12 and 48 and no chirality."""
+    oracle.set_weinberg_rule(0)
+    for x, le, code, sym in _wb_shapes():
+        o = oracle.Oracle(x, [0] * 3, [1] * 3, [0, 0, 0])
+        c = o.cells(np.array([0]))
+        assert c["nf"][0] == {12: 4, 18: 5, 24: 6}[le]
+        r = o.weinberg(np.array([0]))
+        assert r["len"][0] == le
+        assert r["codes"][0].tolist() == code
+        assert r["sym"][0] == sym and r["chiral"][0] == 0
+
+
+@pytest.mark.parametrize("rule", [1, 2, 3])
+def test_weinberg_pins_catch_a_changed_rule(rule):
+    """A one-rule change planted in the oracle's walk (1: the other
+    rotational sense at a vertex seen before; 2: no return along the
+    arrival edge; 3: listing the vertex each dart enters) no longer gives
+    the hand-derived codes: 1 and 2 no longer take every dart once, 3 walks
+    but its smallest code differs."""
+    oracle.set_weinberg_rule(rule)
+    try:
+        wrong = 0
+        for x, le, code, sym in _wb_shapes():
+            o = oracle.Oracle(x, [0] * 3, [1] * 3, [0, 0, 0])
+            try:
+                r = o.weinberg(np.array([0]))
+                wrong += r["codes"][0].tolist() != code
+            except RuntimeError:
+                assert rule in (1, 2)
+                wrong += 1  # the changed walk does not take every dart once
+        assert wrong == 3
+    finally:
+        oracle.set_weinberg_rule(0)
