@@ -62,6 +62,9 @@ def parse():
     p.add_argument("--calibration-copy-mib", type=int, default=0,
                    help="first copy a device buffer of this size (reference for HBM byte counters)")
     p.add_argument("--variants", default="all", help="comma list of variants to run (default all)")
+    p.add_argument("--phase-clocks", action="store_true",
+                   help="load the library built with the grouped cell kernel's phase profile "
+                        "(python -m paper_2209_11606_amd.build --phase-clocks) and report cycles per phase")
     p.add_argument("--workload", default="periodic1m",
                    choices=["periodic1m", "batch4096", "fcc10m", "periodic2d10m", "periodic102m",
                             "localized10m", "localized10m_unclipped", "localized100k_unclipped", "localized2d10m", "clustered10m",
@@ -243,6 +246,8 @@ def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask, radii=None):
             kms.append(v.vc_result_kernel_ms(r))
         out = _summary(v, r, ms, float(np.median(kms)))
         out["tuned"] = tuned
+        if os.environ.get("VOROHIP_PHASE_CLOCKS") == "1":
+            out["phases"] = v.phase_profile(r)
     finally:
         v.vc_result_destroy(r)
         v.vc_batch_destroy(b)
@@ -314,10 +319,12 @@ def main():
         print(f"bench.py: runs on one GPU only (asked for --gpus {a.gpus}); "
               "sharding over several GPUs is designed but not launched.", file=sys.stderr)
         sys.exit(2)
+    if a.phase_clocks:
+        os.environ["VOROHIP_PHASE_CLOCKS"] = "1"
     import torch
     from paper_2209_11606_amd import build as hipbuild
-    if not os.path.exists(hipbuild.LIB):
-        hipbuild.build()
+    if not os.path.exists(hipbuild.LIB_PHASE if a.phase_clocks else hipbuild.LIB):
+        raise SystemExit("bench.py: the library is not built; run __graft_entry__.build() first")
     from paper_2209_11606_amd import vorohip as v
     from paper_2209_11606_amd import workloads as W
 
@@ -488,7 +495,7 @@ def main():
                              empty_cells=r["empty_cells"], tuned=r.get("tuned"),
                              roofline_frac=(None if flops_per_cell is None else
                                             n * flops_per_cell / (r["kernel_ms"] / 1e3) / FP64_VECTOR_PEAK),
-                             diag=r["diag"])
+                             diag=r["diag"], phases=r.get("phases"))
                      for k, r in res.items()},
         "roofline": roof,
         "binning_roofline": binning,

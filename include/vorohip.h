@@ -103,7 +103,7 @@ enum {
  * where more than three faces meet (zero-length edges merged) are single
  * vertices of higher degree. */
 #define VC_FO_LEN 32
-#define VC_DIAG_LEN 16
+#define VC_DIAG_LEN 32
 
 /* per-cell status (VC_F_STATUS) */
 enum { VC_CELL_OK = 0, VC_CELL_SPILLED = 1, VC_CELL_CAPACITY = 2, VC_CELL_DUPLICATE = 3,
@@ -125,6 +125,12 @@ enum {
                              (section 2.1.3: the block bound ends the search) */
     VC_D_LOADED = 10      /* particles loaded from the blocks (before the radius
                              and ball tests) */
+    /* slots 16..31 are written only by a library built with the phase
+       profile of the grouped cell kernel (VC_PHASE_CLOCKS): 16 + k holds the
+       shader-clock cycles its waves spent in phase k (0 claim a cell and set
+       up its box, 1 gather block counts, 2 load and sort a batch, 3 side
+       tests, 4 cuts, 5 statistics, 7 failures and loop control) and 24 + k
+       how many times the phase ran on a wave (30: side-test iterations) */
 };
 
 typedef struct {

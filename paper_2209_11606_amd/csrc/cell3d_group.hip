@@ -1135,24 +1135,67 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
     sh.gs.cell = 0;
     sh.gs.cend = 0;
     lds_fence();
+#ifdef VC_PHASE_CLOCKS
+    // wave-level shader-clock cycles and executions of each phase body
+    unsigned long long pclk[kPhaseSlots] = {}, pcnt[kPhaseSlots] = {};
+    unsigned long long t_prev = clock64();
+#define VC_PHASE_MARK(k, ran)                    \
+    do {                                         \
+        const unsigned long long t_ = clock64(); \
+        pclk[k] += t_ - t_prev;                  \
+        pcnt[k] += (ran) ? 1 : 0;                \
+        t_prev = t_;                             \
+    } while (0)
+#else
+#define VC_PHASE_MARK(k, ran) \
+    do {                      \
+    } while (0)
+#endif
     for (;;) {
+        const bool r_new = __ballot(c.phase == PH_NEW) != 0;
         if (c.phase == PH_NEW) {
             if (cnt[1] > (1u << 30) || sh.gs.cnt[DC_NEWV] > (1u << 30) || sh.gs.cnt[DC_LOADED] > (1u << 30))
                 flush_counters<G, S, MAXP>(A, sh, cnt[0], cnt[1], gl);
             ph_new<G, S, MAXP, F32>(A, sh, c, ncell, gl, gb);
         }
+        VC_PHASE_MARK(0, r_new);
         if (!__ballot(c.phase != PH_DONE)) break;
+        const bool r_gat = __ballot(c.phase == PH_GATHER) != 0;
         if (c.phase == PH_GATHER) ph_gather<G, S, MAXP, F32>(A, sh, c, gl, gb, cnt);
+        VC_PHASE_MARK(1, r_gat);
+        const bool r_bat = __ballot(c.phase == PH_BATCH) != 0;
         if (c.phase == PH_BATCH) ph_batch<G, S, MAXP, F32>(A, sh, c, gl, gb, below);
+        VC_PHASE_MARK(2, r_bat);
+#ifdef VC_PHASE_CLOCKS
+        while (c.phase == PH_TEST) {
+            ph_test<G, S, MAXP, F32>(A, sh, c, ws, cnt, lane, gl, gb);
+            pcnt[6]++;
+        }
+#else
         while (c.phase == PH_TEST) ph_test<G, S, MAXP, F32>(A, sh, c, ws, cnt, lane, gl, gb);
+#endif
+        VC_PHASE_MARK(3, true);
         // cuts and statistics wait until no group can advance without one
         if (!__ballot(c.phase == PH_NEW || c.phase == PH_GATHER || c.phase == PH_BATCH || c.phase < 0)) {
+            const bool r_cut = __ballot(c.phase == PH_CUT) != 0;
             if (c.phase == PH_CUT) ph_cut<G, S, MAXP, F32>(A, sh, c, cnt, gl, gb, below);
+            VC_PHASE_MARK(4, r_cut);
+            const bool r_st = __ballot(c.phase == PH_STATS) != 0;
             if (c.phase == PH_STATS) ph_stats<G, S, MAXP, F32>(A, sh, c, ws, cnt, lane, gl, gb, below);
+            VC_PHASE_MARK(5, r_st);
         }
         if (c.phase < 0) cell_fail<G, S, MAXP, F32>(A, sh, c, -c.phase, gl);
+        VC_PHASE_MARK(7, true);
     }
     flush_counters<G, S, MAXP>(A, sh, cnt[0], cnt[1], gl);
+#ifdef VC_PHASE_CLOCKS
+    if (lane == 0)
+        for (int k = 0; k < kPhaseSlots; k++) {
+            atomicAdd(&A.diag[kPhaseClk + k], pclk[k]);
+            atomicAdd(&A.diag[kPhaseCnt + k], pcnt[k]);
+        }
+#endif
+#undef VC_PHASE_MARK
 }
 
 }  // namespace

@@ -18,6 +18,14 @@ constexpr int kNoShift = 62;    // image code of the zero shift: 25*2 + 5*2 + 2
 constexpr int kWbStride = 384;
 constexpr int kWbMaxD = kWbStride - 3;
 constexpr int kWbMaxV = (kWbStride - 3) / 4;
+// Phase profile of the grouped cell kernel (built with -DVC_PHASE_CLOCKS
+// only): diagnostic slots kPhaseClk + k hold the shader-clock cycles the
+// waves spent in phase k (0 NEW, 1 GATHER, 2 BATCH, 3 TEST, 4 CUT, 5 STATS,
+// 7 the failure path and loop control), kPhaseCnt + k the number of times
+// the phase body ran on a wave (slot 6: TEST iterations).
+constexpr int kPhaseSlots = 8;
+constexpr int kPhaseClk = 16;
+constexpr int kPhaseCnt = 24;
 
 // One particle in the block-sorted array (32 bytes: one aligned pair of
 // 16-byte loads per lane).

@@ -11,7 +11,10 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvorohip.so")
+# VOROHIP_PHASE_CLOCKS=1 loads the build with the grouped cell kernel's phase
+# profile (python -m paper_2209_11606_amd.build --phase-clocks)
+LIB_PATH = os.path.join(_HERE, "libvorohip_phase.so" if os.environ.get("VOROHIP_PHASE_CLOCKS") == "1"
+                        else "libvorohip.so")
 
 VC_OK, VC_E_ARG, VC_E_RANGE, VC_E_DUPLICATE, VC_E_NOMEM, VC_E_HIP, VC_E_CAPACITY, VC_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 VC_CELL_OK, VC_CELL_SPILLED, VC_CELL_CAPACITY, VC_CELL_DUPLICATE, VC_CELL_SKIPPED, VC_CELL_EMPTY = 0, 1, 2, 3, 4, 5
@@ -24,9 +27,10 @@ VC_WEINBERG = 256
  VC_F_NBR_SHIFTS, VC_F_STATUS, VC_F_DIAG, VC_F_PERIMETER, VC_F_WB_OFFSETS, VC_F_WB_CODES, VC_F_WB_SYM,
  VC_F_WB_CHIRAL) = range(16)
 VC_FO_LEN = 32
-VC_DIAG_LEN = 16
+VC_DIAG_LEN = 32
 DIAG_NAMES = ["candidates", "tests", "cuts", "new_vertices", "exact", "recheck", "spilled", "blocks", "fallback",
               "shells", "loaded"]
+PHASE_NAMES = ["new", "gather", "batch", "test", "cut", "stats", "test_iterations", "control"]
 _FIELD_DTYPE = {VC_F_VOLUME: np.float64, VC_F_CENTROID: np.float64, VC_F_NV: np.int32, VC_F_NE: np.int32,
                 VC_F_NF: np.int32, VC_F_FACE_ORDERS: np.uint8, VC_F_NBR_OFFSETS: np.int64, VC_F_NBR_IDS: np.int32,
                 VC_F_NBR_SHIFTS: np.uint8, VC_F_STATUS: np.uint8, VC_F_DIAG: np.uint64, VC_F_PERIMETER: np.float64,
@@ -318,6 +322,13 @@ def fetch(r, mask, n, dim=3):
     d = vc_result_copy(r, VC_F_DIAG)
     out["diag"] = dict(zip(DIAG_NAMES, d[:len(DIAG_NAMES)].tolist()))
     return out
+
+
+def phase_profile(r):
+    """Per-phase shader-clock cycles and run counts of the grouped cell
+    kernel (only a library built with --phase-clocks writes them)."""
+    d = vc_result_copy(r, VC_F_DIAG)
+    return {"cycles": dict(zip(PHASE_NAMES, d[16:24].tolist())), "runs": dict(zip(PHASE_NAMES, d[24:32].tolist()))}
 
 
 def weinberg_codes(res):
