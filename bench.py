@@ -13,18 +13,23 @@ measures the 4,096-tessellation set instead.
 
 Prints one JSON line.  The roofline object covers the dominant kernel (the
 cell kernel): its algorithmic FP64 flops per launch -- the oracle's operation
-counts on a sample of the same workload, weighted (candidate distance 9,
-vertex side test 6, new vertex 12, fan tetrahedron 28), scaled to the cells of
-one launch -- over its HIP-event duration, against the FP64 vector peak.
-Each entry of `variants` carries the same fraction for its own cell
+counts on a sample of the same workload, weighted (every candidate's distance
+test 9, vertex side test 6, new vertex 12, fan tetrahedron 28), scaled to the
+cells of one launch -- over its HIP-event duration, against the FP64 vector
+peak.  Each entry of `variants` carries the same fraction for its own cell
 kernel (roofline_frac), so the plain FP64 and the FP32-filter forms are
 both placed against the peak.
 The cpu_baseline object times the oracle on the host cores on a bounded
-sample of the same workload; cpu_serial times it on one thread.
+sample of the same workload (with the CPU model and core counts);
+cpu_serial times it on one thread.  Each variant's `parity` compares that
+variant's own outputs of the timed run with the oracle's cells of the
+sample: volume and centroid errors (max, mean) and mismatch counts of the
+counts, face orders, overflow flags and neighbour lists.
 binning_roofline is the rebin alone (HIP events) against the HBM peak, with
-188 algorithmic bytes per particle; end_to_end is one pass from positions in
-pinned host memory to every result field in host memory (PCIe included),
-reported beside `value`, never as it.
+56 algorithmic bytes per particle (what the library moves is reported beside
+it); end_to_end is one pass from positions in pinned host memory to every
+result field in host memory (PCIe included), reported beside `value`, never
+as it.
 """
 import argparse
 import json
@@ -41,11 +46,16 @@ sys.path.insert(0, ROOT)
 COUNTERS = os.path.join(ROOT, "profiles", "cells_periodic1M_counters.md")
 KERNEL_SOURCES = ["cell3d.hip", "cell3d_group.hip", "cell_common.h", "vc_internal.h"]
 HBM_PEAK = 8.0e12  # B/s
-# rebin of one particle: device copy of the positions (24 B read + 24 B
-# written), block count (24 B read, 8 B written), provisional slot (12 B read,
-# 4 B written), rank by id and final scatter (24 B of position, 16 B of
-# index, block and range, ~20 B of the block's ids read; 32 B written)
-BIN_BYTES_PER_PARTICLE = 188
+# binning of one particle, algorithmic: its position read (24 B), its
+# block-sorted record written (24 B of position and 4 B of id) and its block
+# count (4 B): 56 B
+BIN_BYTES_PER_PARTICLE = 56
+# what the library's rebin moves per particle: device copy of the positions
+# (24 B read + 24 B written), block count (24 B read, 8 B written),
+# provisional slot (12 B read, 4 B written), rank by id and final scatter
+# (24 B of position, 16 B of index, block and range, ~20 B of the block's ids
+# read; 32 B written)
+BIN_BYTES_IMPLEMENTATION = 188
 FP64_VECTOR_PEAK = 78.6e12  # FLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FLOP_WEIGHTS = dict(candidates=9, vertex_tests=6, new_vertices=12, fan_triangles=28)
 
@@ -139,7 +149,7 @@ def options(v, w, **kw):
     return v.vc_options_init(len(w["lo"]), w["lo"], w["hi"], w["periodic"], **extra)
 
 
-def time_variant(v, torch, xt, w, precision, steps, warmup, mask):
+def time_variant(v, torch, xt, w, precision, steps, warmup, mask, sample=None):
     """Plain form: one container; step = rebin + compute."""
     stream = torch.cuda.current_stream()
     o = options(v, w, precision=precision)
@@ -158,7 +168,7 @@ def time_variant(v, torch, xt, w, precision, steps, warmup, mask):
             step()
         kms.clear()
         ms = _timed(torch, stream, steps, step)
-        out = _summary(v, r, ms, float(np.mean(kms)))
+        out = _summary(v, r, ms, float(np.mean(kms)), sample)
     finally:
         v.vc_result_destroy(r)
         v.vc_container_destroy(c)
@@ -178,7 +188,9 @@ def time_binning(v, torch, xt, w, steps):
     n = xt.shape[0]
     achieved = n * BIN_BYTES_PER_PARTICLE / (ms / 1e3)
     return dict(ms=ms, bytes_per_particle=BIN_BYTES_PER_PARTICLE, achieved_GBps=achieved / 1e9,
-                peak_GBps=HBM_PEAK / 1e9, frac=achieved / HBM_PEAK, bound="hbm")
+                peak_GBps=HBM_PEAK / 1e9, frac=achieved / HBM_PEAK, bound="hbm",
+                implementation_bytes_per_particle=BIN_BYTES_IMPLEMENTATION,
+                implementation_GBps=n * BIN_BYTES_IMPLEMENTATION / (ms / 1e3) / 1e9)
 
 
 def end_to_end(v, torch, xyz, w, precision, mask, reps=3, launch=None):
@@ -218,7 +230,7 @@ def end_to_end(v, torch, xyz, w, precision, mask, reps=3, launch=None):
                 includes="H2D of positions from pinned memory, binning, cells, compaction, D2H of every field")
 
 
-def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask, radii=None):
+def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask, radii=None, sample=None):
     """Batched form: autotuned launch parameters, compute replayed from a
     hipGraph; step = rebin + graph launch.  The cell-kernel duration for the
     roofline comes from eager launches with the same parameters."""
@@ -244,7 +256,7 @@ def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask, radii=None):
         for _ in range(3):
             v.vc_batch_compute(b, r, False, stream)
             kms.append(v.vc_result_kernel_ms(r))
-        out = _summary(v, r, ms, float(np.median(kms)))
+        out = _summary(v, r, ms, float(np.median(kms)), sample)
         out["tuned"] = tuned
         if os.environ.get("VOROHIP_PHASE_CLOCKS") == "1":
             out["phases"] = v.phase_profile(r)
@@ -254,48 +266,169 @@ def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask, radii=None):
     return out
 
 
-def _summary(v, r, ms, kernel_ms):
+def _summary(v, r, ms, kernel_ms, sample=None):
+    """Timing, status and counters of a variant; with `sample` (input
+    indices), the variant's own output fields on those cells, kept for the
+    parity check against the oracle."""
     status = v.vc_result_copy(r, v.VC_F_STATUS)
     diag = dict(zip(v.DIAG_NAMES, v.vc_result_copy(r, v.VC_F_DIAG)[:len(v.DIAG_NAMES)].tolist()))
-    ok = (status <= v.VC_CELL_SPILLED) | (status == v.VC_CELL_EMPTY)
-    return dict(ms_per_step=ms, kernel_ms=kernel_ms, status_ok=bool(np.all(ok)), diag=diag,
-                empty_cells=int(np.sum(status == v.VC_CELL_EMPTY)))
+    base = status & ~np.uint8(v.VC_CELL_FO_OVERFLOW)
+    ok = (base <= v.VC_CELL_SPILLED) | (base == v.VC_CELL_EMPTY)
+    out = dict(ms_per_step=ms, kernel_ms=kernel_ms, status_ok=bool(np.all(ok)), diag=diag,
+               empty_cells=int(np.sum(base == v.VC_CELL_EMPTY)))
+    if sample is not None:
+        n = len(status)
+
+        def get(field):
+            try:
+                return v.vc_result_copy(r, field)
+            except v.VcError:  # not in the statistics mask
+                return None
+        f = {"status": status[sample]}
+        for key, field in (("vol", v.VC_F_VOLUME), ("nv", v.VC_F_NV), ("ne", v.VC_F_NE), ("nf", v.VC_F_NF)):
+            a = get(field)
+            f[key] = None if a is None else a[sample]
+        a = get(v.VC_F_CENTROID)
+        f["cen"] = None if a is None else a.reshape(n, 3)[sample]
+        a = get(v.VC_F_FACE_ORDERS)
+        f["fo"] = None if a is None else a.reshape(n, v.VC_FO_LEN)[sample].astype(np.int32)
+        off, ids, sh = get(v.VC_F_NBR_OFFSETS), get(v.VC_F_NBR_IDS), get(v.VC_F_NBR_SHIFTS)
+        f["nbr"] = None if ids is None else [
+            np.stack([ids[off[i]:off[i + 1]].astype(np.int64), sh[off[i]:off[i + 1]].astype(np.int64)], 1)
+            for i in sample[:NBR_SAMPLE]]
+        out["fields"] = f
+    return out
+
+
+NBR_SAMPLE = 20_000  # sample cells whose neighbour lists are compared
+
+
+def parity(fields, ref, ref_nbr, offsets_of_sample):
+    """Errors of a variant's own outputs against the oracle on the sample:
+    max and mean relative volume error, max centroid error over V^(1/3)
+    (V^(1/2) in 2D), and mismatch counts of the topology fields (counts,
+    face orders, status flags) and of the sorted neighbour lists."""
+    vol_r = ref["vol"]
+    out = dict(cells=int(len(vol_r)))
+    dim = ref["cen"].shape[1]
+    if fields["vol"] is not None:
+        live = vol_r > 0
+        rel = np.abs(fields["vol"] - vol_r)[live] / vol_r[live]
+        out.update(vol_rel_err_max=float(rel.max()), vol_rel_err_mean=float(rel.mean()))
+        if fields["cen"] is not None:
+            scale = vol_r[live] ** (1.0 / dim)
+            cerr = np.abs(fields["cen"][live][:, :dim] - ref["cen"][live]).max(1) / scale
+            out.update(centroid_err_max=float(cerr.max()), centroid_err_mean=float(cerr.mean()))
+    mism = {}
+    for key in ("nv", "ne", "nf"):
+        if (dim == 2 and key == "ne") or fields[key] is None:
+            continue
+        mism[key] = int(np.sum(fields[key] != ref[key]))
+    if fields.get("fo") is not None and dim == 3:
+        mism["fo"] = int(np.sum(np.any(fields["fo"] != ref["fo"], 1)))
+    flag = 64
+    mism["fo_overflow_flag"] = int(np.sum(((fields["status"] & flag) != 0) != ((ref["status"] & flag) != 0)))
+    bad = 0
+    for t, lab in enumerate(ref_nbr if fields["nbr"] is not None else []):
+        got = fields["nbr"][t].copy()
+        base = offsets_of_sample[t]
+        got[got[:, 0] >= 0, 0] -= base  # batch ids are global
+        order = np.lexsort((got[:, 1], got[:, 0]))
+        bad += not np.array_equal(got[order], lab)
+    mism["nbr"] = int(bad)
+    out["mismatches"] = mism
+    out["nbr_cells"] = len(ref_nbr) if fields["nbr"] is not None else 0
+    out["all_equal"] = all(v_ == 0 for v_ in mism.values())
+    return out
+
+
+def host_description():
+    """CPU model, and the logical and physical cores usable by this process."""
+    cpus = sorted(os.sched_getaffinity(0))
+    model, phys, cur = None, set(), {}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if ":" not in line:
+                if cur.get("processor") is not None and int(cur["processor"]) in cpus:
+                    phys.add((cur.get("physical id", "0"), cur.get("core id", cur["processor"])))
+                cur = {}
+                continue
+            k, val = [x.strip() for x in line.split(":", 1)]
+            cur[k] = val
+            if k == "model name" and model is None:
+                model = val
+        if cur.get("processor") is not None and int(cur["processor"]) in cpus:
+            phys.add((cur.get("physical id", "0"), cur.get("core id", cur["processor"])))
+    except OSError:
+        pass
+    return dict(cpu_model=model, logical_cores=len(cpus), physical_cores=len(phys) or None)
+
+
+def sample_cells(members, sample):
+    """The oracle sample: the first cells of each member in member order, up
+    to `sample` cells; returns (member, local indices, global indices)."""
+    out, done, base = [], 0, 0
+    for t, m in enumerate(members):
+        if done >= sample:
+            break
+        k = min(sample - done, len(m["xyz"]))
+        idx = np.arange(k, dtype=np.int64)
+        out.append((t, idx, base + idx))
+        done += k
+        base += len(m["xyz"])
+    return out
 
 
 def cpu_baseline(members, sample):
     """The oracle on the host cores: the first `sample` cells of the
-    workload (in member order), OpenMP dynamic schedule over cells."""
+    workload (in member order), OpenMP dynamic schedule over cells.  Also
+    returns the oracle's cells (untimed neighbour lists for the first
+    NBR_SAMPLE of them), for the parity of every GPU variant."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     done, secs = 0, 0.0
     tot = {}
-    for m in members:
-        if done >= sample:
-            break
+    ref = {k: [] for k in ("vol", "cen", "nv", "ne", "nf", "fo", "status")}
+    ref_nbr, nbr_base = [], []
+    offsets = np.cumsum([0] + [len(m["xyz"]) for m in members])
+    for t, idx, _ in sample_cells(members, sample):
+        m = members[t]
         o = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"], grid=m.get("grid"), clip=m.get("clip", 0.0),
                           radii=m.get("radii"))
-        k = min(sample - done, len(m["xyz"]))
-        idx = np.arange(k, dtype=np.int64)
+        k = len(idx)
         if m.get("weinberg"):
             # cells and their Weinberg codes (the VoroTop pipeline); the
             # statistics pass runs untimed, for the operation counts
-            t = time.perf_counter()
+            t0 = time.perf_counter()
             o.weinberg(idx, nthreads=cores)
-            secs += time.perf_counter() - t
+            secs += time.perf_counter() - t0
             r = o.cells(idx, nthreads=cores, neighbors=False)
         else:
-            t = time.perf_counter()
+            t0 = time.perf_counter()
             r = o.cells(idx, nthreads=cores, neighbors=False)
-            secs += time.perf_counter() - t
+            secs += time.perf_counter() - t0
         done += k
         for key, val in r["counters"].items():
             tot[key] = tot.get(key, 0) + val
-    flops = (FLOP_WEIGHTS["candidates"] * (tot["candidates"] - tot["radius_rejects"])
-             + FLOP_WEIGHTS["vertex_tests"] * tot["vertex_tests"]
-             + FLOP_WEIGHTS["new_vertices"] * tot["new_vertices"]
-             + FLOP_WEIGHTS["fan_triangles"] * tot["fan_triangles"]) / done
+        for key in ref:
+            ref[key].append(r[key])
+        need = NBR_SAMPLE - len(ref_nbr)
+        if need > 0:
+            ref_nbr += o.cells(idx[:need], nthreads=cores)["nbr"]
+            nbr_base += [int(offsets[t])] * min(need, k)
+    ref = {key: np.concatenate(val) for key, val in ref.items()}
+    # every candidate's distance test is counted (9 flops each); the reading
+    # without the candidates the radius bound rejects is reported beside it
+    rest = (FLOP_WEIGHTS["vertex_tests"] * tot["vertex_tests"]
+            + FLOP_WEIGHTS["new_vertices"] * tot["new_vertices"]
+            + FLOP_WEIGHTS["fan_triangles"] * tot["fan_triangles"])
+    flops = (FLOP_WEIGHTS["candidates"] * tot["candidates"] + rest) / done
+    flops_in_range = (FLOP_WEIGHTS["candidates"] * (tot["candidates"] - tot["radius_rejects"]) + rest) / done
     per_cell = {k: val / done for k, val in tot.items()}
-    return dict(value=done / secs, unit="cells/s", cores=cores, kind="oracle", seconds=secs), flops, per_cell
+    per_cell["flops_without_radius_rejects"] = flops_in_range
+    cpu = dict(value=done / secs, unit="cells/s", cores=cores, kind="oracle", seconds=secs)
+    cpu.update(host_description())
+    return cpu, flops, per_cell, (ref, ref_nbr, np.array(nbr_base, np.int64))
 
 
 def cpu_serial(members, sample):
@@ -426,15 +559,18 @@ def main():
     if a.variants != "all":
         keep = set(a.variants.split(","))
         variants = [x for x in variants if x[0] in keep]
+    sample = None
+    if not a.no_cpu_baseline:
+        sample = np.concatenate([g for _, _, g in sample_cells(members, a.cpu_sample)])
     for name, prec, batched in variants:
         if batched:
             opts = [options(v, m, precision=prec) for m in members]
             radii = None
             if members[0].get("radii") is not None:
                 radii = np.concatenate([m["radii"] for m in members])
-            res[name] = time_batched(v, torch, xt, offsets, opts, a.steps, a.warmup, mask, radii)
+            res[name] = time_batched(v, torch, xt, offsets, opts, a.steps, a.warmup, mask, radii, sample)
         else:
-            res[name] = time_variant(v, torch, xt, members[0], prec, a.steps, a.warmup, mask)
+            res[name] = time_variant(v, torch, xt, members[0], prec, a.steps, a.warmup, mask, sample)
         print(f"# {name}: {res[name]['ms_per_step']:.3f} ms/step, cell kernel {res[name]['kernel_ms']:.3f} ms, "
               f"tuned {res[name].get('tuned')}, diag {res[name]['diag']}", file=sys.stderr, flush=True)
     binning = e2e = None
@@ -449,7 +585,12 @@ def main():
     if a.no_cpu_baseline:
         cpu, flops_per_cell = None, None
     else:
-        cpu, flops_per_cell, per_cell = cpu_baseline(members, a.cpu_sample)
+        cpu, flops_per_cell, per_cell, (ref, ref_nbr, nbr_base) = cpu_baseline(members, a.cpu_sample)
+        for name in res:
+            f = res[name].pop("fields", None)
+            if f is not None:
+                res[name]["parity"] = parity(f, ref, ref_nbr, nbr_base)
+                print(f"# {name} parity: {res[name]['parity']}", file=sys.stderr, flush=True)
         if dim == 2:
             flops_per_cell = None  # the flop model is the 3D one
         cpu["sample"] = sample_desc.format(min(a.cpu_sample, n)) + ", OpenMP dynamic,64 over cells"
@@ -470,6 +611,9 @@ def main():
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=FP64_VECTOR_PEAK / 1e12, unit="TFLOP/s",
                     frac=achieved / FP64_VECTOR_PEAK, traffic=traffic,
                     kernel="cell construction (" + key + ")", flops_per_cell=flops_per_cell,
+                    flops_per_cell_reading="every candidate's distance test counted (9), vertex side tests (6), "
+                                           "new vertices (12), fan tetrahedra (28), from the oracle's counts",
+                    flops_per_cell_without_radius_rejects=per_cell.get("flops_without_radius_rejects"),
                     kernel_ms=b["kernel_ms"], measured_fma_peak=measured,
                     # issue-side utilisation from the same counter runs: the
                     # kernel is bound by instruction issue and latency
@@ -495,12 +639,13 @@ def main():
                              empty_cells=r["empty_cells"], tuned=r.get("tuned"),
                              roofline_frac=(None if flops_per_cell is None else
                                             n * flops_per_cell / (r["kernel_ms"] / 1e3) / FP64_VECTOR_PEAK),
-                             diag=r["diag"], phases=r.get("phases"))
+                             diag=r["diag"], phases=r.get("phases"), parity=r.get("parity"))
                      for k, r in res.items()},
         "roofline": roof,
         "binning_roofline": binning,
         "end_to_end": e2e,
         "cpu_baseline": cpu,
+        "oracle_work_per_cell": None if a.no_cpu_baseline else per_cell,
         "cpu_serial": serial,
     }
     print(json.dumps(out), flush=True)

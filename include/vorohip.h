@@ -108,7 +108,12 @@ enum {
 /* per-cell status (VC_F_STATUS) */
 enum { VC_CELL_OK = 0, VC_CELL_SPILLED = 1, VC_CELL_CAPACITY = 2, VC_CELL_DUPLICATE = 3,
        VC_CELL_SKIPPED = 4, /* not in the list of vc_compute_subset */
-       VC_CELL_EMPTY = 5    /* radical tessellation: the cell has no volume */ };
+       VC_CELL_EMPTY = 5,   /* radical tessellation: the cell has no volume */
+       /* flag bit, OR-ed into VC_CELL_OK or VC_CELL_SPILLED: the cell is
+          complete but one of its faces has VC_FO_LEN (32) or more edges, so
+          the face-order vector does not count that face and sums to less
+          than the face count (the other fields are exact) */
+       VC_CELL_FO_OVERFLOW = 64 };
 
 /* diagnostic counters (VC_F_DIAG) */
 enum {
@@ -148,6 +153,12 @@ typedef struct {
                             centred on its particle, cut to the box (section 3.1.3:
                             clipped cells); faces of the clip cube are labelled
                             -7..-12 (x-, x+, y-, y+, z-, z+); 0: the whole box */
+    int capacity;        /* vertex capacity of the main cell kernel: a cell that would
+                            hold more vertices moves to the large-capacity spill pass
+                            (the overflow policy of section 2.2.5 applied to cells);
+                            0: the kernel's own capacity (slots x lanes); a value below
+                            4 in 3D (3 in 2D), fewer than any cut cell has, sends every
+                            cell that is cut at all to the pass */
 } vc_options;
 
 typedef struct vc_container vc_container;

@@ -103,9 +103,12 @@ class Oracle:
     clip > 0 clips every cell by the cube of that side centred on its
     particle (section 3.1.3).  radii (n values) makes it the radical
     tessellation of the polydisperse container (section 2.1.1); a cell that
-    comes out empty has status 1 (EMPTY) and zero volume, counts and faces."""
+    comes out empty has status 1 (EMPTY) and zero volume, counts and faces.
+    A complete cell with a face of 32 or more edges has the status flag 64
+    (FO_OVER): its face-order vector does not count that face."""
 
     EMPTY = 1
+    FO_OVER = 64  # status flag: a face has 32 or more edges, fo does not count it
 
     def __init__(self, xyz, lo, hi, periodic, grid=None, n_opt=5.0, clip=0.0, radii=None):
         lib = _load()

@@ -80,7 +80,7 @@ def _planes(xyz, i, lo, hi, periodic, clip=0.0, radii=None):
 def cell(xyz, i, lo, hi, periodic, clip=0.0, radii=None):
     """Exact cell of particle i (clipped by the cube of side `clip` centred
     on the particle when clip > 0; the radical cell when radii are given).
-    Returns dict(vol, cen, nv, ne, nf, fo, nbr, empty) with vol and cen as
+    Returns dict(vol, cen, nv, ne, nf, fo, nbr, empty, sizes) with vol and cen as
     Fractions and nbr sorted (label, image) pairs."""
     xyz = np.asarray(xyz, dtype=np.float64)
     dim = xyz.shape[1]
@@ -190,7 +190,9 @@ def _stats(verts, planes, dim):
     cen = [c / vol for c in cen]
     nbr = sorted((planes[k][2], planes[k][3]) for k in faces)
     ne = len(edges)
-    return dict(vol=vol, cen=cen, nv=nv, ne=ne if dim == 3 else nv, nf=len(faces), fo=fo, nbr=nbr, empty=False)
+    sizes = sorted(len(vs) for vs in faces.values())
+    return dict(vol=vol, cen=cen, nv=nv, ne=ne if dim == 3 else nv, nf=len(faces), fo=fo, nbr=nbr, empty=False,
+                sizes=sizes)
 
 
 def _ring(pts, normal):

@@ -971,7 +971,12 @@ typedef struct {
     double vol, cen[3], perim;
     int nv, ne, nf;
     int fo[VO_FO];
+    int fo_over; /* a face has VO_FO or more edges: fo does not count it */
 } ostats;
+
+/* status flag of a complete cell with a face of VO_FO or more edges (its
+ * face-order vector then sums to less than F) */
+#define VO_FO_OVER 64
 
 /* statistics of a finished 3D cell: volume and centroid from the tetrahedra
  * (origin, f0, fk, fk+1) of a fan over each face; V, E, F; face orders */
@@ -980,6 +985,7 @@ static void stats3(ocell *c, ostats *st, int32_t *nbr, int32_t *nsh, int maxnb)
     double vol = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
     int e2 = 0;
     memset(st->fo, 0, sizeof(st->fo));
+    st->fo_over = 0;
     /* tetrahedra (o, f0, fk, fk+1) from the particle (o = 0) when it lies
      * strictly inside the cell (every face offset h > 0: always so for a
      * Voronoi cell), else from one vertex of the cell, so that every term is
@@ -1008,6 +1014,7 @@ static void stats3(ocell *c, ostats *st, int32_t *nbr, int32_t *nsh, int maxnb)
         }
         e2 += n;
         if (n < VO_FO) st->fo[n]++;
+        else st->fo_over = 1;
         if (nbr && f < maxnb) {
             nbr[f] = c->pl[c->fplane[f]].label;
             nsh[f] = c->pl[c->fplane[f]].shift;
@@ -1125,7 +1132,9 @@ int vo_cells(const vo_handle *H, const int64_t *idx, int64_t m, int nthreads, do
             ostats st;
             int32_t *nb = nbr ? nbr + (size_t)t * maxnb : NULL;
             int32_t *ns = nsh ? nsh + (size_t)t * maxnb : NULL;
+            st.fo_over = 0;
             if (H->dim == 3) stats3(c, &st, nb, ns, maxnb); else stats2(c, &st, nb, ns, maxnb);
+            if (status && st.fo_over) status[t] |= VO_FO_OVER;
             if (vol) vol[t] = st.vol;
             if (cen) for (int d = 0; d < 3; d++) cen[3 * t + d] = st.cen[d];
             if (nv) nv[t] = st.nv;

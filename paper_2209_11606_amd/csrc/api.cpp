@@ -69,41 +69,67 @@ bool is_device_ptr(const void *p)
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
-// Block offsets up to Chebyshev radius kOffRadius, nearest first: by the
-// integer gap metric m, then by centre distance in block units, then
-// lexicographically (so the order is fixed).
+// Block offsets up to Chebyshev radius kOffRadius in nearest-first order for
+// a particle in the lower half of its block along every axis (the kernels
+// reflect the offsets per axis so that a particle's own half is that lower
+// half): by the expected squared gap to the block, then by centre distance,
+// then lexicographically (so the order is fixed).  With the particle uniform
+// on [0, 1/2) of a block side, the expected squared gap along one axis, in
+// twelfths of a squared side, is 0 for d = 0, 12a^2 + 6a + 1 for d = -(a+1)
+// (the near side) and 12d^2 - 6d + 1 for d > 0 (the far side).
+//
+// Each entry carries the stopping bound of the search (section 2.1.3): the
+// smallest guaranteed squared gap, in quarters of a squared block side, over
+// it and every later entry.  In the reflected frame the gap along an axis is
+// at least (|d| - 1) sides on the near side and (d - 1/2) sides on the far
+// side, so one axis contributes 4 (|d| - 1)^2 or (2d - 1)^2 quarters.  Blocks
+// outside the list (Chebyshev radius kOffRadius + 1 and beyond) are at least
+// kOffRadius sides away, so the bound is capped at 4 kOffRadius^2: stopping
+// at an entry then also covers every block beyond the list, and a cell
+// reaching farther searches the whole list and goes on shell by shell.
 std::vector<Offset> build_offsets(int dim)
 {
-    struct E { int m, c, dx, dy, dz; };
+    struct E { int g, e, c, dx, dy, dz; };
+    auto eg = [](int d) {
+        if (d == 0) return 0;
+        if (d < 0) {
+            const int a = -d - 1;
+            return 12 * a * a + 6 * a + 1;
+        }
+        return 12 * d * d - 6 * d + 1;
+    };
+    auto gq = [](int d) {
+        if (d == 0) return 0;
+        if (d < 0) return 4 * (-d - 1) * (-d - 1);
+        return (2 * d - 1) * (2 * d - 1);
+    };
     std::vector<E> v;
     int rz = dim == 3 ? kOffRadius : 0;
     for (int dz = -rz; dz <= rz; dz++)
         for (int dy = -kOffRadius; dy <= kOffRadius; dy++)
             for (int dx = -kOffRadius; dx <= kOffRadius; dx++) {
                 int d[3] = {dx, dy, dz};
-                int m = 0, c = 0;
+                int g = 0, c = 0, e = 0;
                 for (int k = 0; k < 3; k++) {
-                    int t = std::max(std::abs(d[k]) - 1, 0);
-                    m += t * t;
+                    g += gq(d[k]);
                     c += d[k] * d[k];
+                    e += eg(d[k]);
                 }
-                v.push_back({m, c, dx, dy, dz});
+                v.push_back({g, e, c, dx, dy, dz});
             }
     std::sort(v.begin(), v.end(), [](const E &a, const E &b) {
-        if (a.m != b.m) return a.m < b.m;
+        if (a.e != b.e) return a.e < b.e;
         if (a.c != b.c) return a.c < b.c;
         if (a.dz != b.dz) return a.dz < b.dz;
         if (a.dy != b.dy) return a.dy < b.dy;
         return a.dx < b.dx;
     });
-    // The search stops at the first entry whose gap bound reaches 2R.  Blocks
-    // outside the list (Chebyshev radius kOffRadius + 1 and beyond) have a gap
-    // of at least kOffRadius block sides, so the bound stored with each entry
-    // is capped there: stopping at an entry then also covers every block
-    // beyond the list, and a cell reaching farther searches the whole list and
-    // goes on shell by shell.  The cap keeps the list sorted.
-    std::vector<Offset> out;
-    for (auto &e : v) out.push_back(Offset{e.dx, e.dy, e.dz, std::min(e.m, kOffRadius * kOffRadius)});
+    std::vector<Offset> out(v.size());
+    int rest = 4 * kOffRadius * kOffRadius;
+    for (size_t i = v.size(); i-- > 0;) {
+        rest = std::min(rest, v[i].g);
+        out[i] = Offset{v[i].dx, v[i].dy, v[i].dz, rest};
+    }
     return out;
 }
 
@@ -123,6 +149,7 @@ vc_status check_options(const vc_options *o)
     if (o->cells_per_wave != 0 && o->cells_per_wave != 1 && o->cells_per_wave != 2 && o->cells_per_wave != 4)
         return fail(VC_E_ARG, "options: cells_per_wave must be 0, 1, 2 or 4");
     if (!std::isfinite(o->clip) || o->clip < 0.0) return fail(VC_E_ARG, "options: clip must be finite and >= 0");
+    if (o->capacity < 0) return fail(VC_E_ARG, "options: capacity must be >= 0");
     return VC_OK;
 }
 
@@ -161,6 +188,7 @@ Grid size_grid(const vc_options &o, int64_t n)
 
 struct Launch {
     int slots = 2, waves = 0, chunk = 4, cpw = 1;
+    int vcap = 0;  // vertex capacity before the spill pass (0: the kernel's own)
 };
 
 }  // namespace
@@ -335,6 +363,7 @@ vc_status create_common(vc_container *c, const double *xyz, const int64_t *offse
     c->launch.slots = opts[0].slots > 0 ? opts[0].slots : 2;
     c->launch.chunk = opts[0].chunk > 0 ? opts[0].chunk : 4;
     c->launch.cpw = opts[0].cells_per_wave > 0 ? opts[0].cells_per_wave : 1;
+    c->launch.vcap = opts[0].capacity;
     int cu = device_cu_count();
     c->launch.waves = opts[0].waves > 0 ? opts[0].waves : cu * 16;
     c->max_waves = std::max(c->launch.waves, cu * 32);
@@ -442,6 +471,7 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
 {
     CellArgs A = cell_args(c, r);
     A.chunk = L.chunk;
+    A.vcap = L.vcap;
     if (cell_list) {
         A.cell_list = cell_list;
         A.ncell = ncell;
@@ -461,6 +491,7 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
     B.ncell_dev = c->queue + 2;
     B.ncell = (int)c->n;
     B.chunk = 1;
+    B.vcap = 0;
     if (c->dim == 2) HIP_TRY(launch_cells2d_spill(B, std::min(c->max_waves, 1024), s));
     else HIP_TRY(launch_cells_spill(B, std::min(c->max_waves, 1024), s));
     if (r->mask & VC_WEINBERG) {

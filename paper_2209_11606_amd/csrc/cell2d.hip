@@ -305,6 +305,12 @@ __device__ __forceinline__ int p_consider(const CellArgs &A, L2<G, S, MAXL> &sh,
 #pragma unroll
     for (int s = 0; s < S; s++) nfree += __popcll((~c.live[s] | conf[s]) & (G == 64 ? ~0ull : ((1ull << G) - 1ull)));
     if (nfree < 2) return ST_CAP;
+    if (A.vcap > 0) {
+        int keep = 0;
+#pragma unroll
+        for (int s = 0; s < S; s++) keep += __popcll(c.live[s] & ~conf[s]);
+        if (keep + 2 > A.vcap) return ST_CAP;
+    }
     if (gl == 0) {
         sh.lq[p][0] = q0;
         sh.lq[p][1] = q1;
@@ -455,13 +461,14 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
     const Grid &Gr = T.G;
     const double p[2] = {me.x, me.y};
     const int id = me.id;
-    int bc[2];
+    int bc[2], fl[2];
     double mrg[2];
 #pragma unroll
     for (int d = 0; d < 2; d++) {
         bc[d] = block_coord(Gr, p[d], d);
         double blo = Gr.lo[d] + bc[d] * Gr.bs[d];
         mrg[d] = fmin(p[d] - blo, blo + Gr.bs[d] - p[d]);
+        fl[d] = offset_flip(Gr, p[d], bc[d], d);
     }
     Poly<S, F32> c;
     c.ri = A.rad ? A.rad[si] : 0.0;
@@ -509,14 +516,14 @@ __device__ __forceinline__ int poly_run(const CellArgs &A, L2<G, S, MAXL> &sh, i
 
     bool finished = false;
     for (int o0 = 0; o0 < A.noff; o0 += G) {
-        if (A.offs[o0].m * T.bsmin2 >= c.lim) {
+        if (A.offs[o0].m * 0.25 * T.bsmin2 >= c.lim) {
             finished = true;
             break;
         }
         int o = o0 + gl;
         bool v = o < A.noff;
         Offset of = v ? A.offs[o] : Offset{0, 0, 0, 0};
-        int st = p_gather<G, S, MAXL, F32>(A, sh, c, T, si, p, bc, of.dx, of.dy, v, ws, cnt, lane, gl, gb);
+        int st = p_gather<G, S, MAXL, F32>(A, sh, c, T, si, p, bc, of.dx * fl[0], of.dy * fl[1], v, ws, cnt, lane, gl, gb);
         if (st != ST_OK) return st;
     }
     // beyond the list: whole Chebyshev rings, until the radius bound holds or

@@ -280,6 +280,12 @@ __device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &
 #pragma unroll
     for (int s = 0; s < S; s++) nfree += __popcll(~c.live[s] | conf[s]);
     if (m > nfree || m > S * 64 + 8) return ST_CAP;
+    if (A.vcap > 0) {
+        int keep = 0;
+#pragma unroll
+        for (int s = 0; s < S; s++) keep += __popcll(c.live[s] & ~conf[s]);
+        if (keep + m > A.vcap) return ST_CAP;
+    }
 #pragma unroll
     for (int s = 0; s < S; s++) {
 #pragma unroll
@@ -542,13 +548,14 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     const Grid &G = T.G;
     const double p[3] = {me.x, me.y, me.z};
     const int id = me.id;
-    int bc[3];
+    int bc[3], fl[3];
     double mrg[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
         bc[d] = block_coord(G, p[d], d);
         double blo = G.lo[d] + bc[d] * G.bs[d];
         mrg[d] = fmin(p[d] - blo, blo + G.bs[d] - p[d]);
+        fl[d] = offset_flip(G, p[d], bc[d], d);
     }
     Cell<S, MAXP, F32> c;
     c.ri = A.rad ? A.rad[si] : 0.0;
@@ -617,13 +624,16 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     // blocks go through the block bound too
     bool finished = false;
     for (int o0 = 0; o0 < A.noff; o0 += 64) {
-        if (A.offs[o0].m * T.bsmin2 >= c.lim) {
+        if (A.offs[o0].m * 0.25 * T.bsmin2 >= c.lim) {
             finished = true;
             break;
         }
         int o = o0 + lane;
         bool v = o < A.noff;
         Offset of = v ? A.offs[o] : Offset{0, 0, 0, 0};
+        of.dx *= fl[0];
+        of.dy *= fl[1];
+        of.dz *= fl[2];
         if (o0 > 0 && c.lim > kBbExtended * T.bsmin2) {
             bool met = false;
             const int t[3] = {bc[0] + of.dx, bc[1] + of.dy, bc[2] + of.dz};
@@ -851,7 +861,7 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     __syncthreads();
     // faces with at least three distinct vertices are the cell's faces
     int nface = 0, sumord = 0, rk = 0;
-    bool capfail = false;
+    bool capfail = false, foover = false;
     for (int k0 = 0; k0 < MAXP; k0 += 64) {
         int k = k0 + lane;
         int ord = k < MAXP ? sh.forder[k] : 0;
@@ -869,6 +879,7 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         }
         rk += __popcll(rb);
         sumord += wave_isum(real ? ord : 0);
+        foover = foover || __ballot(real && ord >= kFoLen) != 0;
     }
     nface = rk;
     if (nface > kMaxNbr) capfail = true;
@@ -896,7 +907,7 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         if (A.nf) A.nf[id] = nface;
     }
     if (A.fo && lane < kFoLen) A.fo[(int64_t)id * kFoLen + lane] = (uint8_t)min(sh.fo[lane], 255);
-    return capfail ? ST_CAP : ST_OK;
+    return capfail ? ST_CAP : (foover ? ST_FO_OVER : ST_OK);
 }
 
 // two waves per SIMD for the main kernels (the register allocator is held
@@ -930,6 +941,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MAXP == 48 ?
         for (int ci = base; ci < end; ci++) {
             int si = A.cell_list ? A.cell_list[ci] : ci;
             int st = cell_run<S, MAXP, F32, K>(A, sh, si, ws, cnt);
+            const int fov = st & ST_FO_OVER;
+            st &= ~ST_FO_OVER;
             if (st != ST_OK && A.fo && lane < kFoLen) A.fo[(int64_t)A.part[si].id * kFoLen + lane] = 0;
             if (lane == 0) {
                 int id = A.part[si].id;
@@ -947,7 +960,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MAXP == 48 ?
                 if (st == ST_EMPTY) {
                     A.status[id] = (uint8_t)ST_EMPTY;
                 } else if (st == ST_OK) {
-                    A.status[id] = spill_mode ? 1 : 0;
+                    A.status[id] = (uint8_t)((spill_mode ? 1 : 0) | fov);
                 } else if (st == ST_DUP) {
                     A.status[id] = 3;
                 } else if (!spill_mode) {

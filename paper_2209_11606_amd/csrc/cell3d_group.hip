@@ -150,6 +150,7 @@ __device__ __forceinline__ int gballot_scan(int v, int gb, uint32_t below, int &
 struct GState {
     double p[3];            // the particle
     int bc[3];              // its block
+    int fl[3];              // reflection of the block offsets per axis (+1 or -1)
     int si, id;             // sorted index, input index
     double ri;              // the particle's radius (radical tessellation), else 0
     int shell;              // 0: offset list; r > 0: Chebyshev shell r
@@ -157,32 +158,37 @@ struct GState {
     int bbhit;              // a block of the current shell met the bounding box of the block bound
     int gtot, gc0;          // candidates of the gather, next batch start
     int cell, cend;         // claimed range of the work queue
+    int tcur;               // the tessellation whose record is in the group's Tess
     uint32_t cnt[DC_N];     // counters other than candidates and tests
 };
 
-template <int G, int S, int MAXP>
+// RAD: the radical tessellation's arrays (plane and candidate radii) are
+// held only by its instantiation, which keeps the Voronoi one's LDS small
+// enough for three waves per SIMD
+template <int G, int S, int MAXP, bool RAD>
 struct SL {
     GState gs;
     Tess T;                 // the cell's tessellation
     double pq[MAXP][4];     // planes n.r = h (n = q for a bisector, h = |q|^2 / 2)
-    double prj[MAXP];       // radius of each plane's neighbour (radical planes)
+    double prj[RAD ? MAXP : 1];  // radius of each plane's neighbour (radical planes)
     int32_t plab[MAXP];
     uint8_t psh[MAXP];
     uint8_t pwall[MAXP];
     uint8_t etab[MAXP][MAXP];  // slot of the triangle holding directed edge a->b
     union alignas(16) {
         struct {               // the search
-            double cq[G][4];   // the batch's candidates, nearest first: q, |q|^2
-            double ch[G];      // their plane offsets h
-            double crj[G];     // their radii (radical planes)
+            double cq[G][6];   // the batch's candidates, nearest first: q, |q|^2, plane
+                               // offset h, FP64 side-test band
+            double crj[RAD ? G : 1];  // their radii (radical planes)
             int32_t cid[G];
             int32_t cpre[G];   // the gather's blocks: candidates before, first particle, image code
             int32_t cbeg[G];
-            uint8_t csh[G];
+            uint16_t csh[G];   // the gather's blocks: image code | shifts + 2 in 3-bit fields << 7
             uint8_t ccode[G];
             uint16_t bedge[G * S + 8];
             union {
-                unsigned long long key[G];
+                uint32_t key[G];            // ranking keys (BATCH only)
+                float cfb[G];               // then: the FP32 side-test bands (FP32 filter)
             } x;
         } w;
         struct {               // the statistics of the finished cell
@@ -196,8 +202,8 @@ struct SL {
     } u;
 };
 
-template <int G, int S, int MAXP>
-__device__ __forceinline__ PlaneD splane(const SL<G, S, MAXP> &sh, int k)
+template <class SLT>
+__device__ __forceinline__ PlaneD splane(const SLT &sh, int k)
 {
     PlaneD p;
     p.n0 = sh.pq[k][0];
@@ -208,15 +214,15 @@ __device__ __forceinline__ PlaneD splane(const SL<G, S, MAXP> &sh, int k)
     return p;
 }
 
-template <int G, int S, int MAXP>
-__device__ __forceinline__ PlaneR splane_r(const SL<G, S, MAXP> &sh, int k)
+template <class SLT>
+__device__ __forceinline__ PlaneR splane_r(const SLT &sh, int k)
 {
     return PlaneR{splane(sh, k), sh.gs.ri, sh.prj[k]};
 }
 
 // exact side of plane p at the vertex of planes (a, b, c), radical or not
-template <int G, int S, int MAXP>
-__device__ __forceinline__ int sside3(const SL<G, S, MAXP> &sh, bool rad, uint32_t t3, int p, double *ws)
+template <class SLT>
+__device__ __forceinline__ int sside3(const SLT &sh, bool rad, uint32_t t3, int p, double *ws)
 {
     const int a = t3 & 0xff, b = (t3 >> 8) & 0xff, c = (t3 >> 16) & 0xff;
     if (rad) return exact_side3(splane_r(sh, a), splane_r(sh, b), splane_r(sh, c), splane_r(sh, p), ws);
@@ -270,8 +276,8 @@ __device__ __forceinline__ void update_radius(SCell<S, F32> &c, int gl, const Ce
     c.lim = search_lim(R2, c.R, A, ri);
 }
 
-template <int G, int S, int MAXP, bool F32>
-__device__ __forceinline__ void cell_fail(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, int st, int gl)
+template <int G, int S, int MAXP, bool F32, bool RAD>
+__device__ __forceinline__ void cell_fail(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, int st, int gl)
 {
     const int id = sh.gs.id;
     if (A.fo)
@@ -296,8 +302,8 @@ __device__ __forceinline__ void cell_fail(const CellArgs &A, SL<G, S, MAXP> &sh,
 }
 
 // ---- NEW: claim the next cell and set up the box (Eq. 1-2) ----
-template <int G, int S, int MAXP, bool F32>
-__device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, int ncell, int gl,
+template <int G, int S, int MAXP, bool F32, bool RAD>
+__device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, int ncell, int gl,
                                        int gb)
 {
     if (sh.gs.cell >= sh.gs.cend) {
@@ -320,15 +326,23 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP> &sh, SC
     sh.gs.p[0] = me.x;
     sh.gs.p[1] = me.y;
     sh.gs.p[2] = me.z;
-    {
+    if (me.tess != sh.gs.tcur) {
+        // cells come in block order, so the record changes once per
+        // tessellation of a batch
         const int32_t *src = (const int32_t *)&A.tess[me.tess];
         int32_t *dst = (int32_t *)&sh.T;
         for (int k = gl; k < (int)(sizeof(Tess) / 4); k += G) dst[k] = src[k];
+        lds_fence();
+        sh.gs.tcur = me.tess;
     }
     lds_fence();
     const Grid &G3 = sh.T.G;
 #pragma unroll
-    for (int d = 0; d < 3; d++) sh.gs.bc[d] = block_coord(G3, sh.gs.p[d], d);
+    for (int d = 0; d < 3; d++) {
+        const int k = block_coord(G3, sh.gs.p[d], d);
+        sh.gs.bc[d] = k;
+        sh.gs.fl[d] = offset_flip(G3, sh.gs.p[d], k, d);
+    }
     if (gl < 6) {
         // face 2d + side of the box (Eq. 1-2, clipped as in section 3.1.3)
         const int d = gl >> 1, side = gl & 1;
@@ -337,7 +351,7 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP> &sh, SC
         sh.pwall[gl] = (uint8_t)b.wall;
         sh.plab[gl] = b.lab;
         sh.psh[gl] = b.code;
-        sh.prj[gl] = sh.gs.ri;  // the own images carry the own radius
+        if (RAD) sh.prj[gl] = sh.gs.ri;  // the own images carry the own radius
         sh.pq[gl][0] = d == 0 ? b.nd : 0.0;
         sh.pq[gl][1] = d == 1 ? b.nd : 0.0;
         sh.pq[gl][2] = d == 2 ? b.nd : 0.0;
@@ -387,8 +401,8 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP> &sh, SC
 }
 
 // ---- GATHER: particle counts of the next (up to) G blocks ----
-template <int G, int S, int MAXP, bool F32>
-__device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, int gl, int gb,
+template <int G, int S, int MAXP, bool F32, bool RAD>
+__device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, int gl, int gb,
                                           uint32_t *cnt)
 {
     const Tess &T = sh.T;
@@ -401,16 +415,16 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
             sh.gs.shell = A.off_radius + 1;
             sh.gs.cur = 0;
             sh.gs.cnt[DC_FALLBACK]++;
-        } else if (A.offs[sh.gs.cur].m * T.bsmin2 >= lim) {
+        } else if (A.offs[sh.gs.cur].m * 0.25 * T.bsmin2 >= lim) {
             c.phase = PH_STATS;  // no block left in the offset list can hold a cutting particle
             return;
         } else {
             int o = sh.gs.cur + gl;
             v = o < A.noff;
             Offset of = v ? A.offs[o] : Offset{0, 0, 0, 0};
-            dd[0] = of.dx;
-            dd[1] = of.dy;
-            dd[2] = of.dz;
+            dd[0] = of.dx * sh.gs.fl[0];
+            dd[1] = of.dy * sh.gs.fl[1];
+            dd[2] = of.dz * sh.gs.fl[2];
             sh.gs.cur += G;
         }
     }
@@ -537,7 +551,8 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
     if (total == 0) return;  // stay in GATHER: next blocks
     sh.u.w.cpre[gl] = incl - cntb;
     sh.u.w.cbeg[gl] = beg;
-    sh.u.w.csh[gl] = (uint8_t)(25 * (sv[2] + 2) + 5 * (sv[1] + 2) + (sv[0] + 2));
+    sh.u.w.csh[gl] = (uint16_t)((25 * (sv[2] + 2) + 5 * (sv[1] + 2) + (sv[0] + 2)) |
+                                (((sv[0] + 2) | ((sv[1] + 2) << 3) | ((sv[2] + 2) << 6)) << 7));
     lds_fence();
     sh.gs.gtot = total;
     sh.gs.gc0 = 0;
@@ -545,8 +560,8 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP> &sh,
 }
 
 // ---- BATCH: the next G particles of the gather, sorted by distance ----
-template <int G, int S, int MAXP, bool F32>
-__device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, int gl, int gb,
+template <int G, int S, int MAXP, bool F32, bool RAD>
+__device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, int gl, int gb,
                                          uint32_t below)
 {
     if (sh.gs.gc0 >= sh.gs.gtot) {
@@ -555,7 +570,7 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP> &sh, 
     }
     const Grid &G3 = sh.T.G;
     const int ci = sh.gs.gc0 + gl;
-    unsigned long long key = ~0ull;
+    uint32_t key = ~0u;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, d2 = 0.0, h = 0.0, rj = 0.0;
     int pid = 0, code = 0;
     if (ci < sh.gs.gtot) {
@@ -566,8 +581,9 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP> &sh, 
             else hi = mid - 1;
         }
         int idx = sh.u.w.cbeg[lo] + (ci - sh.u.w.cpre[lo]);
-        code = sh.u.w.csh[lo];
-        int s0 = code % 5 - 2, s1 = (code / 5) % 5 - 2, s2 = code / 25 - 2;
+        const int cs = sh.u.w.csh[lo];
+        code = cs & 0x7f;
+        const int s0 = ((cs >> 7) & 7) - 2, s1 = ((cs >> 10) & 7) - 2, s2 = ((cs >> 13) & 7) - 2;
         Particle q = A.part[idx];
         a0 = q.x - sh.gs.p[0];
         a1 = q.y - sh.gs.p[1];
@@ -586,14 +602,15 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP> &sh, 
             h = 0.5 * d2;
         }
         bool self = (idx == sh.gs.si) && code == kNoShift;
-        // unique keys: the distance with its low five bits replaced by the
-        // lane; candidates closer than 32 ulps may swap, which the radius
-        // margin (2^-30) absorbs when the batch is cut short
+        // unique 32-bit keys: the high word of the distance (its exponent and
+        // 20 mantissa bits) with the low five bits replaced by the lane, so
+        // candidates closer than 2^-15 relative may swap; TEST ends a batch
+        // only past that resolution
         if (!self && d2 < c.lim)
-            key = (__builtin_bit_cast(unsigned long long, d2) & ~31ull) | (unsigned long long)gl;
+            key = ((uint32_t)(__builtin_bit_cast(unsigned long long, d2) >> 32) & ~31u) | (uint32_t)gl;
     }
     // the valid keys, compacted; each counts the smaller ones
-    const bool valid = key != ~0ull;
+    const bool valid = key != ~0u;
     const uint32_t gv = gbal<G>(valid, gb);
     const int bn = __popc(gv);
     if (valid) sh.u.w.x.key[__popc(gv & below)] = key;
@@ -602,14 +619,21 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP> &sh, 
     if (valid && bn > 1)
         for (int j = 0; j < bn; j++) rank += sh.u.w.x.key[j] < key;
     if (valid) {
+        // side-test bands with the radius bound of now: R only shrinks, so
+        // a band taken now stays wide enough for every later test
+        const double band = A.tau * ((fabs(a0) + fabs(a1) + fabs(a2)) * c.R + fabs(h));
         sh.u.w.cq[rank][0] = a0;
         sh.u.w.cq[rank][1] = a1;
         sh.u.w.cq[rank][2] = a2;
         sh.u.w.cq[rank][3] = d2;
-        if (A.rad) {
-            sh.u.w.ch[rank] = h;
-            sh.u.w.crj[rank] = rj;
+        sh.u.w.cq[rank][4] = h;
+        sh.u.w.cq[rank][5] = band;
+        if (F32) {
+            const float g0 = (float)a0, g1 = (float)a1, g2 = (float)a2, gh = (float)h;
+            sh.u.w.x.cfb[rank] =
+                0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + fabsf(gh));
         }
+        if (RAD) sh.u.w.crj[rank] = rj;
         sh.u.w.cid[rank] = pid;
         sh.u.w.ccode[rank] = (uint8_t)code;
     }
@@ -617,15 +641,19 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP> &sh, 
     sh.gs.gc0 += G;
     c.bn = bn;
     c.bk = 0;
-    if (bn) c.phase = PH_TEST;
+    // a candidate at distance zero (a coincident particle) sorts first
+    if (gbal<G>(valid && d2 == 0.0, gb)) c.phase = -ST_DUP;
+    else if (bn) c.phase = PH_TEST;
 }
 
 // ---- TEST: side of every vertex against the next candidate ----
-// Side masks are whole-wave ballots (only the testing groups' lanes are
-// active), so the per-slot work is three FMAs and two compares; a group's
-// bits are taken out only when it has a conflict and parks in CUT.
-template <int G, int S, int MAXP, bool F32>
-__device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, double *ws,
+// Side masks are whole-wave compares (only the testing groups' lanes are
+// active, and a dead slot's lane is masked by the live mask), so the
+// per-slot work is three FMAs and two compares; a group's bits are taken
+// out only when it has a conflict and parks in CUT.  The candidate's
+// offset and bands were set by BATCH.
+template <int G, int S, int MAXP, bool F32, bool RAD>
+__device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, double *ws,
                                         uint32_t *cnt, int lane, int gl, int gb)
 {
     if (c.bk >= c.bn) {
@@ -634,53 +662,51 @@ __device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP> &sh, S
     }
     const int k = c.bk;
     const double q0 = sh.u.w.cq[k][0], q1 = sh.u.w.cq[k][1], q2 = sh.u.w.cq[k][2], d2 = sh.u.w.cq[k][3];
-    if (!(d2 < c.lim)) {
-        c.phase = PH_BATCH;  // sorted: the rest of the batch is farther still
+    const double h = sh.u.w.cq[k][4], band = sh.u.w.cq[k][5];
+    // issue the candidate's three LDS reads together, ahead of the range test
+    __asm__ volatile("" ::: "memory");
+    if (d2 * (1.0 - 0x1p-14) >= c.lim) {
+        // sorted to within 2^-15: the rest of the batch is beyond the
+        // radius bound too (a candidate just beyond it is tested and cuts
+        // nothing)
+        c.phase = PH_BATCH;
         return;
     }
     cnt[0]++;
-    if (d2 == 0.0) {
-        c.phase = -ST_DUP;
-        return;
-    }
     const bool rad = A.rad != nullptr;
-    const double h = rad ? sh.u.w.ch[k] : 0.5 * d2;
-    const double band = A.tau * ((fabs(q0) + fabs(q1) + fabs(q2)) * c.R + fabs(h));
     unsigned long long wc[S], wi[S], wz[S];
     if (F32) {
-        const float g0 = (float)q0, g1 = (float)q1, g2 = (float)q2, gh = (float)h;
-        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + fabsf(gh));
+        const float g0 = (float)q0, g1 = (float)q1, g2 = (float)q2, gh = (float)h, band32 = sh.u.w.x.cfb[k];
         unsigned long long wu[S], wun = 0;
 #pragma unroll
         for (int s = 0; s < S; s++) {
-            const bool lv = (c.live[s] >> gl) & 1;
+            const unsigned long long lv = __builtin_amdgcn_ballot_w64((c.live[s] >> gl) & 1);
             wc[s] = wu[s] = wi[s] = 0;
-            if (!__builtin_amdgcn_ballot_w64(lv)) continue;
-            float sv = fmaf(g0, c.fx[s], fmaf(g1, c.fy[s], fmaf(g2, c.fz[s], -gh)));
-            wc[s] = __builtin_amdgcn_ballot_w64(lv && sv > band32);
-            wu[s] = __builtin_amdgcn_ballot_w64(lv && !(sv > band32) && !(sv < -band32));
+            if (!lv) continue;
+            const float sv = fmaf(g0, c.fx[s], fmaf(g1, c.fy[s], fmaf(g2, c.fz[s], -gh)));
+            wc[s] = lv & __builtin_amdgcn_fcmpf(sv, band32, 2);             // sv > band
+            wu[s] = lv & __builtin_amdgcn_fcmpf(fabsf(sv), band32, 13);     // |sv| <= band or NaN
             wun |= wu[s];
         }
         if (wun) {
 #pragma unroll
             for (int s = 0; s < S; s++) {
                 if (!wu[s]) continue;
-                const bool u = (wu[s] >> lane) & 1;
-                double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
-                wc[s] |= __builtin_amdgcn_ballot_w64(u && sv > band);
-                wi[s] = __builtin_amdgcn_ballot_w64(u && !(sv > band) && !(sv < -band));
+                const double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
+                wc[s] |= wu[s] & __builtin_amdgcn_fcmp(sv, band, 2);
+                wi[s] = wu[s] & __builtin_amdgcn_fcmp(fabs(sv), band, 13);
                 sh.gs.cnt[DC_RECHECK] += __popc((uint32_t)(wu[s] >> gb) & Gw<G>::FULL);
             }
         }
     } else {
 #pragma unroll
         for (int s = 0; s < S; s++) {
-            const bool lv = (c.live[s] >> gl) & 1;
+            const unsigned long long lv = __builtin_amdgcn_ballot_w64((c.live[s] >> gl) & 1);
             wc[s] = wi[s] = 0;
-            if (!__builtin_amdgcn_ballot_w64(lv)) continue;
-            double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
-            wc[s] = __builtin_amdgcn_ballot_w64(lv && sv > band);
-            wi[s] = __builtin_amdgcn_ballot_w64(lv && !(sv > band) && !(sv < -band));
+            if (!lv) continue;
+            const double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
+            wc[s] = lv & __builtin_amdgcn_fcmp(sv, band, 2);         // sv > band
+            wi[s] = lv & __builtin_amdgcn_fcmp(fabs(sv), band, 13);  // |sv| <= band or NaN
         }
     }
     cnt[1] += c.nlive;
@@ -739,8 +765,8 @@ __device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP> &sh, S
 }
 
 // ---- CUT: remove the conflict region, fan new triangles around the plane ----
-template <int G, int S, int MAXP, bool F32>
-__device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, uint32_t *cnt,
+template <int G, int S, int MAXP, bool F32, bool RAD>
+__device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, uint32_t *cnt,
                                        int gl, int gb, uint32_t below)
 {
     const int k = c.bk;
@@ -796,6 +822,15 @@ __device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP> &sh, SC
         c.phase = -ST_CAP;
         return;
     }
+    if (A.vcap > 0) {
+        int keep = 0;
+#pragma unroll
+        for (int s = 0; s < S; s++) keep += __popc(c.live[s] & ~c.conf[s]);
+        if (keep + m > A.vcap) {
+            c.phase = -ST_CAP;
+            return;
+        }
+    }
 #pragma unroll
     for (int s = 0; s < S; s++) {
 #pragma unroll
@@ -811,12 +846,8 @@ __device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP> &sh, SC
         sh.pq[p][0] = sh.u.w.cq[k][0];
         sh.pq[p][1] = sh.u.w.cq[k][1];
         sh.pq[p][2] = sh.u.w.cq[k][2];
-        if (A.rad) {
-            sh.pq[p][3] = sh.u.w.ch[k];
-            sh.prj[p] = sh.u.w.crj[k];
-        } else {
-            sh.pq[p][3] = 0.5 * sh.u.w.cq[k][3];
-        }
+        sh.pq[p][3] = sh.u.w.cq[k][4];
+        if (RAD) sh.prj[p] = sh.u.w.crj[k];
         sh.plab[p] = sh.u.w.cid[k];
         sh.psh[p] = sh.u.w.ccode[k];
         sh.pwall[p] = 0;
@@ -875,8 +906,8 @@ __device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP> &sh, SC
 }
 
 // ---- STATS: volume, centroid, V/E/F, face orders, neighbours ----
-template <int G, int S, int MAXP, bool F32>
-__device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, SCell<S, F32> &c, double *ws,
+template <int G, int S, int MAXP, bool F32, bool RAD>
+__device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, double *ws,
                                          uint32_t *cnt, int lane, int gl, int gb, uint32_t below)
 {
     const int id = sh.gs.id;
@@ -1027,6 +1058,7 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
     }
     lds_fence();
     int rk = 0, sumord = 0;
+    bool foover = false;
     for (int k0 = 0; k0 < MAXP; k0 += G) {
         int k = k0 + gl;
         int ord = k < MAXP ? sh.u.st.forder[k] : 0;
@@ -1042,13 +1074,14 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
         }
         rk += __popc(rb);
         sumord += gisum<G>(real ? ord : 0);
+        foover = foover || gbal<G>(real && ord >= kFoLen, gb) != 0u;
     }
     const int nface = rk;
     const double vol6 = gsum<G>(v6);
     const double M0 = gsum<G>(m0), M1 = gsum<G>(m1), M2 = gsum<G>(m2);
     lds_fence();
     if (nface > kMaxNbr) {
-        cell_fail<G, S, MAXP, F32>(A, sh, c, ST_CAP, gl);
+        cell_fail<G, S, MAXP, F32, RAD>(A, sh, c, ST_CAP, gl);
         return;
     }
     int wl = 0;
@@ -1071,7 +1104,7 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
         if (A.nv) A.nv[id] = nvert;
         if (A.ne) A.ne[id] = sumord / 2;
         if (A.nf) A.nf[id] = nface;
-        A.status[id] = 0;
+        A.status[id] = (uint8_t)(foover ? ST_FO_OVER : ST_OK);
     }
     if (A.fo)
         for (int k = gl; k < kFoLen; k += G) A.fo[(int64_t)id * kFoLen + k] = (uint8_t)min(sh.u.st.fo[k], 255);
@@ -1080,8 +1113,8 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP> &sh, 
 }
 
 // candidates and tests are counted in registers, the rest in the group's LDS
-template <int G, int S, int MAXP>
-__device__ __forceinline__ void flush_counters(const CellArgs &A, SL<G, S, MAXP> &sh, uint32_t &ncand,
+template <int G, int S, int MAXP, bool RAD>
+__device__ __forceinline__ void flush_counters(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, uint32_t &ncand,
                                                uint32_t &ntest, int gl)
 {
     sh.gs.cnt[DC_CAND] += ncand;
@@ -1121,11 +1154,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
     }
     static_assert(((G * S) & (G * S - 1)) == 0 && G * S <= 256, "slot count must be a power of two");
     static_assert(G == 16 || G == 32, "group width");
-    __shared__ SL<G, S, MAXP> shv[Gw<G>::CPW];
+    __shared__ SL<G, S, MAXP, RAD> shv[Gw<G>::CPW];
     const int lane = __lane_id();
     const int gl = lane % G, gb = lane - gl;
     const uint32_t below = (1u << gl) - 1u;
-    SL<G, S, MAXP> &sh = shv[lane / G];
+    SL<G, S, MAXP, RAD> &sh = shv[lane / G];
     double *ws = A.xscratch + (size_t)blockIdx.x * A.xscratch_len;
     uint32_t cnt[2] = {0, 0};  // candidates, vertex tests
     const int ncell = A.ncell;
@@ -1134,6 +1167,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
     if (gl < DC_N) sh.gs.cnt[gl] = 0;
     sh.gs.cell = 0;
     sh.gs.cend = 0;
+    sh.gs.tcur = -1;
     lds_fence();
 #ifdef VC_PHASE_CLOCKS
     // wave-level shader-clock cycles and executions of each phase body
@@ -1146,48 +1180,51 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
         pcnt[k] += (ran) ? 1 : 0;                \
         t_prev = t_;                             \
     } while (0)
+#define VC_PHASE_RAN(ph) (__ballot(c.phase == (ph)) != 0)
 #else
+#define VC_PHASE_RAN(ph) false
 #define VC_PHASE_MARK(k, ran) \
     do {                      \
+        (void)(ran);          \
     } while (0)
 #endif
     for (;;) {
-        const bool r_new = __ballot(c.phase == PH_NEW) != 0;
+        const bool r_new = VC_PHASE_RAN(PH_NEW);
         if (c.phase == PH_NEW) {
             if (cnt[1] > (1u << 30) || sh.gs.cnt[DC_NEWV] > (1u << 30) || sh.gs.cnt[DC_LOADED] > (1u << 30))
-                flush_counters<G, S, MAXP>(A, sh, cnt[0], cnt[1], gl);
-            ph_new<G, S, MAXP, F32>(A, sh, c, ncell, gl, gb);
+                flush_counters<G, S, MAXP, RAD>(A, sh, cnt[0], cnt[1], gl);
+            ph_new<G, S, MAXP, F32, RAD>(A, sh, c, ncell, gl, gb);
         }
         VC_PHASE_MARK(0, r_new);
         if (!__ballot(c.phase != PH_DONE)) break;
-        const bool r_gat = __ballot(c.phase == PH_GATHER) != 0;
-        if (c.phase == PH_GATHER) ph_gather<G, S, MAXP, F32>(A, sh, c, gl, gb, cnt);
+        const bool r_gat = VC_PHASE_RAN(PH_GATHER);
+        if (c.phase == PH_GATHER) ph_gather<G, S, MAXP, F32, RAD>(A, sh, c, gl, gb, cnt);
         VC_PHASE_MARK(1, r_gat);
-        const bool r_bat = __ballot(c.phase == PH_BATCH) != 0;
-        if (c.phase == PH_BATCH) ph_batch<G, S, MAXP, F32>(A, sh, c, gl, gb, below);
+        const bool r_bat = VC_PHASE_RAN(PH_BATCH);
+        if (c.phase == PH_BATCH) ph_batch<G, S, MAXP, F32, RAD>(A, sh, c, gl, gb, below);
         VC_PHASE_MARK(2, r_bat);
 #ifdef VC_PHASE_CLOCKS
         while (c.phase == PH_TEST) {
-            ph_test<G, S, MAXP, F32>(A, sh, c, ws, cnt, lane, gl, gb);
+            ph_test<G, S, MAXP, F32, RAD>(A, sh, c, ws, cnt, lane, gl, gb);
             pcnt[6]++;
         }
 #else
-        while (c.phase == PH_TEST) ph_test<G, S, MAXP, F32>(A, sh, c, ws, cnt, lane, gl, gb);
+        while (c.phase == PH_TEST) ph_test<G, S, MAXP, F32, RAD>(A, sh, c, ws, cnt, lane, gl, gb);
 #endif
         VC_PHASE_MARK(3, true);
         // cuts and statistics wait until no group can advance without one
         if (!__ballot(c.phase == PH_NEW || c.phase == PH_GATHER || c.phase == PH_BATCH || c.phase < 0)) {
-            const bool r_cut = __ballot(c.phase == PH_CUT) != 0;
-            if (c.phase == PH_CUT) ph_cut<G, S, MAXP, F32>(A, sh, c, cnt, gl, gb, below);
+            const bool r_cut = VC_PHASE_RAN(PH_CUT);
+            if (c.phase == PH_CUT) ph_cut<G, S, MAXP, F32, RAD>(A, sh, c, cnt, gl, gb, below);
             VC_PHASE_MARK(4, r_cut);
-            const bool r_st = __ballot(c.phase == PH_STATS) != 0;
-            if (c.phase == PH_STATS) ph_stats<G, S, MAXP, F32>(A, sh, c, ws, cnt, lane, gl, gb, below);
+            const bool r_st = VC_PHASE_RAN(PH_STATS);
+            if (c.phase == PH_STATS) ph_stats<G, S, MAXP, F32, RAD>(A, sh, c, ws, cnt, lane, gl, gb, below);
             VC_PHASE_MARK(5, r_st);
         }
-        if (c.phase < 0) cell_fail<G, S, MAXP, F32>(A, sh, c, -c.phase, gl);
+        if (c.phase < 0) cell_fail<G, S, MAXP, F32, RAD>(A, sh, c, -c.phase, gl);
         VC_PHASE_MARK(7, true);
     }
-    flush_counters<G, S, MAXP>(A, sh, cnt[0], cnt[1], gl);
+    flush_counters<G, S, MAXP, RAD>(A, sh, cnt[0], cnt[1], gl);
 #ifdef VC_PHASE_CLOCKS
     if (lane == 0)
         for (int k = 0; k < kPhaseSlots; k++) {
@@ -1196,6 +1233,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
         }
 #endif
 #undef VC_PHASE_MARK
+#undef VC_PHASE_RAN
 }
 
 }  // namespace

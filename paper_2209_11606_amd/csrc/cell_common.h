@@ -455,7 +455,21 @@ __device__ __forceinline__ double search_lim(double R2, double R, const CellArgs
     return l * l * kMargin;
 }
 
+// Reflection of the nearest-first block offsets along axis d: -1 when the
+// particle lies in the upper half of its block k, so that the list's near
+// side (negative offsets come first within a gap class) is the particle's
+// near side.  The gap classes are symmetric, so the order stays nearest
+// first in the guaranteed gap.
+__device__ __forceinline__ int offset_flip(const Grid &G, double x, int k, int d)
+{
+    const double blo = G.lo[d] + k * G.bs[d];
+    return (x - blo) * 2.0 > G.bs[d] ? -1 : 1;
+}
+
 enum { ST_OK = 0, ST_CAP = 1, ST_DUP = 3, ST_EMPTY = 5 };
+// status flag of a complete cell with a face of kFoLen or more edges: the
+// face-order vector does not count that face
+constexpr int ST_FO_OVER = 64;
 
 // ---------------------------------------------------------------------------
 // Block bound (section 2.1.3).  A particle at q (relative to the cell's

@@ -68,11 +68,13 @@ struct Tess {
     double clip_half; // half the side of the clip cube (section 3.1.3), 0: none
 };
 
-// Block offset relative to a particle's own block.  m = sum over axes of
-// max(|d|-1, 0)^2 is the squared gap to that block in units of the block
-// side, so m * bsmin2 bounds the distance from any point of the own block
-// from below; it is stored capped at kOffRadius^2, the smallest such bound of
-// any block outside the list.  The list is sorted by m (nearest first).
+// Block offset relative to a particle's own block, for a particle in the
+// lower half of its block along every axis (the kernels reflect the offsets
+// per axis to make it so).  m / 4 * bsmin2 bounds from below the squared
+// distance from the particle to this block and to every block after it in
+// the list, and to every block outside the list (m is in quarters of a
+// squared block side); the list is in nearest-first order of the expected
+// gap.
 struct Offset {
     int dx, dy, dz, m;
 };
@@ -90,6 +92,7 @@ struct CellArgs {
     const int32_t *cell_list;  // sorted indices to compute (NULL: 0..ncell-1)
     int32_t *queue;            // work-queue head (zeroed before the launch)
     int chunk;                 // cells per queue grab
+    int vcap;                  // > 0: a cell with more live vertices moves to the spill pass
     double tau;                // FP64 band, relative
     const double *rad;         // radii by sorted index (radical tessellation), or NULL
     const double *rmax;        // largest radius (device scalar)

@@ -12,12 +12,14 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # VOROHIP_PHASE_CLOCKS=1 loads the build with the grouped cell kernel's phase
-# profile (python -m paper_2209_11606_amd.build --phase-clocks)
-LIB_PATH = os.path.join(_HERE, "libvorohip_phase.so" if os.environ.get("VOROHIP_PHASE_CLOCKS") == "1"
-                        else "libvorohip.so")
+# profile (python -m paper_2209_11606_amd.build --phase-clocks); VOROHIP_LIB
+# names another build of the library to load (A/B measurements)
+LIB_PATH = os.environ.get("VOROHIP_LIB") or os.path.join(
+    _HERE, "libvorohip_phase.so" if os.environ.get("VOROHIP_PHASE_CLOCKS") == "1" else "libvorohip.so")
 
 VC_OK, VC_E_ARG, VC_E_RANGE, VC_E_DUPLICATE, VC_E_NOMEM, VC_E_HIP, VC_E_CAPACITY, VC_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 VC_CELL_OK, VC_CELL_SPILLED, VC_CELL_CAPACITY, VC_CELL_DUPLICATE, VC_CELL_SKIPPED, VC_CELL_EMPTY = 0, 1, 2, 3, 4, 5
+VC_CELL_FO_OVERFLOW = 64  # flag bit on a complete cell with a face of 32 or more edges
 VC_FP64, VC_F32_FILTER = 0, 1
 VC_VOLUME, VC_CENTROID, VC_COUNTS, VC_FACE_ORDERS, VC_NEIGHBORS, VC_NEIGHBOR_COUNT, VC_DIAG = 1, 2, 4, 8, 16, 32, 64
 VC_ALL = 127
@@ -41,7 +43,8 @@ class vc_options(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("periodic", ctypes.c_int * 3), ("n_opt", ctypes.c_double), ("grid", ctypes.c_int * 3),
                 ("precision", ctypes.c_int), ("slots", ctypes.c_int), ("waves", ctypes.c_int),
-                ("chunk", ctypes.c_int), ("cells_per_wave", ctypes.c_int), ("clip", ctypes.c_double)]
+                ("chunk", ctypes.c_int), ("cells_per_wave", ctypes.c_int), ("clip", ctypes.c_double),
+                ("capacity", ctypes.c_int)]
 
 
 class vc_tuning(ctypes.Structure):

@@ -185,3 +185,16 @@ def batch(count=4096, seed=1000, lo=100, hi=100_000):
     """The batched workload: count tessellations of log-uniform sizes."""
     sizes = batch_sizes(count, lo, hi, seed)
     return [batch_member(t, int(s)) for t, s in enumerate(sizes)]
+
+
+def ring_face(k=40, rho=0.2, delta=0.05):
+    """A crafted set in the walled unit cube whose two first cells have faces
+    of k edges: particles at (1/2, 1/2, 1/2 -+ delta) and a ring of k
+    particles at distance rho from the axis in the plane z = 1/2.  The face
+    between the two axial particles lies in that plane and is bounded by one
+    edge per ring particle (a k-gon of inradius (rho^2 - delta^2) / (2 rho));
+    each axial cell also has a k-gon face on the wall beyond it."""
+    t = 2.0 * math.pi * np.arange(k) / k
+    ring = np.stack([0.5 + rho * np.cos(t), 0.5 + rho * np.sin(t), np.full(k, 0.5)], 1)
+    axis = np.array([[0.5, 0.5, 0.5 - delta], [0.5, 0.5, 0.5 + delta]])
+    return np.concatenate([axis, ring])

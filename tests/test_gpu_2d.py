@@ -109,3 +109,14 @@ def test_2d_full_size_10m(v):
     idx = np.random.default_rng(1).choice(n, 2000, replace=False)
     r = oracle.Oracle(x, w["lo"], w["hi"], w["periodic"]).cells(idx, nthreads=oracle.num_threads())
     parity2(out, r, idx)
+
+
+@pytest.mark.parametrize("per", [[1, 1], [0, 0]])
+def test_2d_forced_spill(v, per):
+    """Capacity 2 sends every 2D cell to the spill pass at its first cut (a
+    polygon has at least three vertices); every cell is re-run there and
+    equals the oracle's."""
+    x = W.uniform(5000, 2, 1.0, 63)
+    g = run(v, x, [0, 0], [1, 1], per, capacity=2)
+    assert np.all(g["status"] == 1) and g["diag"]["spilled"] == 5000
+    parity2(g, oracle.Oracle(x, [0, 0], [1, 1], per).cells())

@@ -153,3 +153,112 @@ def test_full_size_periodic_1m_bench_path(v):
         assert math.fsum(eager["vol"]) == pytest.approx(100.0 ** 3, rel=1e-12)
         eager["nbr"] = v.neighbor_lists(eager)
         assert_parity(eager, r, idx)
+
+
+def _member_nbr(res, offsets, t, cells):
+    """Sorted (label, image) lists of some cells of member t, labels made
+    local to the member (walls stay negative)."""
+    off, ids, sh = res["nbr_off"], res["nbr_ids"], res["nbr_sh"]
+    out = []
+    for i in cells:
+        g = offsets[t] + i
+        lab = ids[off[g]:off[g + 1]].astype(np.int64)
+        lab[lab >= 0] -= offsets[t]
+        out.append(np.stack([lab, sh[off[g]:off[g + 1]].astype(np.int64)], 1))
+    return out
+
+
+def _symmetric(res, offsets, t):
+    """Neighbour symmetry inside member t: (i -> j, s) pairs with (j -> i, -s)."""
+    a, e = int(offsets[t]), int(offsets[t + 1])
+    off = res["nbr_off"]
+    ids = res["nbr_ids"][off[a]:off[e]].astype(np.int64)
+    sh = res["nbr_sh"][off[a]:off[e]].astype(np.int64)
+    src = np.repeat(np.arange(a, e, dtype=np.int64), np.diff(off[a:e + 1]))
+    keep = ids >= 0
+    src, ids, sh = src[keep], ids[keep], sh[keep]
+    s = np.stack([sh % 5 - 2, (sh // 5) % 5 - 2, sh // 25 - 2], 1)
+    negc = 25 * (-s[:, 2] + 2) + 5 * (-s[:, 1] + 2) + (-s[:, 0] + 2)
+    fwd = np.sort(src * (1 << 40) + ids * 128 + sh)
+    bwd = np.sort(ids * (1 << 40) + src * 128 + negc)
+    return np.array_equal(fwd, bwd)
+
+
+@pytest.mark.timeout(900)
+def test_full_size_batch4096(v):
+    """The 4,096-tessellation batch at its own size (5.85e7 cells; sizes
+    log-uniform in [100, 1e5]; periodic / walled x uniform / perturbed BCC),
+    tuned and replayed from a hipGraph as the benchmark runs it.  The replay
+    equals the eager launch bit for bit.  On every member: the volumes tile
+    the box, Euler's V - E + F = 2 and the face-order sums hold for every
+    cell.  Neighbour symmetry on the 20 largest members and 4 per class.
+    Element-wise parity with the oracle (counts, face orders, neighbour
+    lists, volume, centroid) on 60 cells of 8 members of each class and on
+    50 cells of each of the 20 largest members."""
+    import math
+    from test_gpu_parity import assert_parity
+    members = W.batch(4096)
+    count = len(members)
+    offsets = np.zeros(count + 1, np.int64)
+    for t, m in enumerate(members):
+        offsets[t + 1] = offsets[t] + len(m["xyz"])
+    n = int(offsets[-1])
+    xyz = np.concatenate([m["xyz"] for m in members])
+    opts = [v.vc_options_init(3, m["lo"], m["hi"], m["periodic"]) for m in members]
+    s = torch.cuda.Stream()
+    xt = torch.from_numpy(xyz).to("cuda:0")
+    torch.cuda.synchronize()
+    b = v.vc_batch_create(xt, offsets, opts, s)
+    r = v.vc_batch_result_create(b, v.VC_ALL)
+    try:
+        tuned = v.vc_batch_tune(b, r, s)
+        print("batch4096 tuned", tuned, flush=True)
+        v.vc_batch_compute(b, r, False, s)
+        s.synchronize()
+        eager = v.fetch(r, v.VC_ALL, n)
+        v.vc_batch_compute(b, r, True, s)  # capture and replay
+        v.vc_batch_compute(b, r, True, s)  # replay again
+        s.synchronize()
+        rep = v.fetch(r, v.VC_ALL, n)
+        for k in ("vol", "cen", "nv", "ne", "nf", "fo", "status", "nbr_off", "nbr_ids", "nbr_sh"):
+            assert np.array_equal(rep[k], eager[k]), k
+        del rep
+    finally:
+        v.vc_result_destroy(r)
+        v.vc_batch_destroy(b)
+    g = eager
+    print("batch4096 diag", g["diag"], flush=True)
+    assert np.all(g["status"] <= 1)
+    assert np.all(g["nv"] - g["ne"] + g["nf"] == 2)
+    assert np.all(g["fo"].sum(1) == g["nf"])
+    assert np.all((g["fo"] * np.arange(32)).sum(1) == 2 * g["ne"])
+    for t, m in enumerate(members):
+        box = float(np.prod(np.asarray(m["hi"]) - np.asarray(m["lo"])))
+        assert math.fsum(g["vol"][offsets[t]:offsets[t + 1]]) == pytest.approx(box, rel=1e-12), t
+    sizes = np.diff(offsets)
+    largest = np.argsort(sizes)[-20:]
+    rng = np.random.default_rng(4096)
+    by_kind = {}
+    for t, m in enumerate(members):
+        by_kind.setdefault(m["kind"], []).append(t)
+    assert sorted(by_kind) == ["periodic_bcc", "periodic_uniform", "walled_bcc", "walled_uniform"]
+    picks = [(int(t), 50) for t in largest]
+    for kind, ts in sorted(by_kind.items()):
+        sel = rng.choice(ts, 8, replace=False)
+        picks += [(int(t), 60) for t in sel]
+        for t in list(sel[:4]):
+            assert _symmetric(g, offsets, int(t)), (kind, t)
+    for t in largest:
+        assert _symmetric(g, offsets, int(t)), t
+    checked = 0
+    for t, k in picks:
+        m = members[t]
+        nt = int(sizes[t])
+        cells = np.sort(rng.choice(nt, min(k, nt), replace=False))
+        ref = oracle.Oracle(m["xyz"], m["lo"], m["hi"], m["periodic"]).cells(cells, nthreads=oracle.num_threads())
+        a = int(offsets[t])
+        part = {key: g[key][a + cells] for key in ("vol", "cen", "nv", "ne", "nf", "fo", "status")}
+        part["nbr"] = _member_nbr(g, offsets, t, cells)
+        assert_parity(part, ref, np.arange(len(cells)))
+        checked += len(cells)
+    print(f"batch4096: {checked} cells of {len(picks)} members equal the oracle", flush=True)

@@ -37,7 +37,10 @@ def run(v, x, lo, hi, per, **opt):
 
 def assert_parity(g, r, idx=None, vol_tol=1e-12):
     idx = np.arange(len(g["vol"])) if idx is None else np.asarray(idx)
-    assert np.all(g["status"][idx] <= 1), np.unique(g["status"][idx])
+    st = g["status"][idx].astype(np.int64)
+    assert np.all((st & ~64) <= 1), np.unique(st)
+    # the face-order overflow flag (a face of 32 or more edges) as the oracle's
+    assert np.array_equal((st & 64) != 0, (np.asarray(r["status"]) & 64) != 0)
     for key in ("nv", "ne", "nf"):
         bad = np.nonzero(g[key][idx] != r[key])[0]
         assert len(bad) == 0, (key, idx[bad[:5]], g[key][idx][bad[:5]], r[key][bad[:5]])
@@ -215,3 +218,47 @@ def test_errors(v):
     x[7] = x[8]
     g = run(v, x, [0] * 3, [1] * 3, [0, 0, 0])
     assert g["status"][7] == 3 and g["status"][8] == 3
+
+
+@pytest.mark.parametrize("form", [dict(), dict(cells_per_wave=2), dict(cells_per_wave=4), dict(slots=4)])
+def test_face_order_overflow(v, form):
+    """Two cells with two 40-gon faces each: every launch form reports the
+    overflow flag on exactly those cells, face orders without the 40-gons,
+    and otherwise the oracle's cells."""
+    x = W.ring_face(40)
+    g = run(v, x, [0] * 3, [1] * 3, [0, 0, 0], **form)
+    r = oracle.Oracle(x, [0] * 3, [1] * 3, [0, 0, 0]).cells()
+    assert np.array_equal(g["status"] & 64, np.array([64, 64] + [0] * 40, np.uint8))
+    assert np.all(g["fo"][:2].sum(1) == g["nf"][:2] - 2)
+    assert_parity(g, r)
+
+
+@pytest.mark.parametrize("form", [dict(), dict(cells_per_wave=2), dict(cells_per_wave=4)])
+def test_forced_spill_walled_1k(v, form):
+    """Capacity 3 sends every cell to the large-capacity spill pass at its
+    first cut (a polyhedron has at least four vertices): all 1,000 cells are
+    re-run there (status SPILLED, the spill counter equal to n) and still
+    equal the oracle's cells."""
+    w = W.walled_1k()
+    g = run(v, w["xyz"], w["lo"], w["hi"], w["periodic"], capacity=3, **form)
+    n = len(w["xyz"])
+    assert np.all(g["status"] == v.VC_CELL_SPILLED) and g["diag"]["spilled"] == n
+    assert_parity(g, oracle.Oracle(w["xyz"], w["lo"], w["hi"], w["periodic"]).cells())
+
+
+def test_forced_spill_periodic_20k(v):
+    """Every cell of the periodic 20k set through the spill pass (two cells
+    per wave in the main kernel), against the oracle, with the FP32 filter
+    bitwise equal; a capacity of 24 vertices spills only the larger cells."""
+    side = 20000 ** (1 / 3)
+    x = W.uniform(20000, 3, side, 31)
+    r = oracle.Oracle(x, [0] * 3, [side] * 3, [1, 1, 1]).cells(nthreads=oracle.num_threads())
+    g = run(v, x, [0] * 3, [side] * 3, [1, 1, 1], capacity=3, cells_per_wave=2)
+    assert np.all(g["status"] == v.VC_CELL_SPILLED) and g["diag"]["spilled"] == 20000
+    assert_parity(g, r)
+    f = run(v, x, [0] * 3, [side] * 3, [1, 1, 1], capacity=3, cells_per_wave=2, precision=v.VC_F32_FILTER)
+    same_bits(g, f)
+    h = run(v, x, [0] * 3, [side] * 3, [1, 1, 1], capacity=24, cells_per_wave=2)
+    k = int(np.sum(h["status"] == v.VC_CELL_SPILLED))
+    assert 0 < k < 20000 and h["diag"]["spilled"] == k
+    assert_parity(h, r)

@@ -710,3 +710,22 @@ def test_weinberg_pins_catch_a_changed_rule(rule):
         assert wrong == 3
     finally:
         oracle.set_weinberg_rule(0)
+
+
+def test_face_order_overflow_flag():
+    """A face of 32 or more edges is not counted by the face-order vector
+    (k < 32), and the cell says so with the status flag 64.  The crafted set
+    has two cells with two 40-gon faces each: the exact brute force gives
+    their face sizes, and the oracle's flag is set exactly on the cells with
+    a face of 32 or more edges, with sum(fo) = F minus those faces."""
+    x = W.ring_face(40)
+    o = oracle.Oracle(x, [0] * 3, [1] * 3, [0, 0, 0])
+    r = o.cells()
+    for i in range(len(x)):
+        b = brute.cell(x, i, [0] * 3, [1] * 3, [0, 0, 0])
+        big = sum(1 for k in b["sizes"] if k >= 32)
+        assert r["nf"][i] == b["nf"] and r["nv"][i] == b["nv"] and r["ne"][i] == b["ne"]
+        assert r["fo"][i].tolist() == b["fo"]
+        assert (r["status"][i] == oracle.Oracle.FO_OVER) == (big > 0), (i, r["status"][i], b["sizes"])
+        assert r["fo"][i].sum() == r["nf"][i] - big
+    assert list(brute.cell(x, 0, [0] * 3, [1] * 3, [0, 0, 0])["sizes"]).count(40) == 2
