@@ -109,6 +109,8 @@ enum {
 enum { VC_CELL_OK = 0, VC_CELL_SPILLED = 1, VC_CELL_CAPACITY = 2, VC_CELL_DUPLICATE = 3,
        VC_CELL_SKIPPED = 4, /* not in the list of vc_compute_subset */
        VC_CELL_EMPTY = 5,   /* radical tessellation: the cell has no volume */
+       VC_CELL_RANGE = 6,   /* vc_tessellate_noalloc only: a coordinate of the call
+                               lies outside the box; no field of the call is valid */
        /* flag bit, OR-ed into VC_CELL_OK or VC_CELL_SPILLED: the cell is
           complete but one of its faces has VC_FO_LEN (32) or more edges, so
           the face-order vector does not count that face and sums to less
@@ -317,6 +319,33 @@ void vc_batch_destroy(vc_batch *b);
  * its own device buffer; synchronous.  VC_E_ARG for a null tflops, reps < 1
  * or another precision. */
 vc_status vc_device_fma_rate(int precision, int reps, void *stream, double *tflops);
+
+/* The allocation-free form of vc_container_create followed by vc_compute,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  It calls
+ * no hipMalloc, hipFree or other allocating routine: the block-sorted
+ * particles, the binning arrays, the work-queue counters, the spill list
+ * and the exact predicate's workspace live in one file-scope device array of
+ * about 15.8 MiB that each GPU the library runs on holds until the process
+ * ends.  Inputs and outputs are the caller's device memory:
+ *   xyz: n x dim doubles (particle-major), 1 <= n <= 65536, inside the box
+ *   of *opt (a coordinate outside it marks every cell VC_CELL_RANGE, on the
+ *   device: the call does not synchronise); the grid of *opt may hold at
+ *   most 65536 blocks; no radii.  Launch fields of *opt are used as by
+ *   vc_container_create (waves capped at 512).
+ *   vol (n), cen (3n), nv, ne (n), fo (n x VC_FO_LEN): written when non-NULL;
+ *   nf (n) and status (n) are required.  Fields are indexed by input order
+ *   and equal those of vc_compute with the same options.
+ * Errors (host side, before any work is enqueued): VC_E_ARG for a null
+ * required pointer, n or the block count beyond its maximum, host memory,
+ * or bad options.  Asynchronous on `stream`.  The first call on a device
+ * sets the array up (it takes its address and copies the block-offset
+ * lists into it, synchronously), so make that call outside graph capture.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind: calls that overlap on one device (other streams, other threads)
+ * race and must be serialised by the caller. */
+vc_status vc_tessellate_noalloc(const double *xyz, int64_t n, const vc_options *opt, double *vol, double *cen,
+                                int32_t *nv, int32_t *ne, int32_t *nf, uint8_t *fo, uint8_t *status, void *stream);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *vc_last_error(void);

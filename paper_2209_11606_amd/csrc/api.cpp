@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -572,6 +573,78 @@ vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
     return VC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The allocation-free entry point (vc_tessellate_noalloc).  Every buffer the
+// binning and the cell kernels need beyond the caller's positions and
+// outputs lives in one file-scope device array, `scratch`, of a fixed size;
+// each GPU holds its own copy until the process ends.  Host code never uses
+// the array's name as an address: at the first call on a device its address
+// is taken once with hipGetSymbolAddress and kept per device.
+
+constexpr int64_t kNaMaxN = 1 << 16;       // particles per call
+constexpr int64_t kNaMaxBlocks = 1 << 16;  // blocks of the grid
+constexpr int kNaWaves = 512;              // resident cell waves (exact-predicate workspace)
+constexpr int kNaXLen = 3072;              // workspace doubles per wave
+constexpr int kNaMaxDevices = 64;
+
+constexpr size_t na_align(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kNaOffs3 = 0;  // the 3D and 2D block-offset lists, written at set-up
+constexpr size_t kNaOffs2 = kNaOffs3 + na_align(sizeof(Offset) * 729);
+constexpr size_t kNaTess = kNaOffs2 + na_align(sizeof(Offset) * 81);
+constexpr size_t kNaPart = kNaTess + na_align(sizeof(Tess));
+constexpr size_t kNaBlk = kNaPart + na_align(sizeof(Particle) * kNaMaxN);
+constexpr size_t kNaRank = kNaBlk + na_align(4 * kNaMaxN);
+constexpr size_t kNaSid = kNaRank + na_align(4 * kNaMaxN);
+constexpr size_t kNaInv = kNaSid + na_align(4 * kNaMaxN);
+constexpr size_t kNaSpill = kNaInv + na_align(4 * kNaMaxN);
+constexpr size_t kNaStart = kNaSpill + na_align(4 * kNaMaxN);
+constexpr size_t kNaCount = kNaStart + na_align(4 * (kNaMaxBlocks + 1));
+constexpr size_t kNaScan = kNaCount + na_align(4 * kNaMaxBlocks);
+constexpr size_t kNaErr = kNaScan + na_align(4 * 1024);
+constexpr size_t kNaQueue = kNaErr + 256;
+constexpr size_t kNaDiag = kNaQueue + 256;
+constexpr size_t kNaX = kNaDiag + na_align(8 * VC_DIAG_LEN);
+constexpr size_t kNaBytes = kNaX + (size_t)8 * kNaWaves * kNaXLen;  // about 15.8 MiB
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+__global__ void k_put_tess(Tess t, Tess *dst) { *dst = t; }
+
+// a coordinate outside the box: every cell of the call gets VC_CELL_RANGE
+__global__ void k_flag_range(const int32_t *err, uint8_t *status, int64_t n)
+{
+    if (!*err) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        status[i] = VC_CELL_RANGE;
+}
+
+std::mutex g_na_mutex;
+unsigned char *g_na_ptr[kNaMaxDevices] = {};
+
+// Set-up of the current device, once: the array's device address, and the
+// block-offset lists copied into it.
+vc_status na_scratch(unsigned char **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(VC_E_ARG, "vc_tessellate_noalloc: device %d not supported", dev);
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    if (!g_na_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(VC_E_HIP, "vc_tessellate_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        unsigned char *b = static_cast<unsigned char *>(p);
+        const std::vector<Offset> o3 = build_offsets(3), o2 = build_offsets(2);
+        if (o3.size() != 729 || o2.size() != 81) return fail(VC_E_HIP, "vc_tessellate_noalloc: offset list sizes");
+        HIP_TRY(hipMemcpy(b + kNaOffs3, o3.data(), o3.size() * sizeof(Offset), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b + kNaOffs2, o2.data(), o2.size() * sizeof(Offset), hipMemcpyHostToDevice));
+        g_na_ptr[dev] = b;
+    }
+    *out = g_na_ptr[dev];
+    return VC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -930,6 +1003,99 @@ vc_status vc_device_fma_rate(int precision, int reps, void *stream, double *tflo
     (void)hipFree(out);
     if (e != hipSuccess) return fail(VC_E_HIP, "vc_device_fma_rate: %s", hipGetErrorString(e));
     *tflops = (double)blocks * 256.0 * 8.0 * steps * 2.0 / (best * 1e-3) / 1e12;
+    return VC_OK;
+}
+
+vc_status vc_tessellate_noalloc(const double *xyz, int64_t n, const vc_options *opt, double *vol, double *cen,
+                                int32_t *nv, int32_t *ne, int32_t *nf, uint8_t *fo, uint8_t *status, void *stream)
+{
+    if (!xyz || !opt || !nf || !status) return fail(VC_E_ARG, "vc_tessellate_noalloc: null pointer");
+    if (n < 1 || n > kNaMaxN)
+        return fail(VC_E_ARG, "vc_tessellate_noalloc: n = %lld outside [1, %lld]", (long long)n, (long long)kNaMaxN);
+    vc_status st = check_options(opt);
+    if (st) return st;
+    const void *ptrs[] = {xyz, vol, cen, nv, ne, nf, fo, status};
+    for (const void *q : ptrs)
+        if (q && !is_device_ptr(q))
+            return fail(VC_E_ARG, "vc_tessellate_noalloc: positions and outputs must be device memory");
+    Tess T;
+    std::memset(&T, 0, sizeof T);
+    T.G = size_grid(*opt, n);
+    if (T.G.nb > kNaMaxBlocks)
+        return fail(VC_E_ARG, "vc_tessellate_noalloc: %lld blocks, more than %lld", (long long)T.G.nb,
+                    (long long)kNaMaxBlocks);
+    T.pbase = 0;
+    T.pcount = (int32_t)n;
+    T.bbase = 0;
+    double bmin = T.G.bs[0];
+    for (int d = 1; d < opt->dim; d++) bmin = std::min(bmin, T.G.bs[d]);
+    T.bsmin2 = bmin * bmin;
+    T.clip_half = opt->clip > 0.0 ? 0.5 * opt->clip : 0.0;
+    unsigned char *b = nullptr;
+    if ((st = na_scratch(&b))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Tess *tess = reinterpret_cast<Tess *>(b + kNaTess);
+    Particle *part = reinterpret_cast<Particle *>(b + kNaPart);
+    int32_t *blk = reinterpret_cast<int32_t *>(b + kNaBlk), *rank = reinterpret_cast<int32_t *>(b + kNaRank);
+    int32_t *sid = reinterpret_cast<int32_t *>(b + kNaSid), *inv = reinterpret_cast<int32_t *>(b + kNaInv);
+    int32_t *spill = reinterpret_cast<int32_t *>(b + kNaSpill), *start = reinterpret_cast<int32_t *>(b + kNaStart);
+    int32_t *count = reinterpret_cast<int32_t *>(b + kNaCount), *scan = reinterpret_cast<int32_t *>(b + kNaScan);
+    int32_t *err = reinterpret_cast<int32_t *>(b + kNaErr), *queue = reinterpret_cast<int32_t *>(b + kNaQueue);
+    unsigned long long *diag = reinterpret_cast<unsigned long long *>(b + kNaDiag);
+    double *xs = reinterpret_cast<double *>(b + kNaX);
+    // binning into the array (what must start at zero is cleared by kernels)
+    k_put_tess<<<1, 1, 0, s>>>(T, tess);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_fill_i32(count, T.G.nb, 0, s));
+    HIP_TRY(launch_fill_i32(err, 1, 0, s));
+    HIP_TRY(launch_bin_count(xyz, n, opt->dim, tess, nullptr, blk, rank, count, err, s));
+    HIP_TRY(launch_scan(count, start, T.G.nb, scan, s));
+    HIP_TRY(launch_scatter(xyz, n, opt->dim, nullptr, blk, rank, start, sid, part, inv, s));
+    // cells: the launch sequence of vc_compute on the array's buffers
+    HIP_TRY(launch_fill_i32(queue, 8, 0, s));
+    HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t *>(diag), VC_DIAG_LEN * 2, 0, s));
+    CellArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.tess = tess;
+    A.part = part;
+    A.start = start;
+    A.offs = reinterpret_cast<const Offset *>(b + (opt->dim == 3 ? kNaOffs3 : kNaOffs2));
+    A.noff = opt->dim == 3 ? 729 : 81;
+    A.off_radius = kOffRadius;
+    A.ncell = (int)n;
+    A.queue = queue;
+    A.chunk = opt->chunk > 0 ? opt->chunk : 4;
+    A.vcap = opt->capacity;
+    A.tau = 0x1p-30;
+    A.mask = (vol ? VC_VOLUME : 0) | (cen ? VC_CENTROID : 0) | (nv || ne ? VC_COUNTS : 0) | (fo ? VC_FACE_ORDERS : 0) |
+             VC_NEIGHBOR_COUNT;
+    A.vol = vol;
+    A.cen = cen;
+    A.nv = nv;
+    A.ne = ne;
+    A.nf = nf;
+    A.fo = fo;
+    A.status = status;
+    A.spill_list = spill;
+    A.spill_count = queue + 2;
+    A.diag = diag;
+    A.xscratch = xs;
+    A.xscratch_len = kNaXLen;
+    const int waves = std::min(opt->waves > 0 ? opt->waves : kNaWaves, kNaWaves);
+    const int cpw = opt->cells_per_wave > 0 ? opt->cells_per_wave : 1;
+    if (opt->dim == 2) HIP_TRY(launch_cells2d(A, opt->precision, waves, s));
+    else if (cpw > 1) HIP_TRY(launch_cells_group(A, opt->precision, cpw, waves, s));
+    else HIP_TRY(launch_cells(A, opt->precision, opt->slots > 0 ? opt->slots : 2, waves, s));
+    CellArgs B = A;
+    B.cell_list = spill;
+    B.queue = queue + 1;
+    B.ncell_dev = queue + 2;
+    B.chunk = 1;
+    B.vcap = 0;
+    if (opt->dim == 2) HIP_TRY(launch_cells2d_spill(B, kNaWaves, s));
+    else HIP_TRY(launch_cells_spill(B, kNaWaves, s));
+    k_flag_range<<<(int)std::min<int64_t>((n + 255) / 256, 256), 256, 0, s>>>(err, status, n);
+    HIP_TRY(hipGetLastError());
     return VC_OK;
 }
 

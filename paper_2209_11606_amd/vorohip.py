@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("VOROHIP_LIB") or os.path.join(
 VC_OK, VC_E_ARG, VC_E_RANGE, VC_E_DUPLICATE, VC_E_NOMEM, VC_E_HIP, VC_E_CAPACITY, VC_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 VC_CELL_OK, VC_CELL_SPILLED, VC_CELL_CAPACITY, VC_CELL_DUPLICATE, VC_CELL_SKIPPED, VC_CELL_EMPTY = 0, 1, 2, 3, 4, 5
 VC_CELL_FO_OVERFLOW = 64  # flag bit on a complete cell with a face of 32 or more edges
+VC_CELL_RANGE = 6  # vc_tessellate_noalloc: a coordinate outside the box
 VC_FP64, VC_F32_FILTER = 0, 1
 VC_VOLUME, VC_CENTROID, VC_COUNTS, VC_FACE_ORDERS, VC_NEIGHBORS, VC_NEIGHBOR_COUNT, VC_DIAG = 1, 2, 4, 8, 16, 32, 64
 VC_ALL = 127
@@ -89,6 +90,7 @@ def _load():
         "vc_last_error": (ctypes.c_char_p, []),
         "vc_version": (ctypes.c_char_p, []),
         "vc_device_fma_rate": (I32, [I32, I32, P, P]),
+        "vc_tessellate_noalloc": (I32, [P, I64, P, P, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -103,7 +105,7 @@ EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_
             "vc_result_create", "vc_compute", "vc_compute_subset",
             "vc_result_get", "vc_result_copy", "vc_result_kernel_ms", "vc_result_destroy", "vc_container_destroy", "vc_batch_create",
             "vc_batch_rebin", "vc_batch_result_create", "vc_batch_compute", "vc_batch_tune", "vc_batch_destroy",
-            "vc_last_error", "vc_version", "vc_device_fma_rate"]
+            "vc_last_error", "vc_version", "vc_device_fma_rate", "vc_tessellate_noalloc"]
 
 
 def lib():
@@ -292,6 +294,19 @@ def vc_batch_tune(b, r, stream=None):
     t = vc_tuning()
     _check(_lib.vc_batch_tune(b, r, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(t)))
     return dict(slots=t.slots, waves=t.waves, chunk=t.chunk, cells_per_wave=t.cells_per_wave, ms=t.ms)
+
+
+def vc_tessellate_noalloc(xyz, opts, out, stream=None):
+    """The allocation-free tessellation: xyz a contiguous float64 device
+    tensor (n x dim); out a dict of preallocated device tensors by field name
+    (nf: int32[n] and status: uint8[n] required; vol: float64[n],
+    cen: float64[n, 3], nv, ne: int32[n], fo: uint8[n, 32] optional)."""
+    def ptr(key):
+        t = out.get(key)
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+    _check(_lib.vc_tessellate_noalloc(ctypes.c_void_p(xyz.data_ptr()), int(xyz.shape[0]), ctypes.byref(opts),
+                                      ptr("vol"), ptr("cen"), ptr("nv"), ptr("ne"), ptr("nf"), ptr("fo"),
+                                      ptr("status"), ctypes.c_void_p(_stream_ptr(stream))))
 
 
 def vc_batch_destroy(b):
