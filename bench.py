@@ -204,7 +204,7 @@ def end_to_end(v, torch, xyz, w, precision, mask, reps=3, launch=None):
     host = torch.from_numpy(xyz).pin_memory()
     n, dim = xyz.shape
     if launch:
-        form = {k: int(launch[k]) for k in ("cells_per_wave", "slots", "waves", "chunk")}
+        form = {k: int(launch[k]) for k in ("cells_per_wave", "slots", "waves", "chunk", "capacity")}
     else:
         form = dict(cells_per_wave=2 if dim == 3 else 0)
     o = options(v, w, precision=precision, **form)
@@ -230,7 +230,7 @@ def end_to_end(v, torch, xyz, w, precision, mask, reps=3, launch=None):
                 includes="H2D of positions from pinned memory, binning, cells, compaction, D2H of every field")
 
 
-def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask, radii=None, sample=None):
+def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask, radii=None, sample=None, classes=None):
     """Batched form: autotuned launch parameters, compute replayed from a
     hipGraph; step = rebin + graph launch.  The cell-kernel duration for the
     roofline comes from eager launches with the same parameters."""
@@ -241,6 +241,11 @@ def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask, radii=None, s
         v.vc_batch_set_radii(b, radii, stream)
     r = v.vc_batch_result_create(b, mask)
     try:
+        per_class = None
+        if classes:
+            # the launch form each input class would take on its own (the
+            # batch runs in one launch with the whole-batch choice below)
+            per_class = {k: v.vc_batch_tune_members(b, r, ms, stream) for k, ms in sorted(classes.items())}
         tuned = v.vc_batch_tune(b, r, stream)
         kms = []
         for _ in range(max(1, warmup)):
@@ -258,6 +263,8 @@ def time_batched(v, torch, xt, offsets, opts, steps, warmup, mask, radii=None, s
             kms.append(v.vc_result_kernel_ms(r))
         out = _summary(v, r, ms, float(np.median(kms)), sample)
         out["tuned"] = tuned
+        if per_class:
+            out["tuned_per_class"] = per_class
         if os.environ.get("VOROHIP_PHASE_CLOCKS") == "1":
             out["phases"] = v.phase_profile(r)
     finally:
@@ -568,7 +575,12 @@ def main():
             radii = None
             if members[0].get("radii") is not None:
                 radii = np.concatenate([m["radii"] for m in members])
-            res[name] = time_batched(v, torch, xt, offsets, opts, a.steps, a.warmup, mask, radii, sample)
+            classes = None
+            if len(members) > 1 and members[0].get("kind"):
+                classes = {}
+                for t, m in enumerate(members):
+                    classes.setdefault(m["kind"], []).append(t)
+            res[name] = time_batched(v, torch, xt, offsets, opts, a.steps, a.warmup, mask, radii, sample, classes)
         else:
             res[name] = time_variant(v, torch, xt, members[0], prec, a.steps, a.warmup, mask, sample)
         print(f"# {name}: {res[name]['ms_per_step']:.3f} ms/step, cell kernel {res[name]['kernel_ms']:.3f} ms, "
@@ -639,6 +651,7 @@ def main():
                              empty_cells=r["empty_cells"], tuned=r.get("tuned"),
                              roofline_frac=(None if flops_per_cell is None else
                                             n * flops_per_cell / (r["kernel_ms"] / 1e3) / FP64_VECTOR_PEAK),
+                             tuned_per_class=r.get("tuned_per_class"),
                              diag=r["diag"], phases=r.get("phases"), parity=r.get("parity"))
                      for k, r in res.items()},
         "roofline": roof,

@@ -161,7 +161,17 @@ typedef struct {
                             0: the kernel's own capacity (slots x lanes); a value below
                             4 in 3D (3 in 2D), fewer than any cut cell has, sends every
                             cell that is cut at all to the pass */
+    int force;           /* testing aid, VC_FORCE_* bits, 0 in normal use: take every
+                            side decision through a slower stage that must give
+                            the same result (the bands of section 2.2.2's filter
+                            made wide enough to hold every test) */
 } vc_options;
+
+/* vc_options.force bits. VC_FORCE_RECHECK: every FP32 test of VC_F32_FILTER
+   is taken as unsure and re-done in FP64; VC_FORCE_EXACT: every FP64 side test
+   falls in the band and is decided by the exact predicate. Results are the
+   same as without the bits; only the diagnostic counters and the time differ. */
+enum { VC_FORCE_RECHECK = 1, VC_FORCE_EXACT = 2 };
 
 typedef struct vc_container vc_container;
 typedef struct vc_result vc_result;
@@ -246,14 +256,25 @@ vc_status vc_compute_subset(vc_container *c, vc_result *r, const int64_t *ids, i
  * Waits for that kernel to finish. */
 vc_status vc_result_kernel_ms(vc_result *r, float *ms);
 
-/* Device pointer and element count of a result field (no copy).  The pointer
- * stays valid until vc_result_destroy.  For the neighbour id and shift
- * arrays the count is known only after the compute finished: this call
- * synchronises the stream of the last compute to read it. */
+/* Device pointer and element count of a result field (no copy): the per-cell
+ * statistics the paper reads from each computed cell (section 2.1.2 and the
+ * per-cell accessors of the example listing of section 2.2.3: volume,
+ * centroid, counts, face orders, neighbours), here for all cells at once as
+ * device arrays indexed by input order (this library's design; the paper
+ * reads them from one cell object at a time).  The pointer stays valid
+ * until vc_result_destroy.  For the neighbour id and shift arrays the count
+ * is known only after the compute finished: this call synchronises the
+ * stream of the last compute to read it.  Errors: VC_E_ARG (null pointer,
+ * unknown field), VC_E_STATE (a field not in the statistics mask),
+ * VC_E_HIP. */
 vc_status vc_result_get(vc_result *r, int field, void **dev_ptr, int64_t *count);
 
-/* Copy a result field to host memory (synchronous); bytes must be >= the
- * field size. */
+/* Copy a result field to host memory (synchronous): the fields of
+ * vc_result_get, for callers that want them on the host (the paper's
+ * per-cell output loop of section 2.2.3, done once for every cell).
+ * host_dst receives count elements of the field's type (the sizes listed
+ * with VC_F_*); bytes must be >= that size, else VC_E_ARG; errors as for
+ * vc_result_get. */
 vc_status vc_result_copy(vc_result *r, int field, void *host_dst, int64_t bytes);
 
 void vc_result_destroy(vc_result *r);
@@ -262,7 +283,10 @@ void vc_container_destroy(vc_container *c);
 /* --- batches of independent tessellations (one persistent launch) --------- */
 
 /* Create a batch of n_tess independent 3D containers sharing one set of
- * device arrays.  xyz_concat holds all positions back to back (n_total x 3
+ * device arrays: many separate problems in one launch (the dynamic
+ * scheduling of uneven work in section 2.2.4, applied across containers as
+ * well as across cells; batching is this library's design, the paper
+ * threads one container at a time).  xyz_concat holds all positions back to back (n_total x 3
  * doubles, host or device); offsets[n_tess + 1] (host) gives the first
  * particle of each tessellation (offsets[0] = 0, offsets[n_tess] = n_total,
  * every tessellation non-empty); opts[n_tess] (host) the box, periodicity and
@@ -298,14 +322,31 @@ typedef struct {
     int chunk;          /* cells per work-queue grab */
     int cells_per_wave; /* cells processed together by one wave */
     float ms;           /* kernel time of the winner on the tuning sample */
+    int capacity;       /* vertex capacity before the spill pass (vc_options.capacity;
+                           0: the form's own) */
 } vc_tuning;
 
-/* Autotuner: times each candidate launch configuration on a sample of the
- * batch's cells (every 16th cell in block order), keeps the fastest for later
- * vc_batch_compute calls and returns it in *best (may be NULL).  Overwrites
+/* Autotuner (the launch choices the paper leaves to the OpenMP schedule,
+ * section 2.2.4, made here by measurement): times each launch configuration
+ * -- cells per wave and slots (the form), vertex capacity before the spill
+ * pass (the form's own or three quarters of it), cells per work-queue grab,
+ * resident waves -- on a sample of the batch's cells (32 contiguous runs in
+ * block order, 1/16 of the cells and at least 262,144 of them, so that cells
+ * share their blocks in the cache as in a full launch), each once untimed
+ * and twice timed; then times the best configuration of each form on every
+ * cell and keeps the fastest for later vc_batch_compute calls, returning it
+ * in *best (may be NULL; best->ms is its time on every cell).  Overwrites
  * the contents of r.  Synchronous.  A later vc_batch_compute with graph
  * capture re-captures with the chosen parameters. */
 vc_status vc_batch_tune(vc_batch *b, vc_result *r, void *stream, vc_tuning *best);
+
+/* As vc_batch_tune, on a sample drawn only from the tessellations
+ * members[0..m) (host int64 indices into the batch), the final check on all
+ * of their cells: the launch form best for one class of input.  The choice is kept for the whole batch, like
+ * vc_batch_tune's.  Errors: VC_E_ARG (null or empty list), VC_E_RANGE (an
+ * index outside the batch), VC_E_STATE, VC_E_NOMEM, VC_E_HIP. */
+vc_status vc_batch_tune_members(vc_batch *b, vc_result *r, const int64_t *members, int64_t m, void *stream,
+                                vc_tuning *best);
 
 void vc_batch_destroy(vc_batch *b);
 

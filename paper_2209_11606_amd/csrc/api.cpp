@@ -151,6 +151,8 @@ vc_status check_options(const vc_options *o)
         return fail(VC_E_ARG, "options: cells_per_wave must be 0, 1, 2 or 4");
     if (!std::isfinite(o->clip) || o->clip < 0.0) return fail(VC_E_ARG, "options: clip must be finite and >= 0");
     if (o->capacity < 0) return fail(VC_E_ARG, "options: capacity must be >= 0");
+    if (o->force & ~(VC_FORCE_RECHECK | VC_FORCE_EXACT))
+        return fail(VC_E_ARG, "options: force holds bits other than VC_FORCE_RECHECK | VC_FORCE_EXACT");
     return VC_OK;
 }
 
@@ -187,6 +189,15 @@ Grid size_grid(const vc_options &o, int64_t n)
     return G;
 }
 
+// Side-test bands of the kernels: FP64 decisions within tau * M go to the
+// exact predicate, FP32 filter decisions within tau32 * M to FP64. The
+// VC_FORCE_* bits widen a band past every test.
+void set_bands(CellArgs &A, int force)
+{
+    A.tau = (force & VC_FORCE_EXACT) ? 0x1p+600 : 0x1p-30;
+    A.tau32 = (force & VC_FORCE_RECHECK) ? 0x1p+100f : 0x1p-21f;
+}
+
 struct Launch {
     int slots = 2, waves = 0, chunk = 4, cpw = 1;
     int vcap = 0;  // vertex capacity before the spill pass (0: the kernel's own)
@@ -198,6 +209,7 @@ struct vc_container {
     int dim = 3;
     int64_t n = 0;
     int precision = VC_FP64;
+    int force = 0;               // VC_FORCE_* bits
     std::vector<Tess> htess;
     Tess *tess = nullptr;
     int32_t *ptess = nullptr;    // tessellation of each input particle (batches only)
@@ -361,6 +373,7 @@ vc_status create_common(vc_container *c, const double *xyz, const int64_t *offse
     c->dim = dim;
     c->n = offsets[ntess];
     c->precision = opts[0].precision;
+    c->force = opts[0].force;
     c->launch.slots = opts[0].slots > 0 ? opts[0].slots : 2;
     c->launch.chunk = opts[0].chunk > 0 ? opts[0].chunk : 4;
     c->launch.cpw = opts[0].cells_per_wave > 0 ? opts[0].cells_per_wave : 1;
@@ -439,7 +452,7 @@ CellArgs cell_args(const vc_container *c, const vc_result *r)
     A.ncell_dev = nullptr;
     A.queue = c->queue;
     A.chunk = c->launch.chunk;
-    A.tau = 0x1p-30;
+    set_bands(A, c->force);
     A.mask = r->mask;
     A.vol = r->vol;
     A.cen = r->cen;
@@ -510,6 +523,103 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
     }
     r->last_stream = s;
     return VC_OK;
+}
+
+// Tuning sample: 32 contiguous runs of cells in block order, spread evenly
+// over [lo, hi) and covering `want` cells, so that neighbouring cells share
+// their blocks in the cache as in a full launch (a strided sample of single
+// cells does not, and favours other launch forms).
+void tuning_sample(int64_t lo, int64_t hi, int64_t want, std::vector<int32_t> &v)
+{
+    const int64_t n = hi - lo;
+    if (n <= 0) return;
+    const int64_t runs = std::min<int64_t>(32, n);
+    const int64_t len = std::max<int64_t>(1, (std::min(want, n) + runs - 1) / runs);
+    for (int64_t r = 0; r < runs; r++) {
+        const int64_t a = lo + r * n / runs;
+        for (int64_t i = a; i < std::min(a + len, hi); i++) v.push_back((int32_t)i);
+    }
+}
+
+// Kernel time of one configuration on the cells of `list` (NULL: all): one
+// untimed run, then the faster of `reps` timed runs.
+vc_status time_launch(vc_container *b, vc_result *r, hipStream_t s, const Launch &L, const int32_t *list, int nlist,
+                      int reps, float &out)
+{
+    out = 1e30f;
+    for (int rep = 0; rep <= reps; rep++) {
+        vc_status st = list ? enqueue_compute(b, r, s, true, L, list, nlist) : enqueue_compute(b, r, s, true, L);
+        if (st) return st;
+        if (rep == 0) continue;
+        float ms = 0.f;
+        HIP_TRY(hipEventSynchronize(r->ev1));
+        HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev1));
+        out = std::min(out, ms);
+    }
+    return VC_OK;
+}
+
+// Launch-configuration search.  Every configuration -- form (cells per
+// wave, slots), the vertex capacity before the spill pass (the form's own or
+// three quarters of it), cells per queue grab and resident waves -- is timed
+// on the sample `list` (the faster of two runs after an untimed one); the
+// best configuration of each form is then timed on the whole set `full`
+// (NULL: every cell), and the fastest there wins.  A sample alone can rank
+// the forms wrongly: on few cells a launch is dominated by its start and
+// tail, where the one-cell form loses less than on a full launch.
+vc_status tune(vc_container *b, vc_result *r, hipStream_t s, const int32_t *list, int nlist, const int32_t *full,
+               int nfull, Launch &win, float &wms)
+{
+    const int cu = device_cu_count();
+    const int form_c[][3] = {{1, 2, 128}, {1, 4, 256}, {2, 2, 64}, {4, 4, 64}};  // cpw, slots, capacity
+    const int chunk_c[] = {1, 4, 16, 64};
+    const int waves_c[] = {cu * 8, cu * 16, cu * 32};
+    Launch best_of_form[4];
+    float ms_of_form[4];
+    for (int fi = 0; fi < 4; fi++) {
+        const int *f = form_c[fi];
+        ms_of_form[fi] = 1e30f;
+        for (int cap4 : {4, 3})
+            for (int ch : chunk_c)
+                for (int wv : waves_c) {
+                    Launch L;
+                    L.cpw = f[0];
+                    L.slots = f[1];
+                    L.vcap = cap4 == 4 ? 0 : f[2] * cap4 / 4;
+                    L.chunk = ch;
+                    L.waves = wv;
+                    float ms;
+                    vc_status st = time_launch(b, r, s, L, list, nlist, 2, ms);
+                    if (st) return st;
+                    if (ms < ms_of_form[fi]) {
+                        ms_of_form[fi] = ms;
+                        best_of_form[fi] = L;
+                    }
+                }
+    }
+    wms = 1e30f;
+    for (int fi = 0; fi < 4; fi++) {
+        float ms;
+        vc_status st = time_launch(b, r, s, best_of_form[fi], full, nfull, 1, ms);
+        if (st) return st;
+        if (ms < wms) {
+            wms = ms;
+            win = best_of_form[fi];
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return VC_OK;
+}
+
+void report_tuning(const Launch &win, float wms, vc_tuning *best)
+{
+    if (!best) return;
+    best->slots = win.slots;
+    best->waves = win.waves;
+    best->chunk = win.chunk;
+    best->cells_per_wave = win.cpw;
+    best->ms = wms;
+    best->capacity = win.vcap;
 }
 
 vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
@@ -865,12 +975,12 @@ vc_status vc_batch_create(const double *xyz_concat, const int64_t *offsets, int6
     hipStream_t s = (hipStream_t)stream;
     vc_status st = create_common(b, xyz_concat, offsets, n_tess, opts, s);
     if (!st) {
-        // tuning sample: every 16th cell in block order
-        b->nsample = (int)((b->n + 15) / 16);
-        st = dalloc(&b->sample_list, (size_t)b->nsample);
+        // tuning sample: contiguous runs of cells in block order
+        std::vector<int32_t> v;
+        tuning_sample(0, b->n, std::max<int64_t>(b->n / 16, 1 << 18), v);
+        b->nsample = (int)v.size();
+        st = dalloc(&b->sample_list, v.size());
         if (!st) {
-            std::vector<int32_t> v((size_t)b->nsample);
-            for (int i = 0; i < b->nsample; i++) v[(size_t)i] = 16 * i;
             hipError_t e = hipMemcpy(b->sample_list, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
             if (e != hipSuccess) st = fail(VC_E_HIP, "copy of the tuning sample failed");
         }
@@ -932,45 +1042,51 @@ vc_status vc_batch_tune(vc_batch *b, vc_result *r, void *stream, vc_tuning *best
 {
     if (!b || !r) return fail(VC_E_ARG, "vc_batch_tune: null handle");
     if (r->c != b) return fail(VC_E_STATE, "vc_batch_tune: result was created for another batch");
-    hipStream_t s = (hipStream_t)stream;
-    int cu = device_cu_count();
-    // (cells per wave, slots) pairs; slots only matter for one cell per wave
-    const int form_c[][2] = {{1, 2}, {1, 4}, {2, 2}, {4, 4}};
-    const int chunk_c[] = {1, 4, 16, 64};
-    const int waves_c[] = {cu * 8, cu * 16, cu * 32};
-    Launch win;
-    float wms = 1e30f;
-    for (auto &f : form_c)
-        for (int ch : chunk_c)
-            for (int wv : waves_c) {
-                Launch L;
-                L.cpw = f[0];
-                L.slots = f[1];
-                L.chunk = ch;
-                L.waves = wv;
-                // two runs: the first warms caches, the second is timed
-                for (int rep = 0; rep < 2; rep++) {
-                    vc_status st = enqueue_compute(b, r, s, true, L, b->sample_list, b->nsample);
-                    if (st) return st;
-                }
-                float ms = 0.f;
-                HIP_TRY(hipEventSynchronize(r->ev1));
-                HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev1));
-                if (ms < wms) {
-                    wms = ms;
-                    win = L;
-                }
-            }
-    HIP_TRY(hipStreamSynchronize(s));
+    Launch win = b->launch;
+    float wms = 0.f;
+    vc_status st = tune(b, r, (hipStream_t)stream, b->sample_list, b->nsample, nullptr, -1, win, wms);
+    if (st) return st;
     b->launch = win;
     release_graph(b);
-    if (best) {
-        best->slots = win.slots;
-        best->waves = win.waves;
-        best->chunk = win.chunk;
-        best->cells_per_wave = win.cpw;
-        best->ms = wms;
+    report_tuning(win, wms, best);
+    return VC_OK;
+}
+
+vc_status vc_batch_tune_members(vc_batch *b, vc_result *r, const int64_t *members, int64_t m, void *stream,
+                                vc_tuning *best)
+{
+    if (!b || !r || !members || m < 1) return fail(VC_E_ARG, "vc_batch_tune_members: null or empty argument");
+    if (r->c != b) return fail(VC_E_STATE, "vc_batch_tune_members: result was created for another batch");
+    const int64_t nt = (int64_t)b->htess.size();
+    std::vector<int32_t> all;
+    for (int64_t k = 0; k < m; k++) {
+        if (members[k] < 0 || members[k] >= nt)
+            return fail(VC_E_RANGE, "vc_batch_tune_members: member %lld outside [0, %lld)", (long long)members[k],
+                        (long long)nt);
+        // a tessellation's cells are contiguous in block order
+        const Tess &T = b->htess[(size_t)members[k]];
+        for (int64_t i = T.pbase; i < (int64_t)T.pbase + T.pcount; i++) all.push_back((int32_t)i);
     }
+    std::vector<int32_t> v;
+    tuning_sample(0, (int64_t)all.size(), std::max<int64_t>((int64_t)all.size() / 16, 1 << 18), v);
+    for (auto &x : v) x = all[(size_t)x];
+    int32_t *list = nullptr, *full = nullptr;
+    vc_status st = dalloc(&list, v.size());
+    if (!st) st = dalloc(&full, all.size());
+    Launch win = b->launch;
+    float wms = 0.f;
+    if (!st) {
+        hipError_t e = hipMemcpy(list, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(full, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) st = fail(VC_E_HIP, "vc_batch_tune_members: copy of the sample failed");
+        else st = tune(b, r, (hipStream_t)stream, list, (int)v.size(), full, (int)all.size(), win, wms);
+    }
+    if (list) (void)hipFree(list);
+    if (full) (void)hipFree(full);
+    if (st) return st;
+    b->launch = win;
+    release_graph(b);
+    report_tuning(win, wms, best);
     return VC_OK;
 }
 
@@ -1066,7 +1182,7 @@ vc_status vc_tessellate_noalloc(const double *xyz, int64_t n, const vc_options *
     A.queue = queue;
     A.chunk = opt->chunk > 0 ? opt->chunk : 4;
     A.vcap = opt->capacity;
-    A.tau = 0x1p-30;
+    set_bands(A, opt->force);
     A.mask = (vol ? VC_VOLUME : 0) | (cen ? VC_CENTROID : 0) | (nv || ne ? VC_COUNTS : 0) | (fo ? VC_FACE_ORDERS : 0) |
              VC_NEIGHBOR_COUNT;
     A.vol = vol;

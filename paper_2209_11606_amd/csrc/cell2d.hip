@@ -179,7 +179,7 @@ __device__ __forceinline__ int p_consider(const CellArgs &A, L2<G, S, MAXL> &sh,
     int ntest = 0;
     if (F32) {
         const float g0 = (float)q0, g1 = (float)q1, gh = (float)h;
-        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1)) * ((float)c.R * 1.0000001f) + fabsf(gh));
+        const float band32 = A.tau32 * ((fabsf(g0) + fabsf(g1)) * ((float)c.R * 1.0000001f) + fabsf(gh));
         unsigned long long uns = 0, unsr[S];
 #pragma unroll
         for (int s = 0; s < S; s++) {

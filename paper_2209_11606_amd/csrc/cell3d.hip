@@ -171,7 +171,7 @@ __device__ __forceinline__ int consider(const CellArgs &A, CellLDS<S, MAXP, K> &
     int ntest = 0;
     if (F32) {
         const float g0 = (float)q0, g1 = (float)q1, g2 = (float)q2, gh = (float)h;
-        const float band32 = 0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + fabsf(gh));
+        const float band32 = A.tau32 * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + fabsf(gh));
         unsigned long long uns = 0;
         unsigned long long unsr[S];
 #pragma unroll

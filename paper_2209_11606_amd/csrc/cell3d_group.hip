@@ -631,7 +631,7 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP, RAD> 
         if (F32) {
             const float g0 = (float)a0, g1 = (float)a1, g2 = (float)a2, gh = (float)h;
             sh.u.w.x.cfb[rank] =
-                0x1p-21f * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + fabsf(gh));
+                A.tau32 * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + fabsf(gh));
         }
         if (RAD) sh.u.w.crj[rank] = rj;
         sh.u.w.cid[rank] = pid;

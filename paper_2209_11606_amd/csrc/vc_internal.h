@@ -94,6 +94,7 @@ struct CellArgs {
     int chunk;                 // cells per queue grab
     int vcap;                  // > 0: a cell with more live vertices moves to the spill pass
     double tau;                // FP64 band, relative
+    float tau32;               // FP32 band of the filter, relative
     const double *rad;         // radii by sorted index (radical tessellation), or NULL
     const double *rmax;        // largest radius (device scalar)
     uint32_t mask;             // statistics mask

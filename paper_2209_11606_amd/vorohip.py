@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("VOROHIP_LIB") or os.path.join(
     _HERE, "libvorohip_phase.so" if os.environ.get("VOROHIP_PHASE_CLOCKS") == "1" else "libvorohip.so")
 
 VC_OK, VC_E_ARG, VC_E_RANGE, VC_E_DUPLICATE, VC_E_NOMEM, VC_E_HIP, VC_E_CAPACITY, VC_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+VC_FORCE_RECHECK, VC_FORCE_EXACT = 1, 2
 VC_CELL_OK, VC_CELL_SPILLED, VC_CELL_CAPACITY, VC_CELL_DUPLICATE, VC_CELL_SKIPPED, VC_CELL_EMPTY = 0, 1, 2, 3, 4, 5
 VC_CELL_FO_OVERFLOW = 64  # flag bit on a complete cell with a face of 32 or more edges
 VC_CELL_RANGE = 6  # vc_tessellate_noalloc: a coordinate outside the box
@@ -45,12 +46,12 @@ class vc_options(ctypes.Structure):
                 ("periodic", ctypes.c_int * 3), ("n_opt", ctypes.c_double), ("grid", ctypes.c_int * 3),
                 ("precision", ctypes.c_int), ("slots", ctypes.c_int), ("waves", ctypes.c_int),
                 ("chunk", ctypes.c_int), ("cells_per_wave", ctypes.c_int), ("clip", ctypes.c_double),
-                ("capacity", ctypes.c_int)]
+                ("capacity", ctypes.c_int), ("force", ctypes.c_int)]
 
 
 class vc_tuning(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int), ("waves", ctypes.c_int), ("chunk", ctypes.c_int),
-                ("cells_per_wave", ctypes.c_int), ("ms", ctypes.c_float)]
+                ("cells_per_wave", ctypes.c_int), ("ms", ctypes.c_float), ("capacity", ctypes.c_int)]
 
 
 class VcError(RuntimeError):
@@ -85,6 +86,7 @@ def _load():
         "vc_batch_result_create": (I32, [P, U32, P]),
         "vc_batch_compute": (I32, [P, P, I32, P]),
         "vc_batch_tune": (I32, [P, P, P, P]),
+        "vc_batch_tune_members": (I32, [P, P, P, I64, P, P]),
         "vc_batch_destroy": (None, [P]),
         "vc_result_kernel_ms": (I32, [P, P]),
         "vc_last_error": (ctypes.c_char_p, []),
@@ -104,7 +106,8 @@ EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_
             "vc_batch_set_radii", "vc_grid_size", "vc_container_blocks",
             "vc_result_create", "vc_compute", "vc_compute_subset",
             "vc_result_get", "vc_result_copy", "vc_result_kernel_ms", "vc_result_destroy", "vc_container_destroy", "vc_batch_create",
-            "vc_batch_rebin", "vc_batch_result_create", "vc_batch_compute", "vc_batch_tune", "vc_batch_destroy",
+            "vc_batch_rebin", "vc_batch_result_create", "vc_batch_compute", "vc_batch_tune", "vc_batch_tune_members",
+            "vc_batch_destroy",
             "vc_last_error", "vc_version", "vc_device_fma_rate", "vc_tessellate_noalloc"]
 
 
@@ -139,7 +142,10 @@ def vc_options_init(dim, lo, hi, periodic, **kw):
     hi_a = (ctypes.c_double * 3)(*[float(v) for v in hi])
     pe_a = (ctypes.c_int * 3)(*[int(bool(v)) for v in periodic])
     _check(_lib.vc_options_init(ctypes.byref(o), dim, lo_a, hi_a, pe_a))
+    names = {f for f, _ in vc_options._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"vc_options has no field {k!r}")
         if k == "grid":
             for d, g in enumerate(v):
                 o.grid[d] = int(g)
@@ -290,10 +296,24 @@ def vc_batch_compute(b, r, graph=False, stream=None):
     _check(_lib.vc_batch_compute(b, r, int(bool(graph)), ctypes.c_void_p(_stream_ptr(stream))))
 
 
+def _tuning(t):
+    return dict(slots=t.slots, waves=t.waves, chunk=t.chunk, cells_per_wave=t.cells_per_wave, ms=t.ms,
+                capacity=t.capacity)
+
+
 def vc_batch_tune(b, r, stream=None):
     t = vc_tuning()
     _check(_lib.vc_batch_tune(b, r, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(t)))
-    return dict(slots=t.slots, waves=t.waves, chunk=t.chunk, cells_per_wave=t.cells_per_wave, ms=t.ms)
+    return _tuning(t)
+
+
+def vc_batch_tune_members(b, r, members, stream=None):
+    """Tune on the cells of the listed tessellations only (a class of input)."""
+    m = np.ascontiguousarray(np.asarray(members, dtype=np.int64))
+    t = vc_tuning()
+    _check(_lib.vc_batch_tune_members(b, r, m.ctypes.data, len(m), ctypes.c_void_p(_stream_ptr(stream)),
+                                      ctypes.byref(t)))
+    return _tuning(t)
 
 
 def vc_tessellate_noalloc(xyz, opts, out, stream=None):

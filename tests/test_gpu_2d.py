@@ -120,3 +120,22 @@ def test_2d_forced_spill(v, per):
     g = run(v, x, [0, 0], [1, 1], per, capacity=2)
     assert np.all(g["status"] == 1) and g["diag"]["spilled"] == 5000
     parity2(g, oracle.Oracle(x, [0, 0], [1, 1], per).cells())
+
+
+@pytest.mark.parametrize("per", [[1, 1], [0, 0]])
+def test_2d_forced_recheck_and_exact(v, per):
+    """Every 2D side decision through the FP64 recheck and through the exact
+    predicate: the same cells, bit for bit, as with the default bands, and
+    the oracle's."""
+    x = W.uniform(4000, 2, 1.0, 64)
+    base = run(v, x, [0, 0], [1, 1], per)
+    parity2(base, oracle.Oracle(x, [0, 0], [1, 1], per).cells())
+    for prec, force in ((v.VC_F32_FILTER, v.VC_FORCE_RECHECK), (v.VC_FP64, v.VC_FORCE_EXACT)):
+        g = run(v, x, [0, 0], [1, 1], per, precision=prec, force=force)
+        for k in ("vol", "cen", "perim", "nv", "ne", "nf", "status", "nbr_off", "nbr_ids", "nbr_sh"):
+            assert np.array_equal(g[k], base[k]), k
+        d = g["diag"]
+        if force == v.VC_FORCE_RECHECK:
+            assert d["recheck"] == d["tests"] > 0
+        else:
+            assert d["exact"] >= d["tests"] > 0

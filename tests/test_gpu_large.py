@@ -40,14 +40,17 @@ def test_fcc_10m_perturbed(v):
     for k in ("vol", "cen", "nv", "ne", "nf", "fo", "nbr_off", "nbr_ids", "nbr_sh"):
         assert np.array_equal(a[k], b[k]), k
     print("fcc10m diag fp64", a["diag"], "f32", b["diag"], flush=True)
+    # the FP32 filter defers a small, nonzero share of its tests to FP64, and
+    # some FP64 decisions fall in the band and are taken exactly
+    rate = b["diag"]["recheck"] / b["diag"]["tests"]
+    print(f"fcc10m FP32 recheck rate {rate:.3e}, exact decisions {a['diag']['exact']}", flush=True)
+    assert 1e-6 < rate < 1e-2
+    assert a["diag"]["exact"] > 0
     idx = np.random.default_rng(2).choice(n, 1500, replace=False)
     r = oracle.Oracle(x, w["lo"], w["hi"], w["periodic"]).cells(idx, nthreads=oracle.num_threads())
-    nb = v.neighbor_lists(a)
-    assert np.array_equal(a["nf"][idx], r["nf"]) and np.array_equal(a["nv"][idx], r["nv"])
-    assert np.array_equal(a["fo"][idx], r["fo"])
-    for t, i in enumerate(idx):
-        assert np.array_equal(nb[i], r["nbr"][t])
-    assert np.max(np.abs(a["vol"][idx] - r["vol"]) / r["vol"]) <= 1e-12
+    from test_gpu_parity import assert_parity
+    a["nbr"] = v.neighbor_lists(a)
+    assert_parity(a, r, idx)  # counts, face orders, neighbours, volume and centroid
 
 
 def test_uniform_102m_reduced_mask(v):

@@ -262,3 +262,36 @@ def test_forced_spill_periodic_20k(v):
     k = int(np.sum(h["status"] == v.VC_CELL_SPILLED))
     assert 0 < k < 20000 and h["diag"]["spilled"] == k
     assert_parity(h, r)
+
+
+@pytest.mark.parametrize("form", [dict(), dict(slots=4), dict(cells_per_wave=2), dict(cells_per_wave=4)])
+def test_forced_recheck_and_exact(v, form):
+    """The slow stages of the side test taken on every decision: with
+    VC_FORCE_RECHECK every FP32 filter test is re-done in FP64 (the recheck
+    counter equals the test counter), with VC_FORCE_EXACT every FP64
+    decision goes to the exact predicate (the exact counter reaches the test
+    counter).  The cells are bit for bit those of the default bands and
+    equal the oracle's, on a periodic and on a walled set."""
+    for per, seed in (([1, 1, 1], 17), ([0, 0, 0], 18)):
+        side = 4000 ** (1 / 3)
+        x = W.uniform(4000, 3, side, seed)
+        box = ([0] * 3, [side] * 3, per)
+        base = run(v, x, *box, **form)
+        assert_parity(base, oracle.Oracle(x, *box).cells(nthreads=oracle.num_threads()))
+        f = run(v, x, *box, precision=v.VC_F32_FILTER, force=v.VC_FORCE_RECHECK, **form)
+        same_bits(base, f)
+        assert f["diag"]["recheck"] == f["diag"]["tests"] > 0
+        e = run(v, x, *box, force=v.VC_FORCE_EXACT, **form)
+        same_bits(base, e)
+        assert e["diag"]["exact"] >= e["diag"]["tests"] > 0
+        fe = run(v, x, *box, precision=v.VC_F32_FILTER, force=v.VC_FORCE_RECHECK | v.VC_FORCE_EXACT, **form)
+        same_bits(base, fe)
+        assert fe["diag"]["exact"] >= fe["diag"]["recheck"] == fe["diag"]["tests"]
+
+
+def test_force_bits_checked(v):
+    """Bits outside VC_FORCE_RECHECK | VC_FORCE_EXACT are refused."""
+    x = W.uniform(100, 3, 1.0, 3)
+    with pytest.raises(v.VcError) as e:
+        run(v, x, [0] * 3, [1] * 3, [0] * 3, force=4)
+    assert e.value.code == v.VC_E_ARG
