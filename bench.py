@@ -75,6 +75,10 @@ def parse():
     p.add_argument("--phase-clocks", action="store_true",
                    help="load the library built with the grouped cell kernel's phase profile "
                         "(python -m paper_2209_11606_amd.build --phase-clocks) and report cycles per phase")
+    p.add_argument("--slabs", type=int, default=None,
+                   help="also time the chunked form with this many container-block chunks along z "
+                        "(default: 8 for periodic102m, none otherwise)")
+    p.add_argument("--halo", type=int, default=3, help="layers of blocks on each side of a chunk")
     p.add_argument("--workload", default="periodic1m",
                    choices=["periodic1m", "batch4096", "fcc10m", "periodic2d10m", "periodic102m",
                             "localized10m", "localized10m_unclipped", "localized100k_unclipped", "localized2d10m", "clustered10m",
@@ -85,8 +89,8 @@ def parse():
 
 def kernel_key(precision_name, tuned):
     """Which cell kernel a variant ran: cells per wave and slots per lane."""
-    cpw = tuned["cells_per_wave"] if tuned else 1
-    slots = tuned["slots"] if tuned else 2
+    cpw = tuned.get("cells_per_wave", 1) if tuned else 1
+    slots = tuned.get("slots", 2) if tuned else 2
     return f"{precision_name},cpw={cpw}" + (f",slots={slots}" if cpw == 1 else "")
 
 
@@ -172,6 +176,33 @@ def time_variant(v, torch, xt, w, precision, steps, warmup, mask, sample=None):
     finally:
         v.vc_result_destroy(r)
         v.vc_container_destroy(c)
+    return out
+
+
+def time_chunked(v, torch, xt, w, precision, steps, warmup, mask, nslab, halo, sample=None, launch=None):
+    """Chunked form (vc_tessellate_slabs): step = every cell of the set, in
+    nslab container-block chunks along z with `halo` layers on each side,
+    each chunk binned on its own with the set's grid."""
+    stream = torch.cuda.current_stream()
+    kw = dict(precision=precision)
+    if launch:
+        kw.update({k: launch[k] for k in ("cells_per_wave", "slots", "waves", "chunk", "capacity")})
+    o = options(v, w, **kw)
+    held = []
+
+    def step():
+        while held:
+            v.vc_result_destroy(held.pop())
+        held.append(v.vc_tessellate_slabs(xt, o, mask, nslab, halo, stream))
+    try:
+        for _ in range(warmup):
+            step()
+        ms = _timed(torch, stream, steps, step)
+        out = _summary(v, held[0], ms, v.vc_result_kernel_ms(held[0]), sample)
+        out["tuned"] = dict(launch or {}, chunks=nslab, halo=halo)
+    finally:
+        while held:
+            v.vc_result_destroy(held.pop())
     return out
 
 
@@ -563,6 +594,9 @@ def main():
         variants += [("fp64", v.VC_FP64, False), ("f32_filter", v.VC_F32_FILTER, False)]
     if dim == 3:
         variants += [("fp64_batched", v.VC_FP64, True), ("f32_filter_batched", v.VC_F32_FILTER, True)]
+    nslab = a.slabs if a.slabs is not None else (8 if a.workload == "periodic102m" else 0)
+    if nslab > 0 and dim == 3 and len(members) == 1:
+        variants += [("fp64_chunked", v.VC_FP64, "chunked")]
     if a.variants != "all":
         keep = set(a.variants.split(","))
         variants = [x for x in variants if x[0] in keep]
@@ -570,7 +604,11 @@ def main():
     if not a.no_cpu_baseline:
         sample = np.concatenate([g for _, _, g in sample_cells(members, a.cpu_sample)])
     for name, prec, batched in variants:
-        if batched:
+        if batched == "chunked":
+            tuned = res.get("fp64_batched", {}).get("tuned")
+            res[name] = time_chunked(v, torch, xt, members[0], prec, a.steps, a.warmup, mask, nslab, a.halo,
+                                     sample, launch=tuned)
+        elif batched:
             opts = [options(v, m, precision=prec) for m in members]
             radii = None
             if members[0].get("radii") is not None:

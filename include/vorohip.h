@@ -130,8 +130,10 @@ enum {
     VC_D_FALLBACK = 8,    /* cells that searched beyond the precomputed offsets */
     VC_D_SHELLS = 9,      /* Chebyshev shells of blocks searched beyond them
                              (section 2.1.3: the block bound ends the search) */
-    VC_D_LOADED = 10      /* particles loaded from the blocks (before the radius
+    VC_D_LOADED = 10,     /* particles loaded from the blocks (before the radius
                              and ball tests) */
+    VC_D_RECOMPUTED = 11  /* vc_tessellate_slabs: cells computed again with a
+                             wider halo */
     /* slots 16..31 are written only by a library built with the phase
        profile of the grouped cell kernel (VC_PHASE_CLOCKS): 16 + k holds the
        shader-clock cycles its waves spent in phase k (0 claim a cell and set
@@ -250,6 +252,33 @@ vc_status vc_compute(vc_container *c, vc_result *r, void *stream);
  * checked on the device, and the call then waits for that check).  A repeated
  * index computes its cell twice. */
 vc_status vc_compute_subset(vc_container *c, vc_result *r, const int64_t *ids, int64_t m, void *stream);
+
+/* The cells of one large 3D set computed in container-block chunks along z,
+ * with scratch memory for one chunk at a time instead of the whole set (the
+ * container's blocks of section 2.1.4 taken as the unit of work, as the
+ * paper's parallel schedules take them, section 2.2.4).  The grid is the
+ * set's own (vc_options as for vc_container_create).  Its layers of blocks
+ * along z are cut into nslab chunks of about equal size; a chunk's container
+ * holds the particles of its layers and of `halo` more layers on each side
+ * (wrapped on a periodic z axis), binned on the set's grid, and computes the
+ * cells of its own particles.  A particle beyond the widened range is
+ * farther than a finished cell's search radius (section 2.1.3) unless the
+ * cell's radius reaches past an end of the range; such cells are computed
+ * again with the halo doubled until none is left.  So every cell equals the
+ * one vc_compute gives on the whole set (topology and face orders exactly,
+ * volume and centroid to rounding: candidates enter in the same order, but
+ * a cell computed again may take them in a different one).
+ *
+ * xyz: n x 3 positions, device or host (host ones are copied to the device
+ * first); nslab >= 1 (at most the number of layers), halo >= 1 layers.  mask:
+ * VC_VOLUME, VC_CENTROID, VC_COUNTS, VC_FACE_ORDERS, VC_NEIGHBOR_COUNT and
+ * VC_DIAG only (other bits are VC_E_ARG).  *out receives a new result of n cells by
+ * input index, owned by the caller (vc_result_destroy); it belongs to no
+ * container, and vc_result_kernel_ms gives the time of the whole chunked
+ * computation.  Errors as for vc_container_create; the call returns when
+ * the cells are computed. */
+vc_status vc_tessellate_slabs(const double *xyz, int64_t n, const vc_options *opt, uint32_t mask, int nslab, int halo,
+                              void *stream, vc_result **out);
 
 /* Elapsed time in milliseconds of the main cell kernel of the last
  * vc_compute on r (HIP events recorded around that launch on its stream).

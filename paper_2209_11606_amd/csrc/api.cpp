@@ -885,6 +885,251 @@ vc_status vc_compute_subset(vc_container *c, vc_result *r, const int64_t *ids, i
     return enqueue_compute(c, r, s, true, c->launch, c->subset, (int)m, true);
 }
 
+// ---------------------------------------------------------------------------
+// The chunked form (container-block chunks along z, for one large 3D set).
+// Chunk j owns the layers [k0, k1) of the set's grid along z; its container
+// holds the particles of [k0 - h, k1 + h) (wrapped on a periodic axis) on the
+// full set's grid, so its blocks, in-block order and relative vectors are
+// the full set's, and the cells of its own particles are computed there with
+// the outputs written by input index.  A cell whose search radius reaches
+// past the widened range is flagged (kStatusSlab) and computed again in a later
+// pass with the halo doubled, until none is left; a range that covers every
+// layer needs no certificate.  Scratch is the chunk's, not the set's.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct SlabBufs {
+    int64_t cap = 0;
+    double *xyz = nullptr;
+    int32_t *orig = nullptr;
+    uint8_t *own = nullptr;
+    int32_t *list = nullptr;
+    int64_t tcap = 0;  // pick tiles
+    int32_t *cnt = nullptr, *start = nullptr, *tmp = nullptr;
+    double *lim = nullptr;  // each computed cell's squared search radius, by sorted index
+    ~SlabBufs()
+    {
+        void *ps[] = {xyz, orig, own, list, cnt, start, tmp, lim};
+        for (void *p : ps)
+            if (p) (void)hipFree(p);
+    }
+    vc_status reserve_tiles(int64_t items)
+    {
+        const int64_t t = pick_tiles(items);
+        if (t <= tcap) return VC_OK;
+        void *ps[] = {cnt, start, tmp};
+        for (void *p : ps)
+            if (p) (void)hipFree(p);
+        cnt = start = tmp = nullptr;
+        vc_status st;
+        if ((st = dalloc(&cnt, (size_t)t)) || (st = dalloc(&start, (size_t)t + 1)) ||
+            (st = dalloc(&tmp, (size_t)((t + 2047) / 2048 + 2) * 2)))
+            return st;
+        tcap = t;
+        return VC_OK;
+    }
+    vc_status reserve(int64_t m)
+    {
+        if (m <= cap) return VC_OK;
+        void *ps[] = {xyz, orig, own, list, lim};
+        for (void *p : ps)
+            if (p) (void)hipFree(p);
+        xyz = nullptr;
+        orig = nullptr;
+        own = nullptr;
+        list = nullptr;
+        lim = nullptr;
+        vc_status st;
+        if ((st = dalloc(&xyz, (size_t)m * 3)) || (st = dalloc(&orig, (size_t)m)) || (st = dalloc(&own, (size_t)m)) ||
+            (st = dalloc(&list, (size_t)m)) || (st = dalloc(&lim, (size_t)m)))
+            return st;
+        cap = m;
+        return VC_OK;
+    }
+};
+
+int32_t read_i32(const int32_t *d, hipStream_t s, hipError_t &e)
+{
+    int32_t v = 0;
+    e = hipMemcpyAsync(&v, d, sizeof v, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return v;
+}
+
+// one chunk: select, bin on the full grid, compute the wanted cells of its
+// own layers into r (by input index)
+vc_status slab_pass(const double *dxyz, int64_t n, const vc_options &opt, const Grid &G, int k0, int k1, int h,
+                    const uint8_t *want, vc_result *r, SlabBufs &B, hipStream_t s)
+{
+    const int nz = G.g[2];
+    const int klen = k1 - k0;
+    int e0 = k0 - h, elen = klen + 2 * h;
+    bool cert = true;
+    double zlo = -1e300, zhi = 1e300;
+    if (G.per[2]) {
+        if (elen >= nz) {
+            e0 = 0;
+            elen = nz;
+            cert = false;
+        } else {
+            e0 = ((e0 % nz) + nz) % nz;
+            zlo = G.lo[2] + e0 * G.bs[2];
+            zhi = G.lo[2] + ((e0 + elen) % nz) * G.bs[2];
+        }
+    } else {
+        const int e1 = std::min(nz, k1 + h);
+        e0 = std::max(0, e0);
+        elen = e1 - e0;
+        if (e0 > 0) zlo = G.lo[2] + e0 * G.bs[2];
+        if (e1 < nz) zhi = G.lo[2] + e1 * G.bs[2];
+        cert = e0 > 0 || e1 < nz;
+    }
+    hipError_t he;
+    vc_status st;
+    // cells wanted in this chunk
+    if ((st = B.reserve_tiles(n))) return st;
+    HIP_TRY(launch_own_count(dxyz, n, G, k0, klen, want, kStatusSlab, B.cnt, B.start, B.tmp, s));
+    const int32_t nown = read_i32(B.start + pick_tiles(n), s, he);
+    HIP_TRY(he);
+    if (nown == 0) return VC_OK;
+    // the widened range's particles, in input order
+    HIP_TRY(launch_slab_pick(dxyz, n, G, e0, elen, k0, klen, want, kStatusSlab, nullptr, nullptr, nullptr, B.cnt, B.start,
+                             B.tmp, false, s));
+    const int32_t m = read_i32(B.start + pick_tiles(n), s, he);
+    HIP_TRY(he);
+    if ((st = B.reserve(m))) return st;
+    HIP_TRY(launch_slab_pick(dxyz, n, G, e0, elen, k0, klen, want, kStatusSlab, B.xyz, B.orig, B.own, B.cnt, B.start,
+                             B.tmp, true, s));
+    // the chunk's container on the full set's grid
+    vc_options o = opt;
+    for (int d = 0; d < 3; d++) o.grid[d] = G.g[d];
+    vc_container *c = new (std::nothrow) vc_container();
+    if (!c) return fail(VC_E_NOMEM, "host allocation failed");
+    const int64_t offsets[2] = {0, m};
+    st = create_common(c, B.xyz, offsets, 1, &o, s);
+    if (!st) {
+        st = [&]() -> vc_status {
+            // the wanted cells' sorted slots, then the set's input indices
+            if ((st = B.reserve_tiles(m))) return st;
+            HIP_TRY(launch_slot_list(c->part, B.own, m, B.list, B.cnt, B.start, B.tmp, s));
+            HIP_TRY(launch_remap_ids(c->part, m, B.orig, s));
+            const int32_t nl = read_i32(B.start + pick_tiles(m), s, he);
+            HIP_TRY(he);
+            CellArgs A = cell_args(c, r);
+            A.cell_list = B.list;
+            A.ncell = nl;
+            A.vcap = c->launch.vcap;
+            if (cert) A.lim_out = B.lim;
+            const Launch &L = c->launch;
+            HIP_TRY(launch_fill_i32(c->queue, 8, 0, s));
+            if (L.cpw > 1) HIP_TRY(launch_cells_group(A, c->precision, L.cpw, std::min(L.waves, c->max_waves), s));
+            else HIP_TRY(launch_cells(A, c->precision, L.slots, std::min(L.waves, c->max_waves), s));
+            CellArgs Bs = A;
+            Bs.cell_list = c->spill_list;
+            Bs.queue = c->queue + 1;
+            Bs.ncell_dev = c->queue + 2;
+            Bs.ncell = (int)c->n;
+            Bs.chunk = 1;
+            Bs.vcap = 0;
+            HIP_TRY(launch_cells_spill(Bs, std::min(c->max_waves, 1024), s));
+            if (cert)
+                HIP_TRY(launch_slab_cert(c->part, B.list, nl, B.lim, zlo, zhi, G.per[2] ? G.L[2] : 0.0,
+                                         0x1p-40 * (std::fabs(G.lo[2]) + std::fabs(G.hi[2]) + G.L[2]),
+                                         (uint8_t)kStatusSlab, r->status, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            return VC_OK;
+        }();
+    }
+    free_container(c);
+    return st;
+}
+
+}  // namespace
+
+vc_status vc_tessellate_slabs(const double *xyz, int64_t n, const vc_options *opt, uint32_t mask, int nslab, int halo,
+                              void *stream, vc_result **out)
+{
+    if (!out) return fail(VC_E_ARG, "vc_tessellate_slabs: out is null");
+    *out = nullptr;
+    if (!xyz) return fail(VC_E_ARG, "vc_tessellate_slabs: xyz is null");
+    vc_status st = check_options(opt);
+    if (st) return st;
+    if (opt->dim != 3) return fail(VC_E_ARG, "vc_tessellate_slabs: the chunked form is 3D (dim = %d)", opt->dim);
+    if (n < 1 || n > INT32_MAX / 2) return fail(VC_E_ARG, "vc_tessellate_slabs: n = %lld out of range", (long long)n);
+    if (nslab < 1 || halo < 1) return fail(VC_E_ARG, "vc_tessellate_slabs: need nslab >= 1 and halo >= 1");
+    if (mask & ~(uint32_t)(VC_VOLUME | VC_CENTROID | VC_COUNTS | VC_FACE_ORDERS | VC_NEIGHBOR_COUNT | VC_DIAG))
+        return fail(VC_E_ARG, "vc_tessellate_slabs: mask 0x%x: the chunked form gives per-cell fields only "
+                              "(no neighbour lists, perimeters or Weinberg codes)", mask);
+    hipStream_t s = (hipStream_t)stream;
+    const Grid G = size_grid(*opt, n);
+    const int nz = G.g[2];
+    nslab = std::min(nslab, nz);
+    // the positions on the device (the caller's, or a copy of host ones)
+    double *dcopy = nullptr;
+    const double *dxyz = xyz;
+    if (!is_device_ptr(xyz)) {
+        if ((st = dalloc(&dcopy, (size_t)n * 3))) return st;
+        HIP_TRY(hipMemcpyAsync(dcopy, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+        dxyz = dcopy;
+    }
+    // a fake one-particle container describes the result's shape
+    vc_container shape;
+    shape.dim = 3;
+    shape.n = n;
+    vc_result *r = nullptr;
+    int32_t *flag = nullptr;
+    st = result_create(&shape, mask, &r);
+    if (!st) st = dalloc(&flag, 2);
+    if (!st) {
+        st = [&]() -> vc_status {
+            hipError_t he;
+            HIP_TRY(launch_fill_i32(flag, 2, 0, s));
+            HIP_TRY(launch_range_check(dxyz, n, G, flag, s));
+            if (read_i32(flag, s, he)) {
+                HIP_TRY(he);
+                return fail(VC_E_RANGE, "a coordinate lies outside the box (walled: lo <= x <= hi, periodic: lo <= x "
+                                        "< hi) or is not finite");
+            }
+            HIP_TRY(he);
+            HIP_TRY(launch_fill_u8(r->status, n, 0, s));
+            HIP_TRY(launch_fill_i32((int32_t *)r->diag, VC_DIAG_LEN * 2, 0, s));
+            HIP_TRY(hipEventRecord(r->ev0, s));
+            SlabBufs B;
+            const uint8_t *want = nullptr;  // the first pass computes every cell
+            unsigned long long again = 0;     // cells computed again
+            for (int h = halo;; h *= 2) {
+                for (int j = 0; j < nslab; j++) {
+                    const int k0 = (int)((int64_t)j * nz / nslab), k1 = (int)((int64_t)(j + 1) * nz / nslab);
+                    vc_status e = slab_pass(dxyz, n, *opt, G, k0, k1, h, want, r, B, s);
+                    if (e) return e;
+                }
+                HIP_TRY(launch_fill_i32(flag + 1, 1, 0, s));
+                HIP_TRY(launch_count_bit(r->status, n, kStatusSlab, flag + 1, s));
+                const int32_t left = read_i32(flag + 1, s, he);
+                HIP_TRY(he);
+                if (left == 0) break;
+                again += (unsigned long long)left;
+                want = r->status;  // again, only the flagged cells
+                if (h > 2 * nz) return fail(VC_E_STATE, "vc_tessellate_slabs: %d cells stayed unfinished", left);
+            }
+            HIP_TRY(hipEventRecord(r->ev1, s));
+            HIP_TRY(hipMemcpyAsync(r->diag + VC_D_RECOMPUTED, &again, sizeof again, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            r->last_stream = s;
+            return VC_OK;
+        }();
+    }
+    if (flag) (void)hipFree(flag);
+    if (dcopy) (void)hipFree(dcopy);
+    if (st) {
+        free_result(r);
+        return st;
+    }
+    r->c = nullptr;
+    *out = r;
+    return VC_OK;
+}
+
 vc_status vc_result_kernel_ms(vc_result *r, float *ms)
 {
     if (!r || !ms) return fail(VC_E_ARG, "vc_result_kernel_ms: null pointer");

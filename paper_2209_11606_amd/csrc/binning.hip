@@ -291,6 +291,175 @@ int grid_for(int64_t n)
     return (int)g;
 }
 
+// ---------------------------------------------------------------------------
+// The chunked form (container-block chunks along z).  A chunk is a range of
+// layers of blocks along z; its container holds the particles of the range
+// widened by a halo of layers on each side (wrapped on a periodic axis).
+// Selection keeps the input order (per-tile counts, a scan, then each tile
+// writes its picks in order), so the chunk's in-block order is the full
+// set's.
+// ---------------------------------------------------------------------------
+constexpr int kPickTile = 1024;
+
+// layer k lies in the range of `len` layers from `first` (on a periodic axis
+// the range wraps around the g layers)
+__device__ __forceinline__ bool in_layers(int k, int first, int len, int g, int per)
+{
+    if (per) return ((k - first) % g + g) % g < len;
+    return k >= first && k < first + len;
+}
+
+struct SlabPick {
+    const double *xyz;
+    Grid G;
+    int e0, elen;            // the widened range of layers
+    int k0, klen;            // the chunk's own layers
+    const uint8_t *want;     // NULL: every particle of the chunk; else those with (want[i] & wbit)
+    uint8_t wbit;
+    double *oxyz;            // selected positions, input order
+    int32_t *orig;           // their input indices
+    uint8_t *own;            // 1: a particle of the chunk whose cell is wanted
+    __device__ int layer(int64_t i) const { return block_coord(G, xyz[3 * i + 2], 2); }
+    __device__ bool pick(int64_t i) const { return in_layers(layer(i), e0, elen, G.g[2], G.per[2]); }
+    __device__ void emit(int64_t i, int64_t pos) const
+    {
+        oxyz[3 * pos + 0] = xyz[3 * i + 0];
+        oxyz[3 * pos + 1] = xyz[3 * i + 1];
+        oxyz[3 * pos + 2] = xyz[3 * i + 2];
+        orig[pos] = (int32_t)i;
+        const bool mine = in_layers(layer(i), k0, klen, G.g[2], G.per[2]) && (!want || (want[i] & wbit));
+        own[pos] = mine ? 1 : 0;
+    }
+};
+
+// the particles of the chunk whose cells are wanted (counted only)
+struct OwnPick {
+    const double *xyz;
+    Grid G;
+    int k0, klen;
+    const uint8_t *want;
+    uint8_t wbit;
+    __device__ bool pick(int64_t i) const
+    {
+        return in_layers(block_coord(G, xyz[3 * i + 2], 2), k0, klen, G.g[2], G.per[2]) && (!want || (want[i] & wbit));
+    }
+    __device__ void emit(int64_t, int64_t) const {}
+};
+
+// sorted slots whose particle is wanted, in slot order (part[s].id is the
+// particle's index in the chunk: taken before the ids are remapped)
+struct SlotPick {
+    const Particle *part;
+    const uint8_t *own;
+    int32_t *list;
+    __device__ bool pick(int64_t s) const { return own[part[s].id] != 0; }
+    __device__ void emit(int64_t s, int64_t pos) const { list[pos] = (int32_t)s; }
+};
+
+template <class P>
+__global__ __launch_bounds__(kTB) void k_pick_count(P p, int64_t n, int32_t *__restrict__ cnt)
+{
+    __shared__ int wsum[kTB / 64];
+    const int64_t base = (int64_t)blockIdx.x * kPickTile;
+    int c = 0;
+    for (int j = 0; j < kPickTile / kTB; j++) {
+        const int64_t i = base + (int64_t)j * kTB + threadIdx.x;
+        if (i < n && p.pick(i)) c++;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kTB / 64; w++) t += wsum[w];
+        cnt[blockIdx.x] = t;
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(kTB) void k_pick_scatter(P p, int64_t n, const int32_t *__restrict__ start)
+{
+    __shared__ int wsum[kTB / 64];
+    const int64_t base = (int64_t)blockIdx.x * kPickTile;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t off = start[blockIdx.x];
+    for (int j = 0; j < kPickTile / kTB; j++) {
+        const int64_t i = base + (int64_t)j * kTB + threadIdx.x;
+        const bool pk = i < n && p.pick(i);
+        const unsigned long long b = __ballot(pk);
+        if (lane == 0) wsum[w] = __popcll(b);
+        __syncthreads();
+        int before = 0, tot = 0;
+        for (int k = 0; k < kTB / 64; k++) {
+            if (k < w) before += wsum[k];
+            tot += wsum[k];
+        }
+        if (pk) p.emit(i, off + before + __popcll(b & ((1ull << lane) - 1ull)));
+        off += tot;
+        __syncthreads();
+    }
+}
+
+// the chunk container's particles carry the full set's input indices
+__global__ __launch_bounds__(kTB) void k_remap_ids(Particle *__restrict__ part, int64_t m,
+                                                   const int32_t *__restrict__ orig)
+{
+    for (int64_t s = (int64_t)blockIdx.x * kTB + threadIdx.x; s < m; s += (int64_t)gridDim.x * kTB)
+        part[s].id = orig[part[s].id];
+}
+
+// the range check of the binning, over the whole set (walled: lo <= x <= hi,
+// periodic: lo <= x < hi, NaN fails)
+__global__ __launch_bounds__(kTB) void k_range_check(const double *__restrict__ xyz, int64_t n, Grid G,
+                                                     int32_t *__restrict__ err)
+{
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+        for (int d = 0; d < 3; d++) {
+            const double x = xyz[3 * i + d];
+            bad |= !(G.per[d] ? (x >= G.lo[d] && x < G.hi[d]) : (x >= G.lo[d] && x <= G.hi[d]));
+        }
+    if (bad) atomicOr(err, 1);
+}
+
+// The chunk certificate: a particle farther than a finished cell's search
+// radius (sqrt(lim), section 2.1.3) cannot cut it, so the cell is final when
+// every particle missing from the chunk's container -- those beyond either
+// end [zlo, zhi) of the widened range along z -- is that far; otherwise the
+// cell is flagged to be computed again.  Cells that failed are left as they
+// are.
+__global__ __launch_bounds__(kTB) void k_slab_cert(const Particle *__restrict__ part, const int32_t *__restrict__ list,
+                                                   int64_t m, const double *__restrict__ lim, double zlo, double zhi,
+                                                   double per, double eps, uint8_t bit, uint8_t *__restrict__ status)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kTB + threadIdx.x; k < m; k += (int64_t)gridDim.x * kTB) {
+        const int32_t si = list[k];
+        const int32_t id = part[si].id;
+        const uint8_t st = status[id];
+        if ((st & 63) > 1) continue;
+        const double pz = part[si].z;
+        double dlo = pz - zlo, dhi = zhi - pz;
+        if (dlo < 0.0) dlo += per;
+        if (dhi < 0.0) dhi += per;
+        const double d = fmin(dlo, dhi) - eps;
+        if (!(d > 0.0 && lim[si] < d * d)) status[id] = st | bit;
+    }
+}
+
+// cells whose status carries `bit`
+__global__ __launch_bounds__(kTB) void k_count_bit(const uint8_t *__restrict__ st, int64_t n, uint8_t bit,
+                                                   int32_t *__restrict__ out)
+{
+    int c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+        c += (st[i] & bit) ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+template <class P>
+hipError_t pick_impl(const P &p, int64_t n, int32_t *cnt, int32_t *start, int32_t *tmp, bool scatter, hipStream_t s);
+
 template <typename T>
 hipError_t scan_impl(const int32_t *in, int64_t n, T *out, T *tmp, hipStream_t s)
 {
@@ -304,7 +473,74 @@ hipError_t scan_impl(const int32_t *in, int64_t n, T *out, T *tmp, hipStream_t s
     return hipGetLastError();
 }
 
+// count (and with `scatter`, write) the picks of `p` over n items: cnt and
+// start hold ceil(n / kPickTile) (+ 1) entries, start[last] the total
+template <class P>
+hipError_t pick_impl(const P &p, int64_t n, int32_t *cnt, int32_t *start, int32_t *tmp, bool scatter, hipStream_t s)
+{
+    const int64_t tiles = pick_tiles(n);
+    if (!scatter) {
+        k_pick_count<P><<<(unsigned)tiles, kTB, 0, s>>>(p, n, cnt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return scan_impl<int32_t>(cnt, tiles, start, tmp, s);
+    }
+    k_pick_scatter<P><<<(unsigned)tiles, kTB, 0, s>>>(p, n, start);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int64_t pick_tiles(int64_t n) { return std::max<int64_t>(1, (n + kPickTile - 1) / kPickTile); }
+
+hipError_t launch_slab_pick(const double *xyz, int64_t n, const Grid &G, int e0, int elen, int k0, int klen,
+                            const uint8_t *want, uint8_t wbit, double *oxyz, int32_t *orig, uint8_t *own,
+                            int32_t *cnt, int32_t *start, int32_t *tmp, bool scatter, hipStream_t s)
+{
+    const SlabPick p{xyz, G, e0, elen, k0, klen, want, wbit, oxyz, orig, own};
+    return pick_impl(p, n, cnt, start, tmp, scatter, s);
+}
+
+hipError_t launch_own_count(const double *xyz, int64_t n, const Grid &G, int k0, int klen, const uint8_t *want,
+                            uint8_t wbit, int32_t *cnt, int32_t *start, int32_t *tmp, hipStream_t s)
+{
+    const OwnPick p{xyz, G, k0, klen, want, wbit};
+    return pick_impl(p, n, cnt, start, tmp, false, s);
+}
+
+hipError_t launch_slot_list(const Particle *part, const uint8_t *own, int64_t m, int32_t *list, int32_t *cnt,
+                            int32_t *start, int32_t *tmp, hipStream_t s)
+{
+    const SlotPick p{part, own, list};
+    hipError_t e = pick_impl(p, m, cnt, start, tmp, false, s);
+    if (e != hipSuccess) return e;
+    return pick_impl(p, m, cnt, start, tmp, true, s);
+}
+
+hipError_t launch_remap_ids(Particle *part, int64_t m, const int32_t *orig, hipStream_t s)
+{
+    if (m > 0) k_remap_ids<<<grid_for(m), kTB, 0, s>>>(part, m, orig);
+    return hipGetLastError();
+}
+
+hipError_t launch_range_check(const double *xyz, int64_t n, const Grid &G, int32_t *err, hipStream_t s)
+{
+    if (n > 0) k_range_check<<<grid_for(n), kTB, 0, s>>>(xyz, n, G, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_slab_cert(const Particle *part, const int32_t *list, int64_t m, const double *lim, double zlo,
+                            double zhi, double per, double eps, uint8_t bit, uint8_t *status, hipStream_t s)
+{
+    if (m > 0) k_slab_cert<<<grid_for(m), kTB, 0, s>>>(part, list, m, lim, zlo, zhi, per, eps, bit, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_bit(const uint8_t *st, int64_t n, uint8_t bit, int32_t *out, hipStream_t s)
+{
+    if (n > 0) k_count_bit<<<grid_for(n), kTB, 0, s>>>(st, n, bit, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_bin_count(const double *xyz, int64_t n, int dim, const Tess *tess, const int32_t *ptess,
                             int32_t *blk, int32_t *rank, int32_t *count, int32_t *err, hipStream_t s)

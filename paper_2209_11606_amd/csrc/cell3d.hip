@@ -907,7 +907,9 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
         if (A.nf) A.nf[id] = nface;
     }
     if (A.fo && lane < kFoLen) A.fo[(int64_t)id * kFoLen + lane] = (uint8_t)min(sh.fo[lane], 255);
-    return capfail ? ST_CAP : (foover ? ST_FO_OVER : ST_OK);
+    if (capfail) return ST_CAP;
+    if (A.lim_out && lane == 0) A.lim_out[si] = c.lim;
+    return foover ? ST_FO_OVER : ST_OK;
 }
 
 // two waves per SIMD for the main kernels (the register allocator is held

@@ -1105,6 +1105,7 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> 
         if (A.ne) A.ne[id] = sumord / 2;
         if (A.nf) A.nf[id] = nface;
         A.status[id] = (uint8_t)(foover ? ST_FO_OVER : ST_OK);
+        if (A.lim_out) A.lim_out[sh.gs.si] = c.lim;
     }
     if (A.fo)
         for (int k = gl; k < kFoLen; k += G) A.fo[(int64_t)id * kFoLen + k] = (uint8_t)min(sh.u.st.fo[k], 255);

@@ -471,6 +471,7 @@ enum { ST_OK = 0, ST_CAP = 1, ST_DUP = 3, ST_EMPTY = 5 };
 // face-order vector does not count that face
 constexpr int ST_FO_OVER = 64;
 
+
 // ---------------------------------------------------------------------------
 // Block bound (section 2.1.3).  A particle at q (relative to the cell's
 // particle) cuts the cell only if some vertex v lies strictly beyond its

@@ -23,6 +23,10 @@ constexpr int kWbMaxV = (kWbStride - 3) / 4;
 // waves spent in phase k (0 NEW, 1 GATHER, 2 BATCH, 3 TEST, 4 CUT, 5 STATS,
 // 7 the failure path and loop control), kPhaseCnt + k the number of times
 // the phase body ran on a wave (slot 6: TEST iterations).
+// status flag of the chunked form (a cell to compute again with a wider
+// halo); never left in a returned result
+constexpr int kStatusSlab = 128;
+
 constexpr int kPhaseSlots = 8;
 constexpr int kPhaseClk = 16;
 constexpr int kPhaseCnt = 24;
@@ -115,6 +119,9 @@ struct CellArgs {
     int xscratch_len;          // doubles per wave
     uint8_t *wbg;              // Weinberg codes requested: edge-graph records, id * kWbStride
     int32_t *wbl;              // code length 2E of each record, 0: no code
+    // the chunked form: each finished cell's squared search radius, by
+    // sorted index (NULL: not kept)
+    double *lim_out;
 };
 
 // Launchers (defined in the .hip translation unit).
@@ -143,5 +150,21 @@ hipError_t launch_nbr_compact(const int32_t *nf, int64_t n, const int32_t *nbr, 
                               int64_t *offsets, int32_t *ids, uint8_t *shifts, int32_t *tmp, hipStream_t s);
 hipError_t launch_nbr_offsets(const int32_t *nf, int64_t n, int64_t *offsets, int32_t *tmp, hipStream_t s);
 int device_cu_count();
+// the chunked form: tiles of the order-preserving selection (count and start
+// arrays hold pick_tiles(n) and pick_tiles(n) + 1 entries; the scan's
+// workspace as for launch_scan over pick_tiles(n) entries)
+int64_t pick_tiles(int64_t n);
+hipError_t launch_slab_pick(const double *xyz, int64_t n, const Grid &G, int e0, int elen, int k0, int klen,
+                            const uint8_t *want, uint8_t wbit, double *oxyz, int32_t *orig, uint8_t *own,
+                            int32_t *cnt, int32_t *start, int32_t *tmp, bool scatter, hipStream_t s);
+hipError_t launch_own_count(const double *xyz, int64_t n, const Grid &G, int k0, int klen, const uint8_t *want,
+                            uint8_t wbit, int32_t *cnt, int32_t *start, int32_t *tmp, hipStream_t s);
+hipError_t launch_slot_list(const Particle *part, const uint8_t *own, int64_t m, int32_t *list, int32_t *cnt,
+                            int32_t *start, int32_t *tmp, hipStream_t s);
+hipError_t launch_remap_ids(Particle *part, int64_t m, const int32_t *orig, hipStream_t s);
+hipError_t launch_range_check(const double *xyz, int64_t n, const Grid &G, int32_t *err, hipStream_t s);
+hipError_t launch_slab_cert(const Particle *part, const int32_t *list, int64_t m, const double *lim, double zlo,
+                            double zhi, double per, double eps, uint8_t bit, uint8_t *status, hipStream_t s);
+hipError_t launch_count_bit(const uint8_t *st, int64_t n, uint8_t bit, int32_t *out, hipStream_t s);
 
 }  // namespace vc

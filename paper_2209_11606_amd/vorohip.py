@@ -33,7 +33,7 @@ VC_WEINBERG = 256
 VC_FO_LEN = 32
 VC_DIAG_LEN = 32
 DIAG_NAMES = ["candidates", "tests", "cuts", "new_vertices", "exact", "recheck", "spilled", "blocks", "fallback",
-              "shells", "loaded"]
+              "shells", "loaded", "recomputed"]
 PHASE_NAMES = ["new", "gather", "batch", "test", "cut", "stats", "test_iterations", "control"]
 _FIELD_DTYPE = {VC_F_VOLUME: np.float64, VC_F_CENTROID: np.float64, VC_F_NV: np.int32, VC_F_NE: np.int32,
                 VC_F_NF: np.int32, VC_F_FACE_ORDERS: np.uint8, VC_F_NBR_OFFSETS: np.int64, VC_F_NBR_IDS: np.int32,
@@ -93,6 +93,7 @@ def _load():
         "vc_version": (ctypes.c_char_p, []),
         "vc_device_fma_rate": (I32, [I32, I32, P, P]),
         "vc_tessellate_noalloc": (I32, [P, I64, P, P, P, P, P, P, P, P, P]),
+        "vc_tessellate_slabs": (I32, [P, I64, P, U32, I32, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -108,7 +109,7 @@ EXPORTED = ["vc_options_init", "vc_container_create", "vc_container_rebin", "vc_
             "vc_result_get", "vc_result_copy", "vc_result_kernel_ms", "vc_result_destroy", "vc_container_destroy", "vc_batch_create",
             "vc_batch_rebin", "vc_batch_result_create", "vc_batch_compute", "vc_batch_tune", "vc_batch_tune_members",
             "vc_batch_destroy",
-            "vc_last_error", "vc_version", "vc_device_fma_rate", "vc_tessellate_noalloc"]
+            "vc_last_error", "vc_version", "vc_device_fma_rate", "vc_tessellate_noalloc", "vc_tessellate_slabs"]
 
 
 def lib():
@@ -169,6 +170,21 @@ def vc_container_create(xyz, opts, stream=None):
     h = ctypes.c_void_p()
     _check(_lib.vc_container_create(ctypes.c_void_p(ptr), n, ctypes.byref(opts), ctypes.c_void_p(_stream_ptr(stream)),
                                     ctypes.byref(h)))
+    return h
+
+
+def vc_tessellate_slabs(xyz, opts, mask, nslab, halo, stream=None):
+    """The chunked form for one large 3D set (positions as for
+    vc_container_create): returns a new result handle of n cells by input
+    index, computed in nslab chunks of layers along z with `halo` more
+    layers on each side."""
+    n = xyz.shape[0]
+    if not hasattr(xyz, "data_ptr"):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    ptr = xyz.data_ptr() if hasattr(xyz, "data_ptr") else xyz.ctypes.data
+    h = ctypes.c_void_p()
+    _check(_lib.vc_tessellate_slabs(ctypes.c_void_p(ptr), n, ctypes.byref(opts), mask, int(nslab), int(halo),
+                                    ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
     return h
 
 

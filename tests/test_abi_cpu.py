@@ -69,6 +69,19 @@ def test_argument_validation_without_gpu():
     assert L.vc_device_fma_rate(v.VC_FP64, 0, None, ctypes.byref(t)) == v.VC_E_ARG
     assert L.vc_device_fma_rate(5, 3, None, ctypes.byref(t)) == v.VC_E_ARG
     assert v.vc_version().startswith("vorohip")
+    # the chunked form: dimension, chunk and halo counts, mask
+    o2 = v.vc_options_init(2, [0, 0], [1, 1], [0, 0])
+    S = L.vc_tessellate_slabs
+    assert S(x.ctypes.data, 4, ctypes.byref(o2), v.VC_VOLUME, 2, 1, None, ctypes.byref(h)) == v.VC_E_ARG
+    assert "3D" in v.vc_last_error()
+    assert S(x.ctypes.data, 4, ctypes.byref(o), v.VC_VOLUME, 0, 1, None, ctypes.byref(h)) == v.VC_E_ARG
+    assert S(x.ctypes.data, 4, ctypes.byref(o), v.VC_VOLUME, 2, 0, None, ctypes.byref(h)) == v.VC_E_ARG
+    assert S(x.ctypes.data, 0, ctypes.byref(o), v.VC_VOLUME, 2, 1, None, ctypes.byref(h)) == v.VC_E_ARG
+    assert S(None, 4, ctypes.byref(o), v.VC_VOLUME, 2, 1, None, ctypes.byref(h)) == v.VC_E_ARG
+    assert S(x.ctypes.data, 4, ctypes.byref(o), v.VC_VOLUME, 2, 1, None, None) == v.VC_E_ARG
+    for m in (v.VC_NEIGHBORS, v.VC_WEINBERG, v.VC_PERIMETER, 1 << 12):
+        assert S(x.ctypes.data, 4, ctypes.byref(o), v.VC_VOLUME | m, 2, 1, None, ctypes.byref(h)) == v.VC_E_ARG
+    assert "per-cell fields only" in v.vc_last_error()
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
