@@ -105,7 +105,11 @@ enum {
 #define VC_FO_LEN 32
 #define VC_DIAG_LEN 32
 
-/* per-cell status (VC_F_STATUS) */
+/* per-cell status (VC_F_STATUS).  VC_CELL_SPILLED: complete, computed by a
+   pass after the main one (the main kernel left it: beyond its vertex
+   capacity, or, in the forms with several cells per wavefront, an extended
+   cell whose search reaches past the nearest blocks); VC_CELL_CAPACITY: not
+   computed, beyond the last pass's capacity. */
 enum { VC_CELL_OK = 0, VC_CELL_SPILLED = 1, VC_CELL_CAPACITY = 2, VC_CELL_DUPLICATE = 3,
        VC_CELL_SKIPPED = 4, /* not in the list of vc_compute_subset */
        VC_CELL_EMPTY = 5,   /* radical tessellation: the cell has no volume */
@@ -125,7 +129,7 @@ enum {
     VC_D_NEWV = 3,        /* vertices created */
     VC_D_EXACT = 4,       /* side decisions taken exactly */
     VC_D_RECHECK = 5,     /* FP32 tests re-done in FP64 (VC_F32_FILTER) */
-    VC_D_SPILLED = 6,     /* cells re-run in the large-capacity kernel */
+    VC_D_SPILLED = 6,     /* cells the main pass left to the later passes */
     VC_D_BLOCKS = 7,      /* blocks whose particles were loaded */
     VC_D_FALLBACK = 8,    /* cells that searched beyond the precomputed offsets */
     VC_D_SHELLS = 9,      /* Chebyshev shells of blocks searched beyond them
@@ -396,7 +400,7 @@ vc_status vc_device_fma_rate(int precision, int reps, void *stream, double *tflo
  * no hipMalloc, hipFree or other allocating routine: the block-sorted
  * particles, the binning arrays, the work-queue counters, the spill list
  * and the exact predicate's workspace live in one file-scope device array of
- * about 15.8 MiB that each GPU the library runs on holds until the process
+ * about 16.0 MiB that each GPU the library runs on holds until the process
  * ends.  Inputs and outputs are the caller's device memory:
  *   xyz: n x dim doubles (particle-major), 1 <= n <= 65536, inside the box
  *   of *opt (a coordinate outside it marks every cell VC_CELL_RANGE, on the

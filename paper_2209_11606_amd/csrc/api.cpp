@@ -237,6 +237,7 @@ struct vc_container {
     int32_t *queue = nullptr;    // [0]: main queue head, [1]: spill queue head, [2]: spill count,
                                  // [3..5]: the Weinberg code kernels' heads and list count
     int32_t *spill_list = nullptr;
+    int32_t *spill_list2 = nullptr;  // 3D: overflows of the first spill pass
     int32_t *sample_list = nullptr;  // tuning sample (batches)
     int nsample = 0;
     double *xscratch = nullptr;
@@ -279,6 +280,7 @@ struct vc_result {
     unsigned long long *diag = nullptr;
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the main cell kernel
+    hipEvent_t ev2 = nullptr;                 // after the spill passes
 };
 
 namespace {
@@ -297,7 +299,8 @@ void free_container(vc_container *c)
     if (!c) return;
     release_graph(c);
     void *ps[] = {c->tess, c->ptess, c->xyz, c->part, c->start, c->count, c->blk, c->rank, c->sid, c->inv, c->subset, c->subset_ids, c->err, c->scan_tmp,
-                  c->rad_in, c->rad, c->rmax, c->offs, c->queue, c->spill_list, c->sample_list, c->xscratch};
+                  c->rad_in, c->rad, c->rmax, c->offs, c->queue, c->spill_list, c->spill_list2, c->sample_list,
+                  c->xscratch};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete c;
@@ -312,6 +315,7 @@ void free_result(vc_result *r)
         if (p) (void)hipFree(p);
     if (r->ev0) (void)hipEventDestroy(r->ev0);
     if (r->ev1) (void)hipEventDestroy(r->ev1);
+    if (r->ev2) (void)hipEventDestroy(r->ev2);
     delete r;
 }
 
@@ -423,6 +427,7 @@ vc_status create_common(vc_container *c, const double *xyz, const int64_t *offse
     TRY(dalloc(&c->offs, offs.size()));
     TRY(dalloc(&c->queue, 8));
     TRY(dalloc(&c->spill_list, (size_t)c->n));
+    if (dim == 3) TRY(dalloc(&c->spill_list2, (size_t)c->n));
     TRY(dalloc(&c->xscratch, (size_t)c->max_waves * c->xscratch_len));
 #undef TRY
     HIP_TRY(hipMemcpyAsync(c->tess, c->htess.data(), c->htess.size() * sizeof(Tess), hipMemcpyHostToDevice, s));
@@ -478,6 +483,34 @@ CellArgs cell_args(const vc_container *c, const vc_result *r)
     return A;
 }
 
+// The passes after the main one, over the cells it left (their count is
+// read on the device).  2D: the large-capacity pass.  3D after the grouped
+// kernel: first the one-cell kernel (extended cells and cells beyond the
+// grouped capacity), then the large-capacity pass over what overflows
+// there; 3D after the one-cell kernel: the large-capacity pass.
+hipError_t enqueue_spill(const vc_container *c, const CellArgs &A, int cpw, hipStream_t s)
+{
+    CellArgs B = A;
+    B.cell_list = c->spill_list;
+    B.queue = c->queue + 1;
+    B.ncell_dev = c->queue + 2;
+    B.ncell = (int)c->n;
+    B.chunk = 1;
+    B.vcap = 0;
+    if (c->dim == 2) return launch_cells2d_spill(B, std::min(c->max_waves, 1024), s);
+    if (cpw > 1) {
+        CellArgs H = B;
+        H.spill_list = c->spill_list2;
+        H.spill_count = c->queue + 7;
+        hipError_t e = launch_cells_handoff(H, std::min(c->max_waves, 4096), s);
+        if (e != hipSuccess) return e;
+        B.cell_list = c->spill_list2;
+        B.queue = c->queue + 6;
+        B.ncell_dev = c->queue + 7;
+    }
+    return launch_cells_spill(B, std::min(c->max_waves, 1024), s);
+}
+
 // The launch sequence of one compute (graph-capturable: fill kernels, no
 // memset; events only when `events` is set).
 vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool events, const Launch &L,
@@ -497,17 +530,8 @@ vc_status enqueue_compute(vc_container *c, vc_result *r, hipStream_t s, bool eve
     else if (L.cpw > 1) HIP_TRY(launch_cells_group(A, c->precision, L.cpw, std::min(L.waves, c->max_waves), s));
     else HIP_TRY(launch_cells(A, c->precision, L.slots, std::min(L.waves, c->max_waves), s));
     if (events) HIP_TRY(hipEventRecord(r->ev1, s));
-    // cells beyond the main kernel's capacity: large-capacity pass over the
-    // spill list (its length is read on the device)
-    CellArgs B = A;
-    B.cell_list = c->spill_list;
-    B.queue = c->queue + 1;
-    B.ncell_dev = c->queue + 2;
-    B.ncell = (int)c->n;
-    B.chunk = 1;
-    B.vcap = 0;
-    if (c->dim == 2) HIP_TRY(launch_cells2d_spill(B, std::min(c->max_waves, 1024), s));
-    else HIP_TRY(launch_cells_spill(B, std::min(c->max_waves, 1024), s));
+    HIP_TRY(enqueue_spill(c, A, L.cpw, s));
+    if (events) HIP_TRY(hipEventRecord(r->ev2, s));
     if (r->mask & VC_WEINBERG) {
         // codes of every cell with a record, written at the scan of their lengths
         HIP_TRY(launch_nbr_offsets(r->wbl, r->n, r->wb_off, r->scan_tmp, s));
@@ -552,8 +576,8 @@ vc_status time_launch(vc_container *b, vc_result *r, hipStream_t s, const Launch
         if (st) return st;
         if (rep == 0) continue;
         float ms = 0.f;
-        HIP_TRY(hipEventSynchronize(r->ev1));
-        HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev1));
+        HIP_TRY(hipEventSynchronize(r->ev2));
+        HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev2));
         out = std::min(out, ms);
     }
     return VC_OK;
@@ -675,7 +699,8 @@ vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
     TRY(dalloc(&r->status, n));
     TRY(dalloc(&r->diag, VC_DIAG_LEN));
 #undef TRY
-    if (hipEventCreate(&r->ev0) != hipSuccess || hipEventCreate(&r->ev1) != hipSuccess) {
+    if (hipEventCreate(&r->ev0) != hipSuccess || hipEventCreate(&r->ev1) != hipSuccess ||
+        hipEventCreate(&r->ev2) != hipSuccess) {
         free_result(r);
         return fail(VC_E_HIP, "hipEventCreate failed");
     }
@@ -707,14 +732,15 @@ constexpr size_t kNaRank = kNaBlk + na_align(4 * kNaMaxN);
 constexpr size_t kNaSid = kNaRank + na_align(4 * kNaMaxN);
 constexpr size_t kNaInv = kNaSid + na_align(4 * kNaMaxN);
 constexpr size_t kNaSpill = kNaInv + na_align(4 * kNaMaxN);
-constexpr size_t kNaStart = kNaSpill + na_align(4 * kNaMaxN);
+constexpr size_t kNaSpill2 = kNaSpill + na_align(4 * kNaMaxN);
+constexpr size_t kNaStart = kNaSpill2 + na_align(4 * kNaMaxN);
 constexpr size_t kNaCount = kNaStart + na_align(4 * (kNaMaxBlocks + 1));
 constexpr size_t kNaScan = kNaCount + na_align(4 * kNaMaxBlocks);
 constexpr size_t kNaErr = kNaScan + na_align(4 * 1024);
 constexpr size_t kNaQueue = kNaErr + 256;
 constexpr size_t kNaDiag = kNaQueue + 256;
 constexpr size_t kNaX = kNaDiag + na_align(8 * VC_DIAG_LEN);
-constexpr size_t kNaBytes = kNaX + (size_t)8 * kNaWaves * kNaXLen;  // about 15.8 MiB
+constexpr size_t kNaBytes = kNaX + (size_t)8 * kNaWaves * kNaXLen;  // about 16.0 MiB
 
 static __device__ __align__(256) unsigned char scratch[kNaBytes];
 
@@ -1024,14 +1050,7 @@ vc_status slab_pass(const double *dxyz, int64_t n, const vc_options &opt, const 
             HIP_TRY(launch_fill_i32(c->queue, 8, 0, s));
             if (L.cpw > 1) HIP_TRY(launch_cells_group(A, c->precision, L.cpw, std::min(L.waves, c->max_waves), s));
             else HIP_TRY(launch_cells(A, c->precision, L.slots, std::min(L.waves, c->max_waves), s));
-            CellArgs Bs = A;
-            Bs.cell_list = c->spill_list;
-            Bs.queue = c->queue + 1;
-            Bs.ncell_dev = c->queue + 2;
-            Bs.ncell = (int)c->n;
-            Bs.chunk = 1;
-            Bs.vcap = 0;
-            HIP_TRY(launch_cells_spill(Bs, std::min(c->max_waves, 1024), s));
+            HIP_TRY(enqueue_spill(c, A, L.cpw, s));
             if (cert)
                 HIP_TRY(launch_slab_cert(c->part, B.list, nl, B.lim, zlo, zhi, G.per[2] ? G.L[2] : 0.0,
                                          0x1p-40 * (std::fabs(G.lo[2]) + std::fabs(G.hi[2]) + G.L[2]),
@@ -1447,14 +1466,27 @@ vc_status vc_tessellate_noalloc(const double *xyz, int64_t n, const vc_options *
     if (opt->dim == 2) HIP_TRY(launch_cells2d(A, opt->precision, waves, s));
     else if (cpw > 1) HIP_TRY(launch_cells_group(A, opt->precision, cpw, waves, s));
     else HIP_TRY(launch_cells(A, opt->precision, opt->slots > 0 ? opt->slots : 2, waves, s));
+    // the passes after the main one, as for a container
     CellArgs B = A;
     B.cell_list = spill;
     B.queue = queue + 1;
     B.ncell_dev = queue + 2;
     B.chunk = 1;
     B.vcap = 0;
-    if (opt->dim == 2) HIP_TRY(launch_cells2d_spill(B, kNaWaves, s));
-    else HIP_TRY(launch_cells_spill(B, kNaWaves, s));
+    if (opt->dim == 2) {
+        HIP_TRY(launch_cells2d_spill(B, kNaWaves, s));
+    } else {
+        if (cpw > 1) {
+            CellArgs H = B;
+            H.spill_list = reinterpret_cast<int32_t *>(b + kNaSpill2);
+            H.spill_count = queue + 7;
+            HIP_TRY(launch_cells_handoff(H, kNaWaves, s));
+            B.cell_list = H.spill_list;
+            B.queue = queue + 6;
+            B.ncell_dev = queue + 7;
+        }
+        HIP_TRY(launch_cells_spill(B, kNaWaves, s));
+    }
     k_flag_range<<<(int)std::min<int64_t>((n + 255) / 256, 256), 256, 0, s>>>(err, status, n);
     HIP_TRY(hipGetLastError());
     return VC_OK;

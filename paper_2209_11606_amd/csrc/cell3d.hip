@@ -913,7 +913,11 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
 }
 
 // two waves per SIMD for the main kernels (the register allocator is held
-// to that budget); the spill kernel's LDS allows one
+// to that budget); the spill kernel's LDS allows one.  spill_mode: 0 the
+// main pass (a cell beyond the capacity goes to the spill list), 2 a first
+// spill pass (its cells are marked SPILLED, and a cell beyond the capacity
+// goes on to the next list), 1 the last pass (beyond its capacity a cell is
+// VC_CELL_CAPACITY)
 template <int S, int MAXP, bool F32, int K, bool RAD, bool WB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MAXP == 48 ? 2 : 1))) void k_cells(CellArgs Ain,
                                                                                                      int spill_mode)
@@ -965,14 +969,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MAXP == 48 ?
                     A.status[id] = (uint8_t)((spill_mode ? 1 : 0) | fov);
                 } else if (st == ST_DUP) {
                     A.status[id] = 3;
-                } else if (!spill_mode) {
+                } else if (spill_mode != 1) {
                     A.status[id] = 1;
                     int pos = atomicAdd(A.spill_count, 1);
                     A.spill_list[pos] = si;
                 } else {
                     A.status[id] = 2;
                 }
-                if (st == ST_CAP && !spill_mode) cnt[DC_SPILL]++;
+                if (st == ST_CAP && spill_mode == 0) cnt[DC_SPILL]++;
             }
             __syncthreads();
         }
@@ -1016,6 +1020,22 @@ hipError_t launch_cells(const CellArgs &a, int precision, int slots, int waves, 
     if (slots == 4) VC_CELLS(4);
     else VC_CELLS(2);
 #undef VC_CELLS
+    return hipGetLastError();
+}
+
+// The first spill pass: the one-cell kernel of the main pass (capacity
+// 128), for the cells the grouped kernel left (extended or beyond its
+// capacity); its own overflows go on to the large-capacity pass.
+hipError_t launch_cells_handoff(const CellArgs &a, int waves, hipStream_t s)
+{
+    const bool rad = a.rad != nullptr, wb = a.wbg != nullptr;
+    if (rad) {
+        if (wb) k_cells<2, 48, false, 1, true, true><<<waves, 64, 0, s>>>(a, 2);
+        else k_cells<2, 48, false, 1, true, false><<<waves, 64, 0, s>>>(a, 2);
+    } else {
+        if (wb) k_cells<2, 48, false, 1, false, true><<<waves, 64, 0, s>>>(a, 2);
+        else k_cells<2, 48, false, 1, false, false><<<waves, 64, 0, s>>>(a, 2);
+    }
     return hipGetLastError();
 }
 

@@ -7,7 +7,11 @@
 // with a ballot, in-band vertices are decided exactly, and a cut replaces the
 // conflict region by a fan of new triangles around the new plane.  The
 // candidates come from the grid blocks in nearest-first order (section
-// 2.1.3) and the search ends by the radius bound (section 2.1.3).
+// 2.1.3) and the search ends by the radius bound (section 2.1.3).  A cell
+// whose search radius still reaches four block sides after its nearest
+// blocks, or whose search would run past the precomputed block offsets (an
+// extended cell, section 3.1), is left to the spill pass: the one-cell
+// kernel of cell3d.hip, whose 64 lanes run the block bound's shell search.
 //
 // Mapping.  A cell is owned by a group of G lanes (G = 16 or 32, so 64/G
 // cells share a wavefront).  Each group runs a small state machine:
@@ -153,9 +157,7 @@ struct GState {
     int fl[3];              // reflection of the block offsets per axis (+1 or -1)
     int si, id;             // sorted index, input index
     double ri;              // the particle's radius (radical tessellation), else 0
-    int shell;              // 0: offset list; r > 0: Chebyshev shell r
-    int cur;                // next offset index, or position in the shell
-    int bbhit;              // a block of the current shell met the bounding box of the block bound
+    int cur;                // next offset index
     int gtot, gc0;          // candidates of the gather, next batch start
     int cell, cend;         // claimed range of the work queue
     int tcur;               // the tessellation whose record is in the group's Tess
@@ -395,7 +397,6 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP, RAD> &s
     c.nlive = 8;
     lds_fence();
     update_radius<G, S, F32>(c, gl, A, sh.gs.ri);
-    sh.gs.shell = 0;
     sh.gs.cur = 0;
     c.phase = PH_GATHER;
 }
@@ -410,86 +411,33 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP, RAD>
     const double lim = c.lim;
     int dd[3] = {0, 0, 0};
     bool v = false;
-    if (sh.gs.shell == 0) {
-        if (sh.gs.cur >= A.noff) {
-            sh.gs.shell = A.off_radius + 1;
-            sh.gs.cur = 0;
-            sh.gs.cnt[DC_FALLBACK]++;
-        } else if (A.offs[sh.gs.cur].m * 0.25 * T.bsmin2 >= lim) {
-            c.phase = PH_STATS;  // no block left in the offset list can hold a cutting particle
-            return;
-        } else {
-            int o = sh.gs.cur + gl;
-            v = o < A.noff;
-            Offset of = v ? A.offs[o] : Offset{0, 0, 0, 0};
-            dd[0] = of.dx * sh.gs.fl[0];
-            dd[1] = of.dy * sh.gs.fl[1];
-            dd[2] = of.dz * sh.gs.fl[2];
-            sh.gs.cur += G;
-        }
-    }
-    if (sh.gs.shell > 0) {
-        const int r = sh.gs.shell;
-        if (sh.gs.cur == 0) {
-            if (r > kMaxShell || !(c.lim < 1e300)) {
-                c.phase = -ST_CAP;
-                return;
-            }
-            double lb = 1e300;
-            bool exists = false;
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                double blo = G3.lo[d] + sh.gs.bc[d] * G3.bs[d];
-                double mrg = fmin(sh.gs.p[d] - blo, blo + G3.bs[d] - sh.gs.p[d]);
-                lb = fmin(lb, (r - 1) * G3.bs[d] + mrg);
-                if (G3.per[d] || sh.gs.bc[d] - r >= 0 || sh.gs.bc[d] + r < G3.g[d]) exists = true;
-            }
-            if (!exists || (lb > 0.0 && lb * lb >= lim)) {
-                c.phase = PH_STATS;
-                return;
-            }
-            sh.gs.bbhit = 0;
-            sh.gs.cnt[DC_SHELLS]++;
-        }
-        const int tot = shell_size3(r);
-        const int ix = sh.gs.cur + gl;
-        v = ix < tot;
-        if (v) shell_block3(r, ix, dd[0], dd[1], dd[2]);
-        // block bound (section 2.1.3): blocks outside a wall and blocks
-        // that miss the bounding box of the balls are skipped, and a shell
-        // in which every block misses it ends the search
-        {
-            const double extra = A.rad ? fmax(*A.rmax * *A.rmax - sh.gs.ri * sh.gs.ri, 0.0) : 0.0;
-            double ext[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int s = 0; s < S; s++)
-                if ((c.live[s] >> gl) & 1) bb_ext_add(ext, c.vx[s], c.vy[s], c.vz[s], extra);
-#pragma unroll
-            for (int k = 0; k < 6; k++) ext[k] = gmax_f64<G>(ext[k]);
-            double blo[3];
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                const int t = sh.gs.bc[d] + dd[d];
-                if (!G3.per[d] && (t < 0 || t >= G3.g[d])) v = false;
-                blo[d] = G3.lo[d] + t * G3.bs[d] - sh.gs.p[d];
-            }
-            v = v && bb_in_ext(ext, blo, G3.bs, bb_pad(G3, sh.gs.p, 3), 3);
-        }
-        const int hit = sh.gs.bbhit | (gbal<G>(v, gb) != 0u);
-        sh.gs.bbhit = hit;
+    if (sh.gs.cur >= A.noff) {
+        // past the offset list: the shell search of the block bound is the
+        // one-cell kernel's (the spill pass), as for the extended cells below
+        c.phase = -ST_CAP;
+        return;
+    } else if (A.offs[sh.gs.cur].m * 0.25 * T.bsmin2 >= lim) {
+        c.phase = PH_STATS;  // no block left in the offset list can hold a cutting particle
+        return;
+    } else if (sh.gs.cur >= G && lim > 16.0 * T.bsmin2) {
+        // after the nearest blocks the search radius still reaches four
+        // block sides, past most of the offset list: an extended cell
+        // (section 3.1), left to the one-cell kernel of the spill pass,
+        // which tests the list's blocks against the balls and takes 64
+        // blocks of a shell per step
+        c.phase = -ST_CAP;
+        return;
+    } else {
+        int o = sh.gs.cur + gl;
+        v = o < A.noff;
+        Offset of = v ? A.offs[o] : Offset{0, 0, 0, 0};
+        dd[0] = of.dx * sh.gs.fl[0];
+        dd[1] = of.dy * sh.gs.fl[1];
+        dd[2] = of.dz * sh.gs.fl[2];
         sh.gs.cur += G;
-        if (sh.gs.cur >= tot) {
-            if (!hit) {
-                c.phase = PH_STATS;
-                return;
-            }
-            sh.gs.shell++;
-            sh.gs.cur = 0;
-        }
     }
     // the blocks: periodic wrap by whole periods (at most two each way), walls
     int bb[3], sv[3];
-    double rel[3];
     bool ok = v;
     double d2b = 0.0;
 #pragma unroll
@@ -515,7 +463,6 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP, RAD>
         double blo = G3.lo[d] + t * G3.bs[d];
         double e = fmax(0.0, fmax(blo - sh.gs.p[d], sh.gs.p[d] - (blo + G3.bs[d])));
         d2b += e * e;
-        rel[d] = blo - sh.gs.p[d];
     }
     if (d2b >= lim) ok = false;
     int cntb = 0, beg = 0;
@@ -523,26 +470,6 @@ __device__ __forceinline__ void ph_gather(const CellArgs &A, SL<G, S, MAXP, RAD>
         int blk = T.bbase + bb[0] + G3.g[0] * (bb[1] + G3.g[1] * bb[2]);
         beg = A.start[blk];
         cntb = A.start[blk + 1] - beg;
-    }
-    if (sh.gs.shell > 0) {
-        // shell blocks: only non-empty blocks that meet the balls (the ball
-        // list sits in the search buffers, free between batches)
-        ok = ok && cntb > 0;
-        if (gbal<G>(ok, gb)) {
-            static_assert(sizeof(sh.u) >= sizeof(float4) * G * S, "ball list does not fit");
-            float4 *bbl = reinterpret_cast<float4 *>(&sh.u);
-            const double extra = A.rad ? fmax(*A.rmax * *A.rmax - sh.gs.ri * sh.gs.ri, 0.0) : 0.0;
-            int nv = 0;
-#pragma unroll
-            for (int s = 0; s < S; s++) {
-                const uint32_t m = c.live[s];
-                if ((m >> gl) & 1) bb_put(bbl, nv + __popc(m & ((1u << gl) - 1u)), c.vx[s], c.vy[s], c.vz[s], extra);
-                nv += __popc(m);
-            }
-            lds_fence();
-            ok = ok && bb_meets(bbl, nv, rel, G3.bs, bb_pad(G3, sh.gs.p, 3), 3);
-        }
-        if (!ok) cntb = 0;
     }
     sh.gs.cnt[DC_BLOCKS] += __popc(gbal<G>(ok, gb));
     int incl = gscan_incl<G>(cntb);

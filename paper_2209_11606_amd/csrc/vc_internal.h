@@ -138,6 +138,7 @@ hipError_t launch_radii_check(const double *rin, int64_t n, double *rmax, int32_
 hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_cells(const CellArgs &a, int precision, int slots, int waves, hipStream_t s);
+hipError_t launch_cells_handoff(const CellArgs &a, int waves, hipStream_t s);
 hipError_t launch_cells_spill(const CellArgs &a, int waves, hipStream_t s);
 hipError_t launch_cells_group(const CellArgs &a, int precision, int cells_per_wave, int waves, hipStream_t s);
 hipError_t launch_cells2d(const CellArgs &a, int precision, int waves, hipStream_t s);

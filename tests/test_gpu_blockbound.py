@@ -67,7 +67,10 @@ def test_sc_lattice_fine_grid(v, cpw):
     x, hi = W.sc(m, 1.0)
     out = run(v, x, [0] * 3, hi, [1, 1, 1], grid=[g] * 3, cells_per_wave=cpw)
     n = m ** 3
-    assert np.all(out["status"] == 0)
+    # the grouped forms leave extended cells to the one-cell kernel of the
+    # spill pass after their first gather of 64 / cpw blocks
+    spilled = cpw > 1
+    assert np.all(out["status"] == (v.VC_CELL_SPILLED if spilled else v.VC_CELL_OK))
     assert np.all(out["nf"] == 6) and np.all(out["nv"] == 8) and np.all(out["ne"] == 12)
     assert np.all(np.abs(out["vol"] - 1.0) <= 1e-12)
     assert np.all(np.abs(out["cen"]) <= 1e-12)  # relative to the particle
@@ -82,16 +85,19 @@ def test_sc_lattice_fine_grid(v, cpw):
     assert counts == {(21, 17)}
     d = out["diag"]
     assert d["fallback"] == n and d["shells"] == 17 * n
+    assert d["spilled"] == (n if spilled else 0)
     # blocks loaded: in the offset list every block of the first chunk of 64
-    # (the first cell is the whole box), then the rest of the list (all 9^3
-    # blocks in the grouped form; in the one-cell form, which applies the
-    # block bound to the list once the cell is extended, only non-empty
-    # blocks that meet the balls: none), then, in the shells, the non-empty
-    # blocks that meet the balls, among those of the 26 nearest sites
-    near = 64 if cpw == 1 else 9 ** 3
+    # (the first cell is the whole box), then, as the one-cell kernel
+    # applies the block bound to the list once the cell is extended, only
+    # non-empty blocks that meet the balls (none), then, in the shells, the
+    # non-empty blocks that meet the balls, among those of the 26 nearest
+    # sites; a grouped form first gathers its 64 / cpw nearest blocks
+    near = 64 + (64 // cpw if spilled else 0)
     assert n * (near + 6) <= d["blocks"] <= n * (near + 26)
-    # particles loaded: the cell's own, then those of the blocks loaded
-    assert n * 7 <= d["loaded"] <= n * 27
+    # particles loaded: the cell's own (twice in a grouped form), then
+    # those of the blocks loaded
+    own = 2 if spilled else 1
+    assert n * (6 + own) <= d["loaded"] <= n * (26 + own)
 
 
 @pytest.mark.parametrize("radical", [False, True])
