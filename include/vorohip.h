@@ -66,7 +66,8 @@ enum {
 enum {
     VC_F_VOLUME = 0,      /* double[n] */
     VC_F_CENTROID = 1,    /* double[n * dim], particle-major */
-    VC_F_NV = 2,          /* int32[n] vertex count */
+    VC_F_NV = 2,          /* int32[n] vertex count (counts fit 16 bits; 32-bit arrays
+                             are what torch and numpy index with directly) */
     VC_F_NE = 3,          /* int32[n] edge count */
     VC_F_NF = 4,          /* int32[n] face (neighbour) count */
     VC_F_FACE_ORDERS = 5, /* uint8[n * VC_FO_LEN]: fo[k] = faces with k edges */
@@ -74,7 +75,10 @@ enum {
     VC_F_NBR_IDS = 7,     /* int32[total]: neighbour particle id, or -1..-6 for the
                              walls x-, x+, y-, y+, z-, z+ (2D: -1..-4) */
     VC_F_NBR_SHIFTS = 8,  /* uint8[total]: periodic image code
-                             25(s_z+2) + 5(s_y+2) + (s_x+2), 62 = no shift */
+                             25(s_z+2) + 5(s_y+2) + (s_x+2), 62 = no shift;
+                             base 5, shifts -2..2: in a periodic box that holds
+                             few particles a cell reaches images two periods
+                             away */
     VC_F_STATUS = 9,      /* uint8[n]: VC_CELL_* */
     VC_F_DIAG = 10,       /* int64[VC_DIAG_LEN] */
     VC_F_PERIMETER = 11,  /* double[n], 2D */

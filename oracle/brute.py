@@ -12,6 +12,7 @@ This is independent of the C oracle and of the GPU library (different
 representation, different algorithm, exact arithmetic throughout) and is used
 to pin both on inputs of at most ~50 particles.
 """
+import math
 from fractions import Fraction as Fr
 from itertools import product
 
@@ -80,7 +81,8 @@ def _planes(xyz, i, lo, hi, periodic, clip=0.0, radii=None):
 def cell(xyz, i, lo, hi, periodic, clip=0.0, radii=None):
     """Exact cell of particle i (clipped by the cube of side `clip` centred
     on the particle when clip > 0; the radical cell when radii are given).
-    Returns dict(vol, cen, nv, ne, nf, fo, nbr, empty, sizes) with vol and cen as
+    Returns dict(vol, cen, nv, ne, nf, fo, nbr, empty, sizes, and in 2D perim,
+    the sum of the edge lengths, each the square root of its exact square) with vol and cen as
     Fractions and nbr sorted (label, image) pairs."""
     xyz = np.asarray(xyz, dtype=np.float64)
     dim = xyz.shape[1]
@@ -156,6 +158,7 @@ def _stats(verts, planes, dim):
     vol = Fr(0)
     cen = [Fr(0)] * dim
     fo = [0] * 32
+    perim = []  # 2D: edge lengths, each the square root of an exact square
     for k, vs in faces.items():
         pts = [verts[v][0] for v in vs]
         # signed pieces (origin, face): the particle need not lie inside its
@@ -185,14 +188,18 @@ def _stats(verts, planes, dim):
                 a, b = b, a
             tri = (a[0] * b[1] - a[1] * b[0]) / 2
             vol += tri
+            perim.append(math.sqrt((b[0] - a[0]) ** 2 + (b[1] - a[1]) ** 2))
             for d in range(2):
                 cen[d] += tri * (a[d] + b[d]) / 3
     cen = [c / vol for c in cen]
     nbr = sorted((planes[k][2], planes[k][3]) for k in faces)
     ne = len(edges)
     sizes = sorted(len(vs) for vs in faces.values())
-    return dict(vol=vol, cen=cen, nv=nv, ne=ne if dim == 3 else nv, nf=len(faces), fo=fo, nbr=nbr, empty=False,
-                sizes=sizes)
+    out = dict(vol=vol, cen=cen, nv=nv, ne=ne if dim == 3 else nv, nf=len(faces), fo=fo, nbr=nbr, empty=False,
+               sizes=sizes)
+    if dim == 2:
+        out["perim"] = math.fsum(perim)
+    return out
 
 
 def _ring(pts, normal):

@@ -39,6 +39,9 @@ def _same_cell(r, i, b, spacing=0.0):
     scale = vol ** (1.0 / dim)
     for d, c in enumerate(b["cen"]):
         assert abs(r["cen"][i][d] - float(c)) <= 1e-12 * scale + 1e-13 * spacing
+    if "perim" in b:
+        # each edge's length from the exact vertices, rounded once
+        assert abs(r["perim"][i] - b["perim"]) <= 1e-13 * b["perim"] + 1e-13 * spacing
 
 
 @pytest.mark.parametrize("n,per,seed", [(30, [0, 0, 0], 7), (24, [1, 1, 1], 8), (20, [1, 0, 1], 11)])
