@@ -198,3 +198,20 @@ def ring_face(k=40, rho=0.2, delta=0.05):
     ring = np.stack([0.5 + rho * np.cos(t), 0.5 + rho * np.sin(t), np.full(k, 0.5)], 1)
     axis = np.array([[0.5, 0.5, 0.5 - delta], [0.5, 0.5, 0.5 + delta]])
     return np.concatenate([axis, ring])
+
+
+def thin_lattice(k=5, eps=1e-13, spacing=0.17, theta=0.3, seed=5):
+    """A crafted set for ill-conditioned vertices, in the walled unit cube: a
+    k x k square lattice (spacing `spacing`, turned by `theta` about the z
+    axis, centred) in the plane z = 1/2, each point moved along z by up to
+    eps/2.  Four lattice points around a square are cocircular in the plane,
+    so the cells meet in tall columns whose corners split into short edges,
+    and the three nearly vertical bisector planes of such a vertex have
+    normals within about eps of one plane: the vertex's 3x3 system has
+    |det| / (|n_a| |n_b| |n_c|) of order eps."""
+    g = (np.arange(k) - (k - 1) / 2) * spacing
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    x = 0.5 + np.cos(theta) * X.ravel() - np.sin(theta) * Y.ravel()
+    y = 0.5 + np.sin(theta) * X.ravel() + np.cos(theta) * Y.ravel()
+    z = 0.5 + eps * (rng(seed).random(k * k) - 0.5)
+    return np.ascontiguousarray(np.stack([x, y, z], 1))

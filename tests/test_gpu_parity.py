@@ -295,3 +295,25 @@ def test_force_bits_checked(v):
     with pytest.raises(v.VcError) as e:
         run(v, x, [0] * 3, [1] * 3, [0] * 3, force=4)
     assert e.value.code == v.VC_E_ARG
+
+
+@pytest.mark.parametrize("eps", [1e-8, 1e-13])
+def test_ill_conditioned_vertices(v, eps):
+    """A turned square lattice of 900 points in a slab of thickness eps:
+    the cells are tall columns whose corners split into short edges, and
+    those vertices solve 3x3 systems with |det| / (|n_a||n_b||n_c|) of order
+    eps.  Every form against the oracle (itself pinned on such a set by the
+    exact brute force), the FP32 filter bitwise within a form; on the coarse
+    grid the grouped forms keep the columns, on the default grid they leave
+    them to the one-cell kernel as extended cells."""
+    x = W.thin_lattice(30, eps, spacing=0.025)
+    box = ([0] * 3, [1] * 3, [0] * 3)
+    r = oracle.Oracle(x, *box).cells()
+    for grid in (None, [3, 3, 1]):
+        kw = {} if grid is None else dict(grid=grid)
+        for form in (dict(), dict(slots=4), dict(cells_per_wave=2), dict(cells_per_wave=4)):
+            g = run(v, x, *box, **kw, **form)
+            assert_parity(g, r)
+            same_bits(g, run(v, x, *box, precision=v.VC_F32_FILTER, **kw, **form))
+            if grid is not None and form.get("cells_per_wave", 1) > 1:
+                assert g["diag"]["spilled"] == 0

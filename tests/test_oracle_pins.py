@@ -78,6 +78,21 @@ def test_brute_force_scale(dim):
         _same_cell(r, i, brute.cell(x, i, [0] * dim, [1] * dim, [0] * dim))
 
 
+@pytest.mark.parametrize("eps", [1e-6, 1e-13])
+def test_brute_force_ill_conditioned_vertices(eps):
+    """Cells whose vertices solve nearly singular 3x3 systems (a turned
+    square lattice in a slab of thickness eps: |det| / (|n_a||n_b||n_c|) of
+    order eps at the columns' corners, far past what the side test's band
+    covers by a plain error bound) equal the exact brute force's: the
+    vertex error lies along the near-null direction, which the planes
+    tested against such a vertex do not resolve."""
+    x = W.thin_lattice(5, eps)
+    o = oracle.Oracle(x, [0] * 3, [1] * 3, [0] * 3)
+    r = o.cells()
+    for i in range(len(x)):
+        _same_cell(r, i, brute.cell(x, i, [0] * 3, [1] * 3, [0] * 3))
+
+
 def test_brute_force_nonunit_box():
     """A box with non-unit, unequal sides and an offset origin."""
     lo, hi = [-1.5, 2.0, 0.25], [0.5, 2.75, 1.75]
