@@ -1059,6 +1059,7 @@ vc_status slab_pass(const double *dxyz, int64_t n, const vc_options &opt, const 
             return VC_OK;
         }();
     }
+    if (st) (void)hipStreamSynchronize(s);  // nothing in flight may use the container
     free_container(c);
     return st;
 }
@@ -1086,22 +1087,24 @@ vc_status vc_tessellate_slabs(const double *xyz, int64_t n, const vc_options *op
     // the positions on the device (the caller's, or a copy of host ones)
     double *dcopy = nullptr;
     const double *dxyz = xyz;
-    if (!is_device_ptr(xyz)) {
-        if ((st = dalloc(&dcopy, (size_t)n * 3))) return st;
-        HIP_TRY(hipMemcpyAsync(dcopy, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice, s));
-        dxyz = dcopy;
-    }
-    // a fake one-particle container describes the result's shape
+    const bool on_host = !is_device_ptr(xyz);
+    // an empty container record carries only the result's shape (dim, n)
     vc_container shape;
     shape.dim = 3;
     shape.n = n;
     vc_result *r = nullptr;
     int32_t *flag = nullptr;
+    SlabBufs B;  // chunk buffers, kept across chunks and passes
     st = result_create(&shape, mask, &r);
     if (!st) st = dalloc(&flag, 2);
+    if (!st && on_host) st = dalloc(&dcopy, (size_t)n * 3);
     if (!st) {
         st = [&]() -> vc_status {
             hipError_t he;
+            if (on_host) {
+                HIP_TRY(hipMemcpyAsync(dcopy, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+                dxyz = dcopy;
+            }
             HIP_TRY(launch_fill_i32(flag, 2, 0, s));
             HIP_TRY(launch_range_check(dxyz, n, G, flag, s));
             if (read_i32(flag, s, he)) {
@@ -1113,7 +1116,6 @@ vc_status vc_tessellate_slabs(const double *xyz, int64_t n, const vc_options *op
             HIP_TRY(launch_fill_u8(r->status, n, 0, s));
             HIP_TRY(launch_fill_i32((int32_t *)r->diag, VC_DIAG_LEN * 2, 0, s));
             HIP_TRY(hipEventRecord(r->ev0, s));
-            SlabBufs B;
             const uint8_t *want = nullptr;  // the first pass computes every cell
             unsigned long long again = 0;     // cells computed again
             for (int h = halo;; h *= 2) {
@@ -1138,6 +1140,7 @@ vc_status vc_tessellate_slabs(const double *xyz, int64_t n, const vc_options *op
             return VC_OK;
         }();
     }
+    if (st) (void)hipStreamSynchronize(s);  // nothing in flight may use what is freed
     if (flag) (void)hipFree(flag);
     if (dcopy) (void)hipFree(dcopy);
     if (st) {
