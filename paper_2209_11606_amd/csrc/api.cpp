@@ -646,22 +646,20 @@ void report_tuning(const Launch &win, float wms, vc_tuning *best)
     best->capacity = win.vcap;
 }
 
-vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
+// A result of n cells of dimension dim for the statistics mask, owned by
+// container c (NULL: by none, as the chunked form's).
+vc_status result_alloc(const vc_container *c, int64_t n, int dim, uint32_t mask, vc_result **out)
 {
-    if (!out) return fail(VC_E_ARG, "result_create: out is null");
-    *out = nullptr;
-    if (!c) return fail(VC_E_ARG, "result_create: container is null");
     if (mask & ~(uint32_t)(VC_ALL | VC_PERIMETER | VC_WEINBERG))
         return fail(VC_E_ARG, "result_create: unknown mask bits 0x%x", mask);
-    if ((mask & VC_PERIMETER) && c->dim != 2) return fail(VC_E_ARG, "result_create: the perimeter is a 2D field");
-    if ((mask & VC_WEINBERG) && c->dim != 3) return fail(VC_E_ARG, "result_create: Weinberg codes are a 3D field");
+    if ((mask & VC_PERIMETER) && dim != 2) return fail(VC_E_ARG, "result_create: the perimeter is a 2D field");
+    if ((mask & VC_WEINBERG) && dim != 3) return fail(VC_E_ARG, "result_create: Weinberg codes are a 3D field");
     vc_result *r = new (std::nothrow) vc_result();
     if (!r) return fail(VC_E_NOMEM, "host allocation failed");
     r->c = c;
     r->mask = mask;
-    r->n = c->n;
-    r->dim = c->dim;
-    int64_t n = c->n;
+    r->n = n;
+    r->dim = dim;
     vc_status st = VC_OK;
 #define TRY(x)               \
     do {                     \
@@ -706,6 +704,14 @@ vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
     }
     *out = r;
     return VC_OK;
+}
+
+vc_status result_create(const vc_container *c, uint32_t mask, vc_result **out)
+{
+    if (!out) return fail(VC_E_ARG, "result_create: out is null");
+    *out = nullptr;
+    if (!c) return fail(VC_E_ARG, "result_create: container is null");
+    return result_alloc(c, c->n, c->dim, mask, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1088,14 +1094,10 @@ vc_status vc_tessellate_slabs(const double *xyz, int64_t n, const vc_options *op
     double *dcopy = nullptr;
     const double *dxyz = xyz;
     const bool on_host = !is_device_ptr(xyz);
-    // an empty container record carries only the result's shape (dim, n)
-    vc_container shape;
-    shape.dim = 3;
-    shape.n = n;
     vc_result *r = nullptr;
     int32_t *flag = nullptr;
     SlabBufs B;  // chunk buffers, kept across chunks and passes
-    st = result_create(&shape, mask, &r);
+    st = result_alloc(nullptr, n, 3, mask, &r);
     if (!st) st = dalloc(&flag, 2);
     if (!st && on_host) st = dalloc(&dcopy, (size_t)n * 3);
     if (!st) {
@@ -1147,7 +1149,6 @@ vc_status vc_tessellate_slabs(const double *xyz, int64_t n, const vc_options *op
         free_result(r);
         return st;
     }
-    r->c = nullptr;
     *out = r;
     return VC_OK;
 }
