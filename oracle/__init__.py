@@ -76,6 +76,8 @@ def _load():
         lib.vo_weinberg.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_double, P, ctypes.c_int, P, P, P]
         lib.vo_cell_edges.restype = ctypes.c_int
         lib.vo_cell_edges.argtypes = [P, ctypes.c_int64, ctypes.c_double, P, ctypes.c_int]
+        lib.vo_cell_faces.restype = ctypes.c_int
+        lib.vo_cell_faces.argtypes = [P, ctypes.c_int64, ctypes.c_double, P, P, P, P, ctypes.c_int, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -214,6 +216,25 @@ class Oracle:
         if k < 0:
             raise RuntimeError(f"oracle: cell computation failed with code {k}")
         return buf[:k].copy()
+
+    def faces(self, i, tau=TAU):
+        """Faces of the 3D cell of particle i: a list of (label, image code,
+        vertex array relative to the particle), each face's vertices in one
+        rotational sense."""
+        lab = np.zeros(1024, np.int32)
+        sh = np.zeros(1024, np.int32)
+        ln = np.zeros(1024, np.int32)
+        ring = np.zeros(16384, np.int32)
+        k = _load().vo_cell_faces(self._h, int(i), tau, lab.ctypes.data, sh.ctypes.data, ln.ctypes.data,
+                                  ring.ctypes.data, 1024, 16384)
+        if k < 0:
+            raise RuntimeError(f"oracle: cell computation failed with code {k}")
+        v = self.vertices(i, tau)
+        out, at = [], 0
+        for f in range(k):
+            out.append((int(lab[f]), int(sh[f]), v[ring[at:at + ln[f]]]))
+            at += ln[f]
+        return out
 
     def vertices(self, i, tau=TAU):
         """Vertices of the cell of particle i, relative to the particle."""

@@ -1389,6 +1389,41 @@ int vo_weinberg(const vo_handle *H, const int64_t *idx, int64_t m, int nthreads,
     return err;
 }
 
+/* Faces of the 3D cell of particle i, for geometry checks in tests: for
+ * face f, its plane's label and image code and its vertex count, and its
+ * vertex ids (indices into vo_cell_vertices' list) in one rotational sense,
+ * packed one face after another in `ring`.  Returns the face count (up to
+ * maxf faces and maxring ids written), or a negative error. */
+int vo_cell_faces(const vo_handle *H, int64_t i, double tau, int32_t *lab, int32_t *shift, int32_t *len,
+                  int32_t *ring, int maxf, int maxring)
+{
+    if (!H || H->dim != 3 || i < 0 || i >= H->n) return VO_ERR_ARG;
+    ocell *c = (ocell *)calloc(1, sizeof(ocell));
+    int64_t ccap = 256;
+    ocand *cbuf = (ocand *)malloc((size_t)ccap * sizeof(ocand));
+    if (!c || !cbuf) { free(c); free(cbuf); return VO_ERR_MEM; }
+    c->tau = tau;
+    int rc = compute_cell(H, i, c, &cbuf, &ccap);
+    if (rc == VO_EMPTY) rc = 0;
+    else if (rc == VO_OK) {
+        int at = 0;
+        for (int f = 0; f < c->nf; f++) {
+            if (f < maxf) {
+                const oplane *pl = &c->pl[c->fplane[f]];
+                lab[f] = pl->label;
+                shift[f] = pl->shift;
+                len[f] = c->fn[f];
+            }
+            for (int k = 0; k < c->fn[f]; k++, at++)
+                if (f < maxf && at < maxring) ring[at] = c->fv[f][k];
+        }
+        rc = c->nf;
+    }
+    free(c);
+    free(cbuf);
+    return rc;
+}
+
 /* Undirected edges of the 3D cell of particle i as vertex pairs (u < w),
  * for graph checks in tests.  Returns the edge count (up to maxe written),
  * or a negative error. */

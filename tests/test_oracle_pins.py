@@ -275,6 +275,56 @@ def _invariants(x, lo, hi, per, r):
                 assert (i, neg(c)) in sets[j]
 
 
+def _vector_area(ring):
+    """(1/2) sum of v_k x v_(k+1): the face's area times its unit normal, for
+    the rotational sense of the ring."""
+    return 0.5 * np.cross(ring, np.roll(ring, -1, axis=0)).sum(0)
+
+
+def _shift(code):
+    return np.array([code % 5 - 2, (code // 5) % 5 - 2, code // 25 - 2])
+
+
+@pytest.mark.parametrize("per,side,seed", [([0, 0, 0], 1.0, 31), ([1, 1, 1], 7.0, 32), ([1, 0, 1], 7.0, 33)])
+def test_face_geometry(per, side, seed):
+    """The faces' geometry: every cell's surface closes (the vector areas
+    sum to zero within 1e-12 vol^(2/3)); each face's vector area points along
+    the outward normal of its plane (the neighbour's relative vector, or the
+    wall's normal); and the face a cell shares with a neighbour is that
+    neighbour's face: the same vertex count, the same polygon in absolute
+    coordinates with the periodic image applied (within 1e-12 of the cell
+    size) and the same area (within 1e-12 vol^(2/3))."""
+    n = 343
+    x = W.uniform(n, 3, side, seed)
+    L = np.array([side] * 3)
+    o = oracle.Oracle(x, [0] * 3, [side] * 3, per)
+    r = o.cells()
+    faces = [o.faces(i) for i in range(n)]
+    walls = {-1: [-1, 0, 0], -2: [1, 0, 0], -3: [0, -1, 0], -4: [0, 1, 0], -5: [0, 0, -1], -6: [0, 0, 1]}
+    for i in range(n):
+        scale = r["vol"][i] ** (1.0 / 3.0)
+        assert len(faces[i]) == r["nf"][i]
+        tot = sum(_vector_area(ring) for _, _, ring in faces[i])
+        assert np.abs(tot).max() <= 1e-12 * scale ** 2
+        for lab, code, ring in faces[i]:
+            a = _vector_area(ring)
+            nrm = np.array(walls[lab], float) if lab < 0 else x[lab] + _shift(code) * L - x[i]
+            cos = a @ nrm / (np.linalg.norm(a) * np.linalg.norm(nrm))
+            assert cos > 1 - 1e-9, (i, lab, code, cos)
+            if lab < 0:
+                continue
+            back = 25 * (2 - _shift(code)[2]) + 5 * (2 - _shift(code)[1]) + (2 - _shift(code)[0])
+            match = [g for g in faces[lab] if g[0] == i and g[1] == back]
+            assert len(match) == 1, (i, lab, code)
+            other = match[0][2]
+            assert len(other) == len(ring)
+            pa = x[i] + ring
+            pb = x[lab] + _shift(code) * L + other
+            d = np.linalg.norm(pa[:, None, :] - pb[None, :, :], axis=2).min(1)
+            assert d.max() <= 1e-12 * scale, (i, lab, d.max())
+            assert abs(np.linalg.norm(a) - np.linalg.norm(_vector_area(other))) <= 1e-12 * scale ** 2
+
+
 def test_invariants_walled_1k():
     w = W.walled_1k()
     x = w["xyz"]
