@@ -878,43 +878,6 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> 
     }
     lds_fence();
     const bool rad = A.rad != nullptr;
-    // a vertex whose opposite vertex across an edge lies on the vertex's
-    // fourth plane is degenerate: the edge has zero length (decided exactly)
-    uint32_t zb = 0, ib = 0;
-    for (int j = 0; j < 3 * S; j++) {
-        int t = (j / 3) * G + gl, k = j % 3;
-        uint32_t t3 = sh.u.st.tpl[t];
-        if (t3 == 0xffffffffu) continue;
-        int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
-        uint32_t w3 = sh.u.st.tpl[sh.etab[b][a] & (G * S - 1)];
-        int d = (int)(w3 & 0xff) + (int)((w3 >> 8) & 0xff) + (int)((w3 >> 16) & 0xff) - a - b;
-        d = min(max(d, 0), MAXP - 1);
-        const double *nd = sh.pq[d];
-        const double *v = sh.u.st.pos[t];
-        double sd = nd[0] * v[0] + nd[1] * v[1] + nd[2] * v[2] - nd[3];
-        double bd = A.tau * ((fabs(nd[0]) + fabs(nd[1]) + fabs(nd[2])) * c.R + fabs(nd[3]));
-        if (!(sd < -bd)) ib |= 1u << j;
-    }
-    if (__ballot(ib != 0)) {
-        for (int j = 0; j < 3 * S; j++) {
-            unsigned long long wm = __ballot((ib >> j) & 1);
-            while (wm) {
-                int l = __builtin_ctzll(wm);
-                wm &= wm - 1;
-                if (lane == l) {
-                    int t = (j / 3) * G + gl, k = j % 3;
-                    uint32_t t3 = sh.u.st.tpl[t];
-                    int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
-                    uint32_t w3 = sh.u.st.tpl[sh.etab[b][a] & (G * S - 1)];
-                    int d = (int)(w3 & 0xff) + (int)((w3 >> 8) & 0xff) + (int)((w3 >> 16) & 0xff) - a - b;
-                    d = min(max(d, 0), MAXP - 1);
-                    int sg = sside3(sh, rad, t3, d, ws);
-                    if (sg == 0) zb |= 1u << j;
-                }
-                if ((l / G) == (lane / G)) sh.gs.cnt[DC_EXACT]++;
-            }
-        }
-    }
     // fan apex: the particle when it lies strictly inside the cell (every
     // face offset h > 0, always so for a Voronoi cell), else one vertex
     double o0 = 0.0, o1 = 0.0, o2 = 0.0;
@@ -935,16 +898,33 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> 
             o2 = sh.u.st.pos[t0][2];
         }
     }
+    // one pass over the edges (a, b) of every live triangle: the edge's
+    // degeneracy test and the face orders and fan terms that use it.  A
+    // vertex whose opposite vertex across an edge lies on the vertex's
+    // fourth plane is degenerate: the edge has zero length; a side clearly
+    // inside decides it here, an in-band one exactly below.  A fan
+    // tetrahedron's volume is zero when its edge has zero length, so the
+    // volume and moment sums take every edge; the face-order count skips
+    // zero-length edges.
+    uint32_t zb = 0, ib = 0;
     double v6 = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
     for (int j = 0; j < 3 * S; j++) {
         int t = (j / 3) * G + gl, k = j % 3;
         uint32_t t3 = sh.u.st.tpl[t];
         if (t3 == 0xffffffffu) continue;
         int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
-        if (!((zb >> j) & 1)) atomicAdd(&sh.u.st.forder[a], 1);
-        const double *r0 = sh.u.st.pos[sh.u.st.fref[a]];
-        const double *w0 = sh.u.st.pos[sh.etab[b][a] & (G * S - 1)];
+        const int tw = sh.etab[b][a] & (G * S - 1);
+        uint32_t w3 = sh.u.st.tpl[tw];
+        int d = (int)(w3 & 0xff) + (int)((w3 >> 8) & 0xff) + (int)((w3 >> 16) & 0xff) - a - b;
+        d = min(max(d, 0), MAXP - 1);
+        const double *nd = sh.pq[d];
         const double *v0 = sh.u.st.pos[t];
+        double sd = nd[0] * v0[0] + nd[1] * v0[1] + nd[2] * v0[2] - nd[3];
+        double bd = A.tau * ((fabs(nd[0]) + fabs(nd[1]) + fabs(nd[2])) * c.R + fabs(nd[3]));
+        if (!(sd < -bd)) ib |= 1u << j;
+        else atomicAdd(&sh.u.st.forder[a], 1);
+        const double *r0 = sh.u.st.pos[sh.u.st.fref[a]];
+        const double *w0 = sh.u.st.pos[tw];
         const double r[3] = {r0[0] - o0, r0[1] - o1, r0[2] - o2};
         const double w[3] = {w0[0] - o0, w0[1] - o1, w0[2] - o2};
         const double v[3] = {v0[0] - o0, v0[1] - o1, v0[2] - o2};
@@ -954,6 +934,27 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> 
         m0 += det * (r[0] + w[0] + v[0]);
         m1 += det * (r[1] + w[1] + v[1]);
         m2 += det * (r[2] + w[2] + v[2]);
+    }
+    if (__ballot(ib != 0)) {
+        for (int j = 0; j < 3 * S; j++) {
+            unsigned long long wm = __ballot((ib >> j) & 1);
+            while (wm) {
+                int l = __builtin_ctzll(wm);
+                wm &= wm - 1;
+                if (lane == l) {
+                    int t = (j / 3) * G + gl, k = j % 3;
+                    uint32_t t3 = sh.u.st.tpl[t];
+                    int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
+                    uint32_t w3 = sh.u.st.tpl[sh.etab[b][a] & (G * S - 1)];
+                    int d = (int)(w3 & 0xff) + (int)((w3 >> 8) & 0xff) + (int)((w3 >> 16) & 0xff) - a - b;
+                    d = min(max(d, 0), MAXP - 1);
+                    int sg = sside3(sh, rad, t3, d, ws);
+                    if (sg == 0) zb |= 1u << j;
+                    else atomicAdd(&sh.u.st.forder[a], 1);
+                }
+                if ((l / G) == (lane / G)) sh.gs.cnt[DC_EXACT]++;
+            }
+        }
     }
     int nvert = 0;
 #pragma unroll
