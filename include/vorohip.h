@@ -112,7 +112,9 @@ enum {
 /* per-cell status (VC_F_STATUS).  VC_CELL_SPILLED: complete, computed by a
    pass after the main one (the main kernel left it: beyond its vertex
    capacity, or, in the forms with several cells per wavefront, an extended
-   cell whose search reaches past the nearest blocks); VC_CELL_CAPACITY: not
+   cell whose search reaches past the nearest blocks or a cell with a side
+   decision in the exact predicate's band, which only the one-cell kernel
+   takes); VC_CELL_CAPACITY: not
    computed, beyond the last pass's capacity. */
 enum { VC_CELL_OK = 0, VC_CELL_SPILLED = 1, VC_CELL_CAPACITY = 2, VC_CELL_DUPLICATE = 3,
        VC_CELL_SKIPPED = 4, /* not in the list of vc_compute_subset */

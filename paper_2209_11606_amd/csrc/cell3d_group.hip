@@ -4,14 +4,18 @@
 // The method is the one of cell3d.hip: a cell is a set of dual triangles
 // (one per vertex, three plane ids each) with an edge table in LDS; a
 // candidate plane (the bisector of Eq. 3) is tested against every vertex
-// with a ballot, in-band vertices are decided exactly, and a cut replaces the
-// conflict region by a fan of new triangles around the new plane.  The
-// candidates come from the grid blocks in nearest-first order (section
-// 2.1.3) and the search ends by the radius bound (section 2.1.3).  A cell
-// whose search radius still reaches four block sides after its nearest
-// blocks, or whose search would run past the precomputed block offsets (an
-// extended cell, section 3.1), is left to the spill pass: the one-cell
-// kernel of cell3d.hip, whose 64 lanes run the block bound's shell search.
+// with a ballot, and a cut replaces the conflict region by a fan of new
+// triangles around the new plane.  The candidates come from the grid blocks
+// in nearest-first order (section 2.1.3) and the search ends by the radius
+// bound (section 2.1.3).  Two kinds of cell are left to the spill pass, the
+// one-cell kernel of cell3d.hip: a cell whose search radius still reaches
+// four block sides after its nearest blocks, or whose search would run past
+// the precomputed block offsets (an extended cell, section 3.1), whose 64
+// lanes run the block bound's shell search there; and a cell with a side
+// decision (a vertex test or an edge's degeneracy test) in the band of the
+// exact predicate, which decides it there.  The exact expansions stay out
+// of this kernel: they would hold registers that the cell state needs, for
+// about one side test in 10^8 on random input.
 //
 // Mapping.  A cell is owned by a group of G lanes (G = 16 or 32, so 64/G
 // cells share a wavefront).  Each group runs a small state machine:
@@ -203,33 +207,6 @@ struct SL {
         } st;
     } u;
 };
-
-template <class SLT>
-__device__ __forceinline__ PlaneD splane(const SLT &sh, int k)
-{
-    PlaneD p;
-    p.n0 = sh.pq[k][0];
-    p.n1 = sh.pq[k][1];
-    p.n2 = sh.pq[k][2];
-    p.h = sh.pq[k][3];
-    p.wall = sh.pwall[k];
-    return p;
-}
-
-template <class SLT>
-__device__ __forceinline__ PlaneR splane_r(const SLT &sh, int k)
-{
-    return PlaneR{splane(sh, k), sh.gs.ri, sh.prj[k]};
-}
-
-// exact side of plane p at the vertex of planes (a, b, c), radical or not
-template <class SLT>
-__device__ __forceinline__ int sside3(const SLT &sh, bool rad, uint32_t t3, int p, double *ws)
-{
-    const int a = t3 & 0xff, b = (t3 >> 8) & 0xff, c = (t3 >> 16) & 0xff;
-    if (rad) return exact_side3(splane_r(sh, a), splane_r(sh, b), splane_r(sh, c), splane_r(sh, p), ws);
-    return exact_side3(splane(sh, a), splane(sh, b), splane(sh, c), splane(sh, p), ws);
-}
 
 // one cell and its search state, held by a group (values are the same on
 // every lane of the group, apart from the per-lane slots)
@@ -580,8 +557,8 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP, RAD> 
 // out only when it has a conflict and parks in CUT.  The candidate's
 // offset and bands were set by BATCH.
 template <int G, int S, int MAXP, bool F32, bool RAD>
-__device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, double *ws,
-                                        uint32_t *cnt, int lane, int gl, int gb)
+__device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, uint32_t *cnt,
+                                        int gl, int gb)
 {
     if (c.bk >= c.bn) {
         c.phase = PH_BATCH;
@@ -600,8 +577,8 @@ __device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP, RAD> &
         return;
     }
     cnt[0]++;
-    const bool rad = A.rad != nullptr;
-    unsigned long long wc[S], wi[S], wz[S];
+    unsigned long long wc[S], wi[S];
+    int nre = 0;
     if (F32) {
         const float g0 = (float)q0, g1 = (float)q1, g2 = (float)q2, gh = (float)h, band32 = sh.u.w.x.cfb[k];
         unsigned long long wu[S], wun = 0;
@@ -622,7 +599,7 @@ __device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP, RAD> &
                 const double sv = fma(q0, c.vx[s], fma(q1, c.vy[s], fma(q2, c.vz[s], -h)));
                 wc[s] |= wu[s] & __builtin_amdgcn_fcmp(sv, band, 2);
                 wi[s] = wu[s] & __builtin_amdgcn_fcmp(fabs(sv), band, 13);
-                sh.gs.cnt[DC_RECHECK] += __popc((uint32_t)(wu[s] >> gb) & Gw<G>::FULL);
+                nre += __popc((uint32_t)(wu[s] >> gb) & Gw<G>::FULL);
             }
         }
     } else {
@@ -636,44 +613,30 @@ __device__ __forceinline__ void ph_test(const CellArgs &A, SL<G, S, MAXP, RAD> &
             wi[s] = lv & __builtin_amdgcn_fcmp(fabs(sv), band, 13);  // |sv| <= band or NaN
         }
     }
-    cnt[1] += c.nlive;
-    // in-band vertices: exact decision, one lane of the wave at a time
+    // an in-band vertex needs the exact predicate: the cell is left to the
+    // one-cell kernel of the spill pass, which decides it exactly; the tests
+    // and rechecks of this step are not counted (that kernel counts its own)
+    unsigned long long wib = 0;
 #pragma unroll
-    for (int s = 0; s < S; s++) {
-        unsigned long long wm = wi[s];
-        wz[s] = 0;
-        while (wm) {
-            int l = __builtin_ctzll(wm);
-            wm &= wm - 1;
-            int sg = 0;
-            if (lane == l) {
-                const PlaneD pp = {q0, q1, q2, h, 0};
-                const uint32_t t3 = c.tp[s];
-                if (rad)
-                    sg = exact_side3(splane_r(sh, t3 & 0xff), splane_r(sh, (t3 >> 8) & 0xff),
-                                     splane_r(sh, (t3 >> 16) & 0xff), PlaneR{pp, sh.gs.ri, sh.u.w.crj[k]}, ws);
-                else
-                    sg = exact_side3(splane(sh, t3 & 0xff), splane(sh, (t3 >> 8) & 0xff), splane(sh, (t3 >> 16) & 0xff),
-                                     pp, ws);
-            }
-            sg = __builtin_amdgcn_readlane(sg, l);
-            if (sg > 0) wc[s] |= 1ull << l;
-            if (sg == 0) wz[s] |= 1ull << l;
-            if ((l / G) == (lane / G)) sh.gs.cnt[DC_EXACT]++;
-        }
+    for (int s = 0; s < S; s++) wib |= wi[s];
+    if ((uint32_t)(wib >> gb) & Gw<G>::FULL) {
+        c.phase = -ST_CAP;
+        return;
     }
+    cnt[1] += c.nlive;
+    if (F32) sh.gs.cnt[DC_RECHECK] += nre;
     unsigned long long wany = 0;
 #pragma unroll
     for (int s = 0; s < S; s++) wany |= wc[s];
     if ((uint32_t)(wany >> gb) & Gw<G>::FULL) {
 #pragma unroll
         for (int s = 0; s < S; s++) c.conf[s] = (uint32_t)(wc[s] >> gb) & Gw<G>::FULL;
-        if (rad) {
+        if (A.rad) {
             // a radical plane can leave no vertex strictly inside: the cell
             // is empty (a Voronoi cell always keeps its particle inside)
             uint32_t inside = 0;
 #pragma unroll
-            for (int s = 0; s < S; s++) inside |= c.live[s] & ~c.conf[s] & ~((uint32_t)(wz[s] >> gb) & Gw<G>::FULL);
+            for (int s = 0; s < S; s++) inside |= c.live[s] & ~c.conf[s];
             if (!inside) {
 #pragma unroll
                 for (int s = 0; s < S; s++) {
@@ -834,8 +797,8 @@ __device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP, RAD> &s
 
 // ---- STATS: volume, centroid, V/E/F, face orders, neighbours ----
 template <int G, int S, int MAXP, bool F32, bool RAD>
-__device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, double *ws,
-                                         uint32_t *cnt, int lane, int gl, int gb, uint32_t below)
+__device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> &sh, SCell<S, F32> &c, uint32_t *cnt,
+                                         int gl, int gb, uint32_t below)
 {
     const int id = sh.gs.id;
     if (c.nlive == 0) {
@@ -877,7 +840,6 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> 
         for (int j = 0; j < 3; j++) atomicMin(&sh.u.st.fref[(t3 >> (8 * j)) & 0xff], t);
     }
     lds_fence();
-    const bool rad = A.rad != nullptr;
     // fan apex: the particle when it lies strictly inside the cell (every
     // face offset h > 0, always so for a Voronoi cell), else one vertex
     double o0 = 0.0, o1 = 0.0, o2 = 0.0;
@@ -902,11 +864,12 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> 
     // degeneracy test and the face orders and fan terms that use it.  A
     // vertex whose opposite vertex across an edge lies on the vertex's
     // fourth plane is degenerate: the edge has zero length; a side clearly
-    // inside decides it here, an in-band one exactly below.  A fan
+    // inside decides it here, an in-band one is left to the exact
+    // predicate of the one-cell kernel.  A fan
     // tetrahedron's volume is zero when its edge has zero length, so the
     // volume and moment sums take every edge; the face-order count skips
     // zero-length edges.
-    uint32_t zb = 0, ib = 0;
+    uint32_t ib = 0;
     double v6 = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
     for (int j = 0; j < 3 * S; j++) {
         int t = (j / 3) * G + gl, k = j % 3;
@@ -935,55 +898,18 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> 
         m1 += det * (r[1] + w[1] + v[1]);
         m2 += det * (r[2] + w[2] + v[2]);
     }
-    if (__ballot(ib != 0)) {
-        for (int j = 0; j < 3 * S; j++) {
-            unsigned long long wm = __ballot((ib >> j) & 1);
-            while (wm) {
-                int l = __builtin_ctzll(wm);
-                wm &= wm - 1;
-                if (lane == l) {
-                    int t = (j / 3) * G + gl, k = j % 3;
-                    uint32_t t3 = sh.u.st.tpl[t];
-                    int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
-                    uint32_t w3 = sh.u.st.tpl[sh.etab[b][a] & (G * S - 1)];
-                    int d = (int)(w3 & 0xff) + (int)((w3 >> 8) & 0xff) + (int)((w3 >> 16) & 0xff) - a - b;
-                    d = min(max(d, 0), MAXP - 1);
-                    int sg = sside3(sh, rad, t3, d, ws);
-                    if (sg == 0) zb |= 1u << j;
-                    else atomicAdd(&sh.u.st.forder[a], 1);
-                }
-                if ((l / G) == (lane / G)) sh.gs.cnt[DC_EXACT]++;
-            }
-        }
+    if (gbal<G>(ib != 0, gb)) {
+        // an edge whose length is in band: the exact predicate decides it
+        // in the one-cell kernel of the spill pass (nothing of the cell has
+        // been written yet)
+        lds_fence();
+        c.phase = -ST_CAP;
+        return;
     }
+    // no edge has zero length: every triangle is a vertex of its own
     int nvert = 0;
 #pragma unroll
     for (int s = 0; s < S; s++) nvert += __popc(c.live[s]);
-    if (gbal<G>(zb != 0, gb)) {
-        // merge the triangles of one geometric vertex (label propagation
-        // along zero-length edges)
-        for (int it = 0; it < 4 * S * G; it++) {
-            bool ch = false;
-            for (int j = 0; j < 3 * S; j++) {
-                if (!((zb >> j) & 1)) continue;
-                int t = (j / 3) * G + gl, k = j % 3;
-                uint32_t t3 = sh.u.st.tpl[t];
-                int a = (t3 >> (8 * k)) & 0xff, b = (t3 >> (8 * ((k + 1) % 3))) & 0xff;
-                int o = sh.u.st.lab[sh.etab[b][a] & (G * S - 1)];
-                if (o < sh.u.st.lab[t]) {
-                    sh.u.st.lab[t] = o;
-                    ch = true;
-                }
-            }
-            lds_fence();
-            if (!gbal<G>(ch, gb)) break;
-        }
-        nvert = 0;
-        for (int t0 = 0; t0 < S * G; t0 += G) {
-            int t = t0 + gl;
-            nvert += __popc(gbal<G>(sh.u.st.tpl[t] != 0xffffffffu && sh.u.st.lab[t] == t, gb));
-        }
-    }
     lds_fence();
     int rk = 0, sumord = 0;
     bool foover = false;
@@ -1018,7 +944,7 @@ __device__ __forceinline__ void ph_stats(const CellArgs &A, SL<G, S, MAXP, RAD> 
         // record's scratch (zero-length edge bits, vertex numbers, degrees)
         uint8_t *wsc = reinterpret_cast<uint8_t *>(&sh.u.st.pos[0][0]);
         wl = wb_record<G, S, MAXP>(A.wbg + (int64_t)id * kWbStride, sumord, sh.u.st.tpl, sh.u.st.lab, sh.etab, wsc,
-                                   wsc + G * S, wsc + 2 * G * S, zb, gl, gb);
+                                   wsc + G * S, wsc + 2 * G * S, 0u, gl, gb);
     }
     if (gl == 0) {
         if (A.wbl) A.wbl[id] = wl;
@@ -1059,18 +985,20 @@ __device__ __forceinline__ void flush_counters(const CellArgs &A, SL<G, S, MAXP,
     lds_fence();
 }
 
-// occupancy target in waves per SIMD: the register allocator is held to that
-// budget
-#ifndef VC_SYNC_WAVES
-#define VC_SYNC_WAVES 3
-#endif
-template <int G>
+// Occupancy target in waves per SIMD, to which the register allocator is
+// held.  The plain Voronoi instantiation of the two-cells-per-wave form runs
+// four waves: 128 registers and, with 32 plane slots per cell, 10,016 bytes
+// of LDS per wave (of the 10,240 that sixteen waves per compute unit leave).
+// The radical one (its plane radii take more LDS) and the one that writes
+// Weinberg records (the record's call takes registers) keep 40 plane slots
+// and three waves.  A cell that needs more plane slots goes to the spill pass.
+template <int G, int MAXP>
 struct SyncWaves {
-    static constexpr int value = G == 32 ? VC_SYNC_WAVES : 2;
+    static constexpr int value = G == 32 ? (MAXP <= 32 ? 4 : 3) : 2;
 };
 
 template <int G, int S, int MAXP, bool F32, bool RAD, bool WB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>::value))) void k_cells_sync(CellArgs Ain)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G, MAXP>::value))) void k_cells_sync(CellArgs Ain)
 {
     // the Voronoi instantiation carries no radical code, and one without
     // Weinberg records none of their code: those pointers are compile-time
@@ -1088,7 +1016,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
     const int gl = lane % G, gb = lane - gl;
     const uint32_t below = (1u << gl) - 1u;
     SL<G, S, MAXP, RAD> &sh = shv[lane / G];
-    double *ws = A.xscratch + (size_t)blockIdx.x * A.xscratch_len;
     uint32_t cnt[2] = {0, 0};  // candidates, vertex tests
     const int ncell = A.ncell;
     SCell<S, F32> c;
@@ -1134,11 +1061,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
         VC_PHASE_MARK(2, r_bat);
 #ifdef VC_PHASE_CLOCKS
         while (c.phase == PH_TEST) {
-            ph_test<G, S, MAXP, F32, RAD>(A, sh, c, ws, cnt, lane, gl, gb);
+            ph_test<G, S, MAXP, F32, RAD>(A, sh, c, cnt, gl, gb);
             pcnt[6]++;
         }
 #else
-        while (c.phase == PH_TEST) ph_test<G, S, MAXP, F32, RAD>(A, sh, c, ws, cnt, lane, gl, gb);
+        while (c.phase == PH_TEST) ph_test<G, S, MAXP, F32, RAD>(A, sh, c, cnt, gl, gb);
 #endif
         VC_PHASE_MARK(3, true);
         // cuts and statistics wait until no group can advance without one
@@ -1147,7 +1074,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
             if (c.phase == PH_CUT) ph_cut<G, S, MAXP, F32, RAD>(A, sh, c, cnt, gl, gb, below);
             VC_PHASE_MARK(4, r_cut);
             const bool r_st = VC_PHASE_RAN(PH_STATS);
-            if (c.phase == PH_STATS) ph_stats<G, S, MAXP, F32, RAD>(A, sh, c, ws, cnt, lane, gl, gb, below);
+            if (c.phase == PH_STATS) ph_stats<G, S, MAXP, F32, RAD>(A, sh, c, cnt, gl, gb, below);
             VC_PHASE_MARK(5, r_st);
         }
         if (c.phase < 0) cell_fail<G, S, MAXP, F32, RAD>(A, sh, c, -c.phase, gl);
@@ -1170,28 +1097,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>
 hipError_t launch_cells_group(const CellArgs &a, int precision, int cpw, int waves, hipStream_t s)
 {
     const bool rad = a.rad != nullptr, wb = a.wbg != nullptr, f32 = precision == 1;
-#define VC_GROUP(G, S, P)                                                                        \
+#define VC_GROUP(G, S, P, PR)                                                                    \
     do {                                                                                         \
         if (rad) {                                                                               \
             if (wb) {                                                                            \
-                if (f32) k_cells_sync<G, S, P, true, true, true><<<waves, 64, 0, s>>>(a);        \
-                else k_cells_sync<G, S, P, false, true, true><<<waves, 64, 0, s>>>(a);           \
+                if (f32) k_cells_sync<G, S, PR, true, true, true><<<waves, 64, 0, s>>>(a);       \
+                else k_cells_sync<G, S, PR, false, true, true><<<waves, 64, 0, s>>>(a);          \
             } else {                                                                             \
-                if (f32) k_cells_sync<G, S, P, true, true, false><<<waves, 64, 0, s>>>(a);       \
-                else k_cells_sync<G, S, P, false, true, false><<<waves, 64, 0, s>>>(a);          \
+                if (f32) k_cells_sync<G, S, PR, true, true, false><<<waves, 64, 0, s>>>(a);      \
+                else k_cells_sync<G, S, PR, false, true, false><<<waves, 64, 0, s>>>(a);         \
             }                                                                                    \
         } else {                                                                                 \
             if (wb) {                                                                            \
-                if (f32) k_cells_sync<G, S, P, true, false, true><<<waves, 64, 0, s>>>(a);       \
-                else k_cells_sync<G, S, P, false, false, true><<<waves, 64, 0, s>>>(a);          \
+                if (f32) k_cells_sync<G, S, PR, true, false, true><<<waves, 64, 0, s>>>(a);      \
+                else k_cells_sync<G, S, PR, false, false, true><<<waves, 64, 0, s>>>(a);         \
             } else {                                                                             \
                 if (f32) k_cells_sync<G, S, P, true, false, false><<<waves, 64, 0, s>>>(a);      \
                 else k_cells_sync<G, S, P, false, false, false><<<waves, 64, 0, s>>>(a);         \
             }                                                                                    \
         }                                                                                        \
     } while (0)
-    if (cpw == 4) VC_GROUP(16, 4, 32);
-    else if (cpw == 2) VC_GROUP(32, 2, 40);
+    // plane slots: P for the plain Voronoi instantiations, PR for the
+    // radical and Weinberg ones
+    if (cpw == 4) VC_GROUP(16, 4, 32, 32);
+    else if (cpw == 2) VC_GROUP(32, 2, 32, 40);
     else return hipErrorInvalidValue;
 #undef VC_GROUP
     return hipGetLastError();

@@ -70,12 +70,47 @@ __device__ inline int xs_grow(double *e, int n, double b)
     return k;
 }
 
+// Compress (Shewchuk 1997): the same exact sum in fewer components, still
+// nonoverlapping and increasing in magnitude, in place.  A downward pass of
+// Two-Sum from the largest component keeps only the parts that did not fit,
+// an upward pass renormalises them.
+__device__ inline int xs_compress(double *e, int m)
+{
+    double Q = e[m - 1];
+    int bottom = m - 1;
+    for (int i = m - 2; i >= 0; i--) {
+        double x, y;
+        xs_two_sum(Q, e[i], x, y);
+        if (y != 0.0) {
+            e[bottom--] = x;
+            Q = y;
+        } else {
+            Q = x;
+        }
+    }
+    e[bottom] = Q;
+    int top = 0;
+    for (int i = bottom + 1; i < m; i++) {
+        double x, y;
+        xs_two_sum(e[i], Q, x, y);
+        Q = x;
+        if (y != 0.0) e[top++] = y;
+    }
+    e[top++] = Q;
+    return top;
+}
+
+// the accumulator is compressed whenever it grows past this many components
+// (every Grow-Expansion step walks the whole list, in the global workspace)
+constexpr int kXsCompressAt = 16;
+
 __device__ inline int xs_add_prod(double *e, int n, double a, double b)
 {
     double x, y;
     xs_two_prod(a, b, x, y);
     if (y != 0.0) n = xs_grow(e, n, y);
-    return xs_grow(e, n, x);
+    n = xs_grow(e, n, x);
+    return n > kXsCompressAt ? xs_compress(e, n) : n;
 }
 
 __device__ inline int xs_sign(const double *e, int n)
@@ -146,6 +181,112 @@ __device__ int xs_acc_hdet(double *acc, int n, const double *hl, int nh, double 
     return n;
 }
 
+// ---------------------------------------------------------------------------
+// Double-word stage.  The expression of the exact sign below is first
+// evaluated with pairs hi + lo of doubles (about 106 bits) together with a
+// bound on the error; when the value lies outside its bound the sign is
+// certain, and only values within it (exact ties, as on lattices) go on to
+// the expansions, whose many dependent steps through the workspace cost
+// about a millisecond per call.  The pair operations are the accurate
+// double-word algorithms of Joldes, Muller and Popescu (2017), with relative
+// errors of at most 3u^2 (sum), 2u^2 (product by a double) and 4u^2
+// (product), u = 2^-53.
+// ---------------------------------------------------------------------------
+struct Dw {
+    double hi, lo;
+};
+
+// Fast-Two-Sum: exact when |a| >= |b| (or a = 0)
+__device__ inline Dw dw_fast(double a, double b)
+{
+    double s = a + b;
+    return Dw{s, b - (s - a)};
+}
+
+__device__ inline Dw dw_add(Dw a, Dw b)
+{
+    double sh, sl, th, tl;
+    xs_two_sum(a.hi, b.hi, sh, sl);
+    xs_two_sum(a.lo, b.lo, th, tl);
+    Dw v = dw_fast(sh, sl + th);
+    return dw_fast(v.hi, v.lo + tl);
+}
+
+__device__ inline Dw dw_mul_d(Dw a, double b)
+{
+    double ch, cl;
+    xs_two_prod(a.hi, b, ch, cl);
+    return dw_fast(ch, __builtin_fma(a.lo, b, cl));
+}
+
+__device__ inline Dw dw_mul(Dw a, Dw b)
+{
+    double ch, cl;
+    xs_two_prod(a.hi, b.hi, ch, cl);
+    double t = a.lo * b.lo;
+    t = __builtin_fma(a.hi, b.lo, t);
+    t = __builtin_fma(a.lo, b.hi, t);
+    return dw_fast(ch, cl + t);
+}
+
+// det of the rows u, v, w as a pair; mag = sum of the six |products|.  Each
+// product is an exact pair (Two-Product) times a double; the error is at
+// most 2u^2 mag for the products and 3u^2 mag for each of the five sums.
+__device__ inline Dw dw_det3(const double *u, const double *v, const double *w, double &mag)
+{
+    Dw acc{0.0, 0.0};
+    mag = 0.0;
+    const double x[6] = {u[0], u[1], u[2], -u[0], -u[1], -u[2]};
+    const double y[6] = {v[1], v[2], v[0], v[2], v[0], v[1]};
+    const double z[6] = {w[2], w[0], w[1], w[1], w[2], w[0]};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        double ph, pl;
+        xs_two_prod(x[k], y[k], ph, pl);
+        acc = dw_add(acc, dw_mul_d(Dw{ph, pl}, z[k]));
+        mag += fabs(ph) * fabs(z[k]);
+    }
+    return acc;
+}
+
+// The sign of exact_side3's expression, or 2 when the double-word stage
+// cannot certify it.  Error of the numerator N = sum_i +-h_i D_i, with H_i
+// the sum of |terms| of h_i and P_i the mag of D_i: at most 27u^2 H_i for h_i
+// (nine sums), 17u^2 P_i for D_i, 48u^2 H_i P_i for the product with both
+// propagated, and 9u^2 sum H_i P_i for the three sums: below 2^-100 M with
+// M = sum H_i P_i.  The bound taken is 2^-96 M (and 2^-96 P for the
+// denominator), so |N.hi| above it fixes the sign of N.  Outside
+// [2^-900, 2^900] the expansions decide (underflow and overflow).
+template <class P>
+__device__ inline int dw_side3(const P *const *r, const double (*nv)[3])
+{
+    const int mi[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    Dw num{0.0, 0.0};
+    double bound = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        double hl[kRadicalPlane<P> ? 10 : 6];
+        const int nh = xs_offset(*r[i], hl);
+        Dw h{0.0, 0.0};
+        double hm = 0.0;
+        for (int k = 0; k < nh; k++) {
+            h = dw_add(h, Dw{hl[k], 0.0});
+            hm += fabs(hl[k]);
+        }
+        double pm;
+        Dw d = dw_det3(nv[mi[i][0]], nv[mi[i][1]], nv[mi[i][2]], pm);
+        Dw t = dw_mul(h, d);
+        if (i & 1) t = Dw{-t.hi, -t.lo};
+        num = dw_add(num, t);
+        bound += hm * pm;
+    }
+    double pd;
+    const Dw den = dw_det3(nv[0], nv[1], nv[2], pd);
+    if (!(bound > 0x1p-900 && bound < 0x1p900 && pd > 0x1p-900 && pd < 0x1p900)) return 2;
+    if (!(fabs(num.hi) > bound * 0x1p-96) || !(fabs(den.hi) > pd * 0x1p-96)) return 2;
+    return ((num.hi > 0.0) == (den.hi > 0.0)) ? 1 : -1;
+}
+
 // Exact sign of n_p.v - h_p at v = planes a, b, c:
 //   s * D(a,b,c) = h_a D(b,c,p) - h_b D(a,c,p) + h_c D(a,b,p) - h_p D(a,b,c).
 // P is PlaneD (Voronoi) or PlaneR (radical).
@@ -160,6 +301,8 @@ __device__ __noinline__ int exact_side3(P a, P b, P c, P p, double *ws)
         nv[i][2] = plane_base(*r[i]).n2;
     }
     const int mi[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    const int quick = dw_side3<P>(r, nv);
+    if (quick != 2) return quick;
     double hl[kRadicalPlane<P> ? 10 : 6];  // the plane offset's exact terms
     int n = 0;
     for (int i = 0; i < 4; i++) {

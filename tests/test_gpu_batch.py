@@ -150,10 +150,13 @@ def test_full_size_periodic_1m_bench_path(v):
             for k in ("vol", "cen", "nv", "ne", "nf", "fo", "status", "nbr_off", "nbr_ids", "nbr_sh"):
                 assert np.array_equal(res[k], eager[k]), k
         # a tuned capacity below the kernel's own may send cells to the
-        # spill pass (status SPILLED); nothing else may fail
+        # spill pass (status SPILLED); nothing else may fail.  At full
+        # capacity the grouped forms leave only the cells with a side
+        # decision in the exact predicate's band to the one-cell kernel
+        # (about 16 in this set)
         assert np.all(eager["status"] <= v.VC_CELL_SPILLED)
         if tuned["capacity"] == 0:
-            assert np.all(eager["status"] == v.VC_CELL_OK)
+            assert np.sum(eager["status"] == v.VC_CELL_SPILLED) <= 100
         assert math.fsum(eager["vol"]) == pytest.approx(100.0 ** 3, rel=1e-12)
         eager["nbr"] = v.neighbor_lists(eager)
         assert_parity(eager, r, idx)

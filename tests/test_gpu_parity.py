@@ -269,9 +269,14 @@ def test_forced_recheck_and_exact(v, form):
     """The slow stages of the side test taken on every decision: with
     VC_FORCE_RECHECK every FP32 filter test is re-done in FP64 (the recheck
     counter equals the test counter), with VC_FORCE_EXACT every FP64
-    decision goes to the exact predicate (the exact counter reaches the test
-    counter).  The cells are bit for bit those of the default bands and
-    equal the oracle's, on a periodic and on a walled set."""
+    decision is in the exact predicate's band.  The one-cell forms take
+    them exactly (the exact counter reaches the test counter) and give the
+    cells of the default bands bit for bit; the grouped forms leave every
+    cell with an in-band decision to the FP64 one-cell kernel of the spill
+    pass, so forced, every cell goes there and comes out bit for bit as in
+    the one-cell form.  All equal the oracle's, on a periodic and on a
+    walled set."""
+    grouped = form.get("cells_per_wave", 1) > 1
     for per, seed in (([1, 1, 1], 17), ([0, 0, 0], 18)):
         side = 4000 ** (1 / 3)
         x = W.uniform(4000, 3, side, seed)
@@ -282,11 +287,19 @@ def test_forced_recheck_and_exact(v, form):
         same_bits(base, f)
         assert f["diag"]["recheck"] == f["diag"]["tests"] > 0
         e = run(v, x, *box, force=v.VC_FORCE_EXACT, **form)
-        same_bits(base, e)
-        assert e["diag"]["exact"] >= e["diag"]["tests"] > 0
         fe = run(v, x, *box, precision=v.VC_F32_FILTER, force=v.VC_FORCE_RECHECK | v.VC_FORCE_EXACT, **form)
-        same_bits(base, fe)
-        assert fe["diag"]["exact"] >= fe["diag"]["recheck"] == fe["diag"]["tests"]
+        if grouped:
+            one = run(v, x, *box)
+            for g in (e, fe):
+                assert g["diag"]["spilled"] == len(x) and np.all(g["status"] == v.VC_CELL_SPILLED)
+                assert g["diag"]["exact"] >= g["diag"]["tests"] > 0
+                g = dict(g, status=one["status"])
+                same_bits(one, g)
+        else:
+            same_bits(base, e)
+            assert e["diag"]["exact"] >= e["diag"]["tests"] > 0
+            same_bits(base, fe)
+            assert fe["diag"]["exact"] >= fe["diag"]["recheck"] == fe["diag"]["tests"]
 
 
 def test_force_bits_checked(v):
@@ -304,8 +317,10 @@ def test_ill_conditioned_vertices(v, eps):
     those vertices solve 3x3 systems with |det| / (|n_a||n_b||n_c|) of order
     eps.  Every form against the oracle (itself pinned on such a set by the
     exact brute force), the FP32 filter bitwise within a form; on the coarse
-    grid the grouped forms keep the columns, on the default grid they leave
-    them to the one-cell kernel as extended cells."""
+    grid the grouped forms keep the columns apart from the cells with a
+    side decision in the exact predicate's band (some at eps = 1e-8, all at
+    1e-13), which they leave to the one-cell kernel, as they leave extended
+    cells on the default grid."""
     x = W.thin_lattice(30, eps, spacing=0.025)
     box = ([0] * 3, [1] * 3, [0] * 3)
     r = oracle.Oracle(x, *box).cells()
@@ -316,4 +331,5 @@ def test_ill_conditioned_vertices(v, eps):
             assert_parity(g, r)
             same_bits(g, run(v, x, *box, precision=v.VC_F32_FILTER, **kw, **form))
             if grid is not None and form.get("cells_per_wave", 1) > 1:
-                assert g["diag"]["spilled"] == 0
+                assert g["diag"]["spilled"] == np.sum(g["status"] == v.VC_CELL_SPILLED)
+                assert 0 < g["diag"]["spilled"] < len(x) if eps == 1e-8 else g["diag"]["spilled"] == len(x)
