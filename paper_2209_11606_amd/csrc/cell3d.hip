@@ -938,6 +938,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MAXP == 48 ?
 #pragma unroll
     for (int k = 0; k < DC_N; k++) cnt[k] = 0;
     const int ncell = A.ncell_dev ? __builtin_amdgcn_readfirstlane(*A.ncell_dev) : A.ncell;
+    // claims are dynamic and the waves below this one take every cell, so a
+    // wave with nothing left to claim leaves without touching the queue (a
+    // short spill list then costs a few atomics instead of one per wave)
+    if ((int64_t)blockIdx.x * A.chunk >= ncell) return;
     for (;;) {
         int base = 0;
         if (lane == 0) base = atomicAdd(A.queue, A.chunk);
