@@ -176,7 +176,6 @@ struct SL {
     GState gs;
     Tess T;                 // the cell's tessellation
     double pq[MAXP][4];     // planes n.r = h (n = q for a bisector, h = |q|^2 / 2)
-    double prj[RAD ? MAXP : 1];  // radius of each plane's neighbour (radical planes)
     int32_t plab[MAXP];
     uint8_t psh[MAXP];
     uint8_t pwall[MAXP];
@@ -185,7 +184,6 @@ struct SL {
         struct {               // the search
             double cq[G][6];   // the batch's candidates, nearest first: q, |q|^2, plane
                                // offset h, FP64 side-test band
-            double crj[RAD ? G : 1];  // their radii (radical planes)
             int32_t cid[G];
             int32_t cpre[G];   // the gather's blocks: candidates before, first particle, image code
             int32_t cbeg[G];
@@ -330,7 +328,6 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP, RAD> &s
         sh.pwall[gl] = (uint8_t)b.wall;
         sh.plab[gl] = b.lab;
         sh.psh[gl] = b.code;
-        if (RAD) sh.prj[gl] = sh.gs.ri;  // the own images carry the own radius
         sh.pq[gl][0] = d == 0 ? b.nd : 0.0;
         sh.pq[gl][1] = d == 1 ? b.nd : 0.0;
         sh.pq[gl][2] = d == 2 ? b.nd : 0.0;
@@ -537,7 +534,6 @@ __device__ __forceinline__ void ph_batch(const CellArgs &A, SL<G, S, MAXP, RAD> 
             sh.u.w.x.cfb[rank] =
                 A.tau32 * ((fabsf(g0) + fabsf(g1) + fabsf(g2)) * ((float)c.R * 1.0000001f) + fabsf(gh));
         }
-        if (RAD) sh.u.w.crj[rank] = rj;
         sh.u.w.cid[rank] = pid;
         sh.u.w.ccode[rank] = (uint8_t)code;
     }
@@ -737,7 +733,6 @@ __device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP, RAD> &s
         sh.pq[p][1] = sh.u.w.cq[k][1];
         sh.pq[p][2] = sh.u.w.cq[k][2];
         sh.pq[p][3] = sh.u.w.cq[k][4];
-        if (RAD) sh.prj[p] = sh.u.w.crj[k];
         sh.plab[p] = sh.u.w.cid[k];
         sh.psh[p] = sh.u.w.ccode[k];
         sh.pwall[p] = 0;
@@ -986,12 +981,12 @@ __device__ __forceinline__ void flush_counters(const CellArgs &A, SL<G, S, MAXP,
 }
 
 // Occupancy target in waves per SIMD, to which the register allocator is
-// held.  The plain Voronoi instantiation of the two-cells-per-wave form runs
-// four waves: 128 registers and, with 32 plane slots per cell, 10,016 bytes
-// of LDS per wave (of the 10,240 that sixteen waves per compute unit leave).
-// The radical one (its plane radii take more LDS) and the one that writes
-// Weinberg records (the record's call takes registers) keep 40 plane slots
-// and three waves.  A cell that needs more plane slots goes to the spill pass.
+// held.  The Voronoi and radical instantiations of the two-cells-per-wave
+// form run four waves: 128 registers and, with 32 plane slots per cell,
+// 10,016 bytes of LDS per wave (of the 10,240 that sixteen waves per compute
+// unit leave).  The ones that write Weinberg records (the record's call
+// takes registers) keep 40 plane slots and three waves.  A cell that needs
+// more plane slots goes to the spill pass.
 template <int G, int MAXP>
 struct SyncWaves {
     static constexpr int value = G == 32 ? (MAXP <= 32 ? 4 : 3) : 2;
@@ -1104,8 +1099,8 @@ hipError_t launch_cells_group(const CellArgs &a, int precision, int cpw, int wav
                 if (f32) k_cells_sync<G, S, PR, true, true, true><<<waves, 64, 0, s>>>(a);       \
                 else k_cells_sync<G, S, PR, false, true, true><<<waves, 64, 0, s>>>(a);          \
             } else {                                                                             \
-                if (f32) k_cells_sync<G, S, PR, true, true, false><<<waves, 64, 0, s>>>(a);      \
-                else k_cells_sync<G, S, PR, false, true, false><<<waves, 64, 0, s>>>(a);         \
+                if (f32) k_cells_sync<G, S, P, true, true, false><<<waves, 64, 0, s>>>(a);       \
+                else k_cells_sync<G, S, P, false, true, false><<<waves, 64, 0, s>>>(a);          \
             }                                                                                    \
         } else {                                                                                 \
             if (wb) {                                                                            \
@@ -1117,8 +1112,7 @@ hipError_t launch_cells_group(const CellArgs &a, int precision, int cpw, int wav
             }                                                                                    \
         }                                                                                        \
     } while (0)
-    // plane slots: P for the plain Voronoi instantiations, PR for the
-    // radical and Weinberg ones
+    // plane slots: P without Weinberg records, PR with them
     if (cpw == 4) VC_GROUP(16, 4, 32, 32);
     else if (cpw == 2) VC_GROUP(32, 2, 32, 40);
     else return hipErrorInvalidValue;
