@@ -981,19 +981,19 @@ __device__ __forceinline__ void flush_counters(const CellArgs &A, SL<G, S, MAXP,
 }
 
 // Occupancy target in waves per SIMD, to which the register allocator is
-// held.  The Voronoi and radical instantiations of the two-cells-per-wave
-// form run four waves: 128 registers and, with 32 plane slots per cell,
-// 10,016 bytes of LDS per wave (of the 10,240 that sixteen waves per compute
-// unit leave).  The ones that write Weinberg records (the record's call
-// takes registers) keep 40 plane slots and three waves.  A cell that needs
-// more plane slots goes to the spill pass.
-template <int G, int MAXP>
+// held.  The two-cells-per-wave form runs four waves: 128 registers and,
+// with 32 plane slots per cell, 10,016 bytes of LDS per wave (of the 10,240
+// that sixteen waves per compute unit leave); a cell that needs more plane
+// slots goes to the spill pass.  (The instantiation that writes Weinberg
+// records spills more registers at that budget, around the record's call,
+// and is still faster than at three waves.)
+template <int G>
 struct SyncWaves {
-    static constexpr int value = G == 32 ? (MAXP <= 32 ? 4 : 3) : 2;
+    static constexpr int value = G == 32 ? 4 : 2;
 };
 
 template <int G, int S, int MAXP, bool F32, bool RAD, bool WB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G, MAXP>::value))) void k_cells_sync(CellArgs Ain)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G>::value))) void k_cells_sync(CellArgs Ain)
 {
     // the Voronoi instantiation carries no radical code, and one without
     // Weinberg records none of their code: those pointers are compile-time
@@ -1092,29 +1092,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SyncWaves<G,
 hipError_t launch_cells_group(const CellArgs &a, int precision, int cpw, int waves, hipStream_t s)
 {
     const bool rad = a.rad != nullptr, wb = a.wbg != nullptr, f32 = precision == 1;
-#define VC_GROUP(G, S, P, PR)                                                                    \
+#define VC_GROUP(G, S, P)                                                                        \
     do {                                                                                         \
         if (rad) {                                                                               \
             if (wb) {                                                                            \
-                if (f32) k_cells_sync<G, S, PR, true, true, true><<<waves, 64, 0, s>>>(a);       \
-                else k_cells_sync<G, S, PR, false, true, true><<<waves, 64, 0, s>>>(a);          \
+                if (f32) k_cells_sync<G, S, P, true, true, true><<<waves, 64, 0, s>>>(a);        \
+                else k_cells_sync<G, S, P, false, true, true><<<waves, 64, 0, s>>>(a);           \
             } else {                                                                             \
                 if (f32) k_cells_sync<G, S, P, true, true, false><<<waves, 64, 0, s>>>(a);       \
                 else k_cells_sync<G, S, P, false, true, false><<<waves, 64, 0, s>>>(a);          \
             }                                                                                    \
         } else {                                                                                 \
             if (wb) {                                                                            \
-                if (f32) k_cells_sync<G, S, PR, true, false, true><<<waves, 64, 0, s>>>(a);      \
-                else k_cells_sync<G, S, PR, false, false, true><<<waves, 64, 0, s>>>(a);         \
+                if (f32) k_cells_sync<G, S, P, true, false, true><<<waves, 64, 0, s>>>(a);       \
+                else k_cells_sync<G, S, P, false, false, true><<<waves, 64, 0, s>>>(a);          \
             } else {                                                                             \
                 if (f32) k_cells_sync<G, S, P, true, false, false><<<waves, 64, 0, s>>>(a);      \
                 else k_cells_sync<G, S, P, false, false, false><<<waves, 64, 0, s>>>(a);         \
             }                                                                                    \
         }                                                                                        \
     } while (0)
-    // plane slots: P without Weinberg records, PR with them
-    if (cpw == 4) VC_GROUP(16, 4, 32, 32);
-    else if (cpw == 2) VC_GROUP(32, 2, 32, 40);
+    if (cpw == 4) VC_GROUP(16, 4, 32);
+    else if (cpw == 2) VC_GROUP(32, 2, 32);
     else return hipErrorInvalidValue;
 #undef VC_GROUP
     return hipGetLastError();
