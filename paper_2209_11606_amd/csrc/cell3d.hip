@@ -912,14 +912,17 @@ __device__ __forceinline__ int cell_run(const CellArgs &A, CellLDS<S, MAXP, K> &
     return foover ? ST_FO_OVER : ST_OK;
 }
 
-// two waves per SIMD for the main kernels (the register allocator is held
-// to that budget); the spill kernel's LDS allows one.  spill_mode: 0 the
+// Waves per SIMD (the register allocator is held to that budget): three for
+// the two-slot main kernel (168 registers; its LDS allows three), two for
+// the four-slot one (its LDS allows two), one for the spill kernel.  At
+// three waves the two-slot kernel spills about 50 registers and still runs
+// a fifth faster than at two.  spill_mode: 0 the
 // main pass (a cell beyond the capacity goes to the spill list), 2 a first
 // spill pass (its cells are marked SPILLED, and a cell beyond the capacity
 // goes on to the next list), 1 the last pass (beyond its capacity a cell is
 // VC_CELL_CAPACITY)
 template <int S, int MAXP, bool F32, int K, bool RAD, bool WB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MAXP == 48 ? 2 : 1))) void k_cells(CellArgs Ain,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MAXP == 48 ? (S == 2 ? 3 : 2) : 1))) void k_cells(CellArgs Ain,
                                                                                                      int spill_mode)
 {
     // the Voronoi instantiation carries no radical code, and one without
