@@ -168,9 +168,9 @@ struct GState {
     uint32_t cnt[DC_N];     // counters other than candidates and tests
 };
 
-// RAD: the radical tessellation's arrays (plane and candidate radii) are
-// held only by its instantiation, which keeps the Voronoi one's LDS small
-// enough for three waves per SIMD
+// The group's LDS.  The radical instantiation has the same layout: its
+// plane offsets already hold the radii, and the radii themselves fed only
+// the exact predicate, which this kernel leaves to the one-cell kernel.
 template <int G, int S, int MAXP, bool RAD>
 struct SL {
     GState gs;
@@ -215,7 +215,7 @@ struct SCell {
     float fx[S], fy[S], fz[S];
     uint32_t live[S];            // live slots (group bit fields)
     uint32_t conf[S];            // conflict slots of the pending cut
-    unsigned long long used;     // plane slots in use
+    uint32_t used;               // plane slots in use (at most 32)
     double lim, R;               // squared search radius, radius bound (upper bounds)
     int nlive;                   // live slots (vertices) of the cell
     int phase;
@@ -223,11 +223,12 @@ struct SCell {
 };
 
 template <int MAXP>
-__device__ __forceinline__ int free_plane(unsigned long long used)
+__device__ __forceinline__ int free_plane(uint32_t used)
 {
-    constexpr unsigned long long valid = MAXP >= 64 ? ~0ull : ((1ull << MAXP) - 1ull);
-    unsigned long long fr = ~used & valid;
-    return fr ? __builtin_ctzll(fr) : -1;
+    static_assert(MAXP <= 32, "plane slots");
+    constexpr uint32_t valid = MAXP >= 32 ? ~0u : ((1u << MAXP) - 1u);
+    const uint32_t fr = ~used & valid;
+    return fr ? __builtin_ctz(fr) : -1;
 }
 
 // Radius bound: the largest squared vertex norm, rounded up to 20 mantissa
@@ -367,7 +368,7 @@ __device__ __forceinline__ void ph_new(const CellArgs &A, SL<G, S, MAXP, RAD> &s
             sh.etab[a][b] = (uint8_t)gl;
         }
     }
-    c.used = 0x3full;
+    c.used = 0x3fu;
     c.nlive = 8;
     lds_fence();
     update_radius<G, S, F32>(c, gl, A, sh.gs.ri);
@@ -658,20 +659,16 @@ __device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP, RAD> &s
     const int k = c.bk;
     int p = free_plane<MAXP>(c.used);
     if (p < 0) {
-        unsigned long long u = 0;
+        uint32_t u = 0;
 #pragma unroll
         for (int s = 0; s < S; s++)
             if ((c.live[s] >> gl) & 1)
 #pragma unroll
-                for (int j = 0; j < 3; j++) u |= 1ull << ((c.tp[s] >> (8 * j)) & 0xff);
-        // group OR of the 64-bit plane masks
-        unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+                for (int j = 0; j < 3; j++) u |= 1u << ((c.tp[s] >> (8 * j)) & 0xff);
+        // group OR of the plane masks
 #pragma unroll
-        for (int sh_ = 1; sh_ < G; sh_ <<= 1) {
-            lo |= (unsigned)__shfl_xor((int)lo, sh_);
-            hi |= (unsigned)__shfl_xor((int)hi, sh_);
-        }
-        c.used = ((unsigned long long)hi << 32) | lo;
+        for (int sh_ = 1; sh_ < G; sh_ <<= 1) u |= (uint32_t)__shfl_xor((int)u, sh_);
+        c.used = u;
         p = free_plane<MAXP>(c.used);
         if (p < 0) {
             c.phase = -ST_CAP;
@@ -778,7 +775,7 @@ __device__ __forceinline__ void ph_cut(const CellArgs &A, SL<G, S, MAXP, RAD> &s
         c.live[s] = (c.live[s] & ~c.conf[s]) | gbal<G>(take[s], gb);
         c.conf[s] = 0;
     }
-    c.used |= 1ull << p;
+    c.used |= 1u << p;
     int nl = 0;
 #pragma unroll
     for (int s = 0; s < S; s++) nl += __popc(c.live[s]);
