@@ -182,7 +182,11 @@ typedef struct {
 /* vc_options.force bits. VC_FORCE_RECHECK: every FP32 test of VC_F32_FILTER
    is taken as unsure and re-done in FP64; VC_FORCE_EXACT: every FP64 side test
    falls in the band and is decided by the exact predicate. Results are the
-   same as without the bits; only the diagnostic counters and the time differ. */
+   same as without the bits; only the diagnostic counters and the time differ,
+   except that with VC_FORCE_EXACT the forms with several cells per wavefront
+   (which hold no exact predicate) leave every cell to the one-cell kernel:
+   status VC_CELL_SPILLED, and volumes and centroids as that form computes
+   them (equal to the default's up to rounding; topology identical). */
 enum { VC_FORCE_RECHECK = 1, VC_FORCE_EXACT = 2 };
 
 typedef struct vc_container vc_container;
